@@ -1,0 +1,193 @@
+/*
+ * stda.h -- C ABI of the MI355X (gfx950) Radar-STDA hot path.
+ *
+ * Radar-STDA (arXiv 2307.09063) is a spatial-temporal denoising autoencoder: three consecutive
+ * interfered range-Doppler (RD) maps in, the clean RD map of the latest frame out
+ * (Sec. IV-A, Eq. (encoder_stda), Eq. (decoder_stda)).  This library runs its forward pass,
+ * its hand-written training backward pass, an SGD step, the reconstruction loss, the SINR
+ * metric and the FMCW RD-map synthesizer that produces its inputs, all as hand-written HIP
+ * kernels.
+ *
+ * Conventions shared by every entry point
+ *  - Memory.  Every pointer named *_dev, and every tensor argument, is DEVICE memory owned by
+ *    the caller; host arrays are marked host.  The library never allocates or frees device
+ *    memory: scratch comes in through `ws` (and, between a training forward and its backward,
+ *    `saved`), sized by the matching *_size query.
+ *  - Streams.  Work is enqueued on `stream` (0 = the null stream) and the call returns without
+ *    waiting.  Results are valid once the stream has been synchronised.
+ *  - Errors.  Arguments are validated before anything is enqueued; on error nothing runs and a
+ *    negative stda_status is returned.  STDA_E_HIP carries the HIP error, retrievable with
+ *    stda_last_hip_error().  No C++ exception crosses the ABI.
+ *  - Threads.  Entry points are re-entrant; two calls that share `ws` or `saved` on different
+ *    streams race.
+ *  - Layout.  Boundary maps are FP32, planar: x is [clips][3][H][W] with channel 0 = frame t,
+ *    1 = frame t-1, 2 = frame t-2 (Sec. IV-B, Eq. (concat_operation)); z, y, dz are
+ *    [clips][1][H][W].  H = range bins (samples per chirp), W = Doppler bins (chirps).
+ *    Internally activations are NHWC, FP32 or BF16.
+ */
+#ifndef STDA_H
+#define STDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STDA_OK = 0,
+  STDA_E_INVALID = -1,     /* null pointer, unknown enum, bad count                      */
+  STDA_E_SHAPE = -2,       /* H or W not a multiple of 4, below 8, or above 4096          */
+  STDA_E_WORKSPACE = -3,   /* ws / saved smaller than the size query says                 */
+  STDA_E_HIP = -4,         /* a HIP runtime call or launch failed                         */
+  STDA_E_NONFINITE = -5    /* reserved: a host-side reduction saw NaN / Inf               */
+} stda_status;
+
+typedef enum { STDA_FP32 = 0, STDA_BF16 = 1 } stda_dtype;  /* activation / weight storage  */
+typedef enum { STDA_EVAL = 0, STDA_TRAIN = 1 } stda_mode;    /* BN running vs batch stats   */
+
+/*
+ * A segment is a group of clips of one map size.  Batch-norm statistics in TRAIN mode are
+ * taken over one segment (its clips x H x W); a batch of uneven map sizes is a list of
+ * segments.  x_off / z_off are element offsets of the segment's first clip in the packed x
+ * (3*H*W floats per clip) and z / y / dz (H*W floats per clip).
+ */
+typedef struct {
+  int32_t n;        /* clips in the segment, >= 1                                          */
+  int32_t H, W;     /* range bins, Doppler bins: multiples of 4 in [8, 4096]                */
+  int64_t x_off;
+  int64_t z_off;
+} stda_segment;
+
+/* One entry of the flat FP32 parameter buffer (137,469 floats). */
+typedef struct {
+  char name[40];
+  int64_t offset;   /* element offset into the flat buffer                                 */
+  int32_t ndim;
+  int32_t shape[4]; /* conv: [Cout, Cin/groups, k, k]; deconv: [Cin, Cout/groups, k, k]      */
+  int32_t fan_in;   /* (Cin/groups) * k * k for conv and deconv weights; 0 otherwise        */
+} stda_param_desc;
+
+const char* stda_status_string(int status);
+int stda_last_hip_error(void);
+
+/* Parameter layout (the network of Sec. IV; readings of unstated sizes are fixed here). */
+size_t stda_param_count(void);
+/* Writes min(cap, count) descriptors to host `out`; returns the total count. */
+int stda_param_table(stda_param_desc* out, int cap);
+/* BN layers: 17; running buffer = per layer C means then C variances (1,184 floats). */
+int stda_bn_layer_count(void);
+size_t stda_running_count(void);
+
+/*
+ * Byte sizes of `saved` (kept from a TRAIN forward to its backward) and `ws` (scratch of a
+ * single call; one size serves forward, backward and loss).  `recompute` != 0 keeps only the
+ * block-boundary checkpoints in `saved` and recomputes block internals during the backward.
+ */
+int stda_workspace_size(const stda_segment* segs /*host*/, int n_segs, int dtype, int mode,
+                        int recompute, size_t* saved_bytes /*host out*/,
+                        size_t* ws_bytes /*host out*/);
+
+/*
+ * Forward pass of Radar-STDA (Sec. IV, Eq. (decoder_stda)): z = f(h(x_t, x_t-1, x_t-2)).
+ *   x       [sum 3*H*W]  FP32 boundary maps (segment layout above).
+ *   w       [137,469]    FP32 master parameters; BF16 mode rounds them to nearest-even.
+ *   running [1,184]      BN running mean / variance; read in EVAL, updated in TRAIN
+ *                        (momentum 0.1, unbiased variance), one update per segment in order.
+ *   z       [sum H*W]    FP32 restored map of frame t.
+ *   saved   TRAIN: filled for stda_backward (may be NULL in EVAL).
+ * Returns STDA_OK or an error (nothing enqueued on error).
+ */
+int stda_forward(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* w,
+                 float* running, float* z, void* saved, size_t saved_bytes, void* ws,
+                 size_t ws_bytes, int dtype, int mode, int recompute, hipStream_t stream);
+
+/*
+ * Hand-written adjoint of the TRAIN forward that filled `saved` (same segs, x, w, dtype,
+ * recompute; x is read again for the input-module weight gradient).  dz = dL/dz; writes dw (all 137,469 gradients, summed over segments; no zero
+ * initialisation needed) and, if dx is not NULL, dL/dx.  Weight-gradient partials are reduced
+ * across blocks in FP64.
+ */
+int stda_backward(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* dz,
+                  const float* w, const void* saved, size_t saved_bytes, float* dw, float* dx,
+                  void* ws, size_t ws_bytes, int dtype, int recompute, hipStream_t stream);
+
+/*
+ * Reconstruction loss (a reading: the paper names none): per segment the mean of (z - y)^2
+ * over its clips x H x W, summed over segments, reduced in FP64 into loss_dev[0];
+ * dz = 2 (z - y) / (n_s H W).  ws must hold stda_workspace_size's ws bytes for these segs.
+ */
+int stda_mse_loss(const stda_segment* segs /*host*/, int n_segs, const float* z, const float* y,
+                  double* loss_dev, float* dz, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * SGD with L2 weight decay over the flat master buffer: w <- w - lr (g + weight_decay w).
+ * If w_bf16 is not NULL it receives the round-to-nearest-even BF16 copy of the new w.
+ */
+int stda_sgd_step(float* w, const float* dw, int64_t n, float lr, float weight_decay,
+                  uint16_t* w_bf16, hipStream_t stream);
+
+/*
+ * SINR of Sec. V-B over a batch of maps: per map 10 log10(mean_O m^2 / mean_N m^2) where the
+ * O and N cells are given by the byte masks o_mask / n_mask ([n_maps][H][W], 1 = member).
+ * Sums are FP64; out_dev[n_maps] receives the dB values.
+ */
+int stda_sinr(const float* maps, const uint8_t* o_mask, const uint8_t* n_mask, int n_maps, int H,
+              int W, double* out_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------ RD-map synthesizer */
+#define RD_MAX_TONES 48
+#define RD_MAX_INTF 4
+
+/* Target or clutter tone of one frame: a exp(j 2 pi (fr n + fd m + ph) / 2^32). */
+typedef struct {
+  uint32_t fr;      /* range frequency, cycles/sample in 32-bit fixed point (mod 1)          */
+  uint32_t fd;      /* Doppler frequency, cycles/chirp in 32-bit fixed point (mod 1)         */
+  uint32_t ph;      /* phase at n = m = 0, cycles in 32-bit fixed point                      */
+  float amp;
+} rd_tone;
+
+/*
+ * FMCW interferer of one frame after dechirping (Sec. III-A, Eq. (IF signal)): beat frequency
+ * F(n, m) = 2 q n + f0 + m dl (signed, 2^-32 cycles/sample); the term
+ * a exp(j 2 pi ((f0 + m dl) n + q n^2 + phi_m) / 2^32) is present while |F| < 2^31.
+ * phi_m = word 0 of Philox4x32-10(counter = (m, i, frame, 1), key = (seed, clip)).
+ */
+typedef struct {
+  int64_t q;
+  int64_t f0;
+  int64_t dl;
+  float amp;
+  uint32_t pad;
+} rd_intf;
+
+typedef struct {
+  int32_t n_tones[3];                  /* per frame t, t-1, t-2                             */
+  int32_t n_intf[3];
+  rd_tone tone[3][RD_MAX_TONES];
+  rd_intf intf[3][RD_MAX_INTF];
+} rd_scene;
+
+size_t rd_synth_workspace_size(int n_clips, int N, int M);
+
+/*
+ * RD-map synthesis (Sec. III-A, Eq. (discrete signal), Eq. (IF signal); Sec. III-B,
+ * Eq. (column transform), Eq. (row transform)).  For each clip c and frame f:
+ *   s(n, m) = tones + interferers + noise, noise = sigma/sqrt(2) (g0 + j g1) with g0, g1 from
+ *   Box-Muller on words 0, 1 of Philox4x32-10(counter = (n, m, f, 0), key = (seed, clip_base + c));
+ *   periodic Hann windows on n and m; N-point DFT over n, M-point DFT over m; zero Doppler
+ *   moved to column M/2; 20 log10 |Y| floored at (max - 80 dB); min-max scaled to [0, 1].
+ * scenes: DEVICE array of n_clips rd_scene.  N, M: powers of two in [8, 1024].
+ * x_out [n_clips][3][N][M]: frames t, t-1, t-2 with interference.
+ * clean_out [n_clips][1][N][M] (may be NULL): frame t without interferers, same noise.
+ */
+int rd_synth(const rd_scene* scenes, int n_clips, int N, int M, uint32_t seed, float noise_sigma,
+             int clip_base, float* x_out, float* clean_out, void* ws, size_t ws_bytes,
+             hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STDA_H */

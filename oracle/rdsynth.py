@@ -59,8 +59,8 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
 
 
 def uniform_open(x):
-    """32-bit word -> uniform in (0, 1): top 24 bits, centred in their cell."""
-    return ((np.asarray(x, dtype=np.uint64) >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+    """32-bit word -> uniform in (0, 1): top 23 bits, centred in their cell (exact in FP32)."""
+    return ((np.asarray(x, dtype=np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
 def uniform_half_open(x):

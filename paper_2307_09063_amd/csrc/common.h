@@ -1,0 +1,90 @@
+// Shared device helpers of the Radar-STDA HIP library: storage types, 4-channel vector
+// loads/stores for NHWC rows, per-channel block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define STDA_BLOCK 256
+
+namespace stda {
+
+// BF16 storage: raw 16-bit pattern, converted to/from FP32 at every load/store.
+struct bf16 {
+  uint16_t v;
+};
+
+__device__ __forceinline__ float to_f(float x) { return x; }
+__device__ __forceinline__ float to_f(bf16 x) { return __uint_as_float((uint32_t)x.v << 16); }
+
+template <class T> __device__ __forceinline__ T from_f(float x);
+template <> __device__ __forceinline__ float from_f<float>(float x) { return x; }
+// Round to nearest even; NaN stays a quiet NaN.
+template <> __device__ __forceinline__ bf16 from_f<bf16>(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)0x7fc0};
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+__device__ __forceinline__ float round_bf16(float x) { return to_f(from_f<bf16>(x)); }
+// The value a store of type T keeps.
+template <class T> __device__ __forceinline__ float stored(float x) { return to_f(from_f<T>(x)); }
+
+// Four consecutive channels of an NHWC row (16-byte aligned for FP32, 8-byte for BF16).
+__device__ __forceinline__ void ld4(const float* p, float v[4]) {
+  float4 q = *reinterpret_cast<const float4*>(p);
+  v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+}
+__device__ __forceinline__ void ld4(const bf16* p, float v[4]) {
+  uint2 q = *reinterpret_cast<const uint2*>(p);
+  v[0] = __uint_as_float(q.x << 16);
+  v[1] = __uint_as_float(q.x & 0xffff0000u);
+  v[2] = __uint_as_float(q.y << 16);
+  v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
+__device__ __forceinline__ void st4(float* p, const float v[4]) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void st4(bf16* p, const float v[4]) {
+  uint2 q;
+  q.x = (uint32_t)from_f<bf16>(v[0]).v | ((uint32_t)from_f<bf16>(v[1]).v << 16);
+  q.y = (uint32_t)from_f<bf16>(v[2]).v | ((uint32_t)from_f<bf16>(v[3]).v << 16);
+  *reinterpret_cast<uint2*>(p) = q;
+}
+__device__ __forceinline__ void zero4(float v[4]) { v[0] = v[1] = v[2] = v[3] = 0.f; }
+
+// Per-channel block reduction for the (pixel, channel-group) thread mapping: thread t owns
+// channels 4*(t % G) .. +3 of some pixel; NS statistics per channel.  Sums the NS*4 values
+// of all threads with the same channel group in a fixed order and writes
+// out[s * C + c] (C = 4 G) from threads t < C.  `sm` holds STDA_BLOCK * NS * 4 floats.
+template <int G, int NS>
+__device__ __forceinline__ void block_channel_sums(const float (&v)[NS][4], float* sm, float* out) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sm[(s * 4 + j) * STDA_BLOCK + t] = v[s][j];
+  __syncthreads();
+  constexpr int C = 4 * G;
+  for (int i = t; i < NS * C; i += STDA_BLOCK) {
+    const int s = i / C, c = i % C;
+    const int g = c >> 2, j = c & 3;
+    const float* row = sm + (s * 4 + j) * STDA_BLOCK;
+    float acc = 0.f;
+    for (int p = g; p < STDA_BLOCK; p += G) acc += row[p];
+    out[s * C + c] = acc;
+  }
+  __syncthreads();
+}
+
+// Scale / shift of a batch-norm layer from its (mean, invstd) and affine parameters.
+__device__ __forceinline__ void bn_affine4(const float* stats, const float* gamma, const float* beta,
+                                           int C, int c0, float sc[4], float sh[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float m = stats[c0 + j], is = stats[C + c0 + j];
+    sc[j] = gamma[c0 + j] * is;
+    sh[j] = beta[c0 + j] - m * sc[j];
+  }
+}
+
+}  // namespace stda

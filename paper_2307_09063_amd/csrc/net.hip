@@ -1,0 +1,860 @@
+// Host orchestration of the Radar-STDA forward / backward / loss / SGD behind the C ABI.
+//
+// Network (Radar-STDA, arXiv 2307.09063, Sec. IV): input module (Conv3x3 3->16, BN, ReLU on
+// the channel concatenation of frames t, t-1, t-2), two mobile encoder blocks (16->32->64),
+// two mobile decoder blocks (64->32->16), each block followed by ECA, skip additions of the
+// same-size encoder features after the decoder blocks, output module Conv3x3 16->1 + bias.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/stda.h"
+#include "net_bwd_kernels.h"
+#include "net_kernels.h"
+#include "plan.h"
+
+using namespace stda;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) {                   \
+      g_last_hip = (int)e_;                   \
+      return STDA_E_HIP;                      \
+    }                                         \
+  } while (0)
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+int grid_for(int64_t items, int cap = 2048) {
+  int64_t g = (items + STDA_BLOCK - 1) / STDA_BLOCK;
+  if (g < 1) g = 1;
+  return (int)std::min<int64_t>(g, cap);
+}
+
+}  // namespace
+
+namespace stda {
+
+// ------------------------------------------------------------------- parameter table
+const std::vector<ParamEntry>& param_table() {
+  static std::vector<ParamEntry> tab = [] {
+    std::vector<ParamEntry> t;
+    int64_t off = 0;
+    auto add = [&](const std::string& name, std::vector<int> shape, int fan_in) {
+      ParamEntry e{};
+      std::snprintf(e.name, sizeof(e.name), "%s", name.c_str());
+      e.offset = off;
+      e.ndim = (int)shape.size();
+      int64_t n = 1;
+      for (int i = 0; i < e.ndim; ++i) {
+        e.shape[i] = shape[i];
+        n *= shape[i];
+      }
+      e.fan_in = fan_in;
+      e.count = n;
+      off += n;
+      t.push_back(e);
+    };
+    add("stem.conv.w", {16, 3, 3, 3}, 27);
+    add("stem.bn.gamma", {16}, 0);
+    add("stem.bn.beta", {16}, 0);
+    const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
+    for (int k = 0; k < 4; ++k) {
+      const BlockCfg& b = kBlocks[k];
+      const int c = b.cin, co = b.cout;
+      const std::string n = names[k];
+      add(n + ".s1.pw.w", {c, c, 1, 1}, c);
+      add(n + ".s1.pw_bn.gamma", {c}, 0);
+      add(n + ".s1.pw_bn.beta", {c}, 0);
+      add(n + ".s1.dw.w", {c, 1, 3, 3}, 9);
+      add(n + ".s1.dw_bn.gamma", {c}, 0);
+      add(n + ".s1.dw_bn.beta", {c}, 0);
+      add(n + ".s1.id_bn.gamma", {c}, 0);
+      add(n + ".s1.id_bn.beta", {c}, 0);
+      if (b.dec)
+        add(n + ".s2.main.w", {c, co, 4, 4}, c * 16);
+      else
+        add(n + ".s2.main.w", {co, c, 3, 3}, c * 9);
+      add(n + ".s2.main_bn.gamma", {co}, 0);
+      add(n + ".s2.main_bn.beta", {co}, 0);
+      if (b.dec)
+        add(n + ".s2.res.w", {c, co, 4, 4}, c * 16);
+      else
+        add(n + ".s2.res.w", {co, c, 3, 3}, c * 9);
+      add(n + ".eca.w", {3}, 3);
+    }
+    add("head.conv.w", {1, 16, 3, 3}, 144);
+    add("head.conv.b", {1}, 0);
+    return t;
+  }();
+  return tab;
+}
+
+int64_t param_offset(const char* name) {
+  for (const auto& e : param_table())
+    if (std::strcmp(e.name, name) == 0) return e.offset;
+  return -1;
+}
+
+const NetOffsets& net_offsets() {
+  static NetOffsets o = [] {
+    NetOffsets n{};
+    n.stem_w = param_offset("stem.conv.w");
+    n.stem_g = param_offset("stem.bn.gamma");
+    n.stem_b = param_offset("stem.bn.beta");
+    const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
+    int64_t run = 32;  // stem BN occupies running[0..32)
+    for (int k = 0; k < 4; ++k) {
+      const std::string p = names[k];
+      BlockOffsets& b = n.blk[k];
+      b.pw_w = param_offset((p + ".s1.pw.w").c_str());
+      b.pw_g = param_offset((p + ".s1.pw_bn.gamma").c_str());
+      b.pw_b = param_offset((p + ".s1.pw_bn.beta").c_str());
+      b.dw_w = param_offset((p + ".s1.dw.w").c_str());
+      b.dw_g = param_offset((p + ".s1.dw_bn.gamma").c_str());
+      b.dw_b = param_offset((p + ".s1.dw_bn.beta").c_str());
+      b.id_g = param_offset((p + ".s1.id_bn.gamma").c_str());
+      b.id_b = param_offset((p + ".s1.id_bn.beta").c_str());
+      b.main_w = param_offset((p + ".s2.main.w").c_str());
+      b.main_g = param_offset((p + ".s2.main_bn.gamma").c_str());
+      b.main_b = param_offset((p + ".s2.main_bn.beta").c_str());
+      b.res_w = param_offset((p + ".s2.res.w").c_str());
+      b.eca_w = param_offset((p + ".eca.w").c_str());
+      const int c = kBlocks[k].cin, co = kBlocks[k].cout;
+      b.bn_pw = run;
+      run += 2 * c;
+      b.bn_dw = run;
+      run += 2 * c;
+      b.bn_id = run;
+      run += 2 * c;
+      b.bn_main = run;
+      run += 2 * co;
+    }
+    n.head_w = param_offset("head.conv.w");
+    n.head_b = param_offset("head.conv.b");
+    n.running_count = run;
+    return n;
+  }();
+  return o;
+}
+
+}  // namespace stda
+
+// ===================================================================== weight preparation
+namespace {
+
+// Dense stride-2 weights re-laid out for the implicit-GEMM kernels:
+//   fwd   [tap][K = layer input channels][N = layer output channels]
+//   dgrad [tap][K = layer output channels][N = layer input channels]
+// Conv weights are [Cout][Cin][3][3], deconv weights [Cin][Cout][4][4].
+struct PrepJob {
+  int dec, cin, cout;
+  int64_t src, dst_f, dst_d;
+};
+struct PrepJobs {
+  int n;
+  int bf16;
+  PrepJob j[8];
+};
+
+__global__ void k_prep_dense(const float* __restrict__ w, float* __restrict__ out, PrepJobs jobs) {
+  const PrepJob J = jobs.j[blockIdx.y];
+  const int ks = J.dec ? 4 : 3, taps = ks * ks;
+  const int64_t total = (int64_t)taps * J.cin * J.cout;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    // i enumerates the PyTorch layout
+    int64_t r = i;
+    const int t = (int)(r % taps);
+    r /= taps;
+    int ci, co;
+    if (J.dec) {
+      co = (int)(r % J.cout);
+      ci = (int)(r / J.cout);
+    } else {
+      ci = (int)(r % J.cin);
+      co = (int)(r / J.cin);
+    }
+    float v = w[J.src + i];
+    if (jobs.bf16) v = round_bf16(v);
+    out[J.dst_f + ((int64_t)t * J.cin + ci) * J.cout + co] = v;
+    out[J.dst_d + ((int64_t)t * J.cout + co) * J.cin + ci] = v;
+  }
+}
+
+// Working copy of all parameters; convolution weights rounded to BF16 in BF16 mode.
+struct RoundRanges {
+  int n;
+  int64_t off[24];
+  int64_t cnt[24];
+};
+__global__ void k_working_weights(const float* __restrict__ w, float* __restrict__ wk, int64_t n, RoundRanges rr) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float v = w[i];
+    for (int r = 0; r < rr.n; ++r)
+      if (i >= rr.off[r] && i < rr.off[r] + rr.cnt[r]) v = round_bf16(v);
+    wk[i] = v;
+  }
+}
+
+}  // namespace
+
+// ===================================================================== plan
+namespace stda {
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Bump {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  }
+};
+
+void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute, Plan& P) {
+  (void)recompute;
+  P = Plan{};
+  P.n_segs = n_segs;
+  P.dtype = dtype;
+  P.mode = mode;
+  const size_t es = dtype == STDA_BF16 ? 2 : 4;
+  Bump sv, ws;
+  const bool train = mode == STDA_TRAIN;
+  Bump& acts = train ? sv : ws;
+  // per-call scratch shared by all segments
+  P.ws_wk = ws.take(sizeof(float) * stda_param_count());
+  int64_t dense_elems = 0;
+  for (int k = 0; k < 4; ++k) {
+    const BlockCfg& b = kBlocks[k];
+    const int64_t per = (int64_t)(b.dec ? 16 : 9) * b.cin * b.cout;
+    for (int m = 0; m < 2; ++m) {
+      P.dense_f[k][m] = dense_elems;
+      dense_elems += per;
+      P.dense_d[k][m] = dense_elems;
+      dense_elems += per;
+    }
+  }
+  P.ws_dense = ws.take(sizeof(float) * dense_elems);
+  int64_t max_pix = 0, max_clips = 0;
+  for (int s = 0; s < n_segs; ++s) {
+    max_pix = std::max<int64_t>(max_pix, (int64_t)segs[s].n * segs[s].H * segs[s].W);
+    max_clips = std::max<int64_t>(max_clips, segs[s].n);
+  }
+  const size_t full16 = es * 16 * (size_t)max_pix;  // largest per-level activation
+  P.ws_R = ws.take(full16);
+  // per-block partials: up to 9 x 64 floats per block of a per-pixel kernel (depthwise weight
+  // gradient), or 2 x 64 per (clip, tile) block of the per-clip stage-2 adjoint
+  P.ws_part = ws.take(sizeof(float) * std::max<size_t>((size_t)kMaxGrid * 9 * 64,
+                                                       (size_t)max_clips * kMaxTiles * 2 * 64));
+  P.ws_sums = ws.take(sizeof(double) * 6 * 64);
+  P.ws_gap = ws.take(sizeof(float) * (size_t)max_clips * kMaxTiles * 64);
+  P.ws_eval_stats = ws.take(sizeof(float) * stda_running_count());
+  P.ws_loss = ws.take(sizeof(double) * kMaxGrid);
+  if (train) {
+    for (int i = 0; i < kNumGradBufs; ++i) P.ws_g[i] = ws.take(full16);
+    P.ws_coef_e = ws.take(sizeof(float) * (size_t)max_clips * 64);
+    P.ws_coef = ws.take(sizeof(float) * 4 * 64);
+    P.ws_ecaw = ws.take(sizeof(float) * (size_t)max_clips * 3);
+    P.ws_wpart = ws.take(sizeof(float) * (size_t)kMaxWgradGrid * 32768);
+  }
+  for (int s = 0; s < n_segs; ++s) {
+    SegPlan& S = P.seg[s];
+    const int64_t n = segs[s].n, H = segs[s].H, W = segs[s].W;
+    S.n = (int)n;
+    S.H = (int)H;
+    S.W = (int)W;
+    S.x_off = segs[s].x_off;
+    S.z_off = segs[s].z_off;
+    const int64_t HW = H * W;
+    S.stats = (train ? sv : ws).take(sizeof(float) * stda_running_count());
+    S.S0p = acts.take(es * 16 * n * HW);
+    S.s0 = acts.take(es * 16 * n * HW);
+    for (int k = 0; k < 4; ++k) {
+      const BlockCfg& b = kBlocks[k];
+      const int64_t hin = H >> b.lin, win = W >> b.lin, hout = H >> b.lout, wout = W >> b.lout;
+      BlockActs& A = S.blk[k];
+      A.X1 = acts.take(es * b.cin * n * hin * win);
+      A.T = acts.take(es * b.cout * n * hout * wout);
+      A.Y = acts.take(es * b.cout * n * hout * wout);
+      A.Xn = acts.take(es * b.cout * n * hout * wout);
+      A.a = acts.take(sizeof(float) * b.cout * n);
+      A.g = acts.take(sizeof(float) * b.cout * n);
+    }
+  }
+  P.saved_bytes = train ? sv.off : 0;
+  P.ws_bytes = ws.off;
+}
+
+}  // namespace stda
+
+// ===================================================================== forward
+namespace {
+
+template <class T>
+struct Ctx {
+  const Plan* P;
+  const SegPlan* S;
+  char* sv;  // activations base (saved in TRAIN, ws in EVAL)
+  char* ws;
+  const float* w;   // working weights (rounded in BF16 mode)
+  const float* dl;  // dense layouts
+  hipStream_t st;
+  bool train;
+  template <class U> U* act(size_t off) const { return reinterpret_cast<U*>(sv + off); }
+  template <class U> U* scr(size_t off) const { return reinterpret_cast<U*>(ws + off); }
+  float* stats(int64_t bn_off) const { return reinterpret_cast<float*>((train ? sv : ws) + S->stats) + bn_off; }
+};
+
+int tiles_for(int64_t hw, int G) {
+  const int64_t item_blocks = (hw * G + STDA_BLOCK - 1) / STDA_BLOCK;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
+}
+
+// Column sums of per-block BN partials followed by the statistics finalize.
+template <class T>
+int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* const* stats_out,
+                float* const* running, float* running_base) {
+  (void)running_base;
+  float* part = c.template scr<float>(c.P->ws_part);
+  double* sums = c.template scr<double>(c.P->ws_sums);
+  const int ncols = NB * C * 2;
+  k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nblk, ncols, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0);
+  LAUNCH_CHECK();
+  BnOut o{};
+  for (int i = 0; i < NB; ++i) {
+    o.stats[i] = stats_out[i];
+    o.running[i] = running ? running[i] : nullptr;
+  }
+  k_bn_stats_finalize<<<1, 256, 0, c.st>>>(sums, NB, C, count, o, running ? 1 : 0);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+template <class T, int CIN, int COUT, bool DEC>
+int fwd_block(const Ctx<T>& c, int k, float* running) {
+  const BlockCfg& bc = kBlocks[k];
+  const BlockOffsets& bo = net_offsets().blk[k];
+  const SegPlan& S = *c.S;
+  const BlockActs& A = S.blk[k];
+  const int n = S.n;
+  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
+  const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
+  const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
+  T* X1 = c.template act<T>(A.X1);
+  T* Tm = c.template act<T>(A.T);
+  T* Y = c.template act<T>(A.Y);
+  T* R = c.template scr<T>(c.P->ws_R);
+  float* part = c.template scr<float>(c.P->ws_part);
+  S1Params sp{};
+  sp.wpw = c.w + bo.pw_w;
+  sp.wdw = c.w + bo.dw_w;
+  sp.stats[0] = c.stats(bo.bn_pw);
+  sp.stats[1] = c.stats(bo.bn_dw);
+  sp.stats[2] = c.stats(bo.bn_id);
+  sp.gamma[0] = c.w + bo.pw_g;
+  sp.gamma[1] = c.w + bo.dw_g;
+  sp.gamma[2] = c.w + bo.id_g;
+  sp.beta[0] = c.w + bo.pw_b;
+  sp.beta[1] = c.w + bo.dw_b;
+  sp.beta[2] = c.w + bo.id_b;
+  // stage 1
+  const int g1 = grid_for(Pin * (CIN / 4));
+  if (c.train) {
+    k_stage1<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win);
+    LAUNCH_CHECK();
+    float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
+    float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
+    if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro, running)) return r;
+  }
+  k_stage1<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win);
+  LAUNCH_CHECK();
+  // stage 2: main (with statistics) and residual
+  const float* dl = c.dl;
+  const int g2 = grid_for(Pout * (COUT / 4));
+  constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
+  if (c.train) {
+    k_dense_simt<T, OPF, CIN, COUT, true><<<g2, 256, 0, c.st>>>(X1, dl + c.P->dense_f[k][0], Tm, part, n, hout, wout);
+    LAUNCH_CHECK();
+    float* so[1] = {c.stats(bo.bn_main)};
+    float* ro[1] = {running + bo.bn_main};
+    if (int r = bn_finalize(c, g2, 1, COUT, (double)Pout, so, ro, running)) return r;
+  } else {
+    k_dense_simt<T, OPF, CIN, COUT, false><<<g2, 256, 0, c.st>>>(X1, dl + c.P->dense_f[k][0], Tm, nullptr, n, hout, wout);
+    LAUNCH_CHECK();
+  }
+  k_dense_simt<T, OPF, CIN, COUT, false><<<g2, 256, 0, c.st>>>(X, dl + c.P->dense_f[k][1], R, nullptr, n, hout, wout);
+  LAUNCH_CHECK();
+  // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
+  const int hw = hout * wout;
+  const int tiles = tiles_for(hw, COUT / 4);
+  float* gap = c.template scr<float>(c.P->ws_gap);
+  k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, gap, c.stats(bo.bn_main), c.w + bo.main_g,
+                                                        c.w + bo.main_b, hw);
+  LAUNCH_CHECK();
+  T* Xn = c.template act<T>(A.Xn);
+  const T* skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
+  if (skip)
+    k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, c.st>>>(Y, skip, Xn, gap, c.w + bo.eca_w,
+                                                                c.template act<float>(A.g), c.template act<float>(A.a),
+                                                                hw, tiles);
+  else
+    k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, c.st>>>(Y, nullptr, Xn, gap, c.w + bo.eca_w,
+                                                                 c.template act<float>(A.g),
+                                                                 c.template act<float>(A.a), hw, tiles);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+template <class T>
+int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
+  const SegPlan& S = *c.S;
+  const NetOffsets& no = net_offsets();
+  const int64_t P = (int64_t)S.n * S.H * S.W;
+  const float* xs = x + S.x_off;
+  float* part = c.template scr<float>(c.P->ws_part);
+  T* S0p = c.template act<T>(S.S0p);
+  T* s0 = c.template act<T>(S.s0);
+  const int gs = grid_for(P);
+  if (c.train) {
+    k_stem_fwd<T, true><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, S0p, part, nullptr, nullptr, nullptr, S.n, S.H,
+                                              S.W);
+    LAUNCH_CHECK();
+    float* so[1] = {c.stats(0)};
+    float* ro[1] = {running};
+    if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro, running)) return r;
+    k_bn_relu<T, 16><<<grid_for(P * 4), 256, 0, c.st>>>(S0p, s0, c.stats(0), c.w + no.stem_g, c.w + no.stem_b, P);
+    LAUNCH_CHECK();
+  } else {
+    k_stem_fwd<T, false><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
+                                               c.w + no.stem_b, S.n, S.H, S.W);
+    LAUNCH_CHECK();
+  }
+  if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
+  if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
+  if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
+  if (int r = fwd_block<T, 32, 16, true>(c, 3, running)) return r;
+  k_head_fwd<T><<<grid_for(P), 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w, c.w + no.head_b,
+                                               z + S.z_off, S.n, S.H, S.W);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+int validate_segs(const stda_segment* segs, int n_segs) {
+  if (!segs || n_segs < 1 || n_segs > kMaxSegs) return STDA_E_INVALID;
+  for (int s = 0; s < n_segs; ++s) {
+    const stda_segment& g = segs[s];
+    if (g.n < 1 || g.x_off < 0 || g.z_off < 0) return STDA_E_INVALID;
+    if (g.H < 8 || g.W < 8 || g.H > 4096 || g.W > 4096 || (g.H % 4) || (g.W % 4)) return STDA_E_SHAPE;
+  }
+  return STDA_OK;
+}
+
+// Per-call preparation: working weights and dense layouts.
+int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, const float** wk_out) {
+  float* wk = reinterpret_cast<float*>(ws + P.ws_wk);
+  const int64_t np = (int64_t)stda_param_count();
+  const float* src = w;
+  if (P.dtype == STDA_BF16) {
+    RoundRanges rr{};
+    for (const auto& e : param_table()) {
+      const size_t L = std::strlen(e.name);
+      const bool conv_w = L > 2 && std::strcmp(e.name + L - 2, ".w") == 0 && std::strstr(e.name, "eca") == nullptr;
+      if (conv_w) {
+        rr.off[rr.n] = e.offset;
+        rr.cnt[rr.n] = e.count;
+        ++rr.n;
+      }
+    }
+    k_working_weights<<<grid_for(np, 256), 256, 0, st>>>(w, wk, np, rr);
+    LAUNCH_CHECK();
+    src = wk;
+  }
+  PrepJobs jobs{};
+  jobs.bf16 = P.dtype == STDA_BF16;
+  const NetOffsets& no = net_offsets();
+  for (int k = 0; k < 4; ++k)
+    for (int m = 0; m < 2; ++m) {
+      PrepJob& j = jobs.j[jobs.n++];
+      j.dec = kBlocks[k].dec;
+      j.cin = kBlocks[k].cin;
+      j.cout = kBlocks[k].cout;
+      j.src = m == 0 ? no.blk[k].main_w : no.blk[k].res_w;
+      j.dst_f = P.dense_f[k][m];
+      j.dst_d = P.dense_d[k][m];
+    }
+  k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
+  LAUNCH_CHECK();
+  *wk_out = src;
+  return STDA_OK;
+}
+
+template <class T>
+int forward_all(const Plan& P, const float* x, const float* w, float* running, float* z, char* saved, char* ws,
+                hipStream_t st) {
+  const float* wk = nullptr;
+  if (int r = prepare_weights(P, w, ws, st, &wk)) return r;
+  const bool train = P.mode == STDA_TRAIN;
+  for (int s = 0; s < P.n_segs; ++s) {
+    Ctx<T> c{&P, &P.seg[s], train ? saved : ws, ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, train};
+    if (!train) {
+      BnTable tab{};
+      const NetOffsets& no = net_offsets();
+      (void)no;
+      int off = 0;
+      tab.off[tab.n] = off;
+      tab.C[tab.n++] = 16;
+      off += 32;
+      for (int k = 0; k < 4; ++k) {
+        const int cs[4] = {kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cout};
+        for (int q = 0; q < 4; ++q) {
+          tab.off[tab.n] = off;
+          tab.C[tab.n++] = cs[q];
+          off += 2 * cs[q];
+        }
+      }
+      k_eval_stats<<<1, 256, 0, st>>>(running, c.stats(0), tab);
+      LAUNCH_CHECK();
+    }
+    if (int r = forward_seg<T>(c, x, running, z)) return r;
+  }
+  return STDA_OK;
+}
+
+}  // namespace
+
+// ===================================================================== backward
+namespace {
+
+template <class T>
+int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc) {
+  k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+template <class L>
+constexpr int pch_for() {
+  constexpr int per = (L::K + L::N) * 4;
+  constexpr int p = 40960 / per;
+  return p >= 64 ? 64 : p >= 32 ? 32 : p >= 16 ? 16 : p >= 8 ? 8 : 4;
+}
+
+template <class T, class L>
+int run_wgrad(const Ctx<T>& c, const L& ld, int64_t npix, float* dst, ColMap map, int acc) {
+  constexpr int PCH = pch_for<L>();
+  float* wpart = c.template scr<float>(c.P->ws_wpart);
+  const int64_t chunks = (npix + PCH - 1) / PCH;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, kMaxWgradGrid));
+  k_wgrad<L, PCH><<<grid, 256, 0, c.st>>>(ld, wpart);
+  LAUNCH_CHECK();
+  return colsum_to(c, wpart, grid, L::K * L::N, dst, map, acc);
+}
+
+template <class T>
+int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg, float* const* db, int acc) {
+  float* part = c.template scr<float>(c.P->ws_part);
+  double* sums = c.template scr<double>(c.P->ws_sums);
+  k_colsum<<<(NS * C + 15) / 16, 256, 0, c.st>>>(part, nblk, NS * C, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0);
+  LAUNCH_CHECK();
+  BnBwdOut o{};
+  for (int k = 0; k < NS - 1; ++k) {
+    o.dgamma[k] = dg[k];
+    o.dbeta[k] = db[k];
+  }
+  k_bn_bwd_finalize<<<1, 64, 0, c.st>>>(sums, NS, C, n, o, c.template scr<float>(c.P->ws_coef), acc);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+// Gradient buffers (ws): 0 dd1 (grad of d1), 1 dd0 (grad of d0), 2 de1, 3 de0, 4 ds0,
+// 5 dT, 6 dY, 7 dX1, 8 dXr, 9 dP, 10 dD, 11 dX0, 12 dTp (input module).
+template <class T, int CIN, int COUT, bool DEC>
+int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, float* dw, int acc) {
+  const BlockCfg& bc = kBlocks[k];
+  const BlockOffsets& bo = net_offsets().blk[k];
+  const SegPlan& S = *c.S;
+  const BlockActs& A = S.blk[k];
+  const int n = S.n;
+  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
+  const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
+  const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
+  const T* X1 = c.template act<T>(A.X1);
+  const T* Tm = c.template act<T>(A.T);
+  const T* Y = c.template act<T>(A.Y);
+  auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
+  T *dT = gb(5), *dY = gb(6), *dX1 = gb(7), *dXr = gb(8), *dP = gb(9), *dD = gb(10), *dX0 = gb(11);
+  float* part = c.template scr<float>(c.P->ws_part);
+  float* coef_e = c.template scr<float>(c.P->ws_coef_e);
+  float* ecaw = c.template scr<float>(c.P->ws_ecaw);
+  const int hw = hout * wout;
+  const int tiles = tiles_for(hw, COUT / 4);
+  float* epart = c.template scr<float>(c.P->ws_gap);
+  // ECA adjoint partials and stage-2 BN statistics
+  k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw);
+  LAUNCH_CHECK();
+  k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
+      Gd, Tm, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
+      c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles);
+  LAUNCH_CHECK();
+  if (int r = colsum_to(c, ecaw, n, 3, dw + bo.eca_w, ColMap{MAP_IDENT, 0, 0}, acc)) return r;
+  {
+    float* dg[1] = {dw + bo.main_g};
+    float* db[1] = {dw + bo.main_b};
+    if (int r = bn_bwd(c, tiles * n, 2, COUT, (double)Pout, dg, db, acc)) return r;
+  }
+  k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, c.template act<float>(A.a), coef_e,
+                                                            c.template scr<float>(c.P->ws_coef), c.stats(bo.bn_main),
+                                                            c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw);
+  LAUNCH_CHECK();
+  // dense adjoints: dX1 from dT, dXr from dY
+  constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
+  const int gd = grid_for(Pin * (CIN / 4));
+  k_dense_simt<T, OPD, COUT, CIN, false><<<gd, 256, 0, c.st>>>(dT, c.dl + c.P->dense_d[k][0], dX1, nullptr, n, hin,
+                                                               win);
+  LAUNCH_CHECK();
+  k_dense_simt<T, OPD, COUT, CIN, false><<<gd, 256, 0, c.st>>>(dY, c.dl + c.P->dense_d[k][1], dXr, nullptr, n, hin,
+                                                               win);
+  LAUNCH_CHECK();
+  // dense weight gradients
+  if (DEC) {
+    WgDecS2<T, CIN, COUT> lm{X1, dT, n, hin, win};
+    if (int r = run_wgrad(c, lm, Pin, dw + bo.main_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
+    WgDecS2<T, CIN, COUT> lr{X, dY, n, hin, win};
+    if (int r = run_wgrad(c, lr, Pin, dw + bo.res_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
+  } else {
+    WgEncS2<T, CIN, COUT> lm{X1, dT, n, hout, wout};
+    if (int r = run_wgrad(c, lm, Pout, dw + bo.main_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
+    WgEncS2<T, CIN, COUT> lr{X, dY, n, hout, wout};
+    if (int r = run_wgrad(c, lr, Pout, dw + bo.res_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
+  }
+  // stage 1
+  S1Params sp{};
+  sp.wpw = c.w + bo.pw_w;
+  sp.wdw = c.w + bo.dw_w;
+  sp.stats[0] = c.stats(bo.bn_pw);
+  sp.stats[1] = c.stats(bo.bn_dw);
+  sp.stats[2] = c.stats(bo.bn_id);
+  sp.gamma[0] = c.w + bo.pw_g;
+  sp.gamma[1] = c.w + bo.dw_g;
+  sp.gamma[2] = c.w + bo.id_g;
+  sp.beta[0] = c.w + bo.pw_b;
+  sp.beta[1] = c.w + bo.dw_b;
+  sp.beta[2] = c.w + bo.id_b;
+  const int g1 = grid_for(Pin * (CIN / 4));
+  k_s1_bwd_stats<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win);
+  LAUNCH_CHECK();
+  {
+    float* dg[3] = {dw + bo.pw_g, dw + bo.dw_g, dw + bo.id_g};
+    float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
+    if (int r = bn_bwd(c, g1, 4, CIN, (double)Pin, dg, db, acc)) return r;
+  }
+  k_s1_bwd_apply<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, c.template scr<float>(c.P->ws_coef), sp, dP, dD,
+                                                    dX0, n, hin, win);
+  LAUNCH_CHECK();
+  if (skipg)
+    k_s1_bwd_dx<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(dP, dD, dX0, skipg, sp, dXout, n, hin, win);
+  else
+    k_s1_bwd_dx<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(dP, dD, dX0, nullptr, sp, dXout, n, hin, win);
+  LAUNCH_CHECK();
+  WgPw<T, CIN> lp{X, dP, Pin};
+  if (int r = run_wgrad(c, lp, Pin, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc)) return r;
+  k_dw_wgrad<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, dD, part, n, hin, win);
+  LAUNCH_CHECK();
+  return colsum_to(c, part, g1, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc);
+}
+
+template <class T>
+int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, float* dx, int acc) {
+  const SegPlan& S = *c.S;
+  const NetOffsets& no = net_offsets();
+  const int64_t P = (int64_t)S.n * S.H * S.W;
+  auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
+  const float* dzs = dz + S.z_off;
+  // output module
+  k_head_dgrad<T><<<grid_for(P), 256, 0, c.st>>>(dzs, c.w + no.head_w, gb(0), S.n, S.H, S.W);
+  LAUNCH_CHECK();
+  {
+    WgHead<T> lh{c.template act<T>(S.blk[3].Xn), dzs, S.n, S.H, S.W};
+    if (int r = run_wgrad(c, lh, P, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
+  }
+  // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
+  if (int r = bwd_block<T, 32, 16, true>(c, 3, gb(0), gb(1), nullptr, dw, acc)) return r;
+  if (int r = bwd_block<T, 64, 32, true>(c, 2, gb(1), gb(2), nullptr, dw, acc)) return r;
+  // encoder 1 (input e0: its gradient also receives dd0 through the skip), encoder 0
+  if (int r = bwd_block<T, 32, 64, false>(c, 1, gb(2), gb(3), gb(1), dw, acc)) return r;
+  if (int r = bwd_block<T, 16, 32, false>(c, 0, gb(3), gb(4), gb(0), dw, acc)) return r;
+  // input module
+  float* part = c.template scr<float>(c.P->ws_part);
+  const int g = grid_for(P * 4);
+  k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), c.template act<T>(S.S0p), c.stats(0),
+                                           part, P);
+  LAUNCH_CHECK();
+  {
+    float* dg[1] = {dw + no.stem_g};
+    float* db[1] = {dw + no.stem_b};
+    if (int r = bn_bwd(c, g, 2, 16, (double)P, dg, db, acc)) return r;
+  }
+  k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), c.template act<T>(S.S0p), c.stats(0),
+                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef), gb(12), P);
+  LAUNCH_CHECK();
+  {
+    WgStem<T> ls{x + S.x_off, gb(12), S.n, S.H, S.W};
+    if (int r = run_wgrad(c, ls, P, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, acc)) return r;
+  }
+  if (dx) {
+    k_stem_dx<T><<<grid_for(P), 256, 0, c.st>>>(gb(12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W);
+    LAUNCH_CHECK();
+  }
+  return STDA_OK;
+}
+
+template <class T>
+int backward_all(const Plan& P, const float* dz, const float* x, const float* w, const char* saved, float* dw,
+                 float* dx, char* ws, hipStream_t st) {
+  const float* wk = nullptr;
+  if (int r = prepare_weights(P, w, ws, st, &wk)) return r;
+  for (int s = 0; s < P.n_segs; ++s) {
+    Ctx<T> c{&P, &P.seg[s], const_cast<char*>(saved), ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, true};
+    if (int r = backward_seg<T>(c, dz, x, dw, dx, s > 0 ? 1 : 0)) return r;
+  }
+  return STDA_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+const char* stda_status_string(int s) {
+  switch (s) {
+    case STDA_OK: return "ok";
+    case STDA_E_INVALID: return "invalid argument";
+    case STDA_E_SHAPE: return "unsupported shape (H, W must be multiples of 4 in [8, 4096])";
+    case STDA_E_WORKSPACE: return "workspace or saved buffer too small";
+    case STDA_E_HIP: return "HIP runtime error";
+    case STDA_E_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+int stda_last_hip_error(void) { return g_last_hip; }
+
+size_t stda_param_count(void) {
+  const auto& t = param_table();
+  return (size_t)(t.back().offset + t.back().count);
+}
+
+int stda_param_table(stda_param_desc* out, int cap) {
+  const auto& t = param_table();
+  if (out) {
+    for (int i = 0; i < (int)t.size() && i < cap; ++i) {
+      std::memset(&out[i], 0, sizeof(out[i]));
+      std::snprintf(out[i].name, sizeof(out[i].name), "%s", t[i].name);
+      out[i].offset = t[i].offset;
+      out[i].ndim = t[i].ndim;
+      for (int d = 0; d < 4; ++d) out[i].shape[d] = d < t[i].ndim ? t[i].shape[d] : 0;
+      out[i].fan_in = t[i].fan_in;
+    }
+  }
+  return (int)t.size();
+}
+
+int stda_bn_layer_count(void) { return 17; }
+size_t stda_running_count(void) { return (size_t)net_offsets().running_count; }
+
+int stda_workspace_size(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute,
+                        size_t* saved_bytes, size_t* ws_bytes) {
+  if (int r = validate_segs(segs, n_segs)) return r;
+  if ((dtype != STDA_FP32 && dtype != STDA_BF16) || (mode != STDA_EVAL && mode != STDA_TRAIN)) return STDA_E_INVALID;
+  Plan P;
+  build_plan(segs, n_segs, dtype, mode, recompute, P);
+  if (saved_bytes) *saved_bytes = P.saved_bytes;
+  if (ws_bytes) *ws_bytes = P.ws_bytes;
+  return STDA_OK;
+}
+
+int stda_forward(const stda_segment* segs, int n_segs, const float* x, const float* w, float* running, float* z,
+                 void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int mode, int recompute,
+                 hipStream_t stream) {
+  try {
+    if (int r = validate_segs(segs, n_segs)) return r;
+    if ((dtype != STDA_FP32 && dtype != STDA_BF16) || (mode != STDA_EVAL && mode != STDA_TRAIN)) return STDA_E_INVALID;
+    if (!x || !w || !running || !z || !ws) return STDA_E_INVALID;
+    Plan P;
+    build_plan(segs, n_segs, dtype, mode, recompute, P);
+    if (ws_bytes < P.ws_bytes) return STDA_E_WORKSPACE;
+    if (mode == STDA_TRAIN && (!saved || saved_bytes < P.saved_bytes)) return STDA_E_WORKSPACE;
+    if (dtype == STDA_BF16)
+      return forward_all<bf16>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
+    return forward_all<float>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
+  } catch (...) {
+    return STDA_E_INVALID;
+  }
+}
+
+int stda_backward(const stda_segment* segs, int n_segs, const float* x, const float* dz, const float* w,
+                  const void* saved, size_t saved_bytes, float* dw, float* dx, void* ws, size_t ws_bytes, int dtype,
+                  int recompute, hipStream_t stream) {
+  try {
+    if (int r = validate_segs(segs, n_segs)) return r;
+    if (dtype != STDA_FP32 && dtype != STDA_BF16) return STDA_E_INVALID;
+    if (!x || !dz || !w || !saved || !dw || !ws) return STDA_E_INVALID;
+    Plan P;
+    build_plan(segs, n_segs, dtype, STDA_TRAIN, recompute, P);
+    if (ws_bytes < P.ws_bytes || saved_bytes < P.saved_bytes) return STDA_E_WORKSPACE;
+    if (dtype == STDA_BF16)
+      return backward_all<bf16>(P, dz, x, w, (const char*)saved, dw, dx, (char*)ws, stream);
+    return backward_all<float>(P, dz, x, w, (const char*)saved, dw, dx, (char*)ws, stream);
+  } catch (...) {
+    return STDA_E_INVALID;
+  }
+}
+
+int stda_mse_loss(const stda_segment* segs, int n_segs, const float* z, const float* y, double* loss_dev, float* dz,
+                  void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (int r = validate_segs(segs, n_segs)) return r;
+  if (!z || !y || !loss_dev || !dz || !ws) return STDA_E_INVALID;
+  // the loss uses the first kMaxGrid doubles of ws (any workspace of these segments holds them)
+  if (ws_bytes < sizeof(double) * kMaxGrid) return STDA_E_WORKSPACE;
+  double* part = reinterpret_cast<double*>(ws);
+  int used = 0;
+  for (int s = 0; s < n_segs; ++s) {
+    const int64_t n = (int64_t)segs[s].n * segs[s].H * segs[s].W;
+    const int g = std::min(grid_for(n), kMaxGrid / n_segs);
+    k_mse<<<g, 256, 0, stream>>>(z + segs[s].z_off, y + segs[s].z_off, dz + segs[s].z_off, part + used, n);
+    LAUNCH_CHECK();
+    used += g;
+  }
+  k_sum_f64<<<1, 256, 0, stream>>>(part, used, loss_dev);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+int stda_sinr(const float* maps, const uint8_t* o_mask, const uint8_t* n_mask, int n_maps, int H, int W,
+              double* out_dev, hipStream_t stream) {
+  if (!maps || !o_mask || !n_mask || !out_dev || n_maps < 1 || H < 1 || W < 1) return STDA_E_INVALID;
+  k_sinr<<<n_maps, 256, 0, stream>>>(maps, o_mask, n_mask, (int64_t)H * W, out_dev);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+int stda_sgd_step(float* w, const float* dw, int64_t n, float lr, float weight_decay, uint16_t* w_bf16,
+                  hipStream_t stream) {
+  if (!w || !dw || n < 0) return STDA_E_INVALID;
+  if (n == 0) return STDA_OK;
+  k_sgd<<<grid_for(n, 1024), 256, 0, stream>>>(w, dw, n, lr, weight_decay, w_bf16);
+  LAUNCH_CHECK();
+  return STDA_OK;
+}
+
+}  // extern "C"

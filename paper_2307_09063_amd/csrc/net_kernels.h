@@ -1,0 +1,630 @@
+// Radar-STDA network kernels (gfx950), NHWC activations, FP32 or BF16 storage, FP32 math.
+//
+// Thread mapping of the per-pixel kernels: one thread per (pixel, group of 4 channels), the
+// channel group fastest, so consecutive threads read consecutive 16-byte (FP32) / 8-byte (BF16)
+// pieces of NHWC rows.  Per-channel sums (BN statistics, GAP, wgrad of the depthwise branch)
+// are reduced inside the block in a fixed order and written as per-block partials; separate
+// column-sum kernels reduce the partials across blocks in FP64.  Nothing uses float atomics,
+// so every result is bitwise reproducible run to run.
+#pragma once
+#include "common.h"
+
+namespace stda {
+
+constexpr float BN_EPS = 1e-5f;
+
+__device__ __forceinline__ void pix3(int64_t p, int h, int w, int& b, int& y, int& x) {
+  const int64_t hw = (int64_t)h * w;
+  b = (int)(p / hw);
+  const int r = (int)(p - (int64_t)b * hw);
+  y = r / w;
+  x = r - y * w;
+}
+
+// Sums, per channel, the NS x 4 values each thread holds for its channel group into
+// red[s * C + c] (LDS); sm is scratch of NS * 4 * STDA_BLOCK floats.
+template <int G, int NS>
+__device__ __forceinline__ void block_chan_reduce(const float (&v)[NS][4], float* sm, float* red) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sm[(s * 4 + j) * STDA_BLOCK + t] = v[s][j];
+  __syncthreads();
+  constexpr int C = 4 * G;
+  for (int i = t; i < NS * C; i += STDA_BLOCK) {
+    const int s = i / C, c = i % C;
+    const float* row = sm + (s * 4 + (c & 3)) * STDA_BLOCK;
+    float acc = 0.f;
+    for (int p = c >> 2; p < STDA_BLOCK; p += G) acc += row[p];
+    red[i] = acc;
+  }
+  __syncthreads();
+}
+
+// Sum over the block of NV values per thread (all threads hold the same quantities).
+template <int NV>
+__device__ __forceinline__ void block_vec_reduce(const float (&v)[NV], float* sm, float* red) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sm[i * STDA_BLOCK + t] = v[i];
+  __syncthreads();
+  for (int i = t; i < NV; i += STDA_BLOCK) {
+    float acc = 0.f;
+    for (int p = 0; p < STDA_BLOCK; ++p) acc += sm[i * STDA_BLOCK + p];
+    red[i] = acc;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ cross-block FP64 sums
+// out[col] = sum over rows of part[row * ncols + col], in FP64, fixed order.
+// Block: 16 columns x 16 row groups.  Epilogue kinds map the column to its destination.
+struct ColMap {
+  int kind;   // 0: double out[col]; 1..: scatter float into a weight gradient
+  int a, b;   // kind-specific sizes
+};
+enum : int { MAP_DOUBLE = 0, MAP_ENC_S2 = 1, MAP_DEC_S2 = 2, MAP_PW_CONV = 3, MAP_IDENT = 4,
+             MAP_DW = 5, MAP_STEM = 6, MAP_HEAD = 7 };
+
+__device__ __forceinline__ int64_t colmap_dst(const ColMap m, int col) {
+  switch (m.kind) {
+    case MAP_ENC_S2: {  // col = (tap*Cin + c)*Cout + o -> w[o][c][tap]; a = Cin, b = Cout
+      const int o = col % m.b, r = col / m.b, c = r % m.a, tap = r / m.a;
+      return ((int64_t)o * m.a + c) * 9 + tap;
+    }
+    case MAP_DEC_S2: {  // col = c*(16*Cout) + tap*Cout + o -> w[c][o][tap]; b = Cout
+      const int o = col % m.b, r = col / m.b, tap = r % 16, c = r / 16;
+      return ((int64_t)c * m.b + o) * 16 + tap;
+    }
+    case MAP_PW_CONV: {  // col = c*C + o -> w[o][c]; a = C
+      const int o = col % m.a, c = col / m.a;
+      return (int64_t)o * m.a + c;
+    }
+    case MAP_DW: {  // col = tap*C + c -> w[c][tap]; a = C
+      const int c = col % m.a, tap = col / m.a;
+      return (int64_t)c * 9 + tap;
+    }
+    case MAP_STEM: {  // col = k*16 + o, k = c*9 + tap (k = 27 is padding) -> w[o][c][tap]
+      const int o = col % 16, k = col / 16;
+      return k < 27 ? (int64_t)o * 27 + k : -1;
+    }
+    case MAP_HEAD: {  // col = k*4 + n, k = tap*16 + c, k = 144 the bias column; n > 0 padding
+      const int k = col / 4, n = col % 4;
+      if (n != 0 || k > 144) return -1;
+      if (k == 144) return 144;  // the bias follows the 144 weights
+      return (int64_t)(k % 16) * 9 + k / 16;
+    }
+    default:
+      return col;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, int nrows, int ncols,
+                                                double* __restrict__ dout, float* __restrict__ fout,
+                                                ColMap map, int accumulate) {
+  __shared__ double sm[16][17];
+  const int cl = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const int col = blockIdx.x * 16 + cl;
+  double acc = 0.0;
+  if (col < ncols)
+    for (int r = rg; r < nrows; r += 16) acc += (double)part[(int64_t)r * ncols + col];
+  sm[rg][cl] = acc;
+  __syncthreads();
+  if (rg == 0 && col < ncols) {
+    double s = 0.0;
+    for (int i = 0; i < 16; ++i) s += sm[i][cl];
+    if (map.kind == MAP_DOUBLE) {
+      dout[col] = accumulate ? dout[col] + s : s;
+    } else {
+      const int64_t d = colmap_dst(map, col);
+      if (d >= 0) fout[d] = accumulate ? (float)((double)fout[d] + s) : (float)s;
+    }
+  }
+}
+
+// Batch statistics from column sums: sums[(i*C + c)*2 + {0,1}] = (sum, sum of squares) of
+// BN layer i.  Writes stats_i = [mean C][invstd C]; updates the running buffer when asked.
+struct BnOut {
+  float* stats[3];
+  float* running[3];
+};
+__global__ void k_bn_stats_finalize(const double* __restrict__ sums, int NB, int C, double count,
+                                    BnOut out, int update_running) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NB * C) return;
+  const int i = t / C, c = t % C;
+  const double S = sums[(i * C + c) * 2], Q = sums[(i * C + c) * 2 + 1];
+  const double mean = S / count;
+  double var = Q / count - mean * mean;
+  if (var < 0.0) var = 0.0;
+  out.stats[i][c] = (float)mean;
+  out.stats[i][C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
+  if (update_running) {
+    float* r = out.running[i];
+    const double unb = count > 1.0 ? var * count / (count - 1.0) : var;
+    r[c] = (float)(0.9 * (double)r[c] + 0.1 * mean);
+    r[C + c] = (float)(0.9 * (double)r[C + c] + 0.1 * unb);
+  }
+}
+
+// EVAL statistics: mean and 1/sqrt(var + eps) of every BN layer from the running buffer
+// (both buffers: per layer C means, then C variances / inverse standard deviations).
+struct BnTable {
+  int n;
+  int off[24];
+  int C[24];
+};
+__global__ void k_eval_stats(const float* __restrict__ running, float* __restrict__ stats, BnTable tab) {
+  for (int l = 0; l < tab.n; ++l) {
+    const int C = tab.C[l], off = tab.off[l];
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+      stats[off + c] = running[off + c];
+      stats[off + C + c] = 1.0f / sqrtf(running[off + C + c] + BN_EPS);
+    }
+  }
+}
+
+// --------------------------------------------------------------------- input module
+// Conv3x3 p1, 3 -> 16 on planar FP32 maps.  TRAIN: writes the pre-BN output and per-block
+// (sum, sum of squares) partials [block][16][2].  EVAL: writes ReLU(BN(conv)).
+template <class T, bool TRAIN>
+__global__ __launch_bounds__(256) void k_stem_fwd(const float* __restrict__ x, const float* __restrict__ w,
+                                                  T* __restrict__ out, float* __restrict__ part,
+                                                  const float* __restrict__ stats, const float* __restrict__ gamma,
+                                                  const float* __restrict__ beta, int B, int H, int W) {
+  __shared__ float sm[32 * STDA_BLOCK];
+  __shared__ float red[32];
+  const int64_t P = (int64_t)B * H * W;
+  float acc1[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) acc1[i] = 0.f;
+  float sc[16], sh[16];
+  if (!TRAIN) {
+    for (int o = 0; o < 16; ++o) {
+      sc[o] = gamma[o] * stats[16 + o];
+      sh[o] = beta[o] - stats[o] * sc[o];
+    }
+  }
+  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
+    int b, y, xx;
+    pix3(p, H, W, b, y, xx);
+    float acc[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc[o] = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int ky = 0; ky < 3; ++ky) {
+        const int iy = y + ky - 1;
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          const int ix = xx + kx - 1;
+          const float v = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(((int64_t)b * 3 + c) * H + iy) * W + ix] : 0.f;
+#pragma unroll
+          for (int o = 0; o < 16; ++o) acc[o] += w[o * 27 + c * 9 + ky * 3 + kx] * v;
+        }
+      }
+    T* op = out + p * 16;
+    if (TRAIN) {
+#pragma unroll
+      for (int o = 0; o < 16; ++o) {
+        acc1[2 * o] += acc[o];
+        acc1[2 * o + 1] += acc[o] * acc[o];
+      }
+    } else {
+#pragma unroll
+      for (int o = 0; o < 16; ++o) acc[o] = fmaxf(acc[o] * sc[o] + sh[o], 0.f);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) st4(op + 4 * q, acc + 4 * q);
+  }
+  if (TRAIN) {
+    block_vec_reduce<32>(acc1, sm, red);
+    if (threadIdx.x < 32) part[(int64_t)blockIdx.x * 32 + threadIdx.x] = red[threadIdx.x];
+  }
+}
+
+// out = ReLU(BN(in)) elementwise for C channels (TRAIN input module activation).
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_bn_relu(const T* __restrict__ in, T* __restrict__ out,
+                                                 const float* __restrict__ stats, const float* __restrict__ gamma,
+                                                 const float* __restrict__ beta, int64_t P) {
+  constexpr int G = C / 4;
+  const int64_t items = P * G;
+  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int c0 = (int)(i % G) * 4;
+  float sc[4], sh[4];
+  bn_affine4(stats, gamma, beta, C, c0, sc, sh);
+  for (; i < items; i += stride) {
+    const int64_t p = i / G;
+    float v[4];
+    ld4(in + p * C + c0, v);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = fmaxf(v[j] * sc[j] + sh[j], 0.f);
+    st4(out + p * C + c0, v);
+  }
+}
+
+// --------------------------------------------------------------------- stage 1
+// Branches of stage 1 (mobile encoder / decoder block, first equation group): pointwise
+// (C x C), depthwise 3x3 and identity.  Weights staged in LDS:
+//   wp[c][o]   pointwise, out[o] = sum_c wp[c][o] x[c]
+//   wd[t][o]   depthwise, t = (dy+1)*3 + (dx+1) neighbour offset, out[o] += wd[t][o] x[o](y+dy, x+dx)
+template <int C, bool DEC>
+__device__ __forceinline__ void stage1_load_weights(const float* __restrict__ wpw, const float* __restrict__ wdw,
+                                                    float* wp, float* wd) {
+  for (int i = threadIdx.x; i < C * C; i += STDA_BLOCK) {
+    const int c = i / C, o = i % C;
+    wp[i] = DEC ? wpw[c * C + o] : wpw[o * C + c];
+  }
+  for (int i = threadIdx.x; i < 9 * C; i += STDA_BLOCK) {
+    const int t = i / C, o = i % C;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    // conv: weight tap (dy+1, dx+1); transposed (stride 1, pad 1): flipped tap (1-dy, 1-dx)
+    wd[i] = DEC ? wdw[o * 9 + (1 - dy) * 3 + (1 - dx)] : wdw[o * 9 + (dy + 1) * 3 + (dx + 1)];
+  }
+  __syncthreads();
+}
+
+template <class T, int C>
+__device__ __forceinline__ void stage1_branches(const T* __restrict__ X, int64_t p, int b, int y, int x, int h,
+                                                int w, int c0, const float* wp, const float* wd, float pv[4],
+                                                float dv[4], float xv[4]) {
+  zero4(pv);
+  zero4(dv);
+  const T* row = X + p * C;
+#pragma unroll 4
+  for (int c = 0; c < C; c += 4) {
+    float v[4];
+    ld4(row + c, v);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float4 wq = *reinterpret_cast<const float4*>(wp + (c + j) * C + c0);
+      pv[0] += wq.x * v[j];
+      pv[1] += wq.y * v[j];
+      pv[2] += wq.z * v[j];
+      pv[3] += wq.w * v[j];
+    }
+  }
+  ld4(row + c0, xv);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+    if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
+    float v[4];
+    ld4(X + (((int64_t)b * h + yy) * w + xx) * C + c0, v);
+    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
+    dv[0] += wq.x * v[0];
+    dv[1] += wq.y * v[1];
+    dv[2] += wq.z * v[2];
+    dv[3] += wq.w * v[3];
+  }
+}
+
+// MODE 0: per-block partials of (sum, sumsq) for the three BN inputs -> part[blk][3][C][2].
+// MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)).
+struct S1Params {
+  const float* wpw;
+  const float* wdw;
+  const float* stats[3];  // pw, dw, id
+  const float* gamma[3];
+  const float* beta[3];
+};
+template <class T, int C, bool DEC, int MODE>
+__global__ __launch_bounds__(256) void k_stage1(const T* __restrict__ X, T* __restrict__ X1, float* __restrict__ part,
+                                                S1Params prm, int B, int h, int w) {
+  constexpr int G = C / 4;
+  __shared__ float wp[C * C];
+  __shared__ float wd[9 * C];
+  __shared__ float sm[(MODE == 0 ? 6 : 1) * 4 * STDA_BLOCK];
+  __shared__ float red[6 * C];
+  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
+  const int64_t P = (int64_t)B * h * w;
+  const int64_t items = P * G;
+  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int c0 = (int)(i % G) * 4;
+  float acc[6][4];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) zero4(acc[s]);
+  float sc[3][4], sh[3][4];
+  if (MODE == 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bn_affine4(prm.stats[k], prm.gamma[k], prm.beta[k], C, c0, sc[k], sh[k]);
+  for (; i < items; i += stride) {
+    const int64_t p = i / G;
+    int b, y, x;
+    pix3(p, h, w, b, y, x);
+    float pv[4], dv[4], xv[4];
+    stage1_branches<T, C>(X, p, b, y, x, h, w, c0, wp, wd, pv, dv, xv);
+    if (MODE == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[0][j] += pv[j];
+        acc[1][j] += pv[j] * pv[j];
+        acc[2][j] += dv[j];
+        acc[3][j] += dv[j] * dv[j];
+        acc[4][j] += xv[j];
+        acc[5][j] += xv[j] * xv[j];
+      }
+    } else {
+      float o[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        o[j] = fmaxf(pv[j] * sc[0][j] + sh[0][j] + dv[j] * sc[1][j] + sh[1][j] + xv[j] * sc[2][j] + sh[2][j], 0.f);
+      st4(X1 + p * C + c0, o);
+    }
+  }
+  if (MODE == 0) {
+    block_chan_reduce<G, 6>(acc, sm, red);
+    // red[s*C + c], s = 2k + m  ->  part[blk][k][c][m]
+    for (int q = threadIdx.x; q < 6 * C; q += STDA_BLOCK) {
+      const int s = q / C, c = q % C;
+      part[(int64_t)blockIdx.x * 6 * C + ((s >> 1) * C + c) * 2 + (s & 1)] = red[q];
+    }
+  }
+}
+
+// ---------------------------------------------------------- dense stride-2 layers (SIMT)
+// out[p][n] = sum over taps and input channels of src[...][k] * wl[tap][k][n]:
+//   OP_ENC_FWD   Conv3x3-s2-p1, src grid 2h x 2w -> dst h x w, taps: sy = 2y - 1 + ky
+//   OP_DEC_DGRAD adjoint of DeConv4x4-s2-p1 (a Conv4x4-s2-p1), same tap rule with k = 4
+//   OP_DEC_FWD   DeConv4x4-s2-p1, src h x w -> dst 2h x 2w, ky = ky0, ky0 + 2, ky0 = (y+1)&1,
+//                sy = (y + 1 - ky) / 2
+//   OP_ENC_DGRAD adjoint of Conv3x3-s2-p1 (the same up-sampling rule with k = 3)
+// wl is laid out [ky*k + kx][K][N] (prepared per call from the PyTorch weights).
+enum : int { OP_ENC_FWD = 0, OP_DEC_FWD = 1, OP_ENC_DGRAD = 2, OP_DEC_DGRAD = 3 };
+
+template <int OP> struct OpGeo {
+  static constexpr int KS = (OP == OP_ENC_FWD || OP == OP_ENC_DGRAD) ? 3 : 4;
+  static constexpr bool DOWN = (OP == OP_ENC_FWD || OP == OP_DEC_DGRAD);
+};
+
+template <class T, int OP, int K, int N, bool STATS>
+__global__ __launch_bounds__(256) void k_dense_simt(const T* __restrict__ src, const float* __restrict__ wl,
+                                                    T* __restrict__ dst, float* __restrict__ part, int B, int hd,
+                                                    int wd) {
+  constexpr int G = N / 4;
+  constexpr int KS = OpGeo<OP>::KS;
+  __shared__ float sm[(STATS ? 2 : 1) * 4 * STDA_BLOCK];
+  __shared__ float red[2 * N];
+  const int hs = OpGeo<OP>::DOWN ? hd * 2 : hd / 2;
+  const int ws = OpGeo<OP>::DOWN ? wd * 2 : wd / 2;
+  const int64_t P = (int64_t)B * hd * wd;
+  const int64_t items = P * G;
+  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int n0 = (int)(i % G) * 4;
+  float st[2][4];
+  zero4(st[0]);
+  zero4(st[1]);
+  for (; i < items; i += stride) {
+    const int64_t p = i / G;
+    int b, y, x;
+    pix3(p, hd, wd, b, y, x);
+    float acc[4];
+    zero4(acc);
+#pragma unroll
+    for (int a = 0; a < (OpGeo<OP>::DOWN ? KS : 2); ++a) {
+      const int ky = OpGeo<OP>::DOWN ? a : ((y + 1) & 1) + 2 * a;
+      const int sy = OpGeo<OP>::DOWN ? 2 * y - 1 + ky : (y + 1 - ky) / 2;
+      if (ky >= KS || sy < 0 || sy >= hs) continue;
+#pragma unroll
+      for (int c = 0; c < (OpGeo<OP>::DOWN ? KS : 2); ++c) {
+        const int kx = OpGeo<OP>::DOWN ? c : ((x + 1) & 1) + 2 * c;
+        const int sx = OpGeo<OP>::DOWN ? 2 * x - 1 + kx : (x + 1 - kx) / 2;
+        if (kx >= KS || sx < 0 || sx >= ws) continue;
+        const T* row = src + (((int64_t)b * hs + sy) * ws + sx) * K;
+        const float* wt = wl + (int64_t)(ky * KS + kx) * K * N + n0;
+#pragma unroll 4
+        for (int k = 0; k < K; k += 4) {
+          float v[4];
+          ld4(row + k, v);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const float4 wq = *reinterpret_cast<const float4*>(wt + (k + j) * N);
+            acc[0] += wq.x * v[j];
+            acc[1] += wq.y * v[j];
+            acc[2] += wq.z * v[j];
+            acc[3] += wq.w * v[j];
+          }
+        }
+      }
+    }
+    st4(dst + p * N + n0, acc);
+    if (STATS) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        st[0][j] += acc[j];
+        st[1][j] += acc[j] * acc[j];
+      }
+    }
+  }
+  if (STATS) {
+    block_chan_reduce<G, 2>(st, sm, red);
+    for (int q = threadIdx.x; q < 2 * N; q += STDA_BLOCK) {
+      const int s = q / N, c = q % N;
+      part[(int64_t)blockIdx.x * 2 * N + c * 2 + s] = red[q];
+    }
+  }
+}
+
+// --------------------------------------------------------------- stage 2 apply + GAP
+// Y = ReLU(BN(T)) + R; per-(clip, tile) channel sums of Y for the ECA global average pool.
+// Grid (tiles, clips); gap[clip][tile][C].
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_s2_apply(const T* __restrict__ Tm, const T* __restrict__ R, T* __restrict__ Y,
+                                                  float* __restrict__ gap, const float* __restrict__ stats,
+                                                  const float* __restrict__ gamma, const float* __restrict__ beta,
+                                                  int hw) {
+  constexpr int G = C / 4;
+  __shared__ float sm[4 * STDA_BLOCK];
+  __shared__ float red[C];
+  const int b = blockIdx.y, tiles = gridDim.x;
+  const int64_t items = (int64_t)hw * G;
+  const int64_t base = (int64_t)b * hw * C;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int c0 = (int)(i % G) * 4;
+  float sc[4], sh[4];
+  bn_affine4(stats, gamma, beta, C, c0, sc, sh);
+  float acc[1][4];
+  zero4(acc[0]);
+  for (; i < items; i += (int64_t)tiles * STDA_BLOCK) {
+    const int64_t off = base + (i / G) * C + c0;
+    float t[4], r[4];
+    ld4(Tm + off, t);
+    ld4(R + off, r);
+    float o[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = fmaxf(t[j] * sc[j] + sh[j], 0.f) + r[j];
+    st4(Y + off, o);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[0][j] += stored<T>(o[j]);  // the value as stored
+  }
+  block_chan_reduce<G, 1>(acc, sm, red);
+  for (int q = threadIdx.x; q < C; q += STDA_BLOCK) gap[((int64_t)b * tiles + blockIdx.x) * C + q] = red[q];
+}
+
+// ECA scale of one clip from its GAP partials (Sec. IV-C, Eq. (eca_process_equation)):
+// g = mean over (h, w); s[c] = w0 g[c-1] + w1 g[c] + w2 g[c+1] (zero padded); a = sigmoid(s).
+template <int C>
+__device__ __forceinline__ void eca_scale_clip(const float* __restrict__ gap, int tiles, int hw,
+                                               const float* __restrict__ weca, float* g_s, float* a_s) {
+  for (int c = threadIdx.x; c < C; c += STDA_BLOCK) {
+    double s = 0.0;
+    for (int t = 0; t < tiles; ++t) s += (double)gap[t * C + c];
+    g_s[c] = (float)(s / (double)hw);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += STDA_BLOCK) {
+    const float gm = c > 0 ? g_s[c - 1] : 0.f, gp = c < C - 1 ? g_s[c + 1] : 0.f;
+    const float s = weca[0] * gm + weca[1] * g_s[c] + weca[2] * gp;
+    a_s[c] = 1.f / (1.f + expf(-s));
+  }
+  __syncthreads();
+}
+
+// Next block input Xn = a[clip][c] * Y (+ skip).  Tile 0 of each clip also saves g and a.
+template <class T, int C, bool SKIP>
+__global__ __launch_bounds__(256) void k_eca_next(const T* __restrict__ Y, const T* __restrict__ skip,
+                                                  T* __restrict__ Xn, const float* __restrict__ gap,
+                                                  const float* __restrict__ weca, float* __restrict__ g_out,
+                                                  float* __restrict__ a_out, int hw, int gap_tiles) {
+  constexpr int G = C / 4;
+  __shared__ float g_s[C], a_s[C];
+  const int b = blockIdx.y, tiles = gridDim.x;
+  eca_scale_clip<C>(gap + (int64_t)b * gap_tiles * C, gap_tiles, hw, weca, g_s, a_s);
+  if (blockIdx.x == 0)
+    for (int c = threadIdx.x; c < C; c += STDA_BLOCK) {
+      g_out[b * C + c] = g_s[c];
+      a_out[b * C + c] = a_s[c];
+    }
+  const int64_t items = (int64_t)hw * G;
+  const int64_t base = (int64_t)b * hw * C;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int c0 = (int)(i % G) * 4;
+  for (; i < items; i += (int64_t)tiles * STDA_BLOCK) {
+    const int64_t off = base + (i / G) * C + c0;
+    float y[4], o[4];
+    ld4(Y + off, y);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = a_s[c0 + j] * y[j];
+    if (SKIP) {
+      float s[4];
+      ld4(skip + off, s);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[j] += s[j];
+    }
+    st4(Xn + off, o);
+  }
+}
+
+// --------------------------------------------------------------------- output module
+// z = Conv3x3-p1(d, 16 -> 1) + bias, planar FP32 output.
+template <class T>
+__global__ __launch_bounds__(256) void k_head_fwd(const T* __restrict__ d, const float* __restrict__ w,
+                                                  const float* __restrict__ bias, float* __restrict__ z, int B,
+                                                  int H, int W) {
+  const int64_t P = (int64_t)B * H * W;
+  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
+    int b, y, x;
+    pix3(p, H, W, b, y, x);
+    float acc = bias[0];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+      const T* row = d + (((int64_t)b * H + yy) * W + xx) * 16;
+#pragma unroll
+      for (int c = 0; c < 16; c += 4) {
+        float v[4];
+        ld4(row + c, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc += w[(c + j) * 9 + t] * v[j];
+      }
+    }
+    z[p] = acc;
+  }
+}
+
+// --------------------------------------------------------------------- loss
+// d = z - y (in FP64); dz = 2 d / n; per-block FP64 partial of d^2 / n.
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ z, const float* __restrict__ y,
+                                             float* __restrict__ dz, double* __restrict__ part, int64_t n) {
+  __shared__ double sm[STDA_BLOCK];
+  double acc = 0.0;
+  const double inv = 1.0 / (double)n;
+  for (int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * STDA_BLOCK) {
+    const double d = (double)z[i] - (double)y[i];  // exact difference of two FP32 values
+    dz[i] = (float)(2.0 * d * inv);
+    acc += d * d * inv;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = STDA_BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_sum_f64(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sm[STDA_BLOCK];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += STDA_BLOCK) acc += part[i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = STDA_BLOCK / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// SINR (Sec. V-B) of one map per block: 10 log10(mean_O m^2 / mean_N m^2), FP64 sums.
+__global__ __launch_bounds__(256) void k_sinr(const float* __restrict__ maps, const uint8_t* __restrict__ om,
+                                              const uint8_t* __restrict__ nm, int64_t hw, double* __restrict__ out) {
+  __shared__ double s[4][STDA_BLOCK];
+  const int64_t base = (int64_t)blockIdx.x * hw;
+  double so = 0.0, no = 0.0, sn = 0.0, nn = 0.0;
+  for (int64_t i = threadIdx.x; i < hw; i += STDA_BLOCK) {
+    const double v = (double)maps[base + i];
+    if (om[base + i]) { so += v * v; no += 1.0; }
+    if (nm[base + i]) { sn += v * v; nn += 1.0; }
+  }
+  s[0][threadIdx.x] = so;
+  s[1][threadIdx.x] = no;
+  s[2][threadIdx.x] = sn;
+  s[3][threadIdx.x] = nn;
+  __syncthreads();
+  for (int k = STDA_BLOCK / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k)
+      for (int q = 0; q < 4; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = 10.0 * log10((s[0][0] / s[1][0]) / (s[2][0] / s[3][0]));
+}
+
+}  // namespace stda

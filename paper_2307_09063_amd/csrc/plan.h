@@ -1,0 +1,79 @@
+// Static description of the network and the per-call memory plan of the Radar-STDA library.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/stda.h"
+
+namespace stda {
+
+// Mobile encoder / decoder blocks: input / output widths, decoder flag, input / output level
+// (level l = map downsampled by 2^l).
+struct BlockCfg {
+  int cin, cout;
+  bool dec;
+  int lin, lout;
+};
+constexpr BlockCfg kBlocks[4] = {
+    {16, 32, false, 0, 1},  // encoder block 0
+    {32, 64, false, 1, 2},  // encoder block 1
+    {64, 32, true, 2, 1},   // decoder block 0
+    {32, 16, true, 1, 0},   // decoder block 1
+};
+
+constexpr int kMaxSegs = 8;
+constexpr int kMaxGrid = 2048;       // blocks of per-pixel kernels (bounds partial buffers)
+constexpr int kMaxTiles = 64;        // blocks per clip of per-clip kernels
+constexpr int kMaxWgradGrid = 512;   // blocks of weight-gradient kernels
+constexpr int kNumGradBufs = 13;
+
+struct ParamEntry {
+  char name[40];
+  int64_t offset, count;
+  int ndim;
+  int shape[4];
+  int fan_in;
+};
+
+struct BlockOffsets {
+  int64_t pw_w, pw_g, pw_b, dw_w, dw_g, dw_b, id_g, id_b, main_w, main_g, main_b, res_w, eca_w;
+  int64_t bn_pw, bn_dw, bn_id, bn_main;  // offsets into the running / statistics buffers
+};
+
+struct NetOffsets {
+  int64_t stem_w, stem_g, stem_b, head_w, head_b;
+  BlockOffsets blk[4];
+  int64_t running_count;
+};
+
+const std::vector<ParamEntry>& param_table();
+const NetOffsets& net_offsets();
+
+// Byte offsets of one segment's activations (in `saved` for TRAIN, in `ws` for EVAL).
+struct BlockActs {
+  size_t X1, T, Y, Xn, a, g;
+};
+struct SegPlan {
+  int n, H, W;
+  int64_t x_off, z_off;
+  size_t stats;  // [mean C][invstd C] per BN layer, running-buffer layout
+  size_t S0p, s0;
+  BlockActs blk[4];
+};
+
+struct Plan {
+  int n_segs, dtype, mode;
+  SegPlan seg[kMaxSegs];
+  // ws regions (byte offsets)
+  size_t ws_wk, ws_dense, ws_R, ws_part, ws_sums, ws_gap, ws_eval_stats, ws_loss;
+  size_t ws_g[kNumGradBufs];
+  size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart;
+  int64_t dense_f[4][2], dense_d[4][2];  // element offsets inside ws_dense (main, residual)
+  size_t saved_bytes, ws_bytes;
+};
+
+void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute, Plan& P);
+
+}  // namespace stda

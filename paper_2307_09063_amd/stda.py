@@ -1,0 +1,247 @@
+"""Thin Python binding of libstda.so (include/stda.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels; PyTorch supplies device memory and
+the current stream.  Importing this module loads the library and raises if it is missing:
+there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libstda.so')
+
+STDA_OK = 0
+FP32, BF16 = 0, 1
+EVAL, TRAIN = 0, 1
+
+
+class StdaError(RuntimeError):
+    pass
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [('n', ctypes.c_int32), ('H', ctypes.c_int32), ('W', ctypes.c_int32),
+                ('x_off', ctypes.c_int64), ('z_off', ctypes.c_int64)]
+
+
+class ParamDesc(ctypes.Structure):
+    _fields_ = [('name', ctypes.c_char * 40), ('offset', ctypes.c_int64), ('ndim', ctypes.c_int32),
+                ('shape', ctypes.c_int32 * 4), ('fan_in', ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise StdaError(f'{LIB_PATH} is missing: build it with `python -m paper_2307_09063_amd.build` '
+                        '(there is no CPU fallback)')
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    F, U32 = ctypes.c_float, ctypes.c_uint32
+    sig = {
+        'stda_status_string': (ctypes.c_char_p, [I]),
+        'stda_last_hip_error': (I, []),
+        'stda_param_count': (SZ, []),
+        'stda_param_table': (I, [P, I]),
+        'stda_bn_layer_count': (I, []),
+        'stda_running_count': (SZ, []),
+        'stda_workspace_size': (I, [P, I, I, I, I, P, P]),
+        'stda_forward': (I, [P, I, P, P, P, P, P, SZ, P, SZ, I, I, I, P]),
+        'stda_backward': (I, [P, I, P, P, P, P, SZ, P, P, P, SZ, I, I, P]),
+        'stda_mse_loss': (I, [P, I, P, P, P, P, P, SZ, P]),
+        'stda_sgd_step': (I, [P, P, I64, F, F, P, P]),
+        'stda_sinr': (I, [P, P, P, I, I, I, P, P]),
+        'rd_synth_workspace_size': (SZ, [I, I, I]),
+        'rd_synth': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
+           'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
+           'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'rd_synth_workspace_size',
+           'rd_synth')
+
+
+def _check(status, what):
+    if status != STDA_OK:
+        msg = _lib.stda_status_string(status).decode()
+        hip = _lib.stda_last_hip_error()
+        raise StdaError(f'{what}: {msg} (status {status}, hip {hip})')
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise StdaError('tensor arguments must be device tensors')
+    if not t.is_contiguous():
+        raise StdaError('tensor arguments must be contiguous')
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _seg_array(segs):
+    arr = (Segment * len(segs))()
+    for i, s in enumerate(segs):
+        arr[i] = s if isinstance(s, Segment) else Segment(*s)
+    return arr
+
+
+# ------------------------------------------------------------------------ tables
+def param_count():
+    return int(_lib.stda_param_count())
+
+
+def running_count():
+    return int(_lib.stda_running_count())
+
+
+def param_table():
+    n = _lib.stda_param_table(None, 0)
+    arr = (ParamDesc * n)()
+    _lib.stda_param_table(ctypes.cast(arr, ctypes.c_void_p), n)
+    return [{'name': d.name.decode(), 'offset': d.offset, 'shape': tuple(d.shape[:d.ndim]),
+             'fan_in': d.fan_in} for d in arr]
+
+
+def param_specs():
+    """(name, shape, fan_in) in buffer order, the form the input generators take."""
+    return [(d['name'], d['shape'], d['fan_in']) for d in param_table()]
+
+
+def bn_channels():
+    """Channels of each BN layer in running-buffer order."""
+    out = [16]
+    for cin, cout in ((16, 32), (32, 64), (64, 32), (32, 16)):
+        out += [cin, cin, cin, cout]
+    return out
+
+
+def uniform_segments(n, H, W):
+    return [Segment(n, H, W, 0, 0)]
+
+
+def packed_segments(sizes_counts):
+    """[(n, H, W), ...] -> segments packed back to back."""
+    segs, xo, zo = [], 0, 0
+    for n, H, W in sizes_counts:
+        segs.append(Segment(n, H, W, xo, zo))
+        xo += 3 * n * H * W
+        zo += n * H * W
+    return segs
+
+
+# ------------------------------------------------------------------------ network
+def workspace_size(segs, dtype=FP32, mode=TRAIN, recompute=0):
+    sv, ws = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    arr = _seg_array(segs)
+    _check(_lib.stda_workspace_size(ctypes.cast(arr, ctypes.c_void_p), len(segs), dtype, mode, recompute,
+                                    ctypes.byref(sv), ctypes.byref(ws)), 'stda_workspace_size')
+    return sv.value, ws.value
+
+
+def alloc_bytes(n, device='cuda'):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+def forward(segs, x, w, running, z, saved, ws, dtype=FP32, mode=EVAL, recompute=0):
+    arr = _seg_array(segs)
+    _check(_lib.stda_forward(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(w), _ptr(running),
+                             _ptr(z), _ptr(saved), saved.numel() if saved is not None else 0, _ptr(ws),
+                             ws.numel(), dtype, mode, recompute, _stream()), 'stda_forward')
+
+
+def backward(segs, x, dz, w, saved, dw, dx, ws, dtype=FP32, recompute=0):
+    arr = _seg_array(segs)
+    _check(_lib.stda_backward(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(dz), _ptr(w),
+                              _ptr(saved), saved.numel(), _ptr(dw), _ptr(dx), _ptr(ws), ws.numel(), dtype,
+                              recompute, _stream()), 'stda_backward')
+
+
+def mse_loss(segs, z, y, loss, dz, ws):
+    arr = _seg_array(segs)
+    _check(_lib.stda_mse_loss(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(z), _ptr(y), _ptr(loss),
+                              _ptr(dz), _ptr(ws), ws.numel(), _stream()), 'stda_mse_loss')
+
+
+def sgd_step(w, dw, lr, weight_decay, w_bf16=None):
+    _check(_lib.stda_sgd_step(_ptr(w), _ptr(dw), w.numel(), lr, weight_decay, _ptr(w_bf16), _stream()),
+           'stda_sgd_step')
+
+
+def sinr(maps, o_mask, n_mask, out):
+    n, H, W = maps.shape[0], maps.shape[-2], maps.shape[-1]
+    _check(_lib.stda_sinr(_ptr(maps), _ptr(o_mask), _ptr(n_mask), n, H, W, _ptr(out), _stream()), 'stda_sinr')
+
+
+# ------------------------------------------------------------------------ RD maps
+def rd_synth_workspace_size(n_clips, N, M):
+    return int(_lib.rd_synth_workspace_size(n_clips, N, M))
+
+
+def rd_synth(scenes_dev, n_clips, N, M, seed, noise_sigma, x_out, clean_out=None, ws=None, clip_base=0):
+    if ws is None:
+        ws = alloc_bytes(rd_synth_workspace_size(n_clips, N, M), x_out.device)
+    _check(_lib.rd_synth(_ptr(scenes_dev), n_clips, N, M, int(seed) & 0xFFFFFFFF, float(noise_sigma),
+                         clip_base, _ptr(x_out), _ptr(clean_out), _ptr(ws), ws.numel(), _stream()), 'rd_synth')
+
+
+def upload_scenes(tab, device='cuda'):
+    """Scene table (numpy array of the rd_scene layout) -> device bytes."""
+    raw = np.ascontiguousarray(tab).view(np.uint8).reshape(-1)
+    return torch.from_numpy(raw.copy()).to(device)
+
+
+def synthesize(tab, meta, device='cuda', with_clean=True):
+    """RD maps of a scene table on the GPU: (x [B, 3, N, M], clean [B, 1, N, M] or None)."""
+    B, N, M = len(tab), meta['N'], meta['M']
+    x = torch.empty((B, 3, N, M), dtype=torch.float32, device=device)
+    clean = torch.empty((B, 1, N, M), dtype=torch.float32, device=device) if with_clean else None
+    rd_synth(upload_scenes(tab, device), B, N, M, meta['seed'], meta['noise_sigma'], x, clean)
+    return x, clean
+
+
+# ------------------------------------------------------------------------ autograd
+class STDAFunction(torch.autograd.Function):
+    """z = Radar-STDA(x; w) with the library's TRAIN forward and hand-written backward.
+
+    forward(x [B, 3, H, W], w [137469], running [1184] (updated in place), dtype, recompute)
+    backward returns (dx or None, dw, None, None, None).
+    """
+
+    @staticmethod
+    def forward(ctx, x, w, running, dtype=FP32, recompute=0):
+        B, _, H, W = x.shape
+        segs = uniform_segments(B, H, W)
+        sv_b, ws_b = workspace_size(segs, dtype, TRAIN, recompute)
+        saved = alloc_bytes(sv_b, x.device)
+        ws = alloc_bytes(ws_b, x.device)
+        z = torch.empty((B, 1, H, W), dtype=torch.float32, device=x.device)
+        xc = x.detach().contiguous()
+        forward(segs, xc, w.detach(), running, z, saved, ws, dtype, TRAIN, recompute)
+        ctx.save_for_backward(xc, w)
+        ctx.saved_buf, ctx.ws, ctx.segs, ctx.dtype, ctx.recompute = saved, ws, segs, dtype, recompute
+        return z
+
+    @staticmethod
+    def backward(ctx, dz):
+        x, w = ctx.saved_tensors
+        dw = torch.empty_like(w)
+        dx = torch.empty_like(x) if ctx.needs_input_grad[0] else None
+        backward(ctx.segs, x, dz.contiguous(), w.detach(), ctx.saved_buf, dw, dx, ctx.ws, ctx.dtype,
+                 ctx.recompute)
+        return dx, dw, None, None, None
+
+
+def stda(x, w, running, dtype=FP32, recompute=0):
+    return STDAFunction.apply(x, w, running, dtype, recompute)
