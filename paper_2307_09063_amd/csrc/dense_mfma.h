@@ -1,0 +1,297 @@
+// Dense stride-2 layers of the mobile blocks on the matrix cores (gfx950 MFMA).
+//
+// Implicit GEMM: out[p][n] = sum over taps t and input channels k of src(p, t)[k] * W[t][k][n].
+// One wave computes 16*R GEMM rows (pixels) x all N output channels; a block is 4 waves and
+// loops over row tiles.  A fragments are gathered straight from NHWC rows: lane (m, g) of a
+// 16-row sub-tile loads channels 16s + 4g .. +3 of its pixel (one 16-byte FP32 or 8-byte BF16
+// load).  B fragments are pre-arranged per call in "fragment order" (lane-contiguous), so a
+// wave reads one coalesced 1 KB (FP32) / 512 B (BF16) block per (tap, 16-channel chunk, 16
+// output channels); every block reads the same weights, which therefore stay in L1/L2.
+//
+// FP32: v_mfma_f32_16x16x4f32.  The four channels a lane holds feed four consecutive MFMAs
+// (k-index e of the lane group g is channel 4g + e): a fixed permutation of the reduction order
+// applied identically to A and B.  BF16: v_mfma_f32_16x16x16bf16_1k, lane group g supplying
+// channels 4g .. 4g + 3 of the 16-channel chunk.  Accumulation is FP32 in both cases.
+//
+// Up-sampling operators (DeConv4x4-s2 forward, Conv3x3-s2 adjoint) run one output phase
+// (row parity, column parity) per grid.y so that all rows of a block share their taps.
+#pragma once
+#include <type_traits>
+
+#include "net_kernels.h"
+
+namespace stda {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct FragT;
+template <>
+struct FragT<float> {
+  typedef float4 type;
+};
+template <>
+struct FragT<bf16> {
+  typedef shortx4 type;
+};
+
+__device__ __forceinline__ floatx4 mfma_chunk(const float4 a, const float4 b, floatx4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, c, 0, 0, 0);
+  return c;
+}
+__device__ __forceinline__ floatx4 mfma_chunk(const shortx4 a, const shortx4 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+template <class F>
+__device__ __forceinline__ F frag_zero() {
+  F z;
+  if constexpr (std::is_same<F, float4>::value) {
+    z = make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    z = shortx4{0, 0, 0, 0};
+  }
+  return z;
+}
+
+// Fragment-order weights: frag[((tap * KC + s) * NT + nt) * 64 + lane][e] = W[tap][16 s + 4 g + e]
+// [16 nt + m] (lane = 16 g + m), from [tap][K][N] FP32 layouts; one job per layout.
+struct FragJob {
+  int64_t src, dst;  // element offsets of the [tap][K][N] layout and of the fragment buffer
+  int taps, K, N;
+};
+struct FragJobs {
+  int n;
+  FragJob j[16];
+};
+template <class T>
+__global__ void k_prep_frag(const float* __restrict__ wl, T* __restrict__ frag, FragJobs jobs) {
+  const FragJob J = jobs.j[blockIdx.y];
+  const int KC = J.K / 16, NT = J.N / 16;
+  const int64_t total = (int64_t)J.taps * KC * NT * 64 * 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int e = (int)(i & 3);
+    int64_t r = i >> 2;
+    const int lane = (int)(r & 63);
+    r >>= 6;
+    const int nt = (int)(r % NT);
+    r /= NT;
+    const int s = (int)(r % KC);
+    const int tap = (int)(r / KC);
+    const int k = 16 * s + 4 * (lane >> 4) + e, n = 16 * nt + (lane & 15);
+    frag[J.dst + i] = from_f<T>(wl[J.src + ((int64_t)tap * J.K + k) * J.N + n]);
+  }
+}
+
+template <class T, int OP, int K, int N, int R, bool STATS>
+__global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, const T* __restrict__ wfrag,
+                                                    T* __restrict__ dst, float* __restrict__ part, int B, int hd,
+                                                    int wd) {
+  typedef typename FragT<T>::type F;
+  constexpr int KS = OpGeo<OP>::KS;
+  constexpr bool DOWN = OpGeo<OP>::DOWN;
+  constexpr int NT = N / 16, KC = K / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, g = lane >> 4;
+  const int py = DOWN ? 0 : (int)(blockIdx.y >> 1), px = DOWN ? 0 : (int)(blockIdx.y & 1);
+  const int hr = DOWN ? hd : hd / 2, wr = DOWN ? wd : wd / 2;  // GEMM row grid
+  const int hs = DOWN ? 2 * hd : hd / 2, ws = DOWN ? 2 * wd : wd / 2;
+  const int64_t P = (int64_t)B * hr * wr;
+  const int64_t tiles = (P + 64 * R - 1) / (64 * R);
+  const F* wf = reinterpret_cast<const F*>(wfrag);
+  float st1[NT], st2[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) st1[nt] = st2[nt] = 0.f;
+
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t pbase = (tile * 4 + wave) * 16 * R;
+    int pb[R], prow[R], pcol[R];
+    bool pv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t p = pbase + 16 * r + m;
+      pv[r] = p < P;
+      pix3(pv[r] ? p : 0, hr, wr, pb[r], prow[r], pcol[r]);
+    }
+    floatx4 acc[R][NT];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[r][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll
+    for (int a = 0; a < (DOWN ? KS : 2); ++a) {
+      const int ky = DOWN ? a : ((py + 1) & 1) + 2 * a;
+      if (ky >= KS) continue;
+#pragma unroll
+      for (int c = 0; c < (DOWN ? KS : 2); ++c) {
+        const int kx = DOWN ? c : ((px + 1) & 1) + 2 * c;
+        if (kx >= KS) continue;
+        const int tap = ky * KS + kx;
+        int64_t so[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int sy = DOWN ? 2 * prow[r] - 1 + ky : (2 * prow[r] + py + 1 - ky) / 2;
+          const int sx = DOWN ? 2 * pcol[r] - 1 + kx : (2 * pcol[r] + px + 1 - kx) / 2;
+          const bool ok = pv[r] && sy >= 0 && sy < hs && sx >= 0 && sx < ws;
+          so[r] = ok ? (((int64_t)pb[r] * hs + sy) * ws + sx) * K + 4 * g : -1;
+        }
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+          F av[R];
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            av[r] = so[r] >= 0 ? *reinterpret_cast<const F*>(src + so[r] + 16 * s) : frag_zero<F>();
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const F bv = wf[((tap * KC + s) * NT + nt) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r][nt] = mfma_chunk(av[r], bv, acc[r][nt]);
+          }
+        }
+      }
+    }
+    // epilogue: lane holds rows 4g + i of each 16-row sub-tile, channel 16 nt + m
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t p = pbase + 16 * r + 4 * g + i;
+        if (p >= P) continue;
+        int64_t dp = p;
+        if (!DOWN) {
+          int b, y, x;
+          pix3(p, hr, wr, b, y, x);
+          dp = ((int64_t)b * hd + 2 * y + py) * wd + 2 * x + px;
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const float v = acc[r][nt][i];
+          dst[dp * N + 16 * nt + m] = from_f<T>(v);
+          if (STATS) {
+            st1[nt] += v;
+            st2[nt] += v * v;
+          }
+        }
+      }
+  }
+  if (STATS) {
+    __shared__ float sm[4][2][N];
+    // reduce over the 4 lane groups (same channel), then over the 4 waves, in a fixed order
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      float a1 = st1[nt], a2 = st2[nt];
+      a1 += __shfl_xor(a1, 16);
+      a2 += __shfl_xor(a2, 16);
+      a1 += __shfl_xor(a1, 32);
+      a2 += __shfl_xor(a2, 32);
+      if (g == 0) {
+        sm[wave][0][16 * nt + m] = a1;
+        sm[wave][1][16 * nt + m] = a2;
+      }
+    }
+    __syncthreads();
+    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    for (int q = threadIdx.x; q < 2 * N; q += STDA_BLOCK) {
+      const int c = q >> 1, s = q & 1;
+      part[blk * 2 * N + q] = sm[0][s][c] + sm[1][s][c] + sm[2][s][c] + sm[3][s][c];
+    }
+  }
+}
+
+}  // namespace stda
+
+namespace stda {
+
+// Weight gradients on the matrix cores: dW[k][n] = sum over pixels p of A(p)[k] * B(p)[n], the
+// reduction over pixels being the MFMA's inner dimension.  A block covers one 64 x 64 block of
+// dW (rows kb*64.., columns nb*64..) for one contiguous range of pixels (grid.y splits the
+// pixels); its 4 waves take quarters of that range and are summed in LDS in a fixed order.
+// Lane (i, g): the loader returns 4 consecutive rows 4i..4i+3 (and columns 4j..4j+3) of the
+// lane's pixel; row 4i + t of the block is row i of 16-row tile t (likewise for columns), so
+// one 16-byte load feeds four tiles.  FP32: one pixel per lane group per MFMA (16x16x4).
+// BF16: four pixels per lane group per MFMA (16x16x16), transposed in registers.
+// part[split][k * N + n] holds the block's sums for the real (unpadded) k < K, n < N.
+template <class L, bool BF>
+__global__ __launch_bounds__(256) void k_wgrad_mfma(L ld, float* __restrict__ part) {
+  constexpr int K = L::K, N = L::N;
+  constexpr int NB = (N + 63) / 64;
+  constexpr int PS = BF ? 16 : 4;  // pixels per MFMA step
+  __shared__ float red[64 * 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
+  const int kb = blockIdx.x / NB, nb = blockIdx.x % NB;
+  const int k4 = kb * 64 + 4 * i, n4 = nb * 64 + 4 * i;
+  const bool kv = k4 < K, nv = n4 < N;
+  const int64_t P = ld.npix();
+  const int64_t nsplit = (int64_t)gridDim.y * 4;
+  const int64_t steps = (P + PS - 1) / PS;
+  const int64_t per = (steps + nsplit - 1) / nsplit;
+  const int64_t s0 = ((int64_t)blockIdx.y * 4 + wave) * per;
+  const int64_t s1 = s0 + per < steps ? s0 + per : steps;
+  floatx4 acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t st = s0; st < s1; ++st) {
+    if (!BF) {
+      const int64_t p = st * 4 + g;
+      float a[4], b[4];
+      if (p < P && kv) ld.a4(p, k4, a); else zero4(a);
+      if (p < P && nv) ld.b4(p, n4, b); else zero4(b);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[u], acc[t][u], 0, 0, 0);
+    } else {
+      // pixels st*16 + 4g + e, e = 0..3; values are BF16-exact, so truncation packs them exactly
+      float a[4][4], b[4][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t p = st * 16 + 4 * g + e;
+        if (p < P && kv) ld.a4(p, k4, a[e]); else zero4(a[e]);
+        if (p < P && nv) ld.b4(p, n4, b[e]); else zero4(b[e]);
+      }
+      shortx4 av[4], bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        av[t] = shortx4{(short)(__float_as_uint(a[0][t]) >> 16), (short)(__float_as_uint(a[1][t]) >> 16),
+                        (short)(__float_as_uint(a[2][t]) >> 16), (short)(__float_as_uint(a[3][t]) >> 16)};
+        bv[t] = shortx4{(short)(__float_as_uint(b[0][t]) >> 16), (short)(__float_as_uint(b[1][t]) >> 16),
+                        (short)(__float_as_uint(b[2][t]) >> 16), (short)(__float_as_uint(b[3][t]) >> 16)};
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[t], bv[u], acc[t][u], 0, 0, 0);
+    }
+  }
+  // tile (t, u), lane (i', g'): D[4g' + r][i'] -> block row 4 (4g' + r) + t, block column 4 i' + u
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 4 * (4 * g + r) + t, col = 4 * i + u;
+            const float v = acc[t][u][r];
+            red[row * 64 + col] = w == 0 ? v : red[row * 64 + col] + v;
+          }
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < 64 * 64; q += STDA_BLOCK) {
+    const int row = q >> 6, col = q & 63;
+    const int k = kb * 64 + row, n = nb * 64 + col;
+    if (k < K && n < N) part[(int64_t)blockIdx.y * K * N + (int64_t)k * N + n] = red[q];
+  }
+}
+
+}  // namespace stda

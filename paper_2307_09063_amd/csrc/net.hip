@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/stda.h"
+#include "dense_mfma.h"
 #include "net_bwd_kernels.h"
 #include "net_kernels.h"
 #include "plan.h"
@@ -190,7 +191,7 @@ __global__ void k_prep_dense(const float* __restrict__ w, float* __restrict__ ou
   }
 }
 
-// Working copy of all parameters; convolution weights rounded to BF16 in BF16 mode.
+// Working copy of all parameters; in BF16 mode the listed ranges are rounded to BF16.
 struct RoundRanges {
   int n;
   int64_t off[24];
@@ -245,6 +246,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     }
   }
   P.ws_dense = ws.take(sizeof(float) * dense_elems);
+  P.ws_frag = ws.take(sizeof(float) * dense_elems);  // same element offsets as ws_dense
   int64_t max_pix = 0, max_clips = 0;
   for (int s = 0; s < n_segs; ++s) {
     max_pix = std::max<int64_t>(max_pix, (int64_t)segs[s].n * segs[s].H * segs[s].W);
@@ -277,7 +279,6 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     S.z_off = segs[s].z_off;
     const int64_t HW = H * W;
     S.stats = (train ? sv : ws).take(sizeof(float) * stda_running_count());
-    S.S0p = acts.take(es * 16 * n * HW);
     S.s0 = acts.take(es * 16 * n * HW);
     for (int k = 0; k < 4; ++k) {
       const BlockCfg& b = kBlocks[k];
@@ -289,6 +290,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
       A.Xn = acts.take(es * b.cout * n * hout * wout);
       A.a = acts.take(sizeof(float) * b.cout * n);
       A.g = acts.take(sizeof(float) * b.cout * n);
+      A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
     }
   }
   P.saved_bytes = train ? sv.off : 0;
@@ -318,6 +320,23 @@ struct Ctx {
 int tiles_for(int64_t hw, int G) {
   const int64_t item_blocks = (hw * G + STDA_BLOCK - 1) / STDA_BLOCK;
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
+}
+
+// Dense stride-2 layer on the matrix cores; returns the number of blocks (partials rows).
+template <class T, int OP, int K, int N, bool STATS>
+int launch_dense(const Ctx<T>& c, const T* src, int64_t frag_off, T* dst, float* part, int n, int hd, int wd,
+                 int* nblk) {
+  constexpr int R = 4;
+  constexpr bool down = OpGeo<OP>::DOWN;
+  const int64_t P = (int64_t)n * (down ? (int64_t)hd * wd : (int64_t)(hd / 2) * (wd / 2));
+  const int phases = down ? 1 : 4;
+  const int64_t tiles = (P + 64 * R - 1) / (64 * R);
+  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid / phases));
+  const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
+  k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd);
+  LAUNCH_CHECK();
+  if (nblk) *nblk = gx * phases;
+  return STDA_OK;
 }
 
 // Column sums of per-block BN partials followed by the statistics finalize.
@@ -382,23 +401,28 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   const float* dl = c.dl;
   const int g2 = grid_for(Pout * (COUT / 4));
   constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
+  (void)dl;
+  (void)g2;
   if (c.train) {
-    k_dense_simt<T, OPF, CIN, COUT, true><<<g2, 256, 0, c.st>>>(X1, dl + c.P->dense_f[k][0], Tm, part, n, hout, wout);
-    LAUNCH_CHECK();
+    int nb = 0;
+    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
+      return r;
     float* so[1] = {c.stats(bo.bn_main)};
     float* ro[1] = {running + bo.bn_main};
-    if (int r = bn_finalize(c, g2, 1, COUT, (double)Pout, so, ro, running)) return r;
+    if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro, running)) return r;
   } else {
-    k_dense_simt<T, OPF, CIN, COUT, false><<<g2, 256, 0, c.st>>>(X1, dl + c.P->dense_f[k][0], Tm, nullptr, n, hout, wout);
-    LAUNCH_CHECK();
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
+                                                       nullptr))
+      return r;
   }
-  k_dense_simt<T, OPF, CIN, COUT, false><<<g2, 256, 0, c.st>>>(X, dl + c.P->dense_f[k][1], R, nullptr, n, hout, wout);
-  LAUNCH_CHECK();
+  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+    return r;
   // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
   const int hw = hout * wout;
   const int tiles = tiles_for(hw, COUT / 4);
   float* gap = c.template scr<float>(c.P->ws_gap);
-  k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, gap, c.stats(bo.bn_main), c.w + bo.main_g,
+  uint8_t* mask = c.train ? c.template act<uint8_t>(A.mask) : nullptr;
+  k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, mask, gap, c.stats(bo.bn_main), c.w + bo.main_g,
                                                         c.w + bo.main_b, hw);
   LAUNCH_CHECK();
   T* Xn = c.template act<T>(A.Xn);
@@ -422,23 +446,19 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   const int64_t P = (int64_t)S.n * S.H * S.W;
   const float* xs = x + S.x_off;
   float* part = c.template scr<float>(c.P->ws_part);
-  T* S0p = c.template act<T>(S.S0p);
   T* s0 = c.template act<T>(S.s0);
   const int gs = grid_for(P);
   if (c.train) {
-    k_stem_fwd<T, true><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, S0p, part, nullptr, nullptr, nullptr, S.n, S.H,
-                                              S.W);
+    k_stem_fwd<T, 0><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, nullptr, part, nullptr, nullptr, nullptr, S.n, S.H,
+                                           S.W);
     LAUNCH_CHECK();
     float* so[1] = {c.stats(0)};
     float* ro[1] = {running};
     if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro, running)) return r;
-    k_bn_relu<T, 16><<<grid_for(P * 4), 256, 0, c.st>>>(S0p, s0, c.stats(0), c.w + no.stem_g, c.w + no.stem_b, P);
-    LAUNCH_CHECK();
-  } else {
-    k_stem_fwd<T, false><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
-                                               c.w + no.stem_b, S.n, S.H, S.W);
-    LAUNCH_CHECK();
   }
+  k_stem_fwd<T, 1><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
+                                         c.w + no.stem_b, S.n, S.H, S.W);
+  LAUNCH_CHECK();
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
   if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
@@ -467,9 +487,10 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
   if (P.dtype == STDA_BF16) {
     RoundRanges rr{};
     for (const auto& e : param_table()) {
-      const size_t L = std::strlen(e.name);
-      const bool conv_w = L > 2 && std::strcmp(e.name + L - 2, ".w") == 0 && std::strstr(e.name, "eca") == nullptr;
-      if (conv_w) {
+      // only the weights the matrix cores consume (the stride-2 layers) are rounded; the
+      // SIMT layers (input / output modules, pointwise, depthwise) keep FP32 weights
+      const bool mfma_w = std::strstr(e.name, ".s2.main.w") != nullptr || std::strstr(e.name, ".s2.res.w") != nullptr;
+      if (mfma_w) {
         rr.off[rr.n] = e.offset;
         rr.cnt[rr.n] = e.count;
         ++rr.n;
@@ -493,6 +514,19 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
       j.dst_d = P.dense_d[k][m];
     }
   k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
+  LAUNCH_CHECK();
+  FragJobs fj{};
+  for (int k = 0; k < 4; ++k)
+    for (int m = 0; m < 2; ++m) {
+      const int taps = kBlocks[k].dec ? 16 : 9;
+      fj.j[fj.n++] = FragJob{P.dense_f[k][m], P.dense_f[k][m], taps, kBlocks[k].cin, kBlocks[k].cout};
+      fj.j[fj.n++] = FragJob{P.dense_d[k][m], P.dense_d[k][m], taps, kBlocks[k].cout, kBlocks[k].cin};
+    }
+  const float* dl = reinterpret_cast<const float*>(ws + P.ws_dense);
+  if (P.dtype == STDA_BF16)
+    k_prep_frag<bf16><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<bf16*>(ws + P.ws_frag), fj);
+  else
+    k_prep_frag<float><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<float*>(ws + P.ws_frag), fj);
   LAUNCH_CHECK();
   *wk_out = src;
   return STDA_OK;
@@ -549,15 +583,20 @@ constexpr int pch_for() {
   return p >= 64 ? 64 : p >= 32 ? 32 : p >= 16 ? 16 : p >= 8 ? 8 : 4;
 }
 
+// Weight gradient on the matrix cores; the pixel range is split so that about 1024 blocks run,
+// and the per-split partials are summed in FP64 into the destination.
 template <class T, class L>
 int run_wgrad(const Ctx<T>& c, const L& ld, int64_t npix, float* dst, ColMap map, int acc) {
-  constexpr int PCH = pch_for<L>();
+  constexpr int KB = (L::K + 63) / 64, NB = (L::N + 63) / 64;
+  constexpr bool BF = L::kBF16Operands;
   float* wpart = c.template scr<float>(c.P->ws_wpart);
-  const int64_t chunks = (npix + PCH - 1) / PCH;
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, kMaxWgradGrid));
-  k_wgrad<L, PCH><<<grid, 256, 0, c.st>>>(ld, wpart);
+  const int64_t steps = (npix + (BF ? 15 : 3)) / (BF ? 16 : 4);
+  int64_t splits = std::max<int64_t>(1, 1024 / (KB * NB));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, steps / 64));  // >= 16 steps per wave
+  splits = std::min<int64_t>(splits, kMaxWgradGrid);
+  k_wgrad_mfma<L, BF><<<dim3(KB * NB, (int)splits), 256, 0, c.st>>>(ld, wpart);
   LAUNCH_CHECK();
-  return colsum_to(c, wpart, grid, L::K * L::N, dst, map, acc);
+  return colsum_to(c, wpart, (int)splits, L::K * L::N, dst, map, acc);
 }
 
 template <class T>
@@ -602,8 +641,9 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   // ECA adjoint partials and stage-2 BN statistics
   k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw);
   LAUNCH_CHECK();
+  const uint8_t* mask = c.template act<uint8_t>(A.mask);
   k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
-      Gd, Tm, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
+      Gd, Tm, mask, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
       c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles);
   LAUNCH_CHECK();
   if (int r = colsum_to(c, ecaw, n, 3, dw + bo.eca_w, ColMap{MAP_IDENT, 0, 0}, acc)) return r;
@@ -612,19 +652,18 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
     float* db[1] = {dw + bo.main_b};
     if (int r = bn_bwd(c, tiles * n, 2, COUT, (double)Pout, dg, db, acc)) return r;
   }
-  k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, c.template act<float>(A.a), coef_e,
+  k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, mask, c.template act<float>(A.a), coef_e,
                                                             c.template scr<float>(c.P->ws_coef), c.stats(bo.bn_main),
                                                             c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw);
   LAUNCH_CHECK();
   // dense adjoints: dX1 from dT, dXr from dY
   constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
   const int gd = grid_for(Pin * (CIN / 4));
-  k_dense_simt<T, OPD, COUT, CIN, false><<<gd, 256, 0, c.st>>>(dT, c.dl + c.P->dense_d[k][0], dX1, nullptr, n, hin,
-                                                               win);
-  LAUNCH_CHECK();
-  k_dense_simt<T, OPD, COUT, CIN, false><<<gd, 256, 0, c.st>>>(dY, c.dl + c.P->dense_d[k][1], dXr, nullptr, n, hin,
-                                                               win);
-  LAUNCH_CHECK();
+  (void)gd;
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
+    return r;
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+    return r;
   // dense weight gradients
   if (DEC) {
     WgDecS2<T, CIN, COUT> lm{X1, dT, n, hin, win};
@@ -696,16 +735,17 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   // input module
   float* part = c.template scr<float>(c.P->ws_part);
   const int g = grid_for(P * 4);
-  k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), c.template act<T>(S.S0p), c.stats(0),
-                                           part, P);
+  k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
+                                           part, S.n, S.H, S.W);
   LAUNCH_CHECK();
   {
     float* dg[1] = {dw + no.stem_g};
     float* db[1] = {dw + no.stem_b};
     if (int r = bn_bwd(c, g, 2, 16, (double)P, dg, db, acc)) return r;
   }
-  k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), c.template act<T>(S.S0p), c.stats(0),
-                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef), gb(12), P);
+  k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
+                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef), gb(12), S.n, S.H,
+                                           S.W);
   LAUNCH_CHECK();
   {
     WgStem<T> ls{x + S.x_off, gb(12), S.n, S.H, S.W};

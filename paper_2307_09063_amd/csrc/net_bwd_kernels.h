@@ -1,5 +1,7 @@
 // Hand-written adjoint kernels of the Radar-STDA network (gfx950), NHWC, FP32 or BF16 storage.
 #pragma once
+#include <type_traits>
+
 #include "net_kernels.h"
 
 namespace stda {
@@ -83,6 +85,7 @@ __global__ __launch_bounds__(256) void k_wgrad(L ld, float* __restrict__ part) {
 template <class T, int CIN, int COUT>
 struct WgEncS2 {
   static constexpr int K = 9 * CIN, N = COUT;
+  static constexpr bool kBF16Operands = std::is_same<T, bf16>::value;
   const T* X;
   const T* D;
   int B, ho, wo;
@@ -103,6 +106,7 @@ struct WgEncS2 {
 template <class T, int CIN, int COUT>
 struct WgDecS2 {
   static constexpr int K = CIN, N = 16 * COUT;
+  static constexpr bool kBF16Operands = std::is_same<T, bf16>::value;
   const T* X;
   const T* D;
   int B, hi, wi;
@@ -122,6 +126,7 @@ struct WgDecS2 {
 template <class T, int C>
 struct WgPw {
   static constexpr int K = C, N = C;
+  static constexpr bool kBF16Operands = std::is_same<T, bf16>::value;
   const T* X;
   const T* D;
   int64_t P;
@@ -135,6 +140,7 @@ struct WgPw {
 template <class T>
 struct WgStem {
   static constexpr int K = 28, N = 16;
+  static constexpr bool kBF16Operands = false;  // the boundary input is FP32
   const float* x;
   const T* D;
   int B, H, W;
@@ -160,6 +166,7 @@ struct WgStem {
 template <class T>
 struct WgHead {
   static constexpr int K = 148, N = 4;
+  static constexpr bool kBF16Operands = false;  // dz is FP32
   const T* d;
   const float* dz;
   int B, H, W;
@@ -283,6 +290,7 @@ __device__ __forceinline__ void eca_adjoint_clip(const float* __restrict__ part,
 // each clip writes e (coef_e[clip][C]) and the ECA weight partial (ecaw[clip][3]).
 template <class T, int C>
 __global__ __launch_bounds__(256) void k_s2_bwd_stats(const T* __restrict__ Gd, const T* __restrict__ Tm,
+                                                      const uint8_t* __restrict__ mask,
                                                       const float* __restrict__ epart, const float* __restrict__ a_sv,
                                                       const float* __restrict__ g_sv, const float* __restrict__ weca,
                                                       const float* __restrict__ stats, const float* __restrict__ gamma,
@@ -319,10 +327,11 @@ __global__ __launch_bounds__(256) void k_s2_bwd_stats(const T* __restrict__ Gd, 
     float g[4], t[4];
     ld4(Gd + off, g);
     ld4(Tm + off, t);
+    const unsigned bits = mask[off >> 2];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float th = (t[j] - mu[j]) * is[j];
-      const float dm = (ga[j] * th + be[j] > 0.f) ? a4v[j] * g[j] + e4[j] : 0.f;
+      const float dm = ((bits >> j) & 1u) ? a4v[j] * g[j] + e4[j] : 0.f;
       acc[0][j] += dm;
       acc[1][j] += dm * th;
     }
@@ -353,6 +362,7 @@ __global__ void k_bn_bwd_finalize(const double* __restrict__ sums, int NS, int C
 // Stage-2 adjoint, apply pass: dT = gamma * invstd * (dM - k0 - that * k1); writes dT and dY.
 template <class T, int C>
 __global__ __launch_bounds__(256) void k_s2_bwd_apply(const T* __restrict__ Gd, const T* __restrict__ Tm,
+                                                      const uint8_t* __restrict__ mask,
                                                       const float* __restrict__ a_sv, const float* __restrict__ coef_e,
                                                       const float* __restrict__ coef, const float* __restrict__ stats,
                                                       const float* __restrict__ gamma, const float* __restrict__ beta,
@@ -379,11 +389,12 @@ __global__ __launch_bounds__(256) void k_s2_bwd_apply(const T* __restrict__ Gd, 
     float g[4], t[4], dy[4], dt[4];
     ld4(Gd + off, g);
     ld4(Tm + off, t);
+    const unsigned bits = mask[off >> 2];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float th = (t[j] - mu[j]) * is[j];
       dy[j] = a4v[j] * g[j] + e4[j];
-      const float dm = (ga[j] * th + be[j] > 0.f) ? dy[j] : 0.f;
+      const float dm = ((bits >> j) & 1u) ? dy[j] : 0.f;
       dt[j] = ga[j] * is[j] * (dm - k0[j] - th * k1[j]);
     }
     st4(dT + off, dt);
@@ -550,15 +561,17 @@ __global__ __launch_bounds__(256) void k_s1_bwd_dx(const T* __restrict__ dP, con
 }
 
 // --------------------------------------------------------------------- input-module adjoint
+// The pre-BN output is recomputed from the planar input (4 channels per thread).
 // Statistics: dM = dS * [S > 0] (S = stored module output); part[blk][2][16]: sum dM, sum dM*that.
 template <class T>
 __global__ __launch_bounds__(256) void k_stem_bwd_stats(const T* __restrict__ dS, const T* __restrict__ S,
-                                                        const T* __restrict__ Tp, const float* __restrict__ stats,
-                                                        float* __restrict__ part, int64_t P) {
+                                                        const float* __restrict__ x, const float* __restrict__ w,
+                                                        const float* __restrict__ stats, float* __restrict__ part,
+                                                        int B, int H, int W) {
   constexpr int C = 16, G = 4;
   __shared__ float sm[2 * 4 * STDA_BLOCK];
   __shared__ float red[2 * C];
-  const int64_t items = P * G;
+  const int64_t items = (int64_t)B * H * W * G;
   int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float mu[4], is[4];
@@ -571,11 +584,13 @@ __global__ __launch_bounds__(256) void k_stem_bwd_stats(const T* __restrict__ dS
   zero4(acc[0]);
   zero4(acc[1]);
   for (; i < items; i += (int64_t)gridDim.x * STDA_BLOCK) {
-    const int64_t off = (i / G) * C + c0;
+    const int64_t p = i / G;
+    int b, y, xx;
+    pix3(p, H, W, b, y, xx);
     float g[4], s[4], t[4];
-    ld4(dS + off, g);
-    ld4(S + off, s);
-    ld4(Tp + off, t);
+    ld4(dS + p * C + c0, g);
+    ld4(S + p * C + c0, s);
+    stem_conv<4>(x, w, b, y, xx, H, W, c0, t);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float dm = s[j] > 0.f ? g[j] : 0.f;
@@ -590,11 +605,12 @@ __global__ __launch_bounds__(256) void k_stem_bwd_stats(const T* __restrict__ dS
 // Apply: dTp = gamma * invstd * (dM - k0 - that * k1).
 template <class T>
 __global__ __launch_bounds__(256) void k_stem_bwd_apply(const T* __restrict__ dS, const T* __restrict__ S,
-                                                        const T* __restrict__ Tp, const float* __restrict__ stats,
-                                                        const float* __restrict__ gamma, const float* __restrict__ coef,
-                                                        T* __restrict__ dTp, int64_t P) {
+                                                        const float* __restrict__ x, const float* __restrict__ w,
+                                                        const float* __restrict__ stats, const float* __restrict__ gamma,
+                                                        const float* __restrict__ coef, T* __restrict__ dTp, int B,
+                                                        int H, int W) {
   constexpr int C = 16, G = 4;
-  const int64_t items = P * G;
+  const int64_t items = (int64_t)B * H * W * G;
   int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float mu[4], is[4], ga[4], k0[4], k1[4];
@@ -607,17 +623,19 @@ __global__ __launch_bounds__(256) void k_stem_bwd_apply(const T* __restrict__ dS
     k1[j] = coef[C + c0 + j];
   }
   for (; i < items; i += (int64_t)gridDim.x * STDA_BLOCK) {
-    const int64_t off = (i / G) * C + c0;
+    const int64_t p = i / G;
+    int b, y, xx;
+    pix3(p, H, W, b, y, xx);
     float g[4], s[4], t[4], o[4];
-    ld4(dS + off, g);
-    ld4(S + off, s);
-    ld4(Tp + off, t);
+    ld4(dS + p * C + c0, g);
+    ld4(S + p * C + c0, s);
+    stem_conv<4>(x, w, b, y, xx, H, W, c0, t);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float dm = s[j] > 0.f ? g[j] : 0.f;
       o[j] = ga[j] * is[j] * (dm - k0[j] - (t[j] - mu[j]) * is[j] * k1[j]);
     }
-    st4(dTp + off, o);
+    st4(dTp + p * C + c0, o);
   }
 }
 

@@ -166,21 +166,45 @@ __global__ void k_eval_stats(const float* __restrict__ running, float* __restric
 }
 
 // --------------------------------------------------------------------- input module
-// Conv3x3 p1, 3 -> 16 on planar FP32 maps.  TRAIN: writes the pre-BN output and per-block
-// (sum, sum of squares) partials [block][16][2].  EVAL: writes ReLU(BN(conv)).
-template <class T, bool TRAIN>
+// Conv3x3 p1, 3 -> 16 on the planar FP32 maps (channel concatenation of frames t, t-1, t-2).
+// Channels c0..c0+NCH-1 of pixel (b, y, x).
+template <int NCH>
+__device__ __forceinline__ void stem_conv(const float* __restrict__ x, const float* __restrict__ w, int b, int y,
+                                          int xx, int H, int W, int c0, float* acc) {
+#pragma unroll
+  for (int o = 0; o < NCH; ++o) acc[o] = 0.f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int ky = 0; ky < 3; ++ky) {
+      const int iy = y + ky - 1;
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int ix = xx + kx - 1;
+        const float v = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(((int64_t)b * 3 + c) * H + iy) * W + ix] : 0.f;
+#pragma unroll
+        for (int o = 0; o < NCH; ++o) acc[o] += w[(c0 + o) * 27 + c * 9 + ky * 3 + kx] * v;
+      }
+    }
+}
+
+// MODE 0 (TRAIN statistics): per-block (sum, sum of squares) of the conv output, part[blk][16][2];
+// nothing is stored.  MODE 1: writes ReLU(BN(conv)) with the given statistics (batch or running).
+// The pre-BN output is never stored: it is recomputed (432 MACs per pixel) where needed.
+template <class T, int MODE>
 __global__ __launch_bounds__(256) void k_stem_fwd(const float* __restrict__ x, const float* __restrict__ w,
                                                   T* __restrict__ out, float* __restrict__ part,
                                                   const float* __restrict__ stats, const float* __restrict__ gamma,
                                                   const float* __restrict__ beta, int B, int H, int W) {
-  __shared__ float sm[32 * STDA_BLOCK];
+  __shared__ float sm[MODE == 0 ? 32 * STDA_BLOCK : 1];
   __shared__ float red[32];
   const int64_t P = (int64_t)B * H * W;
   float acc1[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) acc1[i] = 0.f;
   float sc[16], sh[16];
-  if (!TRAIN) {
+  if (MODE == 1) {
+#pragma unroll
     for (int o = 0; o < 16; ++o) {
       sc[o] = gamma[o] * stats[16 + o];
       sh[o] = beta[o] - stats[o] * sc[o];
@@ -190,23 +214,8 @@ __global__ __launch_bounds__(256) void k_stem_fwd(const float* __restrict__ x, c
     int b, y, xx;
     pix3(p, H, W, b, y, xx);
     float acc[16];
-#pragma unroll
-    for (int o = 0; o < 16; ++o) acc[o] = 0.f;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int iy = y + ky - 1;
-#pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int ix = xx + kx - 1;
-          const float v = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(((int64_t)b * 3 + c) * H + iy) * W + ix] : 0.f;
-#pragma unroll
-          for (int o = 0; o < 16; ++o) acc[o] += w[o * 27 + c * 9 + ky * 3 + kx] * v;
-        }
-      }
-    T* op = out + p * 16;
-    if (TRAIN) {
+    stem_conv<16>(x, w, b, y, xx, H, W, 0, acc);
+    if (MODE == 0) {
 #pragma unroll
       for (int o = 0; o < 16; ++o) {
         acc1[2 * o] += acc[o];
@@ -215,35 +224,14 @@ __global__ __launch_bounds__(256) void k_stem_fwd(const float* __restrict__ x, c
     } else {
 #pragma unroll
       for (int o = 0; o < 16; ++o) acc[o] = fmaxf(acc[o] * sc[o] + sh[o], 0.f);
-    }
+      T* op = out + p * 16;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) st4(op + 4 * q, acc + 4 * q);
+      for (int q = 0; q < 4; ++q) st4(op + 4 * q, acc + 4 * q);
+    }
   }
-  if (TRAIN) {
+  if (MODE == 0) {
     block_vec_reduce<32>(acc1, sm, red);
     if (threadIdx.x < 32) part[(int64_t)blockIdx.x * 32 + threadIdx.x] = red[threadIdx.x];
-  }
-}
-
-// out = ReLU(BN(in)) elementwise for C channels (TRAIN input module activation).
-template <class T, int C>
-__global__ __launch_bounds__(256) void k_bn_relu(const T* __restrict__ in, T* __restrict__ out,
-                                                 const float* __restrict__ stats, const float* __restrict__ gamma,
-                                                 const float* __restrict__ beta, int64_t P) {
-  constexpr int G = C / 4;
-  const int64_t items = P * G;
-  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
-  const int c0 = (int)(i % G) * 4;
-  float sc[4], sh[4];
-  bn_affine4(stats, gamma, beta, C, c0, sc, sh);
-  for (; i < items; i += stride) {
-    const int64_t p = i / G;
-    float v[4];
-    ld4(in + p * C + c0, v);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = fmaxf(v[j] * sc[j] + sh[j], 0.f);
-    st4(out + p * C + c0, v);
   }
 }
 
@@ -454,11 +442,13 @@ __global__ __launch_bounds__(256) void k_dense_simt(const T* __restrict__ src, c
 // --------------------------------------------------------------- stage 2 apply + GAP
 // Y = ReLU(BN(T)) + R; per-(clip, tile) channel sums of Y for the ECA global average pool.
 // Grid (tiles, clips); gap[clip][tile][C].
+// The ReLU decision of every element is taken here, once, in FP32, and (TRAIN) stored as a
+// 4-bit mask per (pixel, channel group) byte for the adjoint.
 template <class T, int C>
 __global__ __launch_bounds__(256) void k_s2_apply(const T* __restrict__ Tm, const T* __restrict__ R, T* __restrict__ Y,
-                                                  float* __restrict__ gap, const float* __restrict__ stats,
-                                                  const float* __restrict__ gamma, const float* __restrict__ beta,
-                                                  int hw) {
+                                                  uint8_t* __restrict__ mask, float* __restrict__ gap,
+                                                  const float* __restrict__ stats, const float* __restrict__ gamma,
+                                                  const float* __restrict__ beta, int hw) {
   constexpr int G = C / 4;
   __shared__ float sm[4 * STDA_BLOCK];
   __shared__ float red[C];
@@ -477,9 +467,15 @@ __global__ __launch_bounds__(256) void k_s2_apply(const T* __restrict__ Tm, cons
     ld4(Tm + off, t);
     ld4(R + off, r);
     float o[4];
+    unsigned bits = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) o[j] = fmaxf(t[j] * sc[j] + sh[j], 0.f) + r[j];
+    for (int j = 0; j < 4; ++j) {
+      const float v = t[j] * sc[j] + sh[j];
+      bits |= (v > 0.f ? 1u : 0u) << j;
+      o[j] = fmaxf(v, 0.f) + r[j];
+    }
     st4(Y + off, o);
+    if (mask) mask[off >> 2] = (uint8_t)bits;
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[0][j] += stored<T>(o[j]);  // the value as stored
   }

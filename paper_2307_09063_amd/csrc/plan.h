@@ -53,13 +53,13 @@ const NetOffsets& net_offsets();
 
 // Byte offsets of one segment's activations (in `saved` for TRAIN, in `ws` for EVAL).
 struct BlockActs {
-  size_t X1, T, Y, Xn, a, g;
+  size_t X1, T, Y, Xn, a, g, mask;  // mask: stage-2 ReLU decisions, 4 bits per byte
 };
 struct SegPlan {
   int n, H, W;
   int64_t x_off, z_off;
   size_t stats;  // [mean C][invstd C] per BN layer, running-buffer layout
-  size_t S0p, s0;
+  size_t s0;
   BlockActs blk[4];
 };
 
@@ -69,7 +69,7 @@ struct Plan {
   // ws regions (byte offsets)
   size_t ws_wk, ws_dense, ws_R, ws_part, ws_sums, ws_gap, ws_eval_stats, ws_loss;
   size_t ws_g[kNumGradBufs];
-  size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart;
+  size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart, ws_frag;
   int64_t dense_f[4][2], dense_d[4][2];  // element offsets inside ws_dense (main, residual)
   size_t saved_bytes, ws_bytes;
 };

@@ -49,6 +49,32 @@ def rd_maps(B, N, M, seed, **kw):
     return x.astype(np.float32), clean.astype(np.float32), tab, meta
 
 
+def relu_margin(cache):
+    """Smallest |pre-activation| / rms(pre-activation of its layer) over every ReLU of the
+    network.  Where this is below the FP32 rounding of the pre-activation, FP32 and FP64 may take
+    different ReLU decisions, and either decision is a correct gradient at that precision."""
+    P, C = cache['P'], cache['caches']
+
+    def pre(name):
+        c = C[name]
+        return P[name + '.gamma'][None, :, None, None] * c['xhat'] + P[name + '.beta'][None, :, None, None]
+
+    sites = [pre('stem.bn')] + [pre(f'{k}.s2.main_bn') for k in ('enc0', 'enc1', 'dec0', 'dec1')]
+    sites += [pre(f'{k}.s1.pw_bn') + pre(f'{k}.s1.dw_bn') + pre(f'{k}.s1.id_bn') for k in ('enc0', 'enc1', 'dec0', 'dec1')]
+    return min(float(np.abs(u).min() / np.sqrt((u * u).mean())) for u in sites)
+
+
+def unambiguous(make, w, r, seed, margin=1e-5, tries=100):
+    """First seed >= `seed` whose input (from make(seed)) keeps every ReLU decision at least
+    `margin` (relative) away from its kink in TRAIN mode."""
+    for k in range(tries):
+        inp = make(seed + 1000 * k)
+        _, _, cache = net.forward(w, r, inp[0], 'train')
+        if relu_margin(cache) >= margin:
+            return inp
+    raise RuntimeError('no input with unambiguous ReLU decisions found')
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 

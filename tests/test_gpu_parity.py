@@ -1,6 +1,10 @@
 """GPU-vs-oracle parity of the FP32 path, through the C ABI: forward (EVAL and TRAIN), running
 statistics, loss, backward (every parameter gradient and dx), SGD, the autograd wrapper,
-uneven segments, edge shapes, determinism.  Gate: rel-L2 <= 1e-4 per tensor (FP32)."""
+uneven segments, edge shapes, determinism.  Gate: rel-L2 <= 1e-4 per tensor (FP32).
+
+Inputs are screened so that no ReLU pre-activation lies within a relative 1e-5 of its kink:
+there FP32 and FP64 may legitimately take different decisions, and one flipped decision moves a
+batch-norm shift gradient (a sum of n terms of random sign) by about 1/sqrt(n)."""
 import sys
 
 import numpy as np
@@ -67,8 +71,8 @@ def test_forward_train_and_running(S, shape):
 def test_backward(S, shape):
     B, H, W = shape
     _say('backward', shape)
-    x, y = U.maps(B, H, W, seed=H * 3 + W)
     w, r = U.weights(), U.running()
+    x, y = U.unambiguous(lambda s: U.maps(B, H, W, seed=s), w, r, H * 3 + W)
     z, _, (segs, xd, wd, saved, ws) = _run_forward(S, x, w, r, S.TRAIN)
     # loss and dz on the GPU
     zd = U.dev(z)
@@ -114,8 +118,8 @@ def test_sgd(S):
 def test_autograd_function(S):
     _say('autograd')
     B, H, W = 2, 16, 16
-    x, y = U.maps(B, H, W, seed=11)
     w, r = U.weights(), U.running()
+    x, y = U.unambiguous(lambda s: U.maps(B, H, W, seed=s), w, r, 11)
     xd = U.dev(x).requires_grad_(True)
     wd = U.dev(w).requires_grad_(True)
     rd = U.dev(r.copy())
