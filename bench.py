@@ -24,6 +24,76 @@ WORKLOADS = {
 DEFAULT = 'train_fp32_b64_256x128'
 
 
+# ---------------------------------------------------------------- algorithmic work per kernel
+BLOCKS = {'enc0': (16, 32, False, 0, 1), 'enc1': (32, 64, False, 1, 2),
+          'dec0': (64, 32, True, 2, 1), 'dec1': (32, 16, True, 1, 0)}
+PEAK = {'hbm': 8000.0, 'mfma_f32': 157.3, 'mfma_bf16': 2500.0, 'alu_f32': 157.3}
+
+
+def kernel_work(tag, B, H, W, es):
+    """(FLOPs, HBM bytes, engine) of one launch of the tagged kernel, counting each input read
+    once and each output written once, and every kernel tap as a multiply-add."""
+    kind, _, blk = tag.partition('.')
+    hw0 = H * W
+    if blk in BLOCKS:
+        cin, cout, dec, lin, lout = BLOCKS[blk]
+        hin, hout = hw0 // 4 ** lin, hw0 // 4 ** lout
+        s1_flops = 2.0 * B * hin * (cin * cin + 9 * cin)
+        dense_macs = B * hout * (4 if dec else 9) * cin * cout
+        skip = 1 if blk in ('dec0', 'dec1') else 0
+        table = {
+            'dense_fwd_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'dense_fwd_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'dense_dgrad_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'dense_dgrad_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'wgrad_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'wgrad_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
+            'wgrad_pw': (2.0 * B * hin * cin * cin, 2.0 * B * cin * hin * es, 'mfma'),
+            'wgrad_dw': (2.0 * B * hin * 9 * cin, 2.0 * B * cin * hin * es, 'alu'),
+            's1_stats': (s1_flops, B * cin * hin * es, 'alu'),
+            's1_apply': (s1_flops, 2.0 * B * cin * hin * es, 'alu'),
+            's2_apply': (4.0 * B * hout * cout, B * hout * cout * (3 * es + 0.25), 'alu'),
+            'eca_next': (2.0 * B * hout * cout, B * hout * cout * es * (2 + skip), 'alu'),
+            'eca_bwd': (2.0 * B * hout * cout, 2.0 * B * hout * cout * es, 'alu'),
+            's2_bwd_stats': (8.0 * B * hout * cout, B * hout * cout * (2 * es + 0.25), 'alu'),
+            's2_bwd_apply': (10.0 * B * hout * cout, B * hout * cout * (4 * es + 0.25), 'alu'),
+            's1_bwd_stats': (s1_flops, 3.0 * B * cin * hin * es, 'alu'),
+            's1_bwd_apply': (s1_flops, 7.0 * B * cin * hin * es, 'alu'),
+            's1_bwd_dx': (s1_flops, (4 + skip) * B * cin * hin * es, 'alu'),
+        }
+        return table.get(kind)
+    table = {
+        'stem_stats': (864.0 * B * hw0, 12.0 * B * hw0, 'alu'),
+        'stem_apply': (864.0 * B * hw0, B * hw0 * (12 + 16 * es), 'alu'),
+        'head_fwd': (288.0 * B * hw0, B * hw0 * (16 * es + 4), 'alu'),
+        'head_bwd': (576.0 * B * hw0, B * hw0 * (4 + 32 * es), 'alu'),
+        'stem_bwd_stats': (864.0 * B * hw0, B * hw0 * (32 * es + 12), 'alu'),
+        'stem_bwd_apply': (1728.0 * B * hw0, B * hw0 * (32 * es + 12), 'alu'),
+    }
+    return table.get(kind)
+
+
+def roofline(tag, avg_ms, B, H, W, dtype_bf16):
+    es = 2 if dtype_bf16 else 4
+    w = kernel_work(tag, B, H, W, es)
+    if w is None or avg_ms <= 0:
+        return None
+    flops, nbytes, engine = w
+    peak_c = PEAK['mfma_bf16' if dtype_bf16 else 'mfma_f32'] if engine == 'mfma' else PEAK['alu_f32']
+    t_c = flops / (peak_c * 1e12)
+    t_b = nbytes / (PEAK['hbm'] * 1e9)
+    sec = avg_ms / 1e3
+    if t_c >= t_b:
+        achieved = flops / sec / 1e12
+        return {'bound': engine, 'achieved': round(achieved, 2), 'peak': peak_c, 'unit': 'TFLOP/s',
+                'frac': round(achieved / peak_c, 4), 'traffic': None, 'kernel': tag,
+                'avg_us': round(avg_ms * 1e3, 2), 'algorithmic_flops': flops, 'algorithmic_bytes': nbytes}
+    achieved = nbytes / sec / 1e9
+    return {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': PEAK['hbm'], 'unit': 'GB/s',
+            'frac': round(achieved / PEAK['hbm'], 4), 'traffic': None, 'kernel': tag,
+            'avg_us': round(avg_ms * 1e3, 2), 'algorithmic_flops': flops, 'algorithmic_bytes': nbytes}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -32,6 +102,8 @@ def parse():
     ap.add_argument('--workload', default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-clips', type=int, default=4)
+    ap.add_argument('--train-only', action='store_true', help='skip the EVAL-forward and rd_synth timings')
+    ap.add_argument('--kernel', default=None, help='tag of the kernel for the roofline (default: the dominant one)')
     return ap.parse_args()
 
 
@@ -91,6 +163,19 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # dominant kernel: one step with every tagged launch timed
+    stda.profile_select('*')
+    step()
+    torch.cuda.synchronize()
+    per_tag = stda.profile_report()
+    dominant = args.kernel or max(per_tag, key=lambda t: per_tag[t][1])
+    tot_tagged = sum(v[1] for v in per_tag.values())
+    for t, (n, tms) in sorted(per_tag.items(), key=lambda kv: -kv[1][1])[:40]:
+        print(f'bench:   {t:28s} {n:3d} launches {tms:8.3f} ms ({100 * tms / tot_tagged:4.1f}%)', file=sys.stderr)
+    print(f'bench: dominant kernel {dominant} ({per_tag.get(dominant, (0, 0))[1]:.3f} ms of one step)',
+          file=sys.stderr, flush=True)
+    # timed region; the dominant kernel's launches are bracketed by HIP events on their stream
+    stda.profile_select(dominant)
     print(f'bench: warmup done, timing {args.steps} steps', file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     e0.record()
@@ -99,27 +184,19 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    k_total, k_count = stda.profile_read()
+    stda.profile_select(None)
     ms = e0.elapsed_time(e1) / args.steps
     clips_s = B / (ms / 1e3)
+    roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16)
     print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), wall {wall:.2f}s, loss {loss.item():.5f}',
           file=sys.stderr, flush=True)
 
-    # ---- forward-only EVAL at the forward configuration (B = 32), same kernels
-    fw = inputs.WORKLOADS['cfg2_fwd_256x128']
-    Bf = fw['B']
-    segs_f = stda.uniform_segments(Bf, N, M)
-    _, ws_f = stda.workspace_size(segs_f, stda.FP32, stda.EVAL)
-    wsf = stda.alloc_bytes(ws_f, dev)
-    xf, zf = x[:Bf].contiguous(), torch.empty((Bf, 1, N, M), device=dev)
-    for _ in range(3):
-        stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(10):
-        stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
-    e1.record()
-    torch.cuda.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / 10
+    fwd_ms = None
+    if args.train_only:
+        Bf = 0
+    else:
+        fwd_ms, Bf = eval_forward(stda, inputs, torch, x, w, running, N, M, dev, e0, e1)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -141,13 +218,33 @@ def main():
         'data': 'synthetic (seeded FMCW scenes -> rd_synth on the GPU)',
         'config': {'workload': args.workload, 'clips': B, 'frames': 3, 'range_bins': N, 'doppler_bins': M,
                    'step': 'TRAIN forward + MSE + backward + SGD', 'recompute': recompute},
-        'fwd_eval_fp32_b32': {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)},
-        'rd_synth': {'ms': round(rd_ms, 4), 'clips_per_s': round(B / (rd_ms / 1e3), 1),
-                     'maps_per_clip': 4},
-        'roofline': None,
+        'fwd_eval_fp32_b32': None if fwd_ms is None else {'ms': round(fwd_ms, 4),
+                                                           'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)},
+        'rd_synth': {'ms': round(rd_ms, 4), 'clips_per_s': round(B / (rd_ms / 1e3), 1), 'maps_per_clip': 4},
+        'roofline': roof,
         'cpu_baseline': cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def eval_forward(stda, inputs, torch, x, w, running, N, M, dev, e0, e1):
+    """Forward-only EVAL at the forward configuration (B = 32) on the same maps."""
+    fw = inputs.WORKLOADS['cfg2_fwd_256x128']
+    Bf = fw['B']
+    segs_f = stda.uniform_segments(Bf, N, M)
+    _, ws_f = stda.workspace_size(segs_f, stda.FP32, stda.EVAL)
+    wsf = stda.alloc_bytes(ws_f, dev)
+    xf, zf = x[:Bf].contiguous(), torch.empty((Bf, 1, N, M), device=dev)
+    for _ in range(3):
+        stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    return fwd_ms, Bf
 
 
 def cpu_baseline(nclips, N, M, x, y, w, r):

@@ -137,6 +137,24 @@ int stda_sgd_step(float* w, const float* dw, int64_t n, float lr, float weight_d
 int stda_sinr(const float* maps, const uint8_t* o_mask, const uint8_t* n_mask, int n_maps, int H,
               int W, double* out_dev, hipStream_t stream);
 
+/* ------------------------------------------------------------------ measurement hooks */
+/*
+ * Per-kernel timing.  After stda_profile_select(tag) every launch carrying that tag (for example
+ * "dense_fwd_main.dec1", "wgrad_main.dec0", "s1_bwd_apply.enc0", "stem_bwd_apply") is bracketed
+ * by two HIP events recorded on its launch stream; NULL or "" turns the hook off.  Selecting
+ * resets the record.  stda_profile_read waits for the recorded events and returns the summed
+ * kernel time in milliseconds and the number of bracketed launches.  Tags are listed next to
+ * the launches in the library source; an unknown tag simply records nothing.
+ */
+int stda_profile_select(const char* tag);
+int stda_profile_read(double* total_ms /*host out*/, int* count /*host out*/);
+/*
+ * With the tag "*" every tagged launch is recorded.  stda_profile_report writes one line per
+ * tag, "tag<TAB>launches<TAB>total_ms", into host buf (NUL-terminated, truncated to cap) and the
+ * size it needs into *needed.
+ */
+int stda_profile_report(char* buf /*host out*/, size_t cap, size_t* needed /*host out*/);
+
 /* ------------------------------------------------------------------ RD-map synthesizer */
 #define RD_MAX_TONES 48
 #define RD_MAX_INTF 4

@@ -35,6 +35,56 @@ thread_local int g_last_hip = 0;
   } while (0)
 #define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
 
+// ------------------------------------------------------------------ per-kernel timing hook
+// When a tag is selected, every launch carrying that tag is bracketed by two HIP events
+// recorded on the launch stream; stda_profile_read sums their elapsed times.
+struct Prof {
+  std::mutex mu;
+  std::string tag;  // "*" records every tagged launch
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<std::string> evtag;  // tag of each recorded pair
+  size_t used = 0;
+};
+Prof& prof() {
+  static Prof p;
+  return p;
+}
+struct ProfScope {
+  hipStream_t st;
+  long idx = -1;
+  ProfScope(const std::string& tag, hipStream_t s) : st(s) {
+    Prof& p = prof();
+    if (!p.on) return;
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (p.tag != "*" && tag != p.tag) return;
+    if (p.used + 2 > p.ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        p.ev.push_back(e);
+      }
+    }
+    idx = (long)p.used;
+    p.used += 2;
+    if (p.evtag.size() < p.used / 2) p.evtag.resize(p.used / 2);
+    p.evtag[idx / 2] = tag;
+    hipEventRecord(p.ev[idx], st);
+  }
+  ~ProfScope() {
+    if (idx >= 0) hipEventRecord(prof().ev[idx + 1], st);
+  }
+};
+const char* const kBlockName[4] = {"enc0", "enc1", "dec0", "dec1"};
+std::string tagk(const char* kind, int k) { return std::string(kind) + "." + kBlockName[k]; }
+
+#define KLAUNCH(tag, ...)               \
+  do {                                  \
+    ProfScope ps_((tag), c.st);         \
+    __VA_ARGS__;                        \
+  } while (0);                          \
+  LAUNCH_CHECK()
+
 int grid_for(int64_t items, int cap = 2048) {
   int64_t g = (items + STDA_BLOCK - 1) / STDA_BLOCK;
   if (g < 1) g = 1;
@@ -324,8 +374,8 @@ int tiles_for(int64_t hw, int G) {
 
 // Dense stride-2 layer on the matrix cores; returns the number of blocks (partials rows).
 template <class T, int OP, int K, int N, bool STATS>
-int launch_dense(const Ctx<T>& c, const T* src, int64_t frag_off, T* dst, float* part, int n, int hd, int wd,
-                 int* nblk) {
+int launch_dense(const Ctx<T>& c, const std::string& tag, const T* src, int64_t frag_off, T* dst, float* part, int n,
+                 int hd, int wd, int* nblk) {
   constexpr int R = 4;
   constexpr bool down = OpGeo<OP>::DOWN;
   const int64_t P = (int64_t)n * (down ? (int64_t)hd * wd : (int64_t)(hd / 2) * (wd / 2));
@@ -333,8 +383,7 @@ int launch_dense(const Ctx<T>& c, const T* src, int64_t frag_off, T* dst, float*
   const int64_t tiles = (P + 64 * R - 1) / (64 * R);
   const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid / phases));
   const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
-  k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd);
-  LAUNCH_CHECK();
+  KLAUNCH(tag, k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd));
   if (nblk) *nblk = gx * phases;
   return STDA_OK;
 }
@@ -347,15 +396,13 @@ int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* c
   float* part = c.template scr<float>(c.P->ws_part);
   double* sums = c.template scr<double>(c.P->ws_sums);
   const int ncols = NB * C * 2;
-  k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nblk, ncols, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0);
-  LAUNCH_CHECK();
+  KLAUNCH("colsum", k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nblk, ncols, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0));
   BnOut o{};
   for (int i = 0; i < NB; ++i) {
     o.stats[i] = stats_out[i];
     o.running[i] = running ? running[i] : nullptr;
   }
-  k_bn_stats_finalize<<<1, 256, 0, c.st>>>(sums, NB, C, count, o, running ? 1 : 0);
-  LAUNCH_CHECK();
+  KLAUNCH("bn_finalize", k_bn_stats_finalize<<<1, 256, 0, c.st>>>(sums, NB, C, count, o, running ? 1 : 0));
   return STDA_OK;
 }
 
@@ -389,14 +436,12 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   // stage 1
   const int g1 = grid_for(Pin * (CIN / 4));
   if (c.train) {
-    k_stage1<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win);
-    LAUNCH_CHECK();
+    KLAUNCH(tagk("s1_stats", k), k_stage1<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
     if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro, running)) return r;
   }
-  k_stage1<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win);
-  LAUNCH_CHECK();
+  KLAUNCH(tagk("s1_apply", k), k_stage1<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win));
   // stage 2: main (with statistics) and residual
   const float* dl = c.dl;
   const int g2 = grid_for(Pout * (COUT / 4));
@@ -405,36 +450,38 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   (void)g2;
   if (c.train) {
     int nb = 0;
-    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
+    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
       return r;
     float* so[1] = {c.stats(bo.bn_main)};
     float* ro[1] = {running + bo.bn_main};
     if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro, running)) return r;
   } else {
-    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
                                                        nullptr))
       return r;
   }
-  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
     return r;
   // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
   const int hw = hout * wout;
   const int tiles = tiles_for(hw, COUT / 4);
   float* gap = c.template scr<float>(c.P->ws_gap);
   uint8_t* mask = c.train ? c.template act<uint8_t>(A.mask) : nullptr;
-  k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, mask, gap, c.stats(bo.bn_main), c.w + bo.main_g,
-                                                        c.w + bo.main_b, hw);
-  LAUNCH_CHECK();
+  KLAUNCH(tagk("s2_apply", k), k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, mask, gap, c.stats(bo.bn_main), c.w + bo.main_g,
+                                                        c.w + bo.main_b, hw));
   T* Xn = c.template act<T>(A.Xn);
   const T* skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
-  if (skip)
-    k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, c.st>>>(Y, skip, Xn, gap, c.w + bo.eca_w,
-                                                                c.template act<float>(A.g), c.template act<float>(A.a),
-                                                                hw, tiles);
-  else
-    k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, c.st>>>(Y, nullptr, Xn, gap, c.w + bo.eca_w,
-                                                                 c.template act<float>(A.g),
-                                                                 c.template act<float>(A.a), hw, tiles);
+{
+    ProfScope ps_(tagk("eca_next", k), c.st);
+    if (skip)
+      k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, c.st>>>(Y, skip, Xn, gap, c.w + bo.eca_w,
+                                                                  c.template act<float>(A.g), c.template act<float>(A.a),
+                                                                  hw, tiles);
+    else
+      k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, c.st>>>(Y, nullptr, Xn, gap, c.w + bo.eca_w,
+                                                                   c.template act<float>(A.g),
+                                                                   c.template act<float>(A.a), hw, tiles);
+  }
   LAUNCH_CHECK();
   return STDA_OK;
 }
@@ -449,23 +496,20 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   T* s0 = c.template act<T>(S.s0);
   const int gs = grid_for(P);
   if (c.train) {
-    k_stem_fwd<T, 0><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, nullptr, part, nullptr, nullptr, nullptr, S.n, S.H,
-                                           S.W);
-    LAUNCH_CHECK();
+    KLAUNCH("stem_stats", k_stem_fwd<T, 0><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, nullptr, part, nullptr, nullptr, nullptr, S.n, S.H,
+                                           S.W));
     float* so[1] = {c.stats(0)};
     float* ro[1] = {running};
     if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro, running)) return r;
   }
-  k_stem_fwd<T, 1><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
-                                         c.w + no.stem_b, S.n, S.H, S.W);
-  LAUNCH_CHECK();
+  KLAUNCH("stem_apply", k_stem_fwd<T, 1><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
+                                         c.w + no.stem_b, S.n, S.H, S.W));
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
   if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
   if (int r = fwd_block<T, 32, 16, true>(c, 3, running)) return r;
-  k_head_fwd<T><<<grid_for(P), 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w, c.w + no.head_b,
-                                               z + S.z_off, S.n, S.H, S.W);
-  LAUNCH_CHECK();
+  KLAUNCH("head_fwd", k_head_fwd<T><<<grid_for(P), 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w, c.w + no.head_b,
+                                               z + S.z_off, S.n, S.H, S.W));
   return STDA_OK;
 }
 
@@ -571,8 +615,7 @@ namespace {
 
 template <class T>
 int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc) {
-  k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc);
-  LAUNCH_CHECK();
+  KLAUNCH("colsum", k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
   return STDA_OK;
 }
 
@@ -585,17 +628,22 @@ constexpr int pch_for() {
 
 // Weight gradient on the matrix cores; the pixel range is split so that about 1024 blocks run,
 // and the per-split partials are summed in FP64 into the destination.
+template <int D>
+constexpr int wg_tiles() {
+  return D >= 64 ? 4 : D >= 32 ? 2 : 1;
+}
+
 template <class T, class L>
-int run_wgrad(const Ctx<T>& c, const L& ld, int64_t npix, float* dst, ColMap map, int acc) {
-  constexpr int KB = (L::K + 63) / 64, NB = (L::N + 63) / 64;
+int run_wgrad(const Ctx<T>& c, const std::string& tag, const L& ld, int64_t npix, float* dst, ColMap map, int acc) {
+  constexpr int TK = wg_tiles<L::K>(), TN = wg_tiles<L::N>();
+  constexpr int KB = (L::K + 16 * TK - 1) / (16 * TK), NB = (L::N + 16 * TN - 1) / (16 * TN);
   constexpr bool BF = L::kBF16Operands;
   float* wpart = c.template scr<float>(c.P->ws_wpart);
   const int64_t steps = (npix + (BF ? 15 : 3)) / (BF ? 16 : 4);
   int64_t splits = std::max<int64_t>(1, 1024 / (KB * NB));
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, steps / 64));  // >= 16 steps per wave
   splits = std::min<int64_t>(splits, kMaxWgradGrid);
-  k_wgrad_mfma<L, BF><<<dim3(KB * NB, (int)splits), 256, 0, c.st>>>(ld, wpart);
-  LAUNCH_CHECK();
+  KLAUNCH(tag, k_wgrad_mfma<L, BF, TK, TN><<<dim3(KB * NB, (int)splits), 256, 0, c.st>>>(ld, wpart));
   return colsum_to(c, wpart, (int)splits, L::K * L::N, dst, map, acc);
 }
 
@@ -603,15 +651,13 @@ template <class T>
 int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg, float* const* db, int acc) {
   float* part = c.template scr<float>(c.P->ws_part);
   double* sums = c.template scr<double>(c.P->ws_sums);
-  k_colsum<<<(NS * C + 15) / 16, 256, 0, c.st>>>(part, nblk, NS * C, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0);
-  LAUNCH_CHECK();
+  KLAUNCH("colsum", k_colsum<<<(NS * C + 15) / 16, 256, 0, c.st>>>(part, nblk, NS * C, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0));
   BnBwdOut o{};
   for (int k = 0; k < NS - 1; ++k) {
     o.dgamma[k] = dg[k];
     o.dbeta[k] = db[k];
   }
-  k_bn_bwd_finalize<<<1, 64, 0, c.st>>>(sums, NS, C, n, o, c.template scr<float>(c.P->ws_coef), acc);
-  LAUNCH_CHECK();
+  KLAUNCH("bn_bwd_finalize", k_bn_bwd_finalize<<<1, 64, 0, c.st>>>(sums, NS, C, n, o, c.template scr<float>(c.P->ws_coef), acc));
   return STDA_OK;
 }
 
@@ -639,42 +685,39 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   const int tiles = tiles_for(hw, COUT / 4);
   float* epart = c.template scr<float>(c.P->ws_gap);
   // ECA adjoint partials and stage-2 BN statistics
-  k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw);
-  LAUNCH_CHECK();
+  KLAUNCH(tagk("eca_bwd", k), k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw));
   const uint8_t* mask = c.template act<uint8_t>(A.mask);
-  k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
+  KLAUNCH(tagk("s2_bwd_stats", k), k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
       Gd, Tm, mask, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
-      c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles);
-  LAUNCH_CHECK();
+      c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles));
   if (int r = colsum_to(c, ecaw, n, 3, dw + bo.eca_w, ColMap{MAP_IDENT, 0, 0}, acc)) return r;
   {
     float* dg[1] = {dw + bo.main_g};
     float* db[1] = {dw + bo.main_b};
     if (int r = bn_bwd(c, tiles * n, 2, COUT, (double)Pout, dg, db, acc)) return r;
   }
-  k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, mask, c.template act<float>(A.a), coef_e,
+  KLAUNCH(tagk("s2_bwd_apply", k), k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, mask, c.template act<float>(A.a), coef_e,
                                                             c.template scr<float>(c.P->ws_coef), c.stats(bo.bn_main),
-                                                            c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw);
-  LAUNCH_CHECK();
+                                                            c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw));
   // dense adjoints: dX1 from dT, dXr from dY
   constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
   const int gd = grid_for(Pin * (CIN / 4));
   (void)gd;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
     return r;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
     return r;
   // dense weight gradients
   if (DEC) {
     WgDecS2<T, CIN, COUT> lm{X1, dT, n, hin, win};
-    if (int r = run_wgrad(c, lm, Pin, dw + bo.main_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
+    if (int r = run_wgrad(c, tagk("wgrad_main", k), lm, Pin, dw + bo.main_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
     WgDecS2<T, CIN, COUT> lr{X, dY, n, hin, win};
-    if (int r = run_wgrad(c, lr, Pin, dw + bo.res_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
+    if (int r = run_wgrad(c, tagk("wgrad_res", k), lr, Pin, dw + bo.res_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
   } else {
     WgEncS2<T, CIN, COUT> lm{X1, dT, n, hout, wout};
-    if (int r = run_wgrad(c, lm, Pout, dw + bo.main_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
+    if (int r = run_wgrad(c, tagk("wgrad_main", k), lm, Pout, dw + bo.main_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
     WgEncS2<T, CIN, COUT> lr{X, dY, n, hout, wout};
-    if (int r = run_wgrad(c, lr, Pout, dw + bo.res_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
+    if (int r = run_wgrad(c, tagk("wgrad_res", k), lr, Pout, dw + bo.res_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
   }
   // stage 1
   S1Params sp{};
@@ -690,25 +733,25 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   sp.beta[1] = c.w + bo.dw_b;
   sp.beta[2] = c.w + bo.id_b;
   const int g1 = grid_for(Pin * (CIN / 4));
-  k_s1_bwd_stats<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win);
-  LAUNCH_CHECK();
+  KLAUNCH(tagk("s1_bwd_stats", k), k_s1_bwd_stats<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win));
   {
     float* dg[3] = {dw + bo.pw_g, dw + bo.dw_g, dw + bo.id_g};
     float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
     if (int r = bn_bwd(c, g1, 4, CIN, (double)Pin, dg, db, acc)) return r;
   }
-  k_s1_bwd_apply<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, c.template scr<float>(c.P->ws_coef), sp, dP, dD,
-                                                    dX0, n, hin, win);
-  LAUNCH_CHECK();
-  if (skipg)
-    k_s1_bwd_dx<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(dP, dD, dX0, skipg, sp, dXout, n, hin, win);
-  else
-    k_s1_bwd_dx<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(dP, dD, dX0, nullptr, sp, dXout, n, hin, win);
+  KLAUNCH(tagk("s1_bwd_apply", k), k_s1_bwd_apply<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, c.template scr<float>(c.P->ws_coef), sp, dP, dD,
+                                                    dX0, n, hin, win));
+{
+    ProfScope ps_(tagk("s1_bwd_dx", k), c.st);
+    if (skipg)
+      k_s1_bwd_dx<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(dP, dD, dX0, skipg, sp, dXout, n, hin, win);
+    else
+      k_s1_bwd_dx<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(dP, dD, dX0, nullptr, sp, dXout, n, hin, win);
+  }
   LAUNCH_CHECK();
   WgPw<T, CIN> lp{X, dP, Pin};
-  if (int r = run_wgrad(c, lp, Pin, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc)) return r;
-  k_dw_wgrad<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, dD, part, n, hin, win);
-  LAUNCH_CHECK();
+  if (int r = run_wgrad(c, tagk("wgrad_pw", k), lp, Pin, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc)) return r;
+  KLAUNCH(tagk("wgrad_dw", k), k_dw_wgrad<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, dD, part, n, hin, win));
   return colsum_to(c, part, g1, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc);
 }
 
@@ -720,11 +763,12 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
   const float* dzs = dz + S.z_off;
   // output module
-  k_head_dgrad<T><<<grid_for(P), 256, 0, c.st>>>(dzs, c.w + no.head_w, gb(0), S.n, S.H, S.W);
-  LAUNCH_CHECK();
   {
-    WgHead<T> lh{c.template act<T>(S.blk[3].Xn), dzs, S.n, S.H, S.W};
-    if (int r = run_wgrad(c, lh, P, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
+    float* part = c.template scr<float>(c.P->ws_part);
+    const int gh = grid_for(P * 4);
+    KLAUNCH("head_bwd", k_head_bwd<T><<<gh, 256, 0, c.st>>>(dzs, c.w + no.head_w, c.template act<T>(S.blk[3].Xn), gb(0), part, S.n, S.H,
+                                        S.W));
+    if (int r = colsum_to(c, part, gh, 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
   if (int r = bwd_block<T, 32, 16, true>(c, 3, gb(0), gb(1), nullptr, dw, acc)) return r;
@@ -735,25 +779,19 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   // input module
   float* part = c.template scr<float>(c.P->ws_part);
   const int g = grid_for(P * 4);
-  k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
-                                           part, S.n, S.H, S.W);
-  LAUNCH_CHECK();
+  KLAUNCH("stem_bwd_stats", k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
+                                           part, S.n, S.H, S.W));
   {
     float* dg[1] = {dw + no.stem_g};
     float* db[1] = {dw + no.stem_b};
     if (int r = bn_bwd(c, g, 2, 16, (double)P, dg, db, acc)) return r;
   }
-  k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
-                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef), gb(12), S.n, S.H,
-                                           S.W);
-  LAUNCH_CHECK();
-  {
-    WgStem<T> ls{x + S.x_off, gb(12), S.n, S.H, S.W};
-    if (int r = run_wgrad(c, ls, P, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, acc)) return r;
-  }
+  KLAUNCH("stem_bwd_apply", k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
+                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef),
+                                           dx ? gb(12) : nullptr, part, S.n, S.H, S.W));
+  if (int r = colsum_to(c, part, g, 27 * 16, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, acc)) return r;
   if (dx) {
-    k_stem_dx<T><<<grid_for(P), 256, 0, c.st>>>(gb(12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W);
-    LAUNCH_CHECK();
+    KLAUNCH("stem_dx", k_stem_dx<T><<<grid_for(P), 256, 0, c.st>>>(gb(12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W));
   }
   return STDA_OK;
 }
@@ -807,6 +845,67 @@ int stda_param_table(stda_param_desc* out, int cap) {
     }
   }
   return (int)t.size();
+}
+
+int stda_profile_select(const char* tag) {
+  Prof& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  p.tag = tag ? tag : "";
+  p.on = !p.tag.empty();
+  p.used = 0;
+  return STDA_OK;
+}
+
+int stda_profile_read(double* total_ms, int* count) {
+  if (!total_ms || !count) return STDA_E_INVALID;
+  Prof& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < p.used; i += 2) {
+    HIP_TRY(hipEventSynchronize(p.ev[i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = (int)(p.used / 2);
+  return STDA_OK;
+}
+
+int stda_profile_report(char* buf, size_t cap, size_t* needed) {
+  Prof& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  std::vector<std::string> order;
+  std::vector<double> tot;
+  std::vector<int> cnt;
+  for (size_t i = 0; i + 1 < p.used; i += 2) {
+    HIP_TRY(hipEventSynchronize(p.ev[i + 1]));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+    const std::string& t = p.evtag[i / 2];
+    size_t k = 0;
+    while (k < order.size() && order[k] != t) ++k;
+    if (k == order.size()) {
+      order.push_back(t);
+      tot.push_back(0.0);
+      cnt.push_back(0);
+    }
+    tot[k] += ms;
+    cnt[k] += 1;
+  }
+  std::string out;
+  char line[160];
+  for (size_t k = 0; k < order.size(); ++k) {
+    std::snprintf(line, sizeof(line), "%s\t%d\t%.6f\n", order[k].c_str(), cnt[k], tot[k]);
+    out += line;
+  }
+  if (needed) *needed = out.size() + 1;
+  if (buf && cap > 0) {
+    const size_t n = std::min(cap - 1, out.size());
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  return STDA_OK;
 }
 
 int stda_bn_layer_count(void) { return 17; }

@@ -7,28 +7,51 @@
 namespace stda {
 
 // --------------------------------------------------------------------- output module adjoint
-// dd[c](y, x) = sum_{ky,kx} dz(y - ky + 1, x - kx + 1) w[c][ky][kx]   (16 channels, NHWC)
+// dd[c](y, x) = sum_{ky,kx} dz(y - ky + 1, x - kx + 1) w[c][ky][kx]   (16 channels, NHWC), and
+// the output-module weight gradient from the same dz neighbourhood:
+// dW[c][ky][kx] = sum_p dz(p) d[c](p + (ky - 1, kx - 1)) = sum_q d[c](q) dz(q - (ky - 1, kx - 1)).
+// part[blk][10][16]: rows 0..8 the taps, row 9 channel 0 the bias gradient (sum of dz).
 template <class T>
-__global__ __launch_bounds__(256) void k_head_dgrad(const float* __restrict__ dz, const float* __restrict__ w,
-                                                    T* __restrict__ dd, int B, int H, int W) {
-  const int64_t P = (int64_t)B * H * W;
-  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
+__global__ __launch_bounds__(256) void k_head_bwd(const float* __restrict__ dz, const float* __restrict__ w,
+                                                  const T* __restrict__ d, T* __restrict__ dd,
+                                                  float* __restrict__ part, int B, int H, int W) {
+  constexpr int C = 16, G = 4;
+  __shared__ float sm[4 * 10 * C];
+  __shared__ float red[10 * C];
+  const int64_t items = (int64_t)B * H * W * G;
+  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  const int c0 = (int)(i % G) * 4;
+  float wt[9][4];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wt[t][j] = w[(c0 + j) * 9 + t];
+  float acc[10][4];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) zero4(acc[t]);
+  for (; i < items; i += (int64_t)gridDim.x * STDA_BLOCK) {
+    const int64_t p = i / G;
     int b, y, x;
     pix3(p, H, W, b, y, x);
-    float acc[16];
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = 0.f;
+    float dv[4], o[4];
+    ld4(d + p * C + c0, dv);
+    zero4(o);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int yy = y - t / 3 + 1, xx = x - t % 3 + 1;
       if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
       const float g = dz[((int64_t)b * H + yy) * W + xx];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) acc[c] += w[c * 9 + t] * g;
+      for (int j = 0; j < 4; ++j) {
+        o[j] += wt[t][j] * g;
+        acc[t][j] += dv[j] * g;
+      }
     }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) st4(dd + p * 16 + 4 * q, acc + 4 * q);
+    if (c0 == 0) acc[9][0] += dz[p];
+    st4(dd + p * C + c0, o);
   }
+  block_chan_reduce_shfl<G, 10>(acc, sm, red);
+  for (int q = threadIdx.x; q < 10 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 10 * C + q] = red[q];
 }
 
 // ------------------------------------------------------------------ weight gradients (SIMT)
@@ -602,14 +625,18 @@ __global__ __launch_bounds__(256) void k_stem_bwd_stats(const T* __restrict__ dS
   for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 2 * C + q] = red[q];
 }
 
-// Apply: dTp = gamma * invstd * (dM - k0 - that * k1).
+// Apply: dTp = gamma * invstd * (dM - k0 - that * k1), fused with the input-module weight
+// gradient dW[o][c][tap] = sum_p dTp[o](p) x[c](p + off_tap): part[blk][27][16] (row = c*9 + tap).
+// dTp itself is written only when the input gradient is wanted (dTp != nullptr).
 template <class T>
 __global__ __launch_bounds__(256) void k_stem_bwd_apply(const T* __restrict__ dS, const T* __restrict__ S,
                                                         const float* __restrict__ x, const float* __restrict__ w,
                                                         const float* __restrict__ stats, const float* __restrict__ gamma,
-                                                        const float* __restrict__ coef, T* __restrict__ dTp, int B,
-                                                        int H, int W) {
+                                                        const float* __restrict__ coef, T* __restrict__ dTp,
+                                                        float* __restrict__ part, int B, int H, int W) {
   constexpr int C = 16, G = 4;
+  __shared__ float sm[4 * 27 * C];
+  __shared__ float red[27 * C];
   const int64_t items = (int64_t)B * H * W * G;
   int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
@@ -622,6 +649,9 @@ __global__ __launch_bounds__(256) void k_stem_bwd_apply(const T* __restrict__ dS
     k0[j] = coef[c0 + j];
     k1[j] = coef[C + c0 + j];
   }
+  float acc[27][4];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) zero4(acc[k]);
   for (; i < items; i += (int64_t)gridDim.x * STDA_BLOCK) {
     const int64_t p = i / G;
     int b, y, xx;
@@ -629,14 +659,34 @@ __global__ __launch_bounds__(256) void k_stem_bwd_apply(const T* __restrict__ dS
     float g[4], s[4], t[4], o[4];
     ld4(dS + p * C + c0, g);
     ld4(S + p * C + c0, s);
-    stem_conv<4>(x, w, b, y, xx, H, W, c0, t);
+    float xv[27];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) {
+        const int iy = y + tp / 3 - 1, ix = xx + tp % 3 - 1;
+        xv[c * 9 + tp] = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(((int64_t)b * 3 + c) * H + iy) * W + ix] : 0.f;
+      }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < 27; ++k) a += w[(c0 + j) * 27 + k] * xv[k];
+      t[j] = a;
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float dm = s[j] > 0.f ? g[j] : 0.f;
       o[j] = ga[j] * is[j] * (dm - k0[j] - (t[j] - mu[j]) * is[j] * k1[j]);
     }
-    st4(dTp + p * C + c0, o);
+#pragma unroll
+    for (int k = 0; k < 27; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[k][j] += o[j] * xv[k];
+    if (dTp) st4(dTp + p * C + c0, o);
   }
+  block_chan_reduce_shfl<G, 27>(acc, sm, red);
+  for (int q = threadIdx.x; q < 27 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 27 * C + q] = red[q];
 }
 
 // dx[c](y, x) = sum_o sum_{ky,kx} dTp[o](y - ky + 1, x - kx + 1) w[o][c][ky][kx]; planar FP32.

@@ -42,6 +42,33 @@ __device__ __forceinline__ void block_chan_reduce(const float (&v)[NS][4], float
   __syncthreads();
 }
 
+// Same result layout as block_chan_reduce, for many statistics: lanes of a wave that share a
+// channel group (lane % G) are combined with shuffles, then the 4 waves through LDS, in a fixed
+// order.  sm holds 4 * NS * 4 * G floats.
+template <int G, int NS>
+__device__ __forceinline__ void block_chan_reduce_shfl(float (&v)[NS][4], float* sm, float* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float a = v[s][j];
+#pragma unroll
+      for (int off = G; off < 64; off <<= 1) a += __shfl_xor(a, off);
+      v[s][j] = a;
+    }
+  constexpr int C = 4 * G;
+  if (lane < G)
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sm[(wave * NS + s) * C + 4 * lane + j] = v[s][j];
+  __syncthreads();
+  for (int i = threadIdx.x; i < NS * C; i += STDA_BLOCK)
+    red[i] = sm[i] + sm[NS * C + i] + sm[2 * NS * C + i] + sm[3 * NS * C + i];
+  __syncthreads();
+}
+
 // Sum over the block of NV values per thread (all threads hold the same quantities).
 template <int NV>
 __device__ __forceinline__ void block_vec_reduce(const float (&v)[NV], float* sm, float* red) {
@@ -85,15 +112,14 @@ __device__ __forceinline__ int64_t colmap_dst(const ColMap m, int col) {
       const int c = col % m.a, tap = col / m.a;
       return (int64_t)c * 9 + tap;
     }
-    case MAP_STEM: {  // col = k*16 + o, k = c*9 + tap (k = 27 is padding) -> w[o][c][tap]
+    case MAP_STEM: {  // col = k*16 + o, k = c*9 + tap -> w[o][c][tap]
       const int o = col % 16, k = col / 16;
-      return k < 27 ? (int64_t)o * 27 + k : -1;
+      return (int64_t)o * 27 + k;
     }
-    case MAP_HEAD: {  // col = k*4 + n, k = tap*16 + c, k = 144 the bias column; n > 0 padding
-      const int k = col / 4, n = col % 4;
-      if (n != 0 || k > 144) return -1;
-      if (k == 144) return 144;  // the bias follows the 144 weights
-      return (int64_t)(k % 16) * 9 + k / 16;
+    case MAP_HEAD: {  // col = tap*16 + c -> w[c][tap]; tap row 9: channel 0 = bias, others unused
+      const int tap = col / 16, c = col % 16;
+      if (tap == 9) return c == 0 ? 144 : -1;  // the bias follows the 144 weights
+      return (int64_t)c * 9 + tap;
     }
     default:
       return col;
@@ -107,8 +133,10 @@ __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, 
   const int cl = threadIdx.x & 15, rg = threadIdx.x >> 4;
   const int col = blockIdx.x * 16 + cl;
   double acc = 0.0;
-  if (col < ncols)
+  if (col < ncols) {
+#pragma unroll 8
     for (int r = rg; r < nrows; r += 16) acc += (double)part[(int64_t)r * ncols + col];
+  }
   sm[rg][cl] = acc;
   __syncthreads();
   if (rg == 0 && col < ncols) {

@@ -52,6 +52,9 @@ def _load():
         'stda_mse_loss': (I, [P, I, P, P, P, P, P, SZ, P]),
         'stda_sgd_step': (I, [P, P, I64, F, F, P, P]),
         'stda_sinr': (I, [P, P, P, I, I, I, P, P]),
+        'stda_profile_select': (I, [ctypes.c_char_p]),
+        'stda_profile_read': (I, [P, P]),
+        'stda_profile_report': (I, [P, SZ, P]),
         'rd_synth_workspace_size': (SZ, [I, I, I]),
         'rd_synth': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
     }
@@ -65,8 +68,8 @@ def _load():
 _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
            'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
-           'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'rd_synth_workspace_size',
-           'rd_synth')
+           'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_profile_select',
+           'stda_profile_read', 'stda_profile_report', 'rd_synth_workspace_size', 'rd_synth')
 
 
 def _check(status, what):
@@ -182,6 +185,30 @@ def sgd_step(w, dw, lr, weight_decay, w_bf16=None):
 def sinr(maps, o_mask, n_mask, out):
     n, H, W = maps.shape[0], maps.shape[-2], maps.shape[-1]
     _check(_lib.stda_sinr(_ptr(maps), _ptr(o_mask), _ptr(n_mask), n, H, W, _ptr(out), _stream()), 'stda_sinr')
+
+
+# ------------------------------------------------------------------------ timing hook
+def profile_select(tag):
+    _check(_lib.stda_profile_select(tag.encode() if tag else None), 'stda_profile_select')
+
+
+def profile_read():
+    tot, cnt = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(_lib.stda_profile_read(ctypes.byref(tot), ctypes.byref(cnt)), 'stda_profile_read')
+    return tot.value, cnt.value
+
+
+def profile_report():
+    """{tag: (launches, total_ms)} of the launches recorded since the last select."""
+    need = ctypes.c_size_t(0)
+    _check(_lib.stda_profile_report(None, 0, ctypes.byref(need)), 'stda_profile_report')
+    buf = ctypes.create_string_buffer(need.value + 1)
+    _check(_lib.stda_profile_report(buf, need.value + 1, ctypes.byref(need)), 'stda_profile_report')
+    out = {}
+    for line in buf.value.decode().splitlines():
+        tag, n, ms = line.split('\t')
+        out[tag] = (int(n), float(ms))
+    return out
 
 
 # ------------------------------------------------------------------------ RD maps
