@@ -18,6 +18,7 @@
 #include "net_bwd_kernels.h"
 #include "net_kernels.h"
 #include "plan.h"
+#include "stage1_tile.h"
 
 using namespace stda;
 
@@ -388,6 +389,13 @@ int launch_dense(const Ctx<T>& c, const std::string& tag, const T* src, int64_t 
   return STDA_OK;
 }
 
+// Blocks of the tiled stage-1 kernels: one per tile, at most kMaxGrid (they loop over tiles).
+template <int C>
+int s1_grid(int n, int h, int w) {
+  const int64_t tiles = (int64_t)n * ((h + S1Tile<C>::TH - 1) / S1Tile<C>::TH) * ((w + S1Tile<C>::TW - 1) / S1Tile<C>::TW);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
+}
+
 // Column sums of per-block BN partials followed by the statistics finalize.
 template <class T>
 int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* const* stats_out,
@@ -434,14 +442,14 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   sp.beta[1] = c.w + bo.dw_b;
   sp.beta[2] = c.w + bo.id_b;
   // stage 1
-  const int g1 = grid_for(Pin * (CIN / 4));
+  const int g1 = s1_grid<CIN>(n, hin, win);
   if (c.train) {
-    KLAUNCH(tagk("s1_stats", k), k_stage1<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
+    KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
     if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro, running)) return r;
   }
-  KLAUNCH(tagk("s1_apply", k), k_stage1<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win));
+  KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win));
   // stage 2: main (with statistics) and residual
   const float* dl = c.dl;
   const int g2 = grid_for(Pout * (COUT / 4));
@@ -732,26 +740,29 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   sp.beta[0] = c.w + bo.pw_b;
   sp.beta[1] = c.w + bo.dw_b;
   sp.beta[2] = c.w + bo.id_b;
-  const int g1 = grid_for(Pin * (CIN / 4));
-  KLAUNCH(tagk("s1_bwd_stats", k), k_s1_bwd_stats<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win));
+  const int g1 = s1_grid<CIN>(n, hin, win);
+  KLAUNCH(tagk("s1_bwd_stats", k),
+          k_s1_bwd_stats_tile<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win));
   {
     float* dg[3] = {dw + bo.pw_g, dw + bo.dw_g, dw + bo.id_g};
     float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
     if (int r = bn_bwd(c, g1, 4, CIN, (double)Pin, dg, db, acc)) return r;
   }
-  KLAUNCH(tagk("s1_bwd_apply", k), k_s1_bwd_apply<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, c.template scr<float>(c.P->ws_coef), sp, dP, dD,
-                                                    dX0, n, hin, win));
-{
-    ProfScope ps_(tagk("s1_bwd_dx", k), c.st);
+  float* pwpart = c.template scr<float>(c.P->ws_wpart);
+  {
+    ProfScope ps_(tagk("s1_bwd_fused", k), c.st);
     if (skipg)
-      k_s1_bwd_dx<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(dP, dD, dX0, skipg, sp, dXout, n, hin, win);
+      k_s1_bwd_fused<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, skipg,
+                                                              c.template scr<float>(c.P->ws_coef), sp, dXout, pwpart,
+                                                              part, n, hin, win);
     else
-      k_s1_bwd_dx<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(dP, dD, dX0, nullptr, sp, dXout, n, hin, win);
+      k_s1_bwd_fused<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, nullptr,
+                                                               c.template scr<float>(c.P->ws_coef), sp, dXout, pwpart,
+                                                               part, n, hin, win);
   }
   LAUNCH_CHECK();
-  WgPw<T, CIN> lp{X, dP, Pin};
-  if (int r = run_wgrad(c, tagk("wgrad_pw", k), lp, Pin, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc)) return r;
-  KLAUNCH(tagk("wgrad_dw", k), k_dw_wgrad<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, dD, part, n, hin, win));
+  if (int r = colsum_to(c, pwpart, g1, CIN * CIN, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc))
+    return r;
   return colsum_to(c, part, g1, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc);
 }
 

@@ -1,0 +1,461 @@
+// Stage 1 of the mobile encoder / decoder blocks on LDS tiles (gfx950).
+//
+// Stage 1 (first equation group of the mobile block): u = BN_p(PW(x)) + BN_d(DW3x3(x)) + BN_x(x),
+// x1 = ReLU(u); PW is a dense C x C pointwise layer, DW a depthwise 3x3 (transposed, i.e. with a
+// flipped kernel, in the decoder).  A block stages a TH x TW pixel tile of x plus a halo into
+// LDS with coalesced 16-byte loads (zeros outside the map) and computes every pixel of the tile
+// from LDS; the grid loops over the tiles of all clips.  Thread mapping inside a tile: item =
+// (pixel, group of 4 channels), channel group fastest, so a thread keeps one channel group for
+// its whole life.  LDS rows are padded to C + 4 floats.
+#pragma once
+#include "net_kernels.h"
+
+namespace stda {
+
+template <int C>
+struct S1Tile;
+template <>
+struct S1Tile<16> {
+  static constexpr int TH = 8, TW = 16;
+};
+template <>
+struct S1Tile<32> {
+  static constexpr int TH = 8, TW = 8;
+};
+template <>
+struct S1Tile<64> {
+  static constexpr int TH = 4, TW = 4;
+};
+
+template <int C>
+struct S1Geo {
+  static constexpr int TH = S1Tile<C>::TH, TW = S1Tile<C>::TW, G = C / 4, PS = C + 4;
+};
+
+// Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds
+// [(TH + 2 HALO)][(TW + 2 HALO)][PS] floats.
+template <class T, int C, int TH, int TW, int HALO>
+__device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0, int x0, int h, int w, float* lds) {
+  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4, PS = C + 4;
+  for (int e = threadIdx.x; e < RH * RW * G; e += STDA_BLOCK) {
+    const int q = e % G, px = e / G;
+    const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
+    float v[4];
+    if (y >= 0 && y < h && x >= 0 && x < w)
+      ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v);
+    else
+      zero4(v);
+    *reinterpret_cast<float4*>(lds + px * PS + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+__device__ __forceinline__ void tile_coords(int tile, int h, int w, int TH, int TW, int& b, int& y0, int& x0) {
+  const int ty = (h + TH - 1) / TH, tx = (w + TW - 1) / TW;
+  b = tile / (ty * tx);
+  const int r = tile - b * ty * tx;
+  y0 = (r / tx) * TH;
+  x0 = (r % tx) * TW;
+}
+
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+// Cm[i][n] = sum_k A(i, k) B(k, n) for an M x N x K product held in LDS, on the matrix cores
+// (v_mfma_f32_16x16x4f32); A and B are addressing functors, Cm is row-major with stride ldc.
+// The block's 4 waves take 16 x 16 output tiles in turn.  Caller synchronises around it.
+template <int M, int N, int K, class AF, class BF>
+__device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
+  for (int t = wave; t < (M / 16) * (N / 16); t += 4) {
+    const int m0 = (t / (N / 16)) * 16, n0 = (t % (N / 16)) * 16;
+    floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k = 0; k < K; k += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A(m0 + i, k + g), B(k + g, n0 + i), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Cm[(m0 + 4 * g + r) * ldc + n0 + i] = acc[r];
+  }
+}
+
+// Depthwise branch (4 channels) of the pixel at padded LDS position (r, c).
+template <int C>
+__device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float* wd, float dv[4]) {
+  constexpr int PS = C + 4;
+  zero4(dv);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const float4 v = *reinterpret_cast<const float4*>(xt + ((r + t / 3 - 1) * RW + c + t % 3 - 1) * PS + c0);
+    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
+    dv[0] += wq.x * v.x;
+    dv[1] += wq.y * v.y;
+    dv[2] += wq.z * v.z;
+    dv[3] += wq.w * v.w;
+  }
+}
+
+// Pointwise (4 output channels) and depthwise (4 channels) branches of the pixel whose padded
+// LDS position is (r, c) in a tile of row width RW.
+template <int C>
+__device__ __forceinline__ void s1_branches_lds(const float* xt, int RW, int r, int c, int c0, const float* wp,
+                                                const float* wd, float pv[4], float dv[4], float xv[4]) {
+  constexpr int PS = C + 4;
+  const float* ctr = xt + (r * RW + c) * PS;
+  zero4(pv);
+  zero4(dv);
+#pragma unroll 4
+  for (int k = 0; k < C; k += 4) {
+    const float4 v = *reinterpret_cast<const float4*>(ctr + k);
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float4 wq = *reinterpret_cast<const float4*>(wp + (k + j) * C + c0);
+      pv[0] += wq.x * vv[j];
+      pv[1] += wq.y * vv[j];
+      pv[2] += wq.z * vv[j];
+      pv[3] += wq.w * vv[j];
+    }
+  }
+  const float4 xc = *reinterpret_cast<const float4*>(ctr + c0);
+  xv[0] = xc.x;
+  xv[1] = xc.y;
+  xv[2] = xc.z;
+  xv[3] = xc.w;
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const float4 v = *reinterpret_cast<const float4*>(xt + ((r + t / 3 - 1) * RW + c + t % 3 - 1) * PS + c0);
+    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
+    dv[0] += wq.x * v.x;
+    dv[1] += wq.y * v.y;
+    dv[2] += wq.z * v.z;
+    dv[3] += wq.w * v.w;
+  }
+}
+
+// Forward.  MODE 0: per-block partials of (sum, sumsq) of the three BN inputs,
+// part[blk][3][C][2].  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)).
+template <class T, int C, bool DEC, int MODE>
+__global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __restrict__ X1, float* __restrict__ part,
+                                                 S1Params prm, int B, int h, int w) {
+  typedef S1Geo<C> Gm;
+  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
+  constexpr int PS = Gm::PS;
+  __shared__ float xt[(TH + 2) * RW * PS];
+  __shared__ float pt[TH * TW * PS];  // pointwise branch of the tile (matrix cores)
+  __shared__ float wp[C * C];
+  __shared__ float wd[9 * C];
+  __shared__ float sm[MODE == 0 ? 4 * 6 * C : 1];
+  __shared__ float red[6 * C];
+  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
+  const int c0 = (threadIdx.x % G) * 4;
+  float acc[6][4];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) zero4(acc[s]);
+  float sc[3][4], sh[3][4];
+  if (MODE == 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) bn_affine4(prm.stats[k], prm.gamma[k], prm.beta[k], C, c0, sc[k], sh[k]);
+  const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int b, y0, x0;
+    tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    __syncthreads();
+    load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
+    __syncthreads();
+    // pt[p][o] = sum_c x[p][c] wp[c][o]; tile pixel p = r*TW + cc sits at padded (r + 1, cc + 1)
+    lds_gemm<TH * TW, C, C>([&](int p, int k) { return xt[((p / TW + 1) * RW + p % TW + 1) * PS + k]; },
+                            [&](int k, int n) { return wp[k * C + n]; }, pt, PS);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
+      const int px = e / G, r = px / TW, cc = px % TW;
+      const int y = y0 + r, x = x0 + cc;
+      if (y >= h || x >= w) continue;
+      float pv[4], dv[4], xv[4];
+      const float4 pq = *reinterpret_cast<const float4*>(pt + px * PS + c0);
+      pv[0] = pq.x;
+      pv[1] = pq.y;
+      pv[2] = pq.z;
+      pv[3] = pq.w;
+      const float4 xq = *reinterpret_cast<const float4*>(xt + ((r + 1) * RW + cc + 1) * PS + c0);
+      xv[0] = xq.x;
+      xv[1] = xq.y;
+      xv[2] = xq.z;
+      xv[3] = xq.w;
+      s1_dw_lds<C>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      if (MODE == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[0][j] += pv[j];
+          acc[1][j] += pv[j] * pv[j];
+          acc[2][j] += dv[j];
+          acc[3][j] += dv[j] * dv[j];
+          acc[4][j] += xv[j];
+          acc[5][j] += xv[j] * xv[j];
+        }
+      } else {
+        float o[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          o[j] = fmaxf(pv[j] * sc[0][j] + sh[0][j] + dv[j] * sc[1][j] + sh[1][j] + xv[j] * sc[2][j] + sh[2][j], 0.f);
+        st4(X1 + (((int64_t)b * h + y) * w + x) * C + c0, o);
+      }
+    }
+  }
+  if (MODE == 0) {
+    block_chan_reduce_shfl<G, 6>(acc, sm, red);
+    for (int q = threadIdx.x; q < 6 * C; q += STDA_BLOCK) {
+      const int s = q / C, c = q % C;
+      part[(int64_t)blockIdx.x * 6 * C + ((s >> 1) * C + c) * 2 + (s & 1)] = red[q];
+    }
+  }
+}
+
+// Backward statistics: du = dX1 [X1 > 0]; part[blk][4][C] = sum du, sum du*phat, sum du*dhat,
+// sum du*xhat (branch outputs recomputed from the tile).
+template <class T, int C, bool DEC>
+__global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__ X, const T* __restrict__ X1,
+                                                           const T* __restrict__ dX1, float* __restrict__ part,
+                                                           S1Params prm, int B, int h, int w) {
+  typedef S1Geo<C> Gm;
+  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
+  constexpr int PS = Gm::PS;
+  __shared__ float xt[(TH + 2) * RW * PS];
+  __shared__ float pt[TH * TW * PS];
+  __shared__ float wp[C * C];
+  __shared__ float wd[9 * C];
+  __shared__ float sm[4 * 4 * C];
+  __shared__ float red[4 * C];
+  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
+  const int c0 = (threadIdx.x % G) * 4;
+  float mu[3][4], is[3][4];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mu[k][j] = prm.stats[k][c0 + j];
+      is[k][j] = prm.stats[k][C + c0 + j];
+    }
+  float acc[4][4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) zero4(acc[s]);
+  const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int b, y0, x0;
+    tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    __syncthreads();
+    load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
+    __syncthreads();
+    lds_gemm<TH * TW, C, C>([&](int p, int k) { return xt[((p / TW + 1) * RW + p % TW + 1) * PS + k]; },
+                            [&](int k, int n) { return wp[k * C + n]; }, pt, PS);
+    __syncthreads();
+    for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
+      const int px = e / G, r = px / TW, cc = px % TW;
+      const int y = y0 + r, x = x0 + cc;
+      if (y >= h || x >= w) continue;
+      float pv[4], dv[4], xv[4], x1[4], g[4];
+      const float4 pq = *reinterpret_cast<const float4*>(pt + px * PS + c0);
+      pv[0] = pq.x;
+      pv[1] = pq.y;
+      pv[2] = pq.z;
+      pv[3] = pq.w;
+      const float4 xq = *reinterpret_cast<const float4*>(xt + ((r + 1) * RW + cc + 1) * PS + c0);
+      xv[0] = xq.x;
+      xv[1] = xq.y;
+      xv[2] = xq.z;
+      xv[3] = xq.w;
+      s1_dw_lds<C>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+      ld4(X1 + off, x1);
+      ld4(dX1 + off, g);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float du = x1[j] > 0.f ? g[j] : 0.f;
+        acc[0][j] += du;
+        acc[1][j] += du * (pv[j] - mu[0][j]) * is[0][j];
+        acc[2][j] += du * (dv[j] - mu[1][j]) * is[1][j];
+        acc[3][j] += du * (xv[j] - mu[2][j]) * is[2][j];
+      }
+    }
+  }
+  block_chan_reduce_shfl<G, 4>(acc, sm, red);
+  for (int q = threadIdx.x; q < 4 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 4 * C + q] = red[q];
+}
+
+// Fused backward of stage 1.  With du = dX1 [X1 > 0] and the BN adjoint coefficients
+// k[s][c] = (sum du, sum du*phat, sum du*dhat, sum du*xhat) / n:
+//   dP = g_p is_p (du - k0 - phat k1), dD = g_d is_d (du - k0 - dhat k2),
+//   dX = g_x is_x (du - k0 - xhat k3) + dXr + PW^T(dP) + DW^T(dD) (+ skip gradient),
+// plus the pointwise weight gradient sum_p x[c](p) dP[o](p) -> pwpart[blk][c][o] and the
+// depthwise one sum_p x[c](p + off_t) dD[c](p) -> dwpart[blk][tap][c] (the weight's own tap
+// index, flipped in the decoder).  Per tile: x on a 2-pixel halo, dD on a 1-pixel halo and dP in
+// LDS (never in HBM); the three pointwise products (p = x Wp, dP Wp^T, x^T dP) run on the matrix
+// cores, the last one accumulating in registers across tiles.
+template <class T, int C, bool DEC, bool SKIP>
+__global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
+                                                      const T* __restrict__ dX1, const T* __restrict__ dXr,
+                                                      const T* __restrict__ skip, const float* __restrict__ coef,
+                                                      S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
+                                                      float* __restrict__ dwpart, int B, int h, int w) {
+  typedef S1Geo<C> Gm;
+  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, PS = Gm::PS, M = TH * TW;
+  constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
+  constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
+  constexpr int XT = (TH + 4) * XW * PS;
+  static_assert(XT >= 4 * 9 * C + 9 * C, "reduction scratch aliases the x tile");
+  __shared__ float xt[XT];
+  __shared__ float ddt[(TH + 2) * DWd * PS];
+  __shared__ float dpt[M * PS];
+  __shared__ float qt[M * PS];
+  __shared__ float wp[C * C];
+  __shared__ float wd[9 * C];
+  float* sm = xt;  // used only after the tile loop
+  float* red = xt + 4 * 9 * C;
+  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+  const int c0 = (threadIdx.x % G) * 4;
+  float mu[3][4], is[3][4], ga[3][4], k[4][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mu[q][j] = prm.stats[q][c0 + j];
+      is[q][j] = prm.stats[q][C + c0 + j];
+      ga[q][j] = prm.gamma[q][c0 + j];
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[q][j] = coef[q * C + c0 + j];
+  float dwacc[9][4];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) zero4(dwacc[t]);
+  floatx4_t pwacc[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) pwacc[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  auto xctr = [&](int p) { return ((p / TW + 2) * XW + p % TW + 2) * PS; };  // tile pixel -> x-tile row
+
+  const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int b, y0, x0;
+    tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    __syncthreads();
+    load_tile<T, C, TH, TW, 2>(X, b, y0, x0, h, w, xt);
+    __syncthreads();
+    // A1: pointwise branch of the tile, qt = x Wp
+    lds_gemm<M, C, C>([&](int p, int kk) { return xt[xctr(p) + kk]; }, [&](int kk, int n) { return wp[kk * C + n]; },
+                      qt, PS);
+    __syncthreads();
+    // A2: dD on the tile + halo 1, dP on the tile (zero off the map)
+    for (int e = threadIdx.x; e < (TH + 2) * DWd * G; e += STDA_BLOCK) {
+      const int px = e / G, r = px / DWd, cc = px % DWd;  // position in the dD tile
+      const int y = y0 - 1 + r, x = x0 - 1 + cc;
+      const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
+      float od[4], op[4];
+      zero4(od);
+      zero4(op);
+      if (y >= 0 && y < h && x >= 0 && x < w) {
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        float x1[4], g[4], dv[4];
+        ld4(X1 + off, x1);
+        ld4(dX1 + off, g);
+        s1_dw_lds<C>(xt, XW, r + 1, cc + 1, c0, wd, dv);
+        float pv[4] = {0.f, 0.f, 0.f, 0.f};
+        if (center) {
+          const float4 pq = *reinterpret_cast<const float4*>(qt + ((r - 1) * TW + cc - 1) * PS + c0);
+          pv[0] = pq.x;
+          pv[1] = pq.y;
+          pv[2] = pq.z;
+          pv[3] = pq.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float du = x1[j] > 0.f ? g[j] : 0.f;
+          od[j] = ga[1][j] * is[1][j] * (du - k[0][j] - (dv[j] - mu[1][j]) * is[1][j] * k[2][j]);
+          op[j] = ga[0][j] * is[0][j] * (du - k[0][j] - (pv[j] - mu[0][j]) * is[0][j] * k[1][j]);
+        }
+      }
+      *reinterpret_cast<float4*>(ddt + px * PS + c0) = make_float4(od[0], od[1], od[2], od[3]);
+      if (center)
+        *reinterpret_cast<float4*>(dpt + ((r - 1) * TW + cc - 1) * PS + c0) = make_float4(op[0], op[1], op[2], op[3]);
+    }
+    __syncthreads();
+    // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
+    lds_gemm<M, C, C>([&](int p, int o) { return dpt[p * PS + o]; }, [&](int o, int n) { return wp[n * C + o]; }, qt,
+                      PS);
+    // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles)
+#pragma unroll
+    for (int u = 0; u < NTW; ++u) {
+      const int t = wave + 4 * u;
+      if (t < NT) {
+        const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
+#pragma unroll 4
+        for (int p = 0; p < M; p += 4)
+          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[xctr(p + lg) + m0 + li], dpt[(p + lg) * PS + n0 + li],
+                                                          pwacc[u], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    // B2: dX on the tile, depthwise weight gradient
+    for (int e = threadIdx.x; e < M * G; e += STDA_BLOCK) {
+      const int px = e / G, r = px / TW, cc = px % TW;
+      const int y = y0 + r, x = x0 + cc;
+      if (y >= h || x >= w) continue;
+      const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+      float x1[4], g[4], rr[4], acc[4];
+      ld4(X1 + off, x1);
+      ld4(dX1 + off, g);
+      ld4(dXr + off, rr);
+      const float4 xc = *reinterpret_cast<const float4*>(xt + xctr(px) + c0);
+      const float4 qc = *reinterpret_cast<const float4*>(qt + px * PS + c0);
+      const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float du = x1[j] > 0.f ? g[j] : 0.f;
+        acc[j] = ga[2][j] * is[2][j] * (du - k[0][j] - (xv[j] - mu[2][j]) * is[2][j] * k[3][j]) + rr[j] + qv[j];
+      }
+      if (SKIP) {
+        float sv[4];
+        ld4(skip + off, sv);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] += sv[j];
+      }
+      // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map
+      const float4 ddc = *reinterpret_cast<const float4*>(ddt + ((r + 1) * DWd + cc + 1) * PS + c0);
+      const float ddv[4] = {ddc.x, ddc.y, ddc.z, ddc.w};
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const float4 v = *reinterpret_cast<const float4*>(ddt + ((r + 1 - dy) * DWd + cc + 1 - dx) * PS + c0);
+        const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
+        acc[0] += wq.x * v.x;
+        acc[1] += wq.y * v.y;
+        acc[2] += wq.z * v.z;
+        acc[3] += wq.w * v.w;
+        // depthwise weight gradient: x(q + off_t) * dD(q)
+        const float4 xn = *reinterpret_cast<const float4*>(xt + ((r + 2 + dy) * XW + cc + 2 + dx) * PS + c0);
+        dwacc[t][0] += xn.x * ddv[0];
+        dwacc[t][1] += xn.y * ddv[1];
+        dwacc[t][2] += xn.z * ddv[2];
+        dwacc[t][3] += xn.w * ddv[3];
+      }
+      st4(dX + off, acc);
+    }
+  }
+  __syncthreads();
+  block_chan_reduce_shfl<G, 9>(dwacc, sm, red);
+  for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) {
+    const int t = q / C, c = q % C;
+    const int tw = DEC ? 8 - t : t;
+    dwpart[(int64_t)blockIdx.x * 9 * C + tw * C + c] = red[q];
+  }
+  // pointwise gradient tile (m0, n0): lane holds D[4 lg + r][li] -> (c = m0 + 4 lg + r, o = n0 + li)
+  float* pw = pwpart + (int64_t)blockIdx.x * C * C;
+  for (int t = 0; t < NT; ++t) {
+    const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
+#pragma unroll
+    for (int u = 0; u < NTW; ++u)
+      if (wave + 4 * u == t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pw[(m0 + 4 * lg + r) * C + n0 + li] = pwacc[u][r];
+  }
+}
+
+}  // namespace stda
