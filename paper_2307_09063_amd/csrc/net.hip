@@ -19,6 +19,7 @@
 #include "net_kernels.h"
 #include "plan.h"
 #include "stage1_tile.h"
+#include "stem_tile.h"
 
 using namespace stda;
 
@@ -396,21 +397,24 @@ int s1_grid(int n, int h, int w) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
 }
 
+// Blocks of the tiled input-module kernels (8 x 32 pixel tiles), at most kMaxGrid.
+int stem_grid(int n, int H, int W) {
+  const int64_t tiles = (int64_t)n * ((H + 7) / 8) * ((W + 31) / 32);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
+}
+
 // Column sums of per-block BN partials followed by the statistics finalize.
 template <class T>
 int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* const* stats_out,
                 float* const* running, float* running_base) {
   (void)running_base;
   float* part = c.template scr<float>(c.P->ws_part);
-  double* sums = c.template scr<double>(c.P->ws_sums);
-  const int ncols = NB * C * 2;
-  KLAUNCH("colsum", k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nblk, ncols, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0));
   BnOut o{};
   for (int i = 0; i < NB; ++i) {
     o.stats[i] = stats_out[i];
     o.running[i] = running ? running[i] : nullptr;
   }
-  KLAUNCH("bn_finalize", k_bn_stats_finalize<<<1, 256, 0, c.st>>>(sums, NB, C, count, o, running ? 1 : 0));
+  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(part, nblk, NB, C, count, o, running ? 1 : 0));
   return STDA_OK;
 }
 
@@ -502,16 +506,15 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   const float* xs = x + S.x_off;
   float* part = c.template scr<float>(c.P->ws_part);
   T* s0 = c.template act<T>(S.s0);
-  const int gs = grid_for(P);
+  const int gs = stem_grid(S.n, S.H, S.W);
+  StemArgs sa{xs, c.w + no.stem_w, c.stats(0), c.w + no.stem_g, c.w + no.stem_b, nullptr, part};
   if (c.train) {
-    KLAUNCH("stem_stats", k_stem_fwd<T, 0><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, nullptr, part, nullptr, nullptr, nullptr, S.n, S.H,
-                                           S.W));
+    KLAUNCH("stem_stats", k_stem_tile<T, 0><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, nullptr, S.n, S.H, S.W));
     float* so[1] = {c.stats(0)};
     float* ro[1] = {running};
     if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro, running)) return r;
   }
-  KLAUNCH("stem_apply", k_stem_fwd<T, 1><<<gs, 256, 0, c.st>>>(xs, c.w + no.stem_w, s0, nullptr, c.stats(0), c.w + no.stem_g,
-                                         c.w + no.stem_b, S.n, S.H, S.W));
+  KLAUNCH("stem_apply", k_stem_tile<T, 1><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
   if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
@@ -658,14 +661,13 @@ int run_wgrad(const Ctx<T>& c, const std::string& tag, const L& ld, int64_t npix
 template <class T>
 int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg, float* const* db, int acc) {
   float* part = c.template scr<float>(c.P->ws_part);
-  double* sums = c.template scr<double>(c.P->ws_sums);
-  KLAUNCH("colsum", k_colsum<<<(NS * C + 15) / 16, 256, 0, c.st>>>(part, nblk, NS * C, sums, nullptr, ColMap{MAP_DOUBLE, 0, 0}, 0));
   BnBwdOut o{};
   for (int k = 0; k < NS - 1; ++k) {
     o.dgamma[k] = dg[k];
     o.dbeta[k] = db[k];
   }
-  KLAUNCH("bn_bwd_finalize", k_bn_bwd_finalize<<<1, 64, 0, c.st>>>(sums, NS, C, n, o, c.template scr<float>(c.P->ws_coef), acc));
+  KLAUNCH("bn_bwd_finalize", k_bn_bwd_reduce<<<C / 4, 256, 0, c.st>>>(part, nblk, NS, C, n, o,
+                                                                     c.template scr<float>(c.P->ws_coef), acc));
   return STDA_OK;
 }
 
@@ -789,17 +791,18 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   if (int r = bwd_block<T, 16, 32, false>(c, 0, gb(3), gb(4), gb(0), dw, acc)) return r;
   // input module
   float* part = c.template scr<float>(c.P->ws_part);
-  const int g = grid_for(P * 4);
-  KLAUNCH("stem_bwd_stats", k_stem_bwd_stats<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
-                                           part, S.n, S.H, S.W));
+  const int g = stem_grid(S.n, S.H, S.W);
+  StemArgs sa{x + S.x_off, c.w + no.stem_w, c.stats(0), c.w + no.stem_g, c.w + no.stem_b,
+              c.template scr<float>(c.P->ws_coef), part};
+  KLAUNCH("stem_bwd_stats",
+          k_stem_tile<T, 2><<<g, 256, 0, c.st>>>(sa, gb(4), c.template act<T>(S.s0), nullptr, S.n, S.H, S.W));
   {
     float* dg[1] = {dw + no.stem_g};
     float* db[1] = {dw + no.stem_b};
     if (int r = bn_bwd(c, g, 2, 16, (double)P, dg, db, acc)) return r;
   }
-  KLAUNCH("stem_bwd_apply", k_stem_bwd_apply<T><<<g, 256, 0, c.st>>>(gb(4), c.template act<T>(S.s0), x + S.x_off, c.w + no.stem_w, c.stats(0),
-                                           c.w + no.stem_g, c.template scr<float>(c.P->ws_coef),
-                                           dx ? gb(12) : nullptr, part, S.n, S.H, S.W));
+  KLAUNCH("stem_bwd_apply", k_stem_tile<T, 3><<<g, 256, 0, c.st>>>(sa, gb(4), c.template act<T>(S.s0),
+                                                                   dx ? gb(12) : nullptr, S.n, S.H, S.W));
   if (int r = colsum_to(c, part, g, 27 * 16, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, acc)) return r;
   if (dx) {
     KLAUNCH("stem_dx", k_stem_dx<T><<<grid_for(P), 256, 0, c.st>>>(gb(12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W));

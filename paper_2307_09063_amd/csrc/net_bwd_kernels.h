@@ -382,6 +382,41 @@ __global__ void k_bn_bwd_finalize(const double* __restrict__ sums, int NS, int C
   for (int s = 0; s < NS; ++s) coef[s * C + c] = (float)(sums[s * C + c] / n);
 }
 
+// Cross-block FP64 reduction of BN adjoint partials part[blk][NS][C] fused with
+// k_bn_bwd_finalize's epilogue.  Block = 4 channels (4 NS columns) x 64 / NS row groups.
+__global__ __launch_bounds__(256) void k_bn_bwd_reduce(const float* __restrict__ part, int nrows, int NS, int C,
+                                                       double n, BnBwdOut out, float* __restrict__ coef,
+                                                       int accumulate) {
+  __shared__ double sm[256];
+  const int cols = 4 * NS, groups = 256 / cols;
+  const int col = threadIdx.x % cols, rg = threadIdx.x / cols;
+  const int c0 = blockIdx.x * 4;
+  const int s = col / 4, c = c0 + col % 4;
+  double acc = 0.0;
+  if (rg < groups) {
+#pragma unroll 4
+    for (int r = rg; r < nrows; r += groups) acc += (double)part[(int64_t)r * NS * C + s * C + c];
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  if (threadIdx.x < cols) {
+    double tot = 0.0;
+    for (int k = 0; k < groups; ++k) tot += sm[k * cols + threadIdx.x];
+    sm[threadIdx.x] = tot;  // each slot is read only by the thread that owns it
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int cc = c0 + threadIdx.x;
+    const double db = sm[threadIdx.x];
+    for (int k = 0; k < NS - 1; ++k) {
+      const double dg = sm[(1 + k) * 4 + threadIdx.x];
+      out.dbeta[k][cc] = accumulate ? (float)((double)out.dbeta[k][cc] + db) : (float)db;
+      out.dgamma[k][cc] = accumulate ? (float)((double)out.dgamma[k][cc] + dg) : (float)dg;
+    }
+    for (int q = 0; q < NS; ++q) coef[q * C + cc] = (float)(sm[q * 4 + threadIdx.x] / n);
+  }
+}
+
 // Stage-2 adjoint, apply pass: dT = gamma * invstd * (dM - k0 - that * k1); writes dT and dY.
 template <class T, int C>
 __global__ __launch_bounds__(256) void k_s2_bwd_apply(const T* __restrict__ Gd, const T* __restrict__ Tm,

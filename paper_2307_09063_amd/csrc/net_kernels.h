@@ -176,6 +176,42 @@ __global__ void k_bn_stats_finalize(const double* __restrict__ sums, int NB, int
   }
 }
 
+// Cross-block FP64 reduction of batch-norm statistics partials fused with their finalize.
+// part[blk][NB][C][2]: (sum, sum of squares) per BN layer and channel.  Block = 4 channels of
+// one layer (8 columns) x 32 row groups; fixed summation order.
+__global__ __launch_bounds__(256) void k_bn_stats_reduce(const float* __restrict__ part, int nrows, int NB, int C,
+                                                         double count, BnOut out, int update_running) {
+  __shared__ double sm[32][9];
+  const int col = threadIdx.x & 7, rg = threadIdx.x >> 3;
+  const int i = (blockIdx.x * 4) / C, c0 = (blockIdx.x * 4) % C;
+  const int ncols = NB * C * 2;
+  const int gcol = (i * C + c0) * 2 + col;
+  double acc = 0.0;
+#pragma unroll 4
+  for (int r = rg; r < nrows; r += 32) acc += (double)part[(int64_t)r * ncols + gcol];
+  sm[rg][col] = acc;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int c = c0 + threadIdx.x;
+    double S = 0.0, Q = 0.0;
+    for (int k = 0; k < 32; ++k) {
+      S += sm[k][2 * threadIdx.x];
+      Q += sm[k][2 * threadIdx.x + 1];
+    }
+    const double mean = S / count;
+    double var = Q / count - mean * mean;
+    if (var < 0.0) var = 0.0;
+    out.stats[i][c] = (float)mean;
+    out.stats[i][C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
+    if (update_running) {
+      float* rn = out.running[i];
+      const double unb = count > 1.0 ? var * count / (count - 1.0) : var;
+      rn[c] = (float)(0.9 * (double)rn[c] + 0.1 * mean);
+      rn[C + c] = (float)(0.9 * (double)rn[C + c] + 0.1 * unb);
+    }
+  }
+}
+
 // EVAL statistics: mean and 1/sqrt(var + eps) of every BN layer from the running buffer
 // (both buffers: per layer C means, then C variances / inverse standard deviations).
 struct BnTable {
