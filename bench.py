@@ -20,6 +20,7 @@ WORKLOADS = {
     # name: (inputs recipe, dtype, recompute)
     'train_fp32_b64_256x128': ('cfg3_train_256x128', 'fp32', 0),
     'train_bf16_b256_256x128': ('cfg4_bf16_train_256x128', 'bf16', 1),
+    'train_uneven_bf16_512': ('cfg5_uneven_bf16_train', 'bf16', 0),
 }
 DEFAULT = 'train_fp32_b64_256x128'
 
@@ -48,8 +49,6 @@ def kernel_work(tag, B, H, W, es):
             'dense_dgrad_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
             'wgrad_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
             'wgrad_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
-            'wgrad_pw': (2.0 * B * hin * cin * cin, 2.0 * B * cin * hin * es, 'mfma'),
-            'wgrad_dw': (2.0 * B * hin * 9 * cin, 2.0 * B * cin * hin * es, 'alu'),
             's1_stats': (s1_flops, B * cin * hin * es, 'alu'),
             's1_apply': (s1_flops, 2.0 * B * cin * hin * es, 'alu'),
             's2_apply': (4.0 * B * hout * cout, B * hout * cout * (3 * es + 0.25), 'alu'),
@@ -58,8 +57,9 @@ def kernel_work(tag, B, H, W, es):
             's2_bwd_stats': (8.0 * B * hout * cout, B * hout * cout * (2 * es + 0.25), 'alu'),
             's2_bwd_apply': (10.0 * B * hout * cout, B * hout * cout * (4 * es + 0.25), 'alu'),
             's1_bwd_stats': (s1_flops, 3.0 * B * cin * hin * es, 'alu'),
-            's1_bwd_apply': (s1_flops, 7.0 * B * cin * hin * es, 'alu'),
-            's1_bwd_dx': (s1_flops, (4 + skip) * B * cin * hin * es, 'alu'),
+            # three pointwise products (recompute, transpose, weight gradient) and three depthwise
+            # ones (recompute, transpose, weight gradient); reads x, x1, dx1, dxr (+ skip), writes dx
+            's1_bwd_fused': (2.0 * B * hin * (3 * cin * cin + 27 * cin), (5 + skip) * B * cin * hin * es, 'alu'),
         }
         return table.get(kind)
     table = {
@@ -102,9 +102,100 @@ def parse():
     ap.add_argument('--workload', default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-clips', type=int, default=4)
-    ap.add_argument('--train-only', action='store_true', help='skip the EVAL-forward and rd_synth timings')
+    ap.add_argument('--train-only', action='store_true', help='only the chosen training workload')
+    ap.add_argument('--no-graph', action='store_true', help='time eager steps instead of the captured step')
     ap.add_argument('--kernel', default=None, help='tag of the kernel for the roofline (default: the dominant one)')
     return ap.parse_args()
+
+
+def make_batch(stda, inputs, torch, recipe_name, dev, rd_time=False):
+    """Segments and resident inputs of a workload: RD maps from rd_synth on the GPU."""
+    rc = inputs.WORKLOADS[recipe_name]
+    B = rc['B']
+    if len(rc['sizes']) == 1:
+        groups = [(B,) + tuple(rc['sizes'][0])]
+    else:
+        sizes = inputs.uneven_sizes(B, rc['sizes'], rc['seed'])
+        groups = [(sum(1 for q in sizes if q == sz),) + tuple(sz) for sz in rc['sizes']]
+        groups = [g for g in groups if g[0] > 0]
+    segs = stda.packed_segments(groups)
+    nx = sum(3 * n * H * W for n, H, W in groups)
+    x = torch.empty(nx, device=dev)
+    y = torch.empty(nx // 3, device=dev)
+    rd_ms = 0.0
+    xo = yo = 0
+    for gi, (n, H, W) in enumerate(groups):
+        tab, meta = inputs.make_scenes(n, H, W, rc['seed'] + 101 * gi, targets=rc['targets'], intf=rc['intf'],
+                                       inr=rc['inr'], clutter=rc['clutter'])
+        scenes = stda.upload_scenes(tab, dev)
+        rws = stda.alloc_bytes(stda.rd_synth_workspace_size(n, H, W), dev)
+        xv = x[xo:xo + 3 * n * H * W]
+        yv = y[yo:yo + n * H * W]
+        stda.rd_synth(scenes, n, H, W, meta['seed'], meta['noise_sigma'], xv, yv, rws)
+        if rd_time:
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                stda.rd_synth(scenes, n, H, W, meta['seed'], meta['noise_sigma'], xv, yv, rws)
+            e1.record()
+            torch.cuda.synchronize()
+            rd_ms += e0.elapsed_time(e1) / 5
+        xo += 3 * n * H * W
+        yo += n * H * W
+    torch.cuda.synchronize()
+    return segs, groups, x, y, rd_ms
+
+
+class Trainer:
+    """Buffers of one training workload; eager steps and the captured step graph."""
+
+    def __init__(self, stda, inputs, torch, segs, x, y, dtype, recompute, dev):
+        self.stda, self.torch, self.segs, self.x, self.y = stda, torch, segs, x, y
+        self.dtype, self.recompute = dtype, recompute
+        self.w = torch.from_numpy(inputs.make_weights(stda.param_specs())).to(dev)
+        self.running = torch.from_numpy(inputs.make_running(stda.bn_channels())).to(dev)
+        sv_b, ws_b = stda.workspace_size(segs, dtype, stda.TRAIN, recompute)
+        self.saved, self.ws = stda.alloc_bytes(sv_b, dev), stda.alloc_bytes(ws_b, dev)
+        self.z = torch.empty_like(y)
+        self.dz = torch.empty_like(y)
+        self.dw = torch.empty_like(self.w)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.wb = torch.empty(self.w.numel(), dtype=torch.int16, device=dev) if dtype == stda.BF16 else None
+        self.graph = None
+        self.stream = torch.cuda.Stream()
+
+    def step(self):
+        s = self.stda
+        s.forward(self.segs, self.x, self.w, self.running, self.z, self.saved, self.ws, self.dtype, s.TRAIN,
+                  self.recompute)
+        s.mse_loss(self.segs, self.z, self.y, self.loss, self.dz, self.ws)
+        s.backward(self.segs, self.x, self.dz, self.w, self.saved, self.dw, None, self.ws, self.dtype,
+                   self.recompute)
+        s.sgd_step(self.w, self.dw, 1e-3, 5e-4, self.wb)
+
+    def capture(self):
+        self.torch.cuda.synchronize()
+        self.graph = self.stda.TrainStepGraph(self.segs, self.x, self.y, self.w, self.running, self.z, self.loss,
+                                              self.dz, self.dw, self.saved, self.ws, self.dtype, self.recompute,
+                                              1e-3, 5e-4, self.wb, self.stream)
+
+    def timed(self, steps, graph):
+        """ms per step over `steps` steps, bracketed by synchronisations, timed with HIP events on the
+        stream the work runs on."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        st = self.stream if graph else torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(steps):
+            if graph:
+                self.graph.launch()
+            else:
+                self.step()
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
 
 
 def main():
@@ -113,95 +204,82 @@ def main():
         print(f'bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is '
               'described, not built', file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2307_09063_amd import inputs, stda
 
-    recipe_name, dt_name, recompute = WORKLOADS[args.workload]
-    recipe = inputs.WORKLOADS[recipe_name]
-    dtype = stda.BF16 if dt_name == 'bf16' else stda.FP32
-    B = recipe['B']
-    N, M = recipe['sizes'][0]
     dev = torch.device('cuda:0')
     torch.cuda.set_device(dev)
-
-    # ---- inputs: synthetic RD maps of the paper's workload shape, on the GPU
-    tab, meta = inputs.make_scenes(B, N, M, recipe['seed'], targets=recipe['targets'], intf=recipe['intf'],
-                                   inr=recipe['inr'], clutter=recipe['clutter'])
-    scenes = stda.upload_scenes(tab, dev)
-    x = torch.empty((B, 3, N, M), device=dev)
-    y = torch.empty((B, 1, N, M), device=dev)
-    rws = stda.alloc_bytes(stda.rd_synth_workspace_size(B, N, M), dev)
-    stda.rd_synth(scenes, B, N, M, meta['seed'], meta['noise_sigma'], x, y, rws)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        stda.rd_synth(scenes, B, N, M, meta['seed'], meta['noise_sigma'], x, y, rws)
-    e1.record()
-    torch.cuda.synchronize()
-    rd_ms = e0.elapsed_time(e1) / 5
-
-    w = torch.from_numpy(inputs.make_weights(stda.param_specs())).to(dev)
-    running = torch.from_numpy(inputs.make_running(stda.bn_channels())).to(dev)
-    segs = stda.uniform_segments(B, N, M)
-    sv_b, ws_b = stda.workspace_size(segs, dtype, stda.TRAIN, recompute)
-    saved, ws = stda.alloc_bytes(sv_b, dev), stda.alloc_bytes(ws_b, dev)
-    z = torch.empty((B, 1, N, M), device=dev)
-    dz = torch.empty_like(z)
-    dw = torch.empty_like(w)
-    loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    wb = torch.empty(w.numel(), dtype=torch.int16, device=dev) if dtype == stda.BF16 else None
-
-    def step():
-        stda.forward(segs, x, w, running, z, saved, ws, dtype, stda.TRAIN, recompute)
-        stda.mse_loss(segs, z, y, loss, dz, ws)
-        stda.backward(segs, x, dz, w, saved, dw, None, ws, dtype, recompute)
-        stda.sgd_step(w, dw, 1e-3, 5e-4, wb)
-
+    recipe_name, dt_name, recompute = WORKLOADS[args.workload]
+    dtype = stda.BF16 if dt_name == 'bf16' else stda.FP32
+    segs, groups, x, y, rd_ms = make_batch(stda, inputs, torch, recipe_name, dev, rd_time=not args.train_only)
+    B = sum(g[0] for g in groups)
+    N, M = groups[0][1], groups[0][2]
+    tr = Trainer(stda, inputs, torch, segs, x, y, dtype, recompute, dev)
     for _ in range(args.warmup):
-        step()
+        tr.step()
     torch.cuda.synchronize()
     # dominant kernel: one step with every tagged launch timed
     stda.profile_select('*')
-    step()
+    tr.step()
     torch.cuda.synchronize()
     per_tag = stda.profile_report()
+    stda.profile_select(None)
     dominant = args.kernel or max(per_tag, key=lambda t: per_tag[t][1])
     tot_tagged = sum(v[1] for v in per_tag.values())
     for t, (n, tms) in sorted(per_tag.items(), key=lambda kv: -kv[1][1])[:40]:
         print(f'bench:   {t:28s} {n:3d} launches {tms:8.3f} ms ({100 * tms / tot_tagged:4.1f}%)', file=sys.stderr)
-    print(f'bench: dominant kernel {dominant} ({per_tag.get(dominant, (0, 0))[1]:.3f} ms of one step)',
-          file=sys.stderr, flush=True)
-    # timed region; the dominant kernel's launches are bracketed by HIP events on their stream
-    stda.profile_select(dominant)
-    print(f'bench: warmup done, timing {args.steps} steps', file=sys.stderr, flush=True)
+    print(f'bench: dominant kernel {dominant}', file=sys.stderr, flush=True)
+    # headline: the captured step, replayed
+    use_graph = not args.no_graph
+    if use_graph:
+        tr.capture()
+        tr.timed(2, True)
+    print(f'bench: timing {args.steps} steps ({"graph" if use_graph else "eager"})', file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
+    ms = tr.timed(args.steps, use_graph)
     wall = time.perf_counter() - t0
+    clips_s = B / (ms / 1e3)
+    # roofline: the same steps eagerly, the dominant kernel's launches bracketed by HIP events
+    stda.profile_select(dominant)
+    ms_eager = tr.timed(args.steps, False)
     k_total, k_count = stda.profile_read()
     stda.profile_select(None)
-    ms = e0.elapsed_time(e1) / args.steps
-    clips_s = B / (ms / 1e3)
-    roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16)
-    print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), wall {wall:.2f}s, loss {loss.item():.5f}',
-          file=sys.stderr, flush=True)
+    roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16) if len(groups) == 1 else None
+    print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), eager {ms_eager:.3f} ms, wall {wall:.2f}s, '
+          f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)
 
-    fwd_ms = None
-    if args.train_only:
-        Bf = 0
-    else:
-        fwd_ms, Bf = eval_forward(stda, inputs, torch, x, w, running, N, M, dev, e0, e1)
+    extra = {}
+    if not args.train_only:
+        fwd_ms, Bf = eval_forward(stda, inputs, torch, x[:3 * 32 * N * M] if len(groups) == 1 else None,
+                                  tr.w, tr.running, dev)
+        extra['fwd_eval_fp32_b32_256x128'] = {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)}
+        lat = latency_b1(stda, inputs, torch, tr.w, tr.running, dev)
+        extra['fwd_eval_fp32_b1_64x64_latency_ms'] = round(lat, 4)
+        for other in ('train_bf16_b256_256x128', 'train_uneven_bf16_512'):
+            if other == args.workload:
+                continue
+            rn, dn, rec = WORKLOADS[other]
+            sg, gr, xo, yo, _ = make_batch(stda, inputs, torch, rn, dev)
+            t2 = Trainer(stda, inputs, torch, sg, xo, yo, stda.BF16 if dn == 'bf16' else stda.FP32, rec, dev)
+            t2.step()
+            t2.capture()
+            t2.timed(2, True)
+            m2 = t2.timed(max(3, args.steps // 2), True)
+            n2 = sum(g[0] for g in gr)
+            extra[other] = {'ms_per_step': round(m2, 4), 'clips_per_s': round(n2 / (m2 / 1e3), 1), 'dtype': dn,
+                            'recompute': rec, 'segments': [list(g) for g in gr]}
+            print(f'bench: {other}: {m2:.3f} ms/step ({n2 / (m2 / 1e3):.0f} clips/s)', file=sys.stderr, flush=True)
+            t2.graph.close()
+            del t2, xo, yo
+            torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.cpu_sample_clips, N, M, x[:args.cpu_sample_clips].cpu().numpy(),
-                           y[:args.cpu_sample_clips].cpu().numpy(), w.cpu().numpy(), running.cpu().numpy())
+        k = args.cpu_sample_clips
+        cpu = cpu_baseline(k, N, M, x[:3 * k * N * M].view(k, 3, N, M).cpu().numpy(),
+                           y[:k * N * M].view(k, 1, N, M).cpu().numpy(), tr.w.cpu().numpy(),
+                           tr.running.cpu().numpy())
 
     out = {
         'metric': '3-frame RD clips/s, fwd+bwd training step',
@@ -216,35 +294,64 @@ def main():
         'vs_baseline': None,
         'dtype': 'bf16' if dtype == stda.BF16 else 'f32',
         'data': 'synthetic (seeded FMCW scenes -> rd_synth on the GPU)',
-        'config': {'workload': args.workload, 'clips': B, 'frames': 3, 'range_bins': N, 'doppler_bins': M,
-                   'step': 'TRAIN forward + MSE + backward + SGD', 'recompute': recompute},
-        'fwd_eval_fp32_b32': None if fwd_ms is None else {'ms': round(fwd_ms, 4),
-                                                           'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)},
-        'rd_synth': {'ms': round(rd_ms, 4), 'clips_per_s': round(B / (rd_ms / 1e3), 1), 'maps_per_clip': 4},
+        'config': {'workload': args.workload, 'clips': B, 'frames': 3, 'segments': [list(g) for g in groups],
+                   'step': 'TRAIN forward + MSE + backward + SGD', 'recompute': recompute,
+                   'launch': 'one hipGraph launch per step' if use_graph else 'eager'},
+        'ms_per_step_eager': round(ms_eager, 4),
+        'rd_synth_ms': round(rd_ms, 4),
         'roofline': roof,
         'cpu_baseline': cpu,
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
-def eval_forward(stda, inputs, torch, x, w, running, N, M, dev, e0, e1):
-    """Forward-only EVAL at the forward configuration (B = 32) on the same maps."""
-    fw = inputs.WORKLOADS['cfg2_fwd_256x128']
-    Bf = fw['B']
+def latency_b1(stda, inputs, torch, w, running, dev):
+    """EVAL forward of one clip of 3 x 64 x 64 (the small configuration), ms per call."""
+    rc = inputs.WORKLOADS['cfg1_fwd_64x64']
+    tab, meta = inputs.make_scenes(1, 64, 64, rc['seed'], targets=rc['targets'], intf=rc['intf'], inr=rc['inr'],
+                                   clutter=rc['clutter'])
+    x1, _ = stda.synthesize(tab, meta, dev, with_clean=False)
+    segs = stda.uniform_segments(1, 64, 64)
+    _, wsb = stda.workspace_size(segs, stda.FP32, stda.EVAL)
+    ws = stda.alloc_bytes(wsb, dev)
+    z = torch.empty((1, 1, 64, 64), device=dev)
+    for _ in range(5):
+        stda.forward(segs, x1, w, running, z, None, ws, stda.FP32, stda.EVAL)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        stda.forward(segs, x1, w, running, z, None, ws, stda.FP32, stda.EVAL)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 50
+
+
+def eval_forward(stda, inputs, torch, x, w, running, dev):
+    """Forward-only EVAL at the forward configuration (B = 32 clips of 3 x 256 x 128), ms per call."""
+    rc = inputs.WORKLOADS['cfg2_fwd_256x128']
+    Bf = rc['B']
+    N, M = rc['sizes'][0]
+    if x is None:
+        tab, meta = inputs.make_scenes(Bf, N, M, rc['seed'], targets=rc['targets'], intf=rc['intf'],
+                                       inr=rc['inr'], clutter=rc['clutter'])
+        x, _ = stda.synthesize(tab, meta, dev, with_clean=False)
+    xf = x.reshape(-1)[:3 * Bf * N * M].contiguous()
     segs_f = stda.uniform_segments(Bf, N, M)
     _, ws_f = stda.workspace_size(segs_f, stda.FP32, stda.EVAL)
     wsf = stda.alloc_bytes(ws_f, dev)
-    xf, zf = x[:Bf].contiguous(), torch.empty((Bf, 1, N, M), device=dev)
+    zf = torch.empty((Bf, 1, N, M), device=dev)
     for _ in range(3):
         stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(10):
         stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
     e1.record()
     torch.cuda.synchronize()
-    fwd_ms = e0.elapsed_time(e1) / 10
-    return fwd_ms, Bf
+    return e0.elapsed_time(e1) / 10, Bf
 
 
 def cpu_baseline(nclips, N, M, x, y, w, r):

@@ -137,6 +137,27 @@ int stda_sgd_step(float* w, const float* dw, int64_t n, float lr, float weight_d
 int stda_sinr(const float* maps, const uint8_t* o_mask, const uint8_t* n_mask, int n_maps, int H,
               int W, double* out_dev, hipStream_t stream);
 
+/* ------------------------------------------------------------------ captured training step */
+/*
+ * One training step -- stda_forward (TRAIN), stda_mse_loss against y, stda_backward (dx not
+ * computed), stda_sgd_step -- captured once from the given arguments into a hipGraph and
+ * instantiated.  Every later stda_graph_launch replays exactly those kernels on those buffers
+ * (one host call per step; the buffers' contents may change between launches, their addresses
+ * may not).  `stream` must be a non-null stream (capture is per-thread; nothing is executed while
+ * capturing).  Arguments are validated first; on error nothing is captured and *graph is NULL.
+ * The timing hook must be off while capturing.  Uneven batches are captured as their segment
+ * list, so one launch runs every segment of the step.
+ */
+typedef struct stda_graph_s* stda_graph;
+int stda_train_step_graph_create(const stda_segment* segs /*host*/, int n_segs, const float* x,
+                                 const float* y, float* w, float* running, float* z,
+                                 double* loss_dev, float* dz, float* dw, void* saved,
+                                 size_t saved_bytes, void* ws, size_t ws_bytes, int dtype,
+                                 int recompute, float lr, float weight_decay, uint16_t* w_bf16,
+                                 hipStream_t stream, stda_graph* graph /*host out*/);
+int stda_graph_launch(stda_graph graph, hipStream_t stream);
+int stda_graph_destroy(stda_graph graph);
+
 /* ------------------------------------------------------------------ measurement hooks */
 /*
  * Per-kernel timing.  After stda_profile_select(tag) every launch carrying that tag (for example

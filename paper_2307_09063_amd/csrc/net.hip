@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -275,7 +276,6 @@ struct Bump {
 };
 
 void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute, Plan& P) {
-  (void)recompute;
   P = Plan{};
   P.n_segs = n_segs;
   P.dtype = dtype;
@@ -321,6 +321,24 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     P.ws_ecaw = ws.take(sizeof(float) * (size_t)max_clips * 3);
     P.ws_wpart = ws.take(sizeof(float) * (size_t)kMaxWgradGrid * 32768);
   }
+  // recompute: one scratch set of block internals in ws, shared by every block and segment
+  size_t rx1 = 0, rty = 0, rmask = 0;
+  const bool rec = train && recompute;
+  if (rec) {
+    size_t mx1 = 0, mty = 0;
+    for (int s = 0; s < n_segs; ++s)
+      for (int k = 0; k < 4; ++k) {
+        const BlockCfg& b = kBlocks[k];
+        const size_t n = segs[s].n, H = segs[s].H, W = segs[s].W;
+        mx1 = std::max(mx1, (size_t)b.cin * n * (H >> b.lin) * (W >> b.lin));
+        mty = std::max(mty, (size_t)b.cout * n * (H >> b.lout) * (W >> b.lout));
+      }
+    rx1 = ws.take(es * mx1);
+    const size_t rt = ws.take(es * mty);
+    rty = ws.take(es * mty);
+    rmask = ws.take(mty / 4);
+    P.rec_T = rt;
+  }
   for (int s = 0; s < n_segs; ++s) {
     SegPlan& S = P.seg[s];
     const int64_t n = segs[s].n, H = segs[s].H, W = segs[s].W;
@@ -336,13 +354,21 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
       const BlockCfg& b = kBlocks[k];
       const int64_t hin = H >> b.lin, win = W >> b.lin, hout = H >> b.lout, wout = W >> b.lout;
       BlockActs& A = S.blk[k];
-      A.X1 = acts.take(es * b.cin * n * hin * win);
-      A.T = acts.take(es * b.cout * n * hout * wout);
-      A.Y = acts.take(es * b.cout * n * hout * wout);
+      A.inner_in_ws = rec;
+      if (rec) {
+        A.X1 = rx1;
+        A.T = P.rec_T;
+        A.Y = rty;
+        A.mask = rmask;
+      } else {
+        A.X1 = acts.take(es * b.cin * n * hin * win);
+        A.T = acts.take(es * b.cout * n * hout * wout);
+        A.Y = acts.take(es * b.cout * n * hout * wout);
+        A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
+      }
       A.Xn = acts.take(es * b.cout * n * hout * wout);
       A.a = acts.take(sizeof(float) * b.cout * n);
       A.g = acts.take(sizeof(float) * b.cout * n);
-      A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
     }
   }
   P.saved_bytes = train ? sv.off : 0;
@@ -364,7 +390,11 @@ struct Ctx {
   const float* dl;  // dense layouts
   hipStream_t st;
   bool train;
+  bool rec_pass = false;  // re-running a block's forward inside the backward (recompute mode)
   template <class U> U* act(size_t off) const { return reinterpret_cast<U*>(sv + off); }
+  template <class U> U* inner(const BlockActs& A, size_t off) const {
+    return reinterpret_cast<U*>((A.inner_in_ws ? ws : sv) + off);
+  }
   template <class U> U* scr(size_t off) const { return reinterpret_cast<U*>(ws + off); }
   float* stats(int64_t bn_off) const { return reinterpret_cast<float*>((train ? sv : ws) + S->stats) + bn_off; }
 };
@@ -428,9 +458,9 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
   const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
   const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
-  T* X1 = c.template act<T>(A.X1);
-  T* Tm = c.template act<T>(A.T);
-  T* Y = c.template act<T>(A.Y);
+  T* X1 = c.template inner<T>(A, A.X1);
+  T* Tm = c.template inner<T>(A, A.T);
+  T* Y = c.template inner<T>(A, A.Y);
   T* R = c.template scr<T>(c.P->ws_R);
   float* part = c.template scr<float>(c.P->ws_part);
   S1Params sp{};
@@ -447,7 +477,8 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   sp.beta[2] = c.w + bo.id_b;
   // stage 1
   const int g1 = s1_grid<CIN>(n, hin, win);
-  if (c.train) {
+  const bool stats_pass = c.train && !c.rec_pass;
+  if (stats_pass) {
     KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
@@ -460,7 +491,7 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
   (void)dl;
   (void)g2;
-  if (c.train) {
+  if (stats_pass) {
     int nb = 0;
     if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
       return r;
@@ -478,9 +509,10 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   const int hw = hout * wout;
   const int tiles = tiles_for(hw, COUT / 4);
   float* gap = c.template scr<float>(c.P->ws_gap);
-  uint8_t* mask = c.train ? c.template act<uint8_t>(A.mask) : nullptr;
+  uint8_t* mask = c.train ? c.template inner<uint8_t>(A, A.mask) : nullptr;
   KLAUNCH(tagk("s2_apply", k), k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, mask, gap, c.stats(bo.bn_main), c.w + bo.main_g,
                                                         c.w + bo.main_b, hw));
+  if (c.rec_pass) return STDA_OK;  // the block output is a saved checkpoint
   T* Xn = c.template act<T>(A.Xn);
   const T* skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
 {
@@ -683,9 +715,9 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
   const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
   const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
-  const T* X1 = c.template act<T>(A.X1);
-  const T* Tm = c.template act<T>(A.T);
-  const T* Y = c.template act<T>(A.Y);
+  const T* X1 = c.template inner<T>(A, A.X1);
+  const T* Tm = c.template inner<T>(A, A.T);
+  const T* Y = c.template inner<T>(A, A.Y);
   auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
   T *dT = gb(5), *dY = gb(6), *dX1 = gb(7), *dXr = gb(8), *dP = gb(9), *dD = gb(10), *dX0 = gb(11);
   float* part = c.template scr<float>(c.P->ws_part);
@@ -696,7 +728,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   float* epart = c.template scr<float>(c.P->ws_gap);
   // ECA adjoint partials and stage-2 BN statistics
   KLAUNCH(tagk("eca_bwd", k), k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw));
-  const uint8_t* mask = c.template act<uint8_t>(A.mask);
+  const uint8_t* mask = c.template inner<uint8_t>(A, A.mask);
   KLAUNCH(tagk("s2_bwd_stats", k), k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
       Gd, Tm, mask, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
       c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles));
@@ -784,10 +816,22 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
     if (int r = colsum_to(c, part, gh, 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
+  // recompute mode: re-run a block's forward (saved statistics, no ECA) right before its adjoint
+  Ctx<T> rc = c;
+  rc.rec_pass = true;
+  const bool rec = S.blk[0].inner_in_ws;
+  if (rec)
+    if (int r = fwd_block<T, 32, 16, true>(rc, 3, nullptr)) return r;
   if (int r = bwd_block<T, 32, 16, true>(c, 3, gb(0), gb(1), nullptr, dw, acc)) return r;
+  if (rec)
+    if (int r = fwd_block<T, 64, 32, true>(rc, 2, nullptr)) return r;
   if (int r = bwd_block<T, 64, 32, true>(c, 2, gb(1), gb(2), nullptr, dw, acc)) return r;
   // encoder 1 (input e0: its gradient also receives dd0 through the skip), encoder 0
+  if (rec)
+    if (int r = fwd_block<T, 32, 64, false>(rc, 1, nullptr)) return r;
   if (int r = bwd_block<T, 32, 64, false>(c, 1, gb(2), gb(3), gb(1), dw, acc)) return r;
+  if (rec)
+    if (int r = fwd_block<T, 16, 32, false>(rc, 0, nullptr)) return r;
   if (int r = bwd_block<T, 16, 32, false>(c, 0, gb(3), gb(4), gb(0), dw, acc)) return r;
   // input module
   float* part = c.template scr<float>(c.P->ws_part);
@@ -859,6 +903,78 @@ int stda_param_table(stda_param_desc* out, int cap) {
     }
   }
   return (int)t.size();
+}
+
+struct stda_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int stda_train_step_graph_create(const stda_segment* segs, int n_segs, const float* x, const float* y, float* w,
+                                 float* running, float* z, double* loss, float* dz, float* dw, void* saved,
+                                 size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int recompute, float lr,
+                                 float weight_decay, uint16_t* w_bf16, hipStream_t stream, stda_graph* out) {
+  if (!out || !stream) return STDA_E_INVALID;
+  *out = nullptr;
+  // validate everything before capture starts, so that a failing call leaves nothing captured
+  size_t sv = 0, wb = 0;
+  if (int r = stda_workspace_size(segs, n_segs, dtype, STDA_TRAIN, recompute, &sv, &wb)) return r;
+  if (!x || !y || !w || !running || !z || !loss || !dz || !dw || !saved || !ws) return STDA_E_INVALID;
+  if (saved_bytes < sv || ws_bytes < wb) return STDA_E_WORKSPACE;
+  {
+    Prof& p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (p.on) return STDA_E_INVALID;  // the timing hook records events; keep it out of graphs
+  }
+  HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  int r = stda_forward(segs, n_segs, x, w, running, z, saved, saved_bytes, ws, ws_bytes, dtype, STDA_TRAIN, recompute,
+                       stream);
+  if (!r) r = stda_mse_loss(segs, n_segs, z, y, loss, dz, ws, ws_bytes, stream);
+  if (!r)
+    r = stda_backward(segs, n_segs, x, dz, w, saved, saved_bytes, dw, nullptr, ws, ws_bytes, dtype, recompute,
+                      stream);
+  if (!r) r = stda_sgd_step(w, dw, (int64_t)stda_param_count(), lr, weight_decay, w_bf16, stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &g);
+  if (r) {
+    if (g) hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return STDA_E_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    hipGraphDestroy(g);
+    g_last_hip = (int)e2;
+    return STDA_E_HIP;
+  }
+  stda_graph h = new (std::nothrow) stda_graph_s;
+  if (!h) {
+    hipGraphExecDestroy(ex);
+    hipGraphDestroy(g);
+    return STDA_E_INVALID;
+  }
+  h->graph = g;
+  h->exec = ex;
+  *out = h;
+  return STDA_OK;
+}
+
+int stda_graph_launch(stda_graph g, hipStream_t stream) {
+  if (!g || !g->exec) return STDA_E_INVALID;
+  HIP_TRY(hipGraphLaunch(g->exec, stream));
+  return STDA_OK;
+}
+
+int stda_graph_destroy(stda_graph g) {
+  if (!g) return STDA_OK;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  delete g;
+  return STDA_OK;
 }
 
 int stda_profile_select(const char* tag) {

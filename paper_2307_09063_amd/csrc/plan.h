@@ -54,6 +54,7 @@ const NetOffsets& net_offsets();
 // Byte offsets of one segment's activations (in `saved` for TRAIN, in `ws` for EVAL).
 struct BlockActs {
   size_t X1, T, Y, Xn, a, g, mask;  // mask: stage-2 ReLU decisions, 4 bits per byte
+  bool inner_in_ws;                 // X1, T, Y, mask live in ws (recomputed in the backward)
 };
 struct SegPlan {
   int n, H, W;
@@ -70,6 +71,7 @@ struct Plan {
   size_t ws_wk, ws_dense, ws_R, ws_part, ws_sums, ws_gap, ws_eval_stats, ws_loss;
   size_t ws_g[kNumGradBufs];
   size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart, ws_frag;
+  size_t rec_T;                          // recompute scratch of the stage-2 main output
   int64_t dense_f[4][2], dense_d[4][2];  // element offsets inside ws_dense (main, residual)
   size_t saved_bytes, ws_bytes;
 };

@@ -52,6 +52,10 @@ def _load():
         'stda_mse_loss': (I, [P, I, P, P, P, P, P, SZ, P]),
         'stda_sgd_step': (I, [P, P, I64, F, F, P, P]),
         'stda_sinr': (I, [P, P, P, I, I, I, P, P]),
+        'stda_train_step_graph_create': (I, [P, I, P, P, P, P, P, P, P, P, P, SZ, P, SZ, I, I, F, F, P, P,
+                                             P]),
+        'stda_graph_launch': (I, [P, P]),
+        'stda_graph_destroy': (I, [P]),
         'stda_profile_select': (I, [ctypes.c_char_p]),
         'stda_profile_read': (I, [P, P]),
         'stda_profile_report': (I, [P, SZ, P]),
@@ -68,7 +72,8 @@ def _load():
 _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
            'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
-           'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_profile_select',
+           'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
+           'stda_graph_launch', 'stda_graph_destroy', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'rd_synth_workspace_size', 'rd_synth')
 
 
@@ -185,6 +190,39 @@ def sgd_step(w, dw, lr, weight_decay, w_bf16=None):
 def sinr(maps, o_mask, n_mask, out):
     n, H, W = maps.shape[0], maps.shape[-2], maps.shape[-1]
     _check(_lib.stda_sinr(_ptr(maps), _ptr(o_mask), _ptr(n_mask), n, H, W, _ptr(out), _stream()), 'stda_sinr')
+
+
+# ------------------------------------------------------------------------ captured step
+class TrainStepGraph:
+    """One captured training step (forward, loss, backward, SGD) replayed with launch()."""
+
+    def __init__(self, segs, x, y, w, running, z, loss, dz, dw, saved, ws, dtype=FP32, recompute=0, lr=1e-3,
+                 weight_decay=5e-4, w_bf16=None, stream=None):
+        self.stream = stream or torch.cuda.Stream()
+        self._keep = (x, y, w, running, z, loss, dz, dw, saved, ws, w_bf16)
+        arr = _seg_array(segs)
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(_lib.stda_train_step_graph_create(
+                ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(y), _ptr(w), _ptr(running), _ptr(z),
+                _ptr(loss), _ptr(dz), _ptr(dw), _ptr(saved), saved.numel(), _ptr(ws), ws.numel(), dtype, recompute,
+                lr, weight_decay, _ptr(w_bf16), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                'stda_train_step_graph_create')
+        self.handle = h
+
+    def launch(self):
+        _check(_lib.stda_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)), 'stda_graph_launch')
+
+    def close(self):
+        if self.handle:
+            _lib.stda_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------------ timing hook
