@@ -104,6 +104,8 @@ def parse():
     ap.add_argument('--cpu-sample-clips', type=int, default=4)
     ap.add_argument('--train-only', action='store_true', help='only the chosen training workload')
     ap.add_argument('--no-graph', action='store_true', help='time eager steps instead of the captured step')
+    ap.add_argument('--copy-calib', action='store_true',
+                    help='only run a plain 256 MiB device copy 5 times (counter calibration) and exit')
     ap.add_argument('--kernel', default=None, help='tag of the kernel for the roofline (default: the dominant one)')
     return ap.parse_args()
 
@@ -198,8 +200,42 @@ class Trainer:
         return e0.elapsed_time(e1) / steps
 
 
+def source_hash():
+    """SHA-256 over the library sources: a committed counter summary applies only to this hash."""
+    import hashlib
+    d = os.path.join(ROOT, 'paper_2307_09063_amd', 'csrc')
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith(('.h', '.hip')):
+            with open(os.path.join(d, f), 'rb') as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken on different sources."""
+    path = os.path.join(ROOT, 'profiles', 'traffic.json')
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get('source_sha256') != source_hash() or t.get('kernel_tag') != kernel:
+        return None
+    return t.get('hbm_bytes_per_launch')
+
+
 def main():
     args = parse()
+    if args.copy_calib:
+        import torch
+        src = torch.ones(64 << 20, device='cuda')
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({'copy_bytes_read': src.numel() * 4, 'copy_bytes_written': dst.numel() * 4}))
+        return
     if args.gpus != 1:
         print(f'bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is '
               'described, not built', file=sys.stderr)
@@ -246,6 +282,8 @@ def main():
     k_total, k_count = stda.profile_read()
     stda.profile_select(None)
     roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16) if len(groups) == 1 else None
+    if roof is not None:
+        roof['traffic'] = measured_traffic(dominant)
     print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), eager {ms_eager:.3f} ms, wall {wall:.2f}s, '
           f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)
 

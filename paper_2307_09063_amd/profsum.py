@@ -1,0 +1,111 @@
+"""Summaries of rocprofv3 output databases (SQLite, ``-d DIR``).
+
+    python -m paper_2307_09063_amd.profsum trace DIR [--top N]
+        per-kernel dispatch count, total and average duration, VGPRs and LDS of a
+        ``--kernel-trace`` run
+    python -m paper_2307_09063_amd.profsum traffic --fetch DIR --write DIR \
+            --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel NAME --tag TAG [--out FILE]
+        HBM bytes per dispatch of one kernel from a ``--pmc FETCH_SIZE`` run and a
+        ``--pmc WRITE_SIZE`` run, each scaled by the factor that makes the same counter read
+        exactly N bytes for a plain device copy of N bytes (``bench.py --copy-calib``)
+
+The traffic summary carries the SHA-256 of the library sources it was taken on; bench.py
+reports it only while the sources are unchanged."""
+import argparse
+import glob
+import json
+import os
+import re
+import sqlite3
+import sys
+
+
+def _db(d):
+    found = sorted(glob.glob(os.path.join(d, '**', '*.db'), recursive=True))
+    if not found:
+        raise SystemExit(f'no rocprofv3 database under {d}')
+    return sqlite3.connect(found[0])
+
+
+def short_name(name):
+    s = re.sub(r'\(.*', '', name)
+    return s.replace('stda::', '').replace('(anonymous namespace)::', '').strip()
+
+
+def trace_rows(d):
+    con = _db(d)
+    q = ('select name, count(*), sum(duration), avg(duration), max(vgpr_count), max(lds_size) '
+         'from kernels group by name order by sum(duration) desc')
+    return [(short_name(n), c, s, a, v, l) for n, c, s, a, v, l in con.execute(q).fetchall()]
+
+
+def counter_per_dispatch(d, counter, match):
+    """Mean over dispatches of `counter` (KiB) for kernels whose short name equals `match`."""
+    con = _db(d)
+    rows = con.execute('select kernel_name, dispatch_id, value from counters_collection where counter_name = ?',
+                       (counter,)).fetchall()
+    per = {}
+    for name, disp, v in rows:
+        if short_name(name) == match:
+            per[disp] = per.get(disp, 0.0) + v
+    if not per:
+        raise SystemExit(f'{counter}: no dispatch of {match!r} in {d}')
+    return sum(per.values()) / len(per), len(per)
+
+
+def cmd_trace(a):
+    rows = trace_rows(a.dir)
+    tot = sum(r[2] for r in rows)
+    print(f'total kernel time {tot / 1e6:.3f} ms over {sum(r[1] for r in rows)} dispatches')
+    print(f'{"share":>6} {"calls":>6} {"avg_us":>9} {"vgpr":>5} {"lds_B":>6}  kernel')
+    for n, c, s, av, v, l in rows[:a.top]:
+        print(f'{100 * s / tot:5.1f}% {c:6d} {av / 1e3:9.1f} {v:5d} {l:6d}  {n}')
+
+
+def cmd_traffic(a):
+    fetch, nf = counter_per_dispatch(a.fetch, 'FETCH_SIZE', a.kernel)
+    write, nw = counter_per_dispatch(a.write, 'WRITE_SIZE', a.kernel)
+    cf, _ = counter_per_dispatch(a.copy_fetch, 'FETCH_SIZE', a.copy_kernel)
+    cw, _ = counter_per_dispatch(a.copy_write, 'WRITE_SIZE', a.copy_kernel)
+    f_fac = a.copy_bytes / (cf * 1024.0)
+    w_fac = a.copy_bytes / (cw * 1024.0)
+    hbm = fetch * 1024.0 * f_fac + write * 1024.0 * w_fac
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    out = {'kernel_tag': a.tag, 'kernel': a.kernel, 'source_sha256': bench.source_hash(),
+           'fetch_kib_per_dispatch': round(fetch, 1), 'write_kib_per_dispatch': round(write, 1),
+           'dispatches': [nf, nw], 'copy_bytes': a.copy_bytes,
+           'copy_fetch_kib': round(cf, 1), 'copy_write_kib': round(cw, 1),
+           'fetch_factor': round(f_fac, 5), 'write_factor': round(w_fac, 5),
+           'hbm_read_bytes_per_launch': round(fetch * 1024.0 * f_fac),
+           'hbm_write_bytes_per_launch': round(write * 1024.0 * w_fac),
+           'hbm_bytes_per_launch': round(hbm)}
+    text = json.dumps(out, indent=1)
+    if a.out:
+        with open(a.out, 'w') as f:
+            f.write(text + '\n')
+    print(text)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog='profsum')
+    sub = ap.add_subparsers(dest='cmd', required=True)
+    t = sub.add_parser('trace')
+    t.add_argument('dir')
+    t.add_argument('--top', type=int, default=40)
+    t.set_defaults(fn=cmd_trace)
+    r = sub.add_parser('traffic')
+    for k in ('fetch', 'write', 'copy_fetch', 'copy_write'):
+        r.add_argument('--' + k.replace('_', '-'), dest=k, required=True)
+    r.add_argument('--copy-bytes', type=int, required=True)
+    r.add_argument('--copy-kernel', default='__amd_rocclr_copyBuffer')
+    r.add_argument('--kernel', required=True, help='short kernel name as the trace summary prints it')
+    r.add_argument('--tag', required=True, help='the profiling tag bench.py uses for that kernel')
+    r.add_argument('--out', default=None)
+    r.set_defaults(fn=cmd_traffic)
+    a = ap.parse_args(argv)
+    a.fn(a)
+
+
+if __name__ == '__main__':
+    main()
