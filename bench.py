@@ -212,15 +212,16 @@ def source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    summary is missing or was taken on different sources."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` in `workload` from the committed counter summary, or
+    None when the summary is missing, covers another kernel or workload, or was taken on
+    different sources."""
     path = os.path.join(ROOT, 'profiles', 'traffic.json')
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get('source_sha256') != source_hash() or t.get('kernel_tag') != kernel:
+    if t.get('source_sha256') != source_hash() or t.get('kernel_tag') != kernel or t.get('workload') != workload:
         return None
     return t.get('hbm_bytes_per_launch')
 
@@ -283,7 +284,7 @@ def main():
     stda.profile_select(None)
     roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16) if len(groups) == 1 else None
     if roof is not None:
-        roof['traffic'] = measured_traffic(dominant)
+        roof['traffic'] = measured_traffic(dominant, args.workload)
     print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), eager {ms_eager:.3f} ms, wall {wall:.2f}s, '
           f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)
 

@@ -4,7 +4,7 @@
         per-kernel dispatch count, total and average duration, VGPRs and LDS of a
         ``--kernel-trace`` run
     python -m paper_2307_09063_amd.profsum traffic --fetch DIR --write DIR \
-            --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel NAME --tag TAG [--out FILE]
+            --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel NAME --tag TAG --workload NAME [--out FILE]
         HBM bytes per dispatch of one kernel from a ``--pmc FETCH_SIZE`` run and a
         ``--pmc WRITE_SIZE`` run, each scaled by the factor that makes the same counter read
         exactly N bytes for a plain device copy of N bytes (``bench.py --copy-calib``)
@@ -72,7 +72,7 @@ def cmd_traffic(a):
     hbm = fetch * 1024.0 * f_fac + write * 1024.0 * w_fac
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    out = {'kernel_tag': a.tag, 'kernel': a.kernel, 'source_sha256': bench.source_hash(),
+    out = {'kernel_tag': a.tag, 'workload': a.workload, 'kernel': a.kernel, 'source_sha256': bench.source_hash(),
            'fetch_kib_per_dispatch': round(fetch, 1), 'write_kib_per_dispatch': round(write, 1),
            'dispatches': [nf, nw], 'copy_bytes': a.copy_bytes,
            'copy_fetch_kib': round(cf, 1), 'copy_write_kib': round(cw, 1),
@@ -101,6 +101,7 @@ def main(argv=None):
     r.add_argument('--copy-kernel', default='__amd_rocclr_copyBuffer')
     r.add_argument('--kernel', required=True, help='short kernel name as the trace summary prints it')
     r.add_argument('--tag', required=True, help='the profiling tag bench.py uses for that kernel')
+    r.add_argument('--workload', required=True, help='bench.py workload the counters were taken on')
     r.add_argument('--out', default=None)
     r.set_defaults(fn=cmd_traffic)
     a = ap.parse_args(argv)
