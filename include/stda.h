@@ -176,6 +176,34 @@ int stda_profile_read(double* total_ms /*host out*/, int* count /*host out*/);
  */
 int stda_profile_report(char* buf /*host out*/, size_t cap, size_t* needed /*host out*/);
 
+/* ------------------------------------------------------------------ tile-shape autotuning
+ * The stage-2 dense layers (Conv3x3-s2 / DeConv4x4-s2 and their input gradients) have several
+ * tilings each.  A tunable launch is (kind, dtype, block): kind 0 = stage-2 forward (main and
+ * residual convolution), 1 = stage-2 input gradient (both); block 0..3 = encoder 0, encoder 1,
+ * decoder 0, decoder 1.  The choice is process-wide and read when a launch is enqueued (a
+ * captured graph keeps the choice it was captured with).
+ */
+int stda_tune_count(int kind);  /* number of variants of `kind`, or a negative status */
+int stda_tune_set(int kind, int dtype, int block, int variant);
+int stda_tune_get(int kind, int dtype, int block, int* variant /*host out*/);
+
+/*
+ * Autotuner: for every variant v, sets all tunable launches of `dtype` to v, runs one untimed
+ * training forward + loss + backward on the given buffers and then `reps` timed ones (HIP events
+ * around each tunable launch), and finally sets every tunable launch to its fastest variant.
+ * Arguments are those of stda_forward / stda_mse_loss / stda_backward; `running` is updated by
+ * every trial step (pass a scratch copy), w is not modified, z / loss / dz / dw are overwritten.
+ * The per-variant times and the choice are written as text lines
+ * "kind<TAB>block<TAB>ms_v0<TAB>ms_v1...<TAB>chosen" into host `report` (NUL-terminated,
+ * truncated to cap; may be NULL) and the size needed into *needed (may be NULL).  Blocks the
+ * host until the trials are done.  The per-kernel timing hook must be off.
+ */
+int stda_autotune(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* y,
+                  const float* w, float* running, float* z, double* loss_dev, float* dz, float* dw,
+                  void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, int dtype,
+                  int recompute, int reps, hipStream_t stream, char* report /*host out*/,
+                  size_t cap, size_t* needed /*host out*/);
+
 /* ------------------------------------------------------------------ RD-map synthesizer */
 #define RD_MAX_TONES 48
 #define RD_MAX_INTF 4

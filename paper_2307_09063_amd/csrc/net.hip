@@ -19,6 +19,7 @@
 #include "net_bwd_kernels.h"
 #include "net_kernels.h"
 #include "plan.h"
+#include "s2_tile.h"
 #include "stage1_tile.h"
 #include "stem_tile.h"
 
@@ -404,20 +405,85 @@ int tiles_for(int64_t hw, int G) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
 }
 
-// Dense stride-2 layer on the matrix cores; returns the number of blocks (partials rows).
+// Tiling variant of each dense stage-2 launch, [dtype][0 forward, 1 input gradient][block]:
+// 0..2 the LDS-tiled kernel with the tilings listed in launch_s2_variant, 3 the register-gather
+// kernel.  Set by stda_tune_set (the autotuner); 0 by default.
+constexpr int kS2Variants = 4;
+int g_s2_variant[2][2][4] = {};
+
+template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
+int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
+                  int hd, int wd, int* nblk) {
+  typedef S2Cfg<T, OP, K, N, NB, TH, TW> C;
+  const int64_t ntiles = (int64_t)n * ((hd + TH - 1) / TH) * ((wd + TW - 1) / TW);
+  const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / C::LDS_BYTES);
+  int64_t gx = std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid));
+  if (gx >= 64) gx &= ~(int64_t)7;  // whole XCD groups: tiles are handed out XCD by XCD
+  gx = std::max<int64_t>(gx, 1);
+  KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS><<<dim3((unsigned)gx, N / NB), 256, 0, c.st>>>(src, frag, dst,
+                                                                                                   part, n, hd, wd));
+  if (nblk) *nblk = (int)gx;
+  return STDA_OK;
+}
+
 template <class T, int OP, int K, int N, bool STATS>
-int launch_dense(const Ctx<T>& c, const std::string& tag, const T* src, int64_t frag_off, T* dst, float* part, int n,
-                 int hd, int wd, int* nblk) {
+int launch_gather(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
+                  int hd, int wd, int* nblk) {
   constexpr int R = 4;
   constexpr bool down = OpGeo<OP>::DOWN;
   const int64_t P = (int64_t)n * (down ? (int64_t)hd * wd : (int64_t)(hd / 2) * (wd / 2));
   const int phases = down ? 1 : 4;
   const int64_t tiles = (P + 64 * R - 1) / (64 * R);
   const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid / phases));
-  const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
   KLAUNCH(tag, k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd));
   if (nblk) *nblk = gx * phases;
   return STDA_OK;
+}
+
+// The candidate tilings (NB output channels per workgroup, TH x TW output pixels) of each
+// operator; all fit the 160 KB of LDS of a gfx950 workgroup (checked at compile time).
+template <class T, int OP, int K, int N, bool STATS>
+int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst,
+                      float* part, int n, int hd, int wd, int* nblk) {
+  constexpr bool BF = sizeof(T) == 2;
+#define S2V(NB_, TH_, TW_) launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk)
+  if (v == 3) return launch_gather<T, OP, K, N, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk);
+  if constexpr (OP == OP_ENC_FWD && K == 16) {
+    if constexpr (BF) return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2V(32, 16, 16) : S2V(32, 8, 32);
+    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 16);
+  } else if constexpr (OP == OP_ENC_FWD) {
+    if constexpr (BF) return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2V(32, 8, 16) : S2V(64, 8, 16);
+    else return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 8);
+  } else if constexpr (OP == OP_DEC_FWD && K == 64) {
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(32, 16, 32) : S2V(32, 16, 16);
+    else return v == 1 ? S2V(16, 32, 16) : v == 2 ? S2V(16, 16, 32) : S2V(16, 16, 16);
+  } else if constexpr (OP == OP_DEC_FWD) {
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 32);
+    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 16);
+  } else if constexpr (OP == OP_ENC_DGRAD && K == 32) {
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 32);
+    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 16);
+  } else if constexpr (OP == OP_ENC_DGRAD) {
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(32, 16, 32) : S2V(32, 16, 16);
+    else return v == 1 ? S2V(32, 16, 16) : v == 2 ? S2V(16, 16, 32) : S2V(16, 16, 16);
+  } else if constexpr (OP == OP_DEC_DGRAD && K == 32) {
+    if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(32, 8, 16) : S2V(64, 8, 8);
+    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(16, 8, 8);
+  } else {
+    if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(32, 16, 16) : S2V(32, 8, 16);
+    else return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 8);
+  }
+#undef S2V
+}
+
+// Dense stride-2 layer of block `blk` on the matrix cores; *nblk = rows of BN partials written.
+template <class T, int OP, int K, int N, bool STATS>
+int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const T* src, int64_t frag_off, T* dst,
+                 float* part, int n, int hd, int wd, int* nblk) {
+  const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
+  const bool dgrad = OP == OP_ENC_DGRAD || OP == OP_DEC_DGRAD;
+  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][dgrad ? 1 : 0][blk];
+  return launch_s2_variant<T, OP, K, N, STATS>(v, c, tag, src, frag, dst, part, n, hd, wd, nblk);
 }
 
 // Blocks of the tiled stage-1 kernels: one per tile, at most kMaxGrid (they loop over tiles).
@@ -493,17 +559,17 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   (void)g2;
   if (stats_pass) {
     int nb = 0;
-    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
+    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
       return r;
     float* so[1] = {c.stats(bo.bn_main)};
     float* ro[1] = {running + bo.bn_main};
     if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro, running)) return r;
   } else {
-    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
                                                        nullptr))
       return r;
   }
-  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
     return r;
   // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
   const int hw = hout * wout;
@@ -745,9 +811,9 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
   const int gd = grid_for(Pin * (CIN / 4));
   (void)gd;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
     return r;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
     return r;
   // dense weight gradients
   if (DEC) {
@@ -999,6 +1065,106 @@ int stda_profile_read(double* total_ms, int* count) {
   }
   *total_ms = tot;
   *count = (int)(p.used / 2);
+  return STDA_OK;
+}
+
+int stda_tune_count(int kind) { return (kind == 0 || kind == 1) ? kS2Variants : STDA_E_INVALID; }
+
+int stda_tune_set(int kind, int dtype, int block, int variant) {
+  if ((kind != 0 && kind != 1) || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
+      variant < 0 || variant >= kS2Variants)
+    return STDA_E_INVALID;
+  g_s2_variant[dtype][kind][block] = variant;
+  return STDA_OK;
+}
+
+int stda_tune_get(int kind, int dtype, int block, int* variant) {
+  if ((kind != 0 && kind != 1) || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 || !variant)
+    return STDA_E_INVALID;
+  *variant = g_s2_variant[dtype][kind][block];
+  return STDA_OK;
+}
+
+int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const float* y, const float* w,
+                  float* running, float* z, double* loss_dev, float* dz, float* dw, void* saved, size_t saved_bytes,
+                  void* ws, size_t ws_bytes, int dtype, int recompute, int reps, hipStream_t stream, char* report,
+                  size_t cap, size_t* needed) {
+  if (dtype != STDA_FP32 && dtype != STDA_BF16) return STDA_E_INVALID;
+  if (reps < 1) reps = 1;
+  {
+    Prof& p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (p.on) return STDA_E_INVALID;
+  }
+  auto step = [&]() -> int {
+    int r = stda_forward(segs, n_segs, x, w, running, z, saved, saved_bytes, ws, ws_bytes, dtype, STDA_TRAIN,
+                         recompute, stream);
+    if (!r) r = stda_mse_loss(segs, n_segs, z, y, loss_dev, dz, ws, ws_bytes, stream);
+    if (!r)
+      r = stda_backward(segs, n_segs, x, dz, w, saved, saved_bytes, dw, nullptr, ws, ws_bytes, dtype, recompute,
+                        stream);
+    return r;
+  };
+  int saved_choice[2][4];
+  std::memcpy(saved_choice, g_s2_variant[dtype], sizeof(saved_choice));
+  double cost[2][4][kS2Variants] = {};
+  for (int v = 0; v < kS2Variants; ++v) {
+    for (int kind = 0; kind < 2; ++kind)
+      for (int b = 0; b < 4; ++b) g_s2_variant[dtype][kind][b] = v;
+    int r = step();  // untimed
+    if (!r) {
+      stda_profile_select("*");
+      for (int i = 0; i < reps && !r; ++i) r = step();
+    }
+    if (r) {
+      stda_profile_select(nullptr);
+      std::memcpy(g_s2_variant[dtype], saved_choice, sizeof(saved_choice));
+      return r;
+    }
+    Prof& p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    for (size_t i = 0; i + 1 < p.used; i += 2) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(p.ev[i + 1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]);
+      if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        p.on = false;
+        p.tag.clear();
+        p.used = 0;
+        std::memcpy(g_s2_variant[dtype], saved_choice, sizeof(saved_choice));
+        return STDA_E_HIP;
+      }
+      const std::string& t = p.evtag[i / 2];
+      const int kind = t.rfind("dense_fwd_", 0) == 0 ? 0 : t.rfind("dense_dgrad_", 0) == 0 ? 1 : -1;
+      if (kind < 0) continue;
+      for (int b = 0; b < 4; ++b)
+        if (t.size() > 5 && t.compare(t.size() - 4, 4, kBlockName[b]) == 0) cost[kind][b][v] += ms;
+    }
+    p.on = false;
+    p.tag.clear();
+    p.used = 0;
+  }
+  std::string out;
+  char line[256];
+  for (int kind = 0; kind < 2; ++kind)
+    for (int b = 0; b < 4; ++b) {
+      int best = 0;
+      for (int v = 1; v < kS2Variants; ++v)
+        if (cost[kind][b][v] < cost[kind][b][best]) best = v;
+      g_s2_variant[dtype][kind][b] = best;
+      int n = std::snprintf(line, sizeof(line), "%d\t%d", kind, b);
+      for (int v = 0; v < kS2Variants; ++v)
+        n += std::snprintf(line + n, sizeof(line) - n, "\t%.4f", cost[kind][b][v] / reps);
+      std::snprintf(line + n, sizeof(line) - n, "\t%d\n", best);
+      out += line;
+    }
+  if (needed) *needed = out.size() + 1;
+  if (report && cap > 0) {
+    const size_t k = std::min(cap - 1, out.size());
+    std::memcpy(report, out.data(), k);
+    report[k] = '\0';
+  }
   return STDA_OK;
 }
 

@@ -59,6 +59,10 @@ def _load():
         'stda_profile_select': (I, [ctypes.c_char_p]),
         'stda_profile_read': (I, [P, P]),
         'stda_profile_report': (I, [P, SZ, P]),
+        'stda_tune_count': (I, [I]),
+        'stda_tune_set': (I, [I, I, I, I]),
+        'stda_tune_get': (I, [I, I, I, P]),
+        'stda_autotune': (I, [P, I, P, P, P, P, P, P, P, P, P, SZ, P, SZ, I, I, I, P, P, SZ, P]),
         'rd_synth_workspace_size': (SZ, [I, I, I]),
         'rd_synth': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
     }
@@ -74,7 +78,8 @@ EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'std
            'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_profile_select',
-           'stda_profile_read', 'stda_profile_report', 'rd_synth_workspace_size', 'rd_synth')
+           'stda_profile_read', 'stda_profile_report', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
+           'stda_autotune', 'rd_synth_workspace_size', 'rd_synth')
 
 
 def _check(status, what):
@@ -246,6 +251,48 @@ def profile_report():
     for line in buf.value.decode().splitlines():
         tag, n, ms = line.split('\t')
         out[tag] = (int(n), float(ms))
+    return out
+
+
+# ------------------------------------------------------------------------ tile-shape autotuning
+TUNE_FWD, TUNE_DGRAD = 0, 1
+
+
+def tune_count(kind):
+    n = _lib.stda_tune_count(kind)
+    if n < 0:
+        _check(n, 'stda_tune_count')
+    return n
+
+
+def tune_set(kind, dtype, block, variant):
+    _check(_lib.stda_tune_set(kind, dtype, block, variant), 'stda_tune_set')
+
+
+def tune_get(kind, dtype, block):
+    v = ctypes.c_int(0)
+    _check(_lib.stda_tune_get(kind, dtype, block, ctypes.byref(v)), 'stda_tune_get')
+    return v.value
+
+
+def tune_table(dtype):
+    """{(kind, block): variant} currently in force for `dtype`."""
+    return {(k, b): tune_get(k, dtype, b) for k in (TUNE_FWD, TUNE_DGRAD) for b in range(4)}
+
+
+def autotune(segs, x, y, w, running, z, loss, dz, dw, saved, ws, dtype=FP32, recompute=0, reps=3):
+    """Run the library's autotuner on these buffers (running is updated by the trial steps; w is
+    not).  Returns {(kind, block): (chosen variant, [ms per variant])}; the choice is in force."""
+    arr = _seg_array(segs)
+    need = ctypes.c_size_t(0)
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.stda_autotune(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(y), _ptr(w), _ptr(running),
+                              _ptr(z), _ptr(loss), _ptr(dz), _ptr(dw), _ptr(saved), saved.numel(), _ptr(ws), ws.numel(),
+                              dtype, recompute, reps, _stream(), buf, len(buf), ctypes.byref(need)), 'stda_autotune')
+    out = {}
+    for line in buf.value.decode().splitlines():
+        f = line.split('\t')
+        out[(int(f[0]), int(f[1]))] = (int(f[-1]), [float(v) for v in f[2:-1]])
     return out
 
 

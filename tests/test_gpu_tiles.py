@@ -1,0 +1,135 @@
+"""The tiling variants of the stage-2 dense layers (the autotuner's candidates), through the C ABI.
+
+* EVAL forward: every variant gives bit-identical z (each output element sums its taps and
+  channels in the same order whatever the tiling), on shapes whose maps leave ragged tiles at
+  every level.
+* FP32 TRAIN forward + backward of every variant against the FP64 oracle (inputs screened for
+  ReLU decisions within 1e-5 of their kink, as in the other FP32 parity tests).
+* BF16 TRAIN forward of every variant against the oracle at the BF16 gate.
+* The autotuner: its choice is one of the candidates, it leaves the master weights untouched,
+  and the network still matches the oracle afterwards."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import net
+from tests import gpu_util as U
+
+pytestmark = pytest.mark.gpu
+SHAPES = [(2, 40, 36), (1, 72, 88)]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture()
+def S():
+    from paper_2307_09063_amd import stda
+    yield stda
+    for dt in (stda.FP32, stda.BF16):
+        for kind in (stda.TUNE_FWD, stda.TUNE_DGRAD):
+            for b in range(4):
+                stda.tune_set(kind, dt, b, 0)
+
+
+def _set_all(S, dtype, v):
+    for kind in (S.TUNE_FWD, S.TUNE_DGRAD):
+        for b in range(4):
+            S.tune_set(kind, dtype, b, v)
+
+
+def _forward(S, x, w, r, mode, dtype):
+    B, _, H, W = x.shape
+    segs = S.uniform_segments(B, H, W)
+    sv, wsb = S.workspace_size(segs, dtype, mode)
+    saved = S.alloc_bytes(sv) if mode == S.TRAIN else None
+    ws = S.alloc_bytes(wsb)
+    xd, wd, rd = U.dev(x), U.dev(w), U.dev(r.copy())
+    z = torch.empty((B, 1, H, W), device='cuda')
+    S.forward(segs, xd, wd, rd, z, saved, ws, dtype, mode)
+    torch.cuda.synchronize()
+    return z, rd, (segs, xd, wd, saved, ws)
+
+
+@pytest.mark.parametrize('dtype', [0, 1], ids=['fp32', 'bf16'])
+@pytest.mark.parametrize('shape', SHAPES)
+def test_variants_eval_bitwise(S, dtype, shape):
+    B, H, W = shape
+    x, _ = U.maps(B, H, W, seed=H + W)
+    w, r = U.weights(), U.running()
+    outs = []
+    for v in range(S.tune_count(S.TUNE_FWD)):
+        _say('variant eval', dtype, shape, v)
+        _set_all(S, dtype, v)
+        z, _, _ = _forward(S, x, w, r, S.EVAL, dtype)
+        outs.append(z.cpu().numpy())
+    for v in range(1, len(outs)):
+        np.testing.assert_array_equal(outs[v], outs[0])
+    zr, _, _ = net.forward(w, r, x, 'eval')
+    assert U.rel_l2(outs[0], zr) < (1e-4 if dtype == 0 else 2e-2)
+
+
+@pytest.mark.parametrize('v', [0, 1, 2, 3])
+def test_variant_fp32_train_backward(S, v):
+    B, H, W = SHAPES[0]
+    _say('variant train fp32', v)
+    _set_all(S, S.FP32, v)
+    w, r = U.weights(), U.running()
+    x, _ = U.unambiguous(lambda s: U.maps(B, H, W, seed=s), w, r, 77)
+    z, rd, (segs, xd, wd, saved, ws) = _forward(S, x, w, r, S.TRAIN, S.FP32)
+    zr, rr, cache = net.forward(w, r, x, 'train')
+    assert U.rel_l2(z.cpu().numpy(), zr) < 1e-4
+    assert U.rel_l2(rd.cpu().numpy(), rr) < 1e-4
+    g = np.random.default_rng(v).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
+    dw = torch.full((net.param_count(),), float('nan'), device='cuda')
+    dx = torch.empty_like(xd)
+    S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws)
+    torch.cuda.synchronize()
+    gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
+    errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
+    bad = {k: e for k, e in errs.items() if not e < 1e-4}
+    assert not bad, bad
+    assert U.rel_l2(dx.cpu().numpy(), dxr) < 1e-4
+
+
+@pytest.mark.parametrize('v', [0, 1, 2, 3])
+def test_variant_bf16_train_forward(S, v):
+    B, H, W = SHAPES[1]
+    _say('variant train bf16', v)
+    _set_all(S, S.BF16, v)
+    x, _ = U.maps(B, H, W, seed=5)
+    w, r = U.weights(), U.running()
+    z, rd, _ = _forward(S, x, w, r, S.TRAIN, S.BF16)
+    zr, rr, _ = net.forward(w, r, x, 'train')
+    assert U.rel_l2(z.cpu().numpy(), zr) < 2e-2
+    assert U.rel_l2(rd.cpu().numpy(), rr) < 2e-2
+
+
+@pytest.mark.parametrize('dtype', [0, 1], ids=['fp32', 'bf16'])
+def test_autotune(S, dtype):
+    B, H, W = 2, 32, 24
+    _say('autotune', dtype)
+    w0, r = U.weights(), U.running()
+    x, y = U.maps(B, H, W, seed=9)
+    segs = S.uniform_segments(B, H, W)
+    sv, wsb = S.workspace_size(segs, dtype, S.TRAIN)
+    saved, ws = S.alloc_bytes(sv), S.alloc_bytes(wsb)
+    xd, yd, wd, rs = U.dev(x), U.dev(y), U.dev(w0), U.dev(r.copy())
+    z = torch.empty((B, 1, H, W), device='cuda')
+    loss = torch.zeros(1, dtype=torch.float64, device='cuda')
+    dz, dw = torch.empty_like(z), torch.empty(net.param_count(), device='cuda')
+    res = S.autotune(segs, xd, yd, wd, rs, z, loss, dz, dw, saved, ws, dtype, reps=2)
+    torch.cuda.synchronize()
+    n = S.tune_count(S.TUNE_FWD)
+    assert sorted(res) == [(k, b) for k in (0, 1) for b in range(4)]
+    for (kind, b), (choice, ms) in res.items():
+        assert 0 <= choice < n and len(ms) == n and all(t > 0 for t in ms)
+        assert ms[choice] == min(ms)
+        assert S.tune_get(kind, dtype, b) == choice
+    np.testing.assert_array_equal(wd.cpu().numpy(), w0)
+    zt, _, _ = _forward(S, x, w0, r, S.EVAL, dtype)
+    zr, _, _ = net.forward(w0, r, x, 'eval')
+    assert U.rel_l2(zt.cpu().numpy(), zr) < (1e-4 if dtype == 0 else 2e-2)
