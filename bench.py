@@ -106,6 +106,7 @@ def parse():
     ap.add_argument('--no-graph', action='store_true', help='time eager steps instead of the captured step')
     ap.add_argument('--copy-calib', action='store_true',
                     help='only run a plain 256 MiB device copy 5 times (counter calibration) and exit')
+    ap.add_argument('--no-tune', action='store_true', help='keep the default tilings (skip the autotuner)')
     ap.add_argument('--kernel', default=None, help='tag of the kernel for the roofline (default: the dominant one)')
     return ap.parse_args()
 
@@ -175,6 +176,16 @@ class Trainer:
         s.backward(self.segs, self.x, self.dz, self.w, self.saved, self.dw, None, self.ws, self.dtype,
                    self.recompute)
         s.sgd_step(self.w, self.dw, 1e-3, 5e-4, self.wb)
+
+    def autotune(self, reps=2):
+        """The library's autotuner on this workload's buffers (running statistics on a scratch copy);
+        returns the chosen tiling variant of every tunable launch."""
+        scratch = self.running.clone()
+        res = self.stda.autotune(self.segs, self.x, self.y, self.w, scratch, self.z, self.loss, self.dz, self.dw,
+                                 self.saved, self.ws, self.dtype, self.recompute, reps)
+        self.torch.cuda.synchronize()
+        names = {0: 'fwd', 1: 'dgrad', 2: 'wgrad'}
+        return {f'{names[k]}.{("enc0", "enc1", "dec0", "dec1")[b]}': v[0] for (k, b), v in sorted(res.items())}
 
     def capture(self):
         self.torch.cuda.synchronize()
@@ -253,6 +264,9 @@ def main():
     B = sum(g[0] for g in groups)
     N, M = groups[0][1], groups[0][2]
     tr = Trainer(stda, inputs, torch, segs, x, y, dtype, recompute, dev)
+    tiles = None if args.no_tune else tr.autotune()
+    if tiles:
+        print(f'bench: autotuned tilings {tiles}', file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         tr.step()
     torch.cuda.synchronize()
@@ -301,13 +315,14 @@ def main():
             rn, dn, rec = WORKLOADS[other]
             sg, gr, xo, yo, _ = make_batch(stda, inputs, torch, rn, dev)
             t2 = Trainer(stda, inputs, torch, sg, xo, yo, stda.BF16 if dn == 'bf16' else stda.FP32, rec, dev)
+            tiles2 = None if args.no_tune else t2.autotune()
             t2.step()
             t2.capture()
             t2.timed(2, True)
             m2 = t2.timed(max(3, args.steps // 2), True)
             n2 = sum(g[0] for g in gr)
             extra[other] = {'ms_per_step': round(m2, 4), 'clips_per_s': round(n2 / (m2 / 1e3), 1), 'dtype': dn,
-                            'recompute': rec, 'segments': [list(g) for g in gr]}
+                            'recompute': rec, 'segments': [list(g) for g in gr], 'tiles': tiles2}
             print(f'bench: {other}: {m2:.3f} ms/step ({n2 / (m2 / 1e3):.0f} clips/s)', file=sys.stderr, flush=True)
             t2.graph.close()
             del t2, xo, yo
@@ -335,7 +350,7 @@ def main():
         'data': 'synthetic (seeded FMCW scenes -> rd_synth on the GPU)',
         'config': {'workload': args.workload, 'clips': B, 'frames': 3, 'segments': [list(g) for g in groups],
                    'step': 'TRAIN forward + MSE + backward + SGD', 'recompute': recompute,
-                   'launch': 'one hipGraph launch per step' if use_graph else 'eager'},
+                   'launch': 'one hipGraph launch per step' if use_graph else 'eager', 'tiles': tiles},
         'ms_per_step_eager': round(ms_eager, 4),
         'rd_synth_ms': round(rd_ms, 4),
         'roofline': roof,

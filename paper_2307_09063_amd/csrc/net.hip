@@ -405,11 +405,13 @@ int tiles_for(int64_t hw, int G) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
 }
 
-// Tiling variant of each dense stage-2 launch, [dtype][0 forward, 1 input gradient][block]:
-// 0..2 the LDS-tiled kernel with the tilings listed in launch_s2_variant, 3 the register-gather
-// kernel.  Set by stda_tune_set (the autotuner); 0 by default.
+// Tiling variant of each dense stage-2 launch, [dtype][0 forward, 1 input gradient, 2 weight
+// gradient][block]: 0..2 the LDS-tiled kernels with the tilings listed in launch_s2_variant and
+// launch_wgrad_variant, 3 the register-gather kernels.  Set by stda_tune_set (the autotuner); 0 by
+// default.
 constexpr int kS2Variants = 4;
-int g_s2_variant[2][2][4] = {};
+constexpr int kTuneKinds = 3;
+int g_s2_variant[2][kTuneKinds][4] = {};
 
 template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
 int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
@@ -723,8 +725,9 @@ int forward_all(const Plan& P, const float* x, const float* w, float* running, f
 namespace {
 
 template <class T>
-int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc) {
-  KLAUNCH("colsum", k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
+int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc,
+              const std::string& tag = "colsum") {
+  KLAUNCH(tag, k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
   return STDA_OK;
 }
 
@@ -753,7 +756,50 @@ int run_wgrad(const Ctx<T>& c, const std::string& tag, const L& ld, int64_t npix
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, steps / 64));  // >= 16 steps per wave
   splits = std::min<int64_t>(splits, kMaxWgradGrid);
   KLAUNCH(tag, k_wgrad_mfma<L, BF, TK, TN><<<dim3(KB * NB, (int)splits), 256, 0, c.st>>>(ld, wpart));
-  return colsum_to(c, wpart, (int)splits, L::K * L::N, dst, map, acc);
+  return colsum_to(c, wpart, (int)splits, L::K * L::N, dst, map, acc,
+                   tag.rfind("wgrad_", 0) == 0 ? "wgrad_sum" + tag.substr(5) : std::string("colsum"));
+}
+
+// Stage-2 weight gradient of block `blk` on LDS tiles (or, variant 3, the register-gather
+// kernel); encoder: Lo = output gradient on the hout x wout grid, Hi = layer input; decoder:
+// Lo = layer input on the hin x win grid, Hi = output gradient.
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const T* lo, const T* hi, int n, int h, int w,
+                     float* dst, ColMap map, int acc) {
+  typedef WgCfg<T, DEC, CL, CH, TH, TW> Cfg;
+  const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
+  int64_t gx = std::min<int64_t>(ntiles, cols <= 8192 ? kMaxWgradGrid : kMaxWgradGrid / 2);
+  if (gx >= 64) gx &= ~(int64_t)7;
+  gx = std::max<int64_t>(gx, 1);
+  float* wpart = c.template scr<float>(c.P->ws_wpart);
+  KLAUNCH(tag, k_s2_wgrad<T, DEC, CL, CH, TH, TW><<<(unsigned)gx, 256, 0, c.st>>>(lo, hi, wpart, n, h, w));
+  return colsum_to(c, wpart, (int)gx, (int)cols, dst, map, acc, "wgrad_sum" + tag.substr(5));
+}
+
+template <class T, bool DEC, int CIN, int COUT>
+int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, const T* d, int n, int hin, int win,
+                 float* dst, int acc) {
+  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][2][blk];
+  constexpr int CL = DEC ? CIN : COUT, CH = DEC ? COUT : CIN;
+  const T* lo = DEC ? x : d;
+  const T* hi = DEC ? d : x;
+  const int h = DEC ? hin : hin / 2, w = DEC ? win : win / 2;
+  const ColMap map{DEC ? MAP_DEC_S2 : MAP_ENC_S2, CIN, COUT};
+  constexpr bool SMALL = CL * CH <= 512;  // 16 x 32 channel pairs: larger tiles fit
+#define WGV(TH_, TW_) launch_wgrad_cfg<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
+  if (v == 3) {
+    if constexpr (DEC) {
+      WgDecS2<T, CIN, COUT> ld{x, d, n, hin, win};
+      return run_wgrad(c, tag, ld, (int64_t)n * hin * win, dst, map, acc);
+    } else {
+      WgEncS2<T, CIN, COUT> ld{x, d, n, hin / 2, win / 2};
+      return run_wgrad(c, tag, ld, (int64_t)n * (hin / 2) * (win / 2), dst, map, acc);
+    }
+  }
+  if constexpr (SMALL) return v == 1 ? WGV(8, 8) : v == 2 ? WGV(16, 16) : WGV(8, 16);
+  else return v == 1 ? WGV(4, 16) : v == 2 ? WGV(8, 16) : WGV(8, 8);
+#undef WGV
 }
 
 template <class T>
@@ -816,17 +862,10 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
     return r;
   // dense weight gradients
-  if (DEC) {
-    WgDecS2<T, CIN, COUT> lm{X1, dT, n, hin, win};
-    if (int r = run_wgrad(c, tagk("wgrad_main", k), lm, Pin, dw + bo.main_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
-    WgDecS2<T, CIN, COUT> lr{X, dY, n, hin, win};
-    if (int r = run_wgrad(c, tagk("wgrad_res", k), lr, Pin, dw + bo.res_w, ColMap{MAP_DEC_S2, CIN, COUT}, acc)) return r;
-  } else {
-    WgEncS2<T, CIN, COUT> lm{X1, dT, n, hout, wout};
-    if (int r = run_wgrad(c, tagk("wgrad_main", k), lm, Pout, dw + bo.main_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
-    WgEncS2<T, CIN, COUT> lr{X, dY, n, hout, wout};
-    if (int r = run_wgrad(c, tagk("wgrad_res", k), lr, Pout, dw + bo.res_w, ColMap{MAP_ENC_S2, CIN, COUT}, acc)) return r;
-  }
+  if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_main", k), X1, dT, n, hin, win, dw + bo.main_w, acc))
+    return r;
+  if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_res", k), X, dY, n, hin, win, dw + bo.res_w, acc))
+    return r;
   // stage 1
   S1Params sp{};
   sp.wpw = c.w + bo.pw_w;
@@ -1068,10 +1107,10 @@ int stda_profile_read(double* total_ms, int* count) {
   return STDA_OK;
 }
 
-int stda_tune_count(int kind) { return (kind == 0 || kind == 1) ? kS2Variants : STDA_E_INVALID; }
+int stda_tune_count(int kind) { return (kind >= 0 && kind < kTuneKinds) ? kS2Variants : STDA_E_INVALID; }
 
 int stda_tune_set(int kind, int dtype, int block, int variant) {
-  if ((kind != 0 && kind != 1) || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
+  if (kind < 0 || kind >= kTuneKinds || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
       variant < 0 || variant >= kS2Variants)
     return STDA_E_INVALID;
   g_s2_variant[dtype][kind][block] = variant;
@@ -1079,7 +1118,8 @@ int stda_tune_set(int kind, int dtype, int block, int variant) {
 }
 
 int stda_tune_get(int kind, int dtype, int block, int* variant) {
-  if ((kind != 0 && kind != 1) || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 || !variant)
+  if (kind < 0 || kind >= kTuneKinds || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
+      !variant)
     return STDA_E_INVALID;
   *variant = g_s2_variant[dtype][kind][block];
   return STDA_OK;
@@ -1105,11 +1145,11 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
                         stream);
     return r;
   };
-  int saved_choice[2][4];
+  int saved_choice[kTuneKinds][4];
   std::memcpy(saved_choice, g_s2_variant[dtype], sizeof(saved_choice));
-  double cost[2][4][kS2Variants] = {};
+  double cost[kTuneKinds][4][kS2Variants] = {};
   for (int v = 0; v < kS2Variants; ++v) {
-    for (int kind = 0; kind < 2; ++kind)
+    for (int kind = 0; kind < kTuneKinds; ++kind)
       for (int b = 0; b < 4; ++b) g_s2_variant[dtype][kind][b] = v;
     int r = step();  // untimed
     if (!r) {
@@ -1136,7 +1176,10 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
         return STDA_E_HIP;
       }
       const std::string& t = p.evtag[i / 2];
-      const int kind = t.rfind("dense_fwd_", 0) == 0 ? 0 : t.rfind("dense_dgrad_", 0) == 0 ? 1 : -1;
+      const int kind = t.rfind("dense_fwd_", 0) == 0     ? 0
+                       : t.rfind("dense_dgrad_", 0) == 0 ? 1
+                       : t.rfind("wgrad_", 0) == 0       ? 2
+                                                         : -1;
       if (kind < 0) continue;
       for (int b = 0; b < 4; ++b)
         if (t.size() > 5 && t.compare(t.size() - 4, 4, kBlockName[b]) == 0) cost[kind][b][v] += ms;
@@ -1147,7 +1190,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
   }
   std::string out;
   char line[256];
-  for (int kind = 0; kind < 2; ++kind)
+  for (int kind = 0; kind < kTuneKinds; ++kind)
     for (int b = 0; b < 4; ++b) {
       int best = 0;
       for (int v = 1; v < kS2Variants; ++v)

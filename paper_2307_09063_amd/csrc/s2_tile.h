@@ -257,3 +257,170 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
 }
 
 }  // namespace stda
+
+namespace stda {
+
+// Weight gradients of the stage-2 dense layers on LDS tiles.
+//
+//   R[tap][ch][cl] = sum over low-resolution pixels (b, y, x) of
+//                    Hi(b, 2y - 1 + ky, 2x - 1 + kx)[ch] * Lo(b, y, x)[cl],   tap = ky * KS + kx
+//
+// Conv3x3-s2 (encoder): Lo = output gradient (cl = o), Hi = layer input (ch = c), KS = 3.
+// DeConv4x4-s2 (decoder): Lo = layer input (cl = c), Hi = output gradient (ch = o), KS = 4.
+// A workgroup walks TH x TW low-resolution tiles (XCD-contiguous ranges, as the forward does) and
+// stages, as FP32, Lo transposed to [cl][pixel] and the Hi rectangle of the tile split into its
+// four parity planes [py][px][ch][Y][X], so that tap (ky, kx) reads plane (ky & 1, kx & 1) at
+// (y + ky / 2, x + kx / 2): a unit-stride window.  The reduction over pixels is the MFMA's inner
+// dimension: lane group g takes 4 consecutive pixels of a row (one 16-byte read of Lo; the Hi
+// window is read as 4 scalars since the tap shift breaks 16-byte alignment).  FP32:
+// v_mfma_f32_16x16x4f32, the 4 pixels feeding 4 MFMAs; BF16: v_mfma_f32_16x16x16bf16_1k with
+// lane group g supplying pixels 4g .. 4g + 3 of 16 (values are BF16-exact, so truncating the
+// staged FP32 packs them exactly).  Wave w owns the (tap, 16-channel ch tile) pairs w, w + 4, ...
+// with all cl tiles, accumulating across its tiles; the result is written once per workgroup as
+// part[blk][k * NCOL + n] in the layout of the weight's column map (encoder: k = tap * CH + ch,
+// n = cl; decoder: k = cl, n = tap * CH + ch), reduced across workgroups afterwards in FP64.
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+struct WgCfg {
+  static constexpr int KS = DEC ? 4 : 3, TAPS = KS * KS;
+  static constexpr int SH = 2 * TH + KS - 2, SW = 2 * TW + KS - 2;  // Hi rectangle
+  static constexpr int PY = TH + 1, PX = TW + 1;                    // parity-plane extent
+  static constexpr int PXP = PX + 3;                                // plane row pitch (floats)
+  static constexpr int PLANE = CH * PY * PXP;
+  static constexpr int LP = TH * TW + 4;                            // Lo row pitch (floats)
+  static constexpr int MTC = CH / 16, NTC = CL / 16;
+  static constexpr int PAIRS = TAPS * MTC, PW_ = (PAIRS + 3) / 4;   // (tap, ch tile) pairs per wave
+  static constexpr int LDS_FLOATS = CL * LP + 4 * PLANE;
+  static_assert(TW % 4 == 0 && (TH * TW) % 16 == 0, "pixel groups of 4 inside a row, chunks of 16");
+  static_assert(LDS_FLOATS * 4 <= 160 * 1024, "LDS of one workgroup");
+};
+
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+__global__ __launch_bounds__(256) void k_s2_wgrad(const T* __restrict__ lo, const T* __restrict__ hi,
+                                                  float* __restrict__ part, int B, int h, int w) {
+  typedef WgCfg<T, DEC, CL, CH, TH, TW> C;
+  constexpr int KS = C::KS, PW_ = C::PW_, NTC = C::NTC, MTC = C::MTC, LP = C::LP, PXP = C::PXP, PY = C::PY;
+  constexpr bool BF = sizeof(T) == 2;
+  constexpr int VE = 16 / sizeof(T);
+  __shared__ __attribute__((aligned(16))) float lds[C::LDS_FLOATS];
+  float* const ls = lds;              // [CL][LP]
+  float* const hs = lds + CL * LP;    // [4][CH][PY][PXP]
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
+  const int H2 = 2 * h, W2 = 2 * w;
+
+  floatx4 acc[PW_][NTC];
+#pragma unroll
+  for (int u = 0; u < PW_; ++u)
+#pragma unroll
+    for (int j = 0; j < NTC; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nty = (h + TH - 1) / TH, ntx = (w + TW - 1) / TW;
+  const int64_t ntiles = (int64_t)B * nty * ntx;
+  int64_t t_begin, t_end, t_step;
+  if ((gridDim.x & 7) == 0) {
+    const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int64_t chunk = (ntiles + 7) / 8;
+    t_begin = xcd * chunk + l;
+    t_end = (xcd + 1) * chunk < ntiles ? (xcd + 1) * chunk : ntiles;
+    t_step = per;
+  } else {
+    t_begin = blockIdx.x;
+    t_end = ntiles;
+    t_step = gridDim.x;
+  }
+  for (int64_t t = t_begin; t < t_end; t += t_step) {
+    int b, y0, x0;
+    s2_tile_origin(t, nty, ntx, TH, TW, b, y0, x0);
+    __syncthreads();
+    // Lo tile -> ls[cl][p] (zeros off the map)
+    {
+      constexpr int CHV = CL / VE, TOTAL = TH * TW * CHV;
+      for (int e = threadIdx.x; e < TOTAL; e += STDA_BLOCK) {
+        const int cv = e % CHV, p = e / CHV;
+        const int y = y0 + p / TW, x = x0 + p % TW;
+        float v[VE];
+        if (y < h && x < w) {
+          const T* src = lo + (((int64_t)b * h + y) * w + x) * CL + cv * VE;
+#pragma unroll
+          for (int q = 0; q < VE; q += 4) ld4(src + q, v + q);
+        } else {
+#pragma unroll
+          for (int q = 0; q < VE; ++q) v[q] = 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < VE; ++q) ls[(cv * VE + q) * LP + p] = v[q];
+      }
+    }
+    // Hi rectangle -> parity planes hs[(py * 2 + px)][ch][Y][X]
+    {
+      constexpr int CHV = CH / VE, TOTAL = C::SH * C::SW * CHV;
+      for (int e = threadIdx.x; e < TOTAL; e += STDA_BLOCK) {
+        const int cv = e % CHV, px_ = e / CHV;
+        const int ly = px_ / C::SW, lx = px_ % C::SW;
+        const int sy = 2 * y0 - 1 + ly, sx = 2 * x0 - 1 + lx;
+        float v[VE];
+        if (sy >= 0 && sy < H2 && sx >= 0 && sx < W2) {
+          const T* src = hi + (((int64_t)b * H2 + sy) * W2 + sx) * CH + cv * VE;
+#pragma unroll
+          for (int q = 0; q < VE; q += 4) ld4(src + q, v + q);
+        } else {
+#pragma unroll
+          for (int q = 0; q < VE; ++q) v[q] = 0.f;
+        }
+        float* dst = hs + ((ly & 1) * 2 + (lx & 1)) * C::PLANE + (ly >> 1) * PXP + (lx >> 1);
+#pragma unroll
+        for (int q = 0; q < VE; ++q) dst[(cv * VE + q) * PY * PXP] = v[q];
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c16 = 0; c16 < TH * TW / 16; ++c16) {
+      const int p0 = 16 * c16 + 4 * g, ty = p0 / TW, tx = p0 % TW;
+      float4 bq[NTC];
+#pragma unroll
+      for (int j = 0; j < NTC; ++j) bq[j] = *reinterpret_cast<const float4*>(ls + (16 * j + i) * LP + p0);
+#pragma unroll
+      for (int u = 0; u < PW_; ++u) {
+        const int q = wave + 4 * u;
+        if (q >= C::PAIRS) continue;
+        const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
+        const float* a = hs + ((ky & 1) * 2 + (kx & 1)) * C::PLANE + ((16 * mt + i) * PY + ty + (ky >> 1)) * PXP +
+                         tx + (kx >> 1);
+        const float a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3];
+#pragma unroll
+        for (int j = 0; j < NTC; ++j) {
+          if constexpr (BF) {
+            const shortx4 av = {(short)(__float_as_uint(a0) >> 16), (short)(__float_as_uint(a1) >> 16),
+                                (short)(__float_as_uint(a2) >> 16), (short)(__float_as_uint(a3) >> 16)};
+            const shortx4 bv = {(short)(__float_as_uint(bq[j].x) >> 16), (short)(__float_as_uint(bq[j].y) >> 16),
+                                (short)(__float_as_uint(bq[j].z) >> 16), (short)(__float_as_uint(bq[j].w) >> 16)};
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[u][j], 0, 0, 0);
+          } else {
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bq[j].x, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bq[j].y, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, bq[j].z, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, bq[j].w, acc[u][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // lane (i, g) holds D[4g + r][i]: ch = 16 mt + 4g + r, cl = 16 j + i
+  constexpr int NCOL = DEC ? C::TAPS * CH : CL;
+  float* out = part + (int64_t)blockIdx.x * C::TAPS * CH * CL;
+#pragma unroll
+  for (int u = 0; u < PW_; ++u) {
+    const int q = wave + 4 * u;
+    if (q >= C::PAIRS) continue;
+    const int tap = q / MTC, mt = q % MTC;
+#pragma unroll
+    for (int j = 0; j < NTC; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + 4 * g + r, cl = 16 * j + i;
+        const int64_t idx = DEC ? (int64_t)cl * NCOL + tap * CH + ch : ((int64_t)tap * CH + ch) * NCOL + cl;
+        out[idx] = acc[u][j][r];
+      }
+  }
+}
+
+}  // namespace stda

@@ -255,7 +255,8 @@ def profile_report():
 
 
 # ------------------------------------------------------------------------ tile-shape autotuning
-TUNE_FWD, TUNE_DGRAD = 0, 1
+TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD = 0, 1, 2
+TUNE_KINDS = (TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD)
 
 
 def tune_count(kind):
@@ -277,7 +278,7 @@ def tune_get(kind, dtype, block):
 
 def tune_table(dtype):
     """{(kind, block): variant} currently in force for `dtype`."""
-    return {(k, b): tune_get(k, dtype, b) for k in (TUNE_FWD, TUNE_DGRAD) for b in range(4)}
+    return {(k, b): tune_get(k, dtype, b) for k in TUNE_KINDS for b in range(4)}
 
 
 def autotune(segs, x, y, w, running, z, loss, dz, dw, saved, ws, dtype=FP32, recompute=0, reps=3):

@@ -1,4 +1,5 @@
-"""The tiling variants of the stage-2 dense layers (the autotuner's candidates), through the C ABI.
+"""The tiling variants of the stage-2 dense layers and of their weight gradients (the autotuner's
+candidates), through the C ABI.
 
 * EVAL forward: every variant gives bit-identical z (each output element sums its taps and
   channels in the same order whatever the tiling), on shapes whose maps leave ragged tiles at
@@ -30,13 +31,13 @@ def S():
     from paper_2307_09063_amd import stda
     yield stda
     for dt in (stda.FP32, stda.BF16):
-        for kind in (stda.TUNE_FWD, stda.TUNE_DGRAD):
+        for kind in stda.TUNE_KINDS:
             for b in range(4):
                 stda.tune_set(kind, dt, b, 0)
 
 
 def _set_all(S, dtype, v):
-    for kind in (S.TUNE_FWD, S.TUNE_DGRAD):
+    for kind in S.TUNE_KINDS:
         for b in range(4):
             S.tune_set(kind, dtype, b, v)
 
@@ -124,7 +125,7 @@ def test_autotune(S, dtype):
     res = S.autotune(segs, xd, yd, wd, rs, z, loss, dz, dw, saved, ws, dtype, reps=2)
     torch.cuda.synchronize()
     n = S.tune_count(S.TUNE_FWD)
-    assert sorted(res) == [(k, b) for k in (0, 1) for b in range(4)]
+    assert sorted(res) == [(k, b) for k in S.TUNE_KINDS for b in range(4)]
     for (kind, b), (choice, ms) in res.items():
         assert 0 <= choice < n and len(ms) == n and all(t > 0 for t in ms)
         assert ms[choice] == min(ms)
@@ -133,3 +134,38 @@ def test_autotune(S, dtype):
     zt, _, _ = _forward(S, x, w0, r, S.EVAL, dtype)
     zr, _, _ = net.forward(w0, r, x, 'eval')
     assert U.rel_l2(zt.cpu().numpy(), zr) < (1e-4 if dtype == 0 else 2e-2)
+
+
+@pytest.mark.parametrize('dtype', [0, 1], ids=['fp32', 'bf16'])
+def test_wgrad_variants_agree(S, dtype):
+    """Only the weight-gradient tiling changes: forward, dx and every gradient that does not come
+    from a stage-2 weight are bit-identical, and the stage-2 weight gradients differ only by the
+    order of their FP32 pixel sums."""
+    B, H, W = SHAPES[1]
+    x, y = U.maps(B, H, W, seed=31)
+    w, r = U.weights(), U.running()
+    g = np.random.default_rng(3).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
+    res = []
+    for v in range(S.tune_count(S.TUNE_WGRAD)):
+        _say('wgrad variant', dtype, v)
+        for b in range(4):
+            S.tune_set(S.TUNE_WGRAD, dtype, b, v)
+        z, _, (segs, xd, wd, saved, ws) = _forward(S, x, w, r, S.TRAIN, dtype)
+        dw = torch.full((net.param_count(),), float('nan'), device='cuda')
+        dx = torch.empty_like(xd)
+        S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws, dtype)
+        torch.cuda.synchronize()
+        res.append((z.cpu().numpy(), dw.cpu().numpy(), dx.cpu().numpy()))
+    stage2 = {f'{k}.s2.{m}.w' for k in ('enc0', 'enc1', 'dec0', 'dec1') for m in ('main', 'res')}
+    for v in range(1, len(res)):
+        np.testing.assert_array_equal(res[v][0], res[0][0])
+        np.testing.assert_array_equal(res[v][2], res[0][2])
+        off = 0
+        for name, shape, _ in net.param_specs():
+            n = int(np.prod(shape))
+            a, b = res[v][1][off:off + n], res[0][1][off:off + n]
+            if name in stage2:
+                assert U.rel_l2(a, b) < 1e-5, (name, v)
+            else:
+                np.testing.assert_array_equal(a, b)
+            off += n
