@@ -6,7 +6,9 @@
 // LDS with coalesced 16-byte loads (zeros outside the map) and computes every pixel of the tile
 // from LDS; the grid loops over the tiles of all clips.  Thread mapping inside a tile: item =
 // (pixel, group of 4 channels), channel group fastest, so a thread keeps one channel group for
-// its whole life.  LDS rows are padded to C + 4 floats.
+// its whole life.  LDS tiles are [pixel][C] floats laid out by S1Lds (see there) so that both
+// access patterns avoid bank conflicts: one thread per (pixel, chunk) reading float4s, and
+// matrix-core operands reading one channel of 16 consecutive pixels.
 #pragma once
 #include "net_kernels.h"
 
@@ -29,14 +31,34 @@ struct S1Tile<64> {
 
 template <int C>
 struct S1Geo {
-  static constexpr int TH = S1Tile<C>::TH, TW = S1Tile<C>::TW, G = C / 4, PS = C + 4;
+  static constexpr int TH = S1Tile<C>::TH, TW = S1Tile<C>::TW, G = C / 4;
 };
 
-// Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds
-// [(TH + 2 HALO)][(TW + 2 HALO)][PS] floats.
+// LDS layout of a [pixel][C] tile.  64 channels: rows of C floats whose 16-byte chunk q sits in
+// slot q ^ (px & 15), so that 16 consecutive pixels cover all 64 banks in both access patterns.
+// 16 and 32 channels: rows padded to C + 4 floats (linear addresses, which the compiler folds
+// into instruction offsets; the swizzle measured slower there).
+template <int C>
+struct S1Lds {
+  static constexpr bool SWZ = C == 64;
+  static constexpr int PITCH = SWZ ? C : C + 4;
+};
+// Float offset of chunk q (channels 4q .. 4q + 3) of LDS pixel px, and of channel c.
+template <int C>
+__device__ __forceinline__ int s1c(int px, int q) {
+  if constexpr (S1Lds<C>::SWZ) return px * C + ((q ^ (px & (C / 4 - 1))) << 2);
+  else return px * S1Lds<C>::PITCH + (q << 2);
+}
+template <int C>
+__device__ __forceinline__ int s1e(int px, int c) {
+  return s1c<C>(px, c >> 2) + (c & 3);
+}
+
+// Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds, pixel
+// (row, col) of the haloed tile at LDS pixel row * (TW + 2 HALO) + col.
 template <class T, int C, int TH, int TW, int HALO>
 __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0, int x0, int h, int w, float* lds) {
-  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4, PS = C + 4;
+  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4;
   for (int e = threadIdx.x; e < RH * RW * G; e += STDA_BLOCK) {
     const int q = e % G, px = e / G;
     const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
@@ -45,7 +67,7 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0
       ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v);
     else
       zero4(v);
-    *reinterpret_cast<float4*>(lds + px * PS + 4 * q) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(lds + s1c<C>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -59,9 +81,24 @@ __device__ __forceinline__ void tile_coords(int tile, int h, int w, int TH, int 
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
 
-// Cm[i][n] = sum_k A(i, k) B(k, n) for an M x N x K product held in LDS, on the matrix cores
-// (v_mfma_f32_16x16x4f32); A and B are addressing functors, Cm is row-major with stride ldc.
-// The block's 4 waves take 16 x 16 output tiles in turn.  Caller synchronises around it.
+// store(i, n, sum_k A(i, k) B(k, n)) for an M x N x K product held in LDS, on the matrix cores
+// (v_mfma_f32_16x16x4f32); A and B are addressing functors.  The block's 4 waves take 16 x 16
+// output tiles in turn.  Caller synchronises around it.
+template <int M, int N, int K, class AF, class BF, class SF>
+__device__ __forceinline__ void lds_gemm_s(AF A, BF B, SF store) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
+  for (int t = wave; t < (M / 16) * (N / 16); t += 4) {
+    const int m0 = (t / (N / 16)) * 16, n0 = (t % (N / 16)) * 16;
+    floatx4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int k = 0; k < K; k += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A(m0 + i, k + g), B(k + g, n0 + i), acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) store(m0 + 4 * g + r, n0 + i, acc[r]);
+  }
+}
+
+// The same product stored row-major into Cm with row stride ldc.
 template <int M, int N, int K, class AF, class BF>
 __device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
@@ -79,49 +116,10 @@ __device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
 // Depthwise branch (4 channels) of the pixel at padded LDS position (r, c).
 template <int C>
 __device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float* wd, float dv[4]) {
-  constexpr int PS = C + 4;
   zero4(dv);
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const float4 v = *reinterpret_cast<const float4*>(xt + ((r + t / 3 - 1) * RW + c + t % 3 - 1) * PS + c0);
-    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
-    dv[0] += wq.x * v.x;
-    dv[1] += wq.y * v.y;
-    dv[2] += wq.z * v.z;
-    dv[3] += wq.w * v.w;
-  }
-}
-
-// Pointwise (4 output channels) and depthwise (4 channels) branches of the pixel whose padded
-// LDS position is (r, c) in a tile of row width RW.
-template <int C>
-__device__ __forceinline__ void s1_branches_lds(const float* xt, int RW, int r, int c, int c0, const float* wp,
-                                                const float* wd, float pv[4], float dv[4], float xv[4]) {
-  constexpr int PS = C + 4;
-  const float* ctr = xt + (r * RW + c) * PS;
-  zero4(pv);
-  zero4(dv);
-#pragma unroll 4
-  for (int k = 0; k < C; k += 4) {
-    const float4 v = *reinterpret_cast<const float4*>(ctr + k);
-    const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float4 wq = *reinterpret_cast<const float4*>(wp + (k + j) * C + c0);
-      pv[0] += wq.x * vv[j];
-      pv[1] += wq.y * vv[j];
-      pv[2] += wq.z * vv[j];
-      pv[3] += wq.w * vv[j];
-    }
-  }
-  const float4 xc = *reinterpret_cast<const float4*>(ctr + c0);
-  xv[0] = xc.x;
-  xv[1] = xc.y;
-  xv[2] = xc.z;
-  xv[3] = xc.w;
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const float4 v = *reinterpret_cast<const float4*>(xt + ((r + t / 3 - 1) * RW + c + t % 3 - 1) * PS + c0);
+    const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
     const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
     dv[0] += wq.x * v.x;
     dv[1] += wq.y * v.y;
@@ -137,9 +135,8 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
                                                  S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
-  constexpr int PS = Gm::PS;
-  __shared__ float xt[(TH + 2) * RW * PS];
-  __shared__ float pt[TH * TW * PS];  // pointwise branch of the tile (matrix cores)
+  __shared__ float xt[(TH + 2) * RW * S1Lds<C>::PITCH];
+  __shared__ float pt[TH * TW * S1Lds<C>::PITCH];  // pointwise branch of the tile (matrix cores)
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
   __shared__ float sm[MODE == 0 ? 4 * 6 * C : 1];
@@ -161,20 +158,21 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
     load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
     __syncthreads();
     // pt[p][o] = sum_c x[p][c] wp[c][o]; tile pixel p = r*TW + cc sits at padded (r + 1, cc + 1)
-    lds_gemm<TH * TW, C, C>([&](int p, int k) { return xt[((p / TW + 1) * RW + p % TW + 1) * PS + k]; },
-                            [&](int k, int n) { return wp[k * C + n]; }, pt, PS);
+    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C>((p / TW + 1) * RW + p % TW + 1, k)]; },
+                              [&](int k, int n) { return wp[k * C + n]; },
+                              [&](int p, int n, float v) { pt[s1e<C>(p, n)] = v; });
     __syncthreads();
     for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
       if (y >= h || x >= w) continue;
       float pv[4], dv[4], xv[4];
-      const float4 pq = *reinterpret_cast<const float4*>(pt + px * PS + c0);
+      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C>(px, c0 >> 2));
       pv[0] = pq.x;
       pv[1] = pq.y;
       pv[2] = pq.z;
       pv[3] = pq.w;
-      const float4 xq = *reinterpret_cast<const float4*>(xt + ((r + 1) * RW + cc + 1) * PS + c0);
+      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 1) * RW + cc + 1, c0 >> 2));
       xv[0] = xq.x;
       xv[1] = xq.y;
       xv[2] = xq.z;
@@ -216,9 +214,8 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
                                                            S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
-  constexpr int PS = Gm::PS;
-  __shared__ float xt[(TH + 2) * RW * PS];
-  __shared__ float pt[TH * TW * PS];
+  __shared__ float xt[(TH + 2) * RW * S1Lds<C>::PITCH];
+  __shared__ float pt[TH * TW * S1Lds<C>::PITCH];
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
   __shared__ float sm[4 * 4 * C];
@@ -243,20 +240,21 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     __syncthreads();
     load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
     __syncthreads();
-    lds_gemm<TH * TW, C, C>([&](int p, int k) { return xt[((p / TW + 1) * RW + p % TW + 1) * PS + k]; },
-                            [&](int k, int n) { return wp[k * C + n]; }, pt, PS);
+    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C>((p / TW + 1) * RW + p % TW + 1, k)]; },
+                              [&](int k, int n) { return wp[k * C + n]; },
+                              [&](int p, int n, float v) { pt[s1e<C>(p, n)] = v; });
     __syncthreads();
     for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
       if (y >= h || x >= w) continue;
       float pv[4], dv[4], xv[4], x1[4], g[4];
-      const float4 pq = *reinterpret_cast<const float4*>(pt + px * PS + c0);
+      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C>(px, c0 >> 2));
       pv[0] = pq.x;
       pv[1] = pq.y;
       pv[2] = pq.z;
       pv[3] = pq.w;
-      const float4 xq = *reinterpret_cast<const float4*>(xt + ((r + 1) * RW + cc + 1) * PS + c0);
+      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 1) * RW + cc + 1, c0 >> 2));
       xv[0] = xq.x;
       xv[1] = xq.y;
       xv[2] = xq.z;
@@ -295,15 +293,15 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
                                                       S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
                                                       float* __restrict__ dwpart, int B, int h, int w) {
   typedef S1Geo<C> Gm;
-  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, PS = Gm::PS, M = TH * TW;
+  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, M = TH * TW;
   constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
   constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
-  constexpr int XT = (TH + 4) * XW * PS;
+  constexpr int XT = (TH + 4) * XW * S1Lds<C>::PITCH;
   static_assert(XT >= 4 * 9 * C + 9 * C, "reduction scratch aliases the x tile");
   __shared__ float xt[XT];
-  __shared__ float ddt[(TH + 2) * DWd * PS];
-  __shared__ float dpt[M * PS];
-  __shared__ float qt[M * PS];
+  __shared__ float ddt[(TH + 2) * DWd * S1Lds<C>::PITCH];
+  __shared__ float dpt[M * S1Lds<C>::PITCH];
+  __shared__ float qt[M * S1Lds<C>::PITCH];
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
   float* sm = xt;  // used only after the tile loop
@@ -330,7 +328,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
   floatx4_t pwacc[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) pwacc[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-  auto xctr = [&](int p) { return ((p / TW + 2) * XW + p % TW + 2) * PS; };  // tile pixel -> x-tile row
+  auto xpx = [&](int p) { return (p / TW + 2) * XW + p % TW + 2; };  // tile pixel -> x-tile LDS pixel
 
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -340,8 +338,9 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
     load_tile<T, C, TH, TW, 2>(X, b, y0, x0, h, w, xt);
     __syncthreads();
     // A1: pointwise branch of the tile, qt = x Wp
-    lds_gemm<M, C, C>([&](int p, int kk) { return xt[xctr(p) + kk]; }, [&](int kk, int n) { return wp[kk * C + n]; },
-                      qt, PS);
+    lds_gemm_s<M, C, C>([&](int p, int kk) { return xt[s1e<C>(xpx(p), kk)]; },
+                        [&](int kk, int n) { return wp[kk * C + n]; },
+                        [&](int p, int n, float v) { qt[s1e<C>(p, n)] = v; });
     __syncthreads();
     // A2: dD on the tile + halo 1, dP on the tile (zero off the map)
     for (int e = threadIdx.x; e < (TH + 2) * DWd * G; e += STDA_BLOCK) {
@@ -359,7 +358,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
         s1_dw_lds<C>(xt, XW, r + 1, cc + 1, c0, wd, dv);
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
-          const float4 pq = *reinterpret_cast<const float4*>(qt + ((r - 1) * TW + cc - 1) * PS + c0);
+          const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C>((r - 1) * TW + cc - 1, c0 >> 2));
           pv[0] = pq.x;
           pv[1] = pq.y;
           pv[2] = pq.z;
@@ -372,14 +371,15 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
           op[j] = ga[0][j] * is[0][j] * (du - k[0][j] - (pv[j] - mu[0][j]) * is[0][j] * k[1][j]);
         }
       }
-      *reinterpret_cast<float4*>(ddt + px * PS + c0) = make_float4(od[0], od[1], od[2], od[3]);
+      *reinterpret_cast<float4*>(ddt + s1c<C>(px, c0 >> 2)) = make_float4(od[0], od[1], od[2], od[3]);
       if (center)
-        *reinterpret_cast<float4*>(dpt + ((r - 1) * TW + cc - 1) * PS + c0) = make_float4(op[0], op[1], op[2], op[3]);
+        *reinterpret_cast<float4*>(dpt + s1c<C>((r - 1) * TW + cc - 1, c0 >> 2)) =
+            make_float4(op[0], op[1], op[2], op[3]);
     }
     __syncthreads();
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
-    lds_gemm<M, C, C>([&](int p, int o) { return dpt[p * PS + o]; }, [&](int o, int n) { return wp[n * C + o]; }, qt,
-                      PS);
+    lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
+                        [&](int p, int n, float v) { qt[s1e<C>(p, n)] = v; });
     // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles)
 #pragma unroll
     for (int u = 0; u < NTW; ++u) {
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
         const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
 #pragma unroll 4
         for (int p = 0; p < M; p += 4)
-          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[xctr(p + lg) + m0 + li], dpt[(p + lg) * PS + n0 + li],
+          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C>(xpx(p + lg), m0 + li)], dpt[s1e<C>(p + lg, n0 + li)],
                                                           pwacc[u], 0, 0, 0);
       }
     }
@@ -403,8 +403,8 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
       ld4(X1 + off, x1);
       ld4(dX1 + off, g);
       ld4(dXr + off, rr);
-      const float4 xc = *reinterpret_cast<const float4*>(xt + xctr(px) + c0);
-      const float4 qc = *reinterpret_cast<const float4*>(qt + px * PS + c0);
+      const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C>(xpx(px), c0 >> 2));
+      const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C>(px, c0 >> 2));
       const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -418,19 +418,19 @@ __global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, c
         for (int j = 0; j < 4; ++j) acc[j] += sv[j];
       }
       // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map
-      const float4 ddc = *reinterpret_cast<const float4*>(ddt + ((r + 1) * DWd + cc + 1) * PS + c0);
+      const float4 ddc = *reinterpret_cast<const float4*>(ddt + s1c<C>((r + 1) * DWd + cc + 1, c0 >> 2));
       const float ddv[4] = {ddc.x, ddc.y, ddc.z, ddc.w};
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const float4 v = *reinterpret_cast<const float4*>(ddt + ((r + 1 - dy) * DWd + cc + 1 - dx) * PS + c0);
+        const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
         const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
         acc[0] += wq.x * v.x;
         acc[1] += wq.y * v.y;
         acc[2] += wq.z * v.z;
         acc[3] += wq.w * v.w;
         // depthwise weight gradient: x(q + off_t) * dD(q)
-        const float4 xn = *reinterpret_cast<const float4*>(xt + ((r + 2 + dy) * XW + cc + 2 + dx) * PS + c0);
+        const float4 xn = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 2 + dy) * XW + cc + 2 + dx, c0 >> 2));
         dwacc[t][0] += xn.x * ddv[0];
         dwacc[t][1] += xn.y * ddv[1];
         dwacc[t][2] += xn.z * ddv[2];
