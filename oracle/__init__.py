@@ -7,10 +7,12 @@ its Python binding never do, and they share no code with it.
   layers   -- convolution / transposed convolution / depthwise / BN / ReLU / ECA and adjoints
   net      -- the network, its hand-written backward, MSE loss, SGD, the parameter layout
   rdsynth  -- FMCW beat signal, windows, 2-D DFT, dB normalisation, Philox noise, SINR / EVM
+  detect   -- CA-CFAR peak detection on restored maps and the fraction of reference peaks found
 
 Parity unpinned (no figure, code or data of the paper fixes them; they are readings):
 the block count and widths, the input/output module contents, the depthwise choice of the
 stage-1 3x3 branch, the decoder residual (DeConv4x4-s2), the ECA width and placement, the skip
-endpoints, the loss, and the realism of the synthetic scenes against measured data.
+endpoints, the loss, the CA-CFAR window sizes and edge rules, and the realism of the synthetic
+scenes against measured data.
 """
-from . import layers, net, rdsynth  # noqa: F401
+from . import detect, layers, net, rdsynth  # noqa: F401
