@@ -101,7 +101,7 @@ def parse():
     ap.add_argument('--warmup', type=int, default=3)
     ap.add_argument('--workload', default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-sample-clips', type=int, default=4)
+    ap.add_argument('--cpu-sample-clips', type=int, default=8)
     ap.add_argument('--train-only', action='store_true', help='only the chosen training workload')
     ap.add_argument('--no-graph', action='store_true', help='time eager steps instead of the captured step')
     ap.add_argument('--copy-calib', action='store_true',
@@ -304,9 +304,9 @@ def main():
 
     extra = {}
     if not args.train_only:
-        fwd_ms, Bf = eval_forward(stda, inputs, torch, x[:3 * 32 * N * M] if len(groups) == 1 else None,
-                                  tr.w, tr.running, dev)
+        fwd_ms, Bf, det = eval_forward(stda, inputs, torch, tr.w, tr.running, dev)
         extra['fwd_eval_fp32_b32_256x128'] = {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)}
+        extra['detect_b32_256x128'] = det
         lat = latency_b1(stda, inputs, torch, tr.w, tr.running, dev)
         extra['fwd_eval_fp32_b1_64x64_latency_ms'] = round(lat, 4)
         for other in ('train_bf16_b256_256x128', 'train_uneven_bf16_512'):
@@ -382,16 +382,18 @@ def latency_b1(stda, inputs, torch, w, running, dev):
     return e0.elapsed_time(e1) / 50
 
 
-def eval_forward(stda, inputs, torch, x, w, running, dev):
-    """Forward-only EVAL at the forward configuration (B = 32 clips of 3 x 256 x 128), ms per call."""
+def eval_forward(stda, inputs, torch, w, running, dev):
+    """Forward-only EVAL at the forward configuration (B = 32 clips of 3 x 256 x 128, its own seeded
+    scenes), ms per call; then the detection step on the restored maps (CA-CFAR with the
+    reference-peak hit count, EVM and SINR against the interference-free maps), ms per call."""
+    import numpy as np
     rc = inputs.WORKLOADS['cfg2_fwd_256x128']
     Bf = rc['B']
     N, M = rc['sizes'][0]
-    if x is None:
-        tab, meta = inputs.make_scenes(Bf, N, M, rc['seed'], targets=rc['targets'], intf=rc['intf'],
-                                       inr=rc['inr'], clutter=rc['clutter'])
-        x, _ = stda.synthesize(tab, meta, dev, with_clean=False)
-    xf = x.reshape(-1)[:3 * Bf * N * M].contiguous()
+    tab, meta = inputs.make_scenes(Bf, N, M, rc['seed'], targets=rc['targets'], intf=rc['intf'],
+                                   inr=rc['inr'], clutter=rc['clutter'])
+    x, clean = stda.synthesize(tab, meta, dev)
+    xf = x.reshape(-1).contiguous()
     segs_f = stda.uniform_segments(Bf, N, M)
     _, ws_f = stda.workspace_size(segs_f, stda.FP32, stda.EVAL)
     wsf = stda.alloc_bytes(ws_f, dev)
@@ -405,7 +407,34 @@ def eval_forward(stda, inputs, torch, x, w, running, dev):
         stda.forward(segs_f, xf, w, running, zf, None, wsf, stda.FP32, stda.EVAL)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 10, Bf
+    fwd_ms = e0.elapsed_time(e1) / 10
+    masks = [inputs.sinr_masks(meta['peaks'][b], N, M) for b in range(Bf)]
+    om = torch.from_numpy(np.stack([m[0] for m in masks]).astype(np.uint8)).to(dev)
+    nm = torch.from_numpy(np.stack([m[1] for m in masks]).astype(np.uint8)).to(dev)
+    det = torch.empty((Bf, N, M), dtype=torch.uint8, device=dev)
+    counts = torch.empty((Bf, 2), dtype=torch.int32, device=dev)
+    ev = torch.empty(Bf, dtype=torch.float64, device=dev)
+    sn = torch.empty(Bf, dtype=torch.float64, device=dev)
+
+    def detect_step():
+        stda.cfar(zf, det, **stda.CFAR_DEFAULT, o_mask=om, counts=counts)
+        stda.evm(zf, clean, om, ev)
+        stda.sinr(zf, om, nm, sn)
+
+    for _ in range(3):
+        detect_step()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        detect_step()
+    e1.record()
+    torch.cuda.synchronize()
+    det_ms = e0.elapsed_time(e1) / 10
+    c = counts.cpu().numpy()
+    return fwd_ms, Bf, {'ms': round(det_ms, 4), 'maps_per_s': round(Bf / (det_ms / 1e3), 1),
+                        'cfar': dict(stda.CFAR_DEFAULT), 'peaks_hit': int(c[:, 1].sum()),
+                        'peaks': int(om.sum().item()), 'detections': int(c[:, 0].sum()),
+                        'note': 'random-init weights: detection quality is not meaningful, only timing'}
 
 
 def cpu_baseline(nclips, N, M, x, y, w, r):

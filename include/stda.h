@@ -130,12 +130,60 @@ int stda_sgd_step(float* w, const float* dw, int64_t n, float lr, float weight_d
                   uint16_t* w_bf16, hipStream_t stream);
 
 /*
+ * AdamW (Table 5 names AdamW with weight decay and step annealing; moment coefficients and the
+ * annealing period are not given, so they are parameters here).  State in DEVICE memory, owned
+ * by the caller and initialised once (t = 0; m and v zero):
+ *   lr_t = lr * gamma^floor(t / step_size) (step_size 0: constant), t = steps already taken;
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;
+ *   w <- w (1 - lr_t weight_decay) - lr_t (m / (1 - b1^(t+1))) / (sqrt(v / (1 - b2^(t+1))) + eps);
+ * then t <- t + 1 on the device (so a captured graph replays consecutive steps).  m, v: [n] FP32
+ * (device); w_bf16 as in stda_sgd_step.
+ */
+typedef struct {
+  double lr, beta1, beta2, eps, weight_decay, gamma;  /* FP64 so that 1 - beta is exact enough */
+  int32_t step_size;
+  int32_t t;
+} stda_adamw_state;
+int stda_adamw_step(float* w, const float* dw, float* m, float* v, int64_t n,
+                    stda_adamw_state* state_dev, uint16_t* w_bf16, hipStream_t stream);
+
+/*
  * SINR of Sec. V-B over a batch of maps: per map 10 log10(mean_O m^2 / mean_N m^2) where the
  * O and N cells are given by the byte masks o_mask / n_mask ([n_maps][H][W], 1 = member).
  * Sums are FP64; out_dev[n_maps] receives the dB values.
  */
 int stda_sinr(const float* maps, const uint8_t* o_mask, const uint8_t* n_mask, int n_maps, int H,
               int W, double* out_dev, hipStream_t stream);
+
+/* ------------------------------------------------------------------ detection step */
+/*
+ * CA-CFAR peak detection on restored maps (Sec. V-B names a cell-averaging CFAR as the peak
+ * detector whose hits the average precision of Eq. (21) counts; its parameters are a reading).
+ * Square-law statistic p = m^2 of each map value m.  The training cells of a cell are those of
+ * the (2(guard_r+train_r)+1) x (2(guard_d+train_d)+1) window around it (rows = range, columns =
+ * Doppler) outside the (2 guard_r+1) x (2 guard_d+1) guard window; columns wrap around (the
+ * Doppler axis is circular), rows outside the map do not count.  With N training cells summing to
+ * S (FP64), the cell is detected when p > alpha(N) S / N, alpha(N) = N (pfa^(-1/N) - 1).
+ *   maps     [n_maps][H][W] FP32 (device)
+ *   det      [n_maps][H][W] bytes out, 1 = detection (device)
+ *   o_mask   [n_maps][H][W] reference-peak cells, 1 = member, or NULL (device)
+ *   counts   [n_maps][2] int32 out or NULL (device): detections, detections on o_mask cells
+ * guard_r + train_r and guard_d + train_d must not exceed STDA_CFAR_MAX_HALO and the windows
+ * must fit the map (STDA_E_SHAPE); at least one training extent must be positive and
+ * 0 < pfa < 1 (STDA_E_INVALID).
+ */
+#define STDA_CFAR_MAX_HALO 8
+int stda_cfar(const float* maps, int n_maps, int H, int W, int guard_r, int guard_d, int train_r,
+              int train_d, double pfa, uint8_t* det, const uint8_t* o_mask, int32_t* counts,
+              hipStream_t stream);
+
+/*
+ * EVM of Sec. V-B, Eq. (20), per map: the mean over the o_mask cells of |clean - est| / |clean|,
+ * FP64 sums, into out_dev[n_maps]; a map without o_mask cells gives 0.  All arrays are
+ * [n_maps][H][W] on the device.
+ */
+int stda_evm(const float* est, const float* clean, const uint8_t* o_mask, int n_maps, int H, int W,
+             double* out_dev, hipStream_t stream);
 
 /* ------------------------------------------------------------------ captured training step */
 /*

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, 'csrc')
 LIB = os.path.join(HERE, 'libstda.so')
-SOURCES = ['net.hip', 'rd.hip']
+SOURCES = ['net.hip', 'rd.hip', 'detect.hip', 'optim.hip']
 ARCH = os.environ.get('STDA_ARCH', 'gfx950')
 
 HIPCC_FLAGS = ['-O3', '-std=c++17', '-fPIC', f'--offload-arch={ARCH}',

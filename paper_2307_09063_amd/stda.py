@@ -63,6 +63,9 @@ def _load():
         'stda_tune_set': (I, [I, I, I, I]),
         'stda_tune_get': (I, [I, I, I, P]),
         'stda_autotune': (I, [P, I, P, P, P, P, P, P, P, P, P, SZ, P, SZ, I, I, I, P, P, SZ, P]),
+        'stda_cfar': (I, [P, I, I, I, I, I, I, I, ctypes.c_double, P, P, P, P]),
+        'stda_evm': (I, [P, P, P, I, I, I, P, P]),
+        'stda_adamw_step': (I, [P, P, P, P, I64, P, P, P]),
         'rd_synth_workspace_size': (SZ, [I, I, I]),
         'rd_synth': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
     }
@@ -79,7 +82,7 @@ EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'std
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
-           'stda_autotune', 'rd_synth_workspace_size', 'rd_synth')
+           'stda_autotune', 'stda_cfar', 'stda_evm', 'stda_adamw_step', 'rd_synth_workspace_size', 'rd_synth')
 
 
 def _check(status, what):
@@ -192,9 +195,54 @@ def sgd_step(w, dw, lr, weight_decay, w_bf16=None):
            'stda_sgd_step')
 
 
+class AdamW:
+    """Device state of stda_adamw_step: moments m, v and the hyper-parameter / step-counter record
+    (lr, beta1, beta2, eps, weight_decay, gamma as FP64, then step_size and t as int32)."""
+    STATE_BYTES, T_OFFSET = 56, 52
+
+    def __init__(self, n, lr=1e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=5e-4, gamma=0.1, step_size=0,
+                 device='cuda'):
+        import numpy as np
+        self.n = n
+        self.m = torch.zeros(n, device=device)
+        self.v = torch.zeros(n, device=device)
+        rec = np.zeros(7, dtype=np.float64)
+        rec[:6] = [lr, betas[0], betas[1], eps, weight_decay, gamma]
+        ints = rec.view(np.int32)
+        ints[12], ints[13] = step_size, 0
+        self.state = torch.from_numpy(rec.view(np.uint8).copy()).to(device)
+
+    @property
+    def t(self):
+        import numpy as np
+        return int(self.state.cpu().numpy().view(np.int32)[13])
+
+    def step(self, w, dw, w_bf16=None):
+        _check(_lib.stda_adamw_step(_ptr(w), _ptr(dw), _ptr(self.m), _ptr(self.v), self.n, _ptr(self.state),
+                                    _ptr(w_bf16), _stream()), 'stda_adamw_step')
+
+
 def sinr(maps, o_mask, n_mask, out):
     n, H, W = maps.shape[0], maps.shape[-2], maps.shape[-1]
     _check(_lib.stda_sinr(_ptr(maps), _ptr(o_mask), _ptr(n_mask), n, H, W, _ptr(out), _stream()), 'stda_sinr')
+
+
+# ------------------------------------------------------------------------ detection step
+CFAR_DEFAULT = dict(guard_r=2, guard_d=2, train_r=4, train_d=4, pfa=1e-3)
+
+
+def cfar(maps, det, guard_r=2, guard_d=2, train_r=4, train_d=4, pfa=1e-3, o_mask=None, counts=None):
+    """CA-CFAR of maps [n, (1,) H, W] (FP32, device) into det (uint8, same cells); counts
+    (int32 [n, 2]) receives detections and detections on o_mask cells when given."""
+    n, H, W = maps.shape[0], maps.shape[-2], maps.shape[-1]
+    _check(_lib.stda_cfar(_ptr(maps), n, H, W, guard_r, guard_d, train_r, train_d, float(pfa), _ptr(det),
+                          _ptr(o_mask), _ptr(counts), _stream()), 'stda_cfar')
+
+
+def evm(est, clean, o_mask, out):
+    """EVM per map (FP64 out [n]) over the o_mask cells."""
+    n, H, W = est.shape[0], est.shape[-2], est.shape[-1]
+    _check(_lib.stda_evm(_ptr(est), _ptr(clean), _ptr(o_mask), n, H, W, _ptr(out), _stream()), 'stda_evm')
 
 
 # ------------------------------------------------------------------------ captured step

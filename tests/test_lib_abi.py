@@ -53,9 +53,10 @@ def test_param_table_matches_oracle(S):
 def test_struct_layouts_against_header(tmp_path):
     prog = tmp_path / 'layout.c'
     prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "stda.h"\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rd_scene),'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(rd_scene),'
                     ' offsetof(rd_scene, tone), offsetof(rd_scene, intf), sizeof(rd_intf),'
-                    ' sizeof(stda_segment), offsetof(stda_segment, x_off), sizeof(stda_param_desc));return 0;}\n')
+                    ' sizeof(stda_segment), offsetof(stda_segment, x_off), sizeof(stda_param_desc),'
+                    ' sizeof(stda_adamw_state), offsetof(stda_adamw_state, t));return 0;}\n')
     exe = tmp_path / 'layout'
     subprocess.run(['gcc', '-D__HIP_PLATFORM_AMD__', '-I', os.path.join(ROOT, 'include'), '-I',
                     '/opt/rocm/include', str(prog), '-o', str(exe)], check=True)
@@ -63,7 +64,8 @@ def test_struct_layouts_against_header(tmp_path):
     d = inputs.SCENE_DTYPE
     from paper_2307_09063_amd import stda
     assert vals == [d.itemsize, d.fields['tone'][1], d.fields['intf'][1], inputs.INTF_DTYPE.itemsize,
-                    ctypes.sizeof(stda.Segment), stda.Segment.x_off.offset, ctypes.sizeof(stda.ParamDesc)]
+                    ctypes.sizeof(stda.Segment), stda.Segment.x_off.offset, ctypes.sizeof(stda.ParamDesc),
+                    stda.AdamW.STATE_BYTES, stda.AdamW.T_OFFSET]
 
 
 def _segs(S, *t):
@@ -98,6 +100,14 @@ def test_validation_before_launch(S):
     assert lib.rd_synth(fake, 1, 64, 2048, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -2
     assert lib.rd_synth(fake, 1, 64, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, 16, None) == -3
     assert lib.stda_status_string(-2).decode().startswith('unsupported shape')
+    # CA-CFAR / EVM argument checks
+    d = ctypes.c_double
+    assert lib.stda_cfar(None, 1, 64, 64, 2, 2, 4, 4, d(1e-3), fake, None, None, None) == -1
+    assert lib.stda_cfar(fake, 1, 64, 64, 2, 2, 0, 0, d(1e-3), fake, None, None, None) == -1  # no training
+    assert lib.stda_cfar(fake, 1, 64, 64, 2, 2, 4, 4, d(1.0), fake, None, None, None) == -1   # pfa
+    assert lib.stda_cfar(fake, 1, 64, 64, 2, 2, 7, 4, d(1e-3), fake, None, None, None) == -2  # halo > 8
+    assert lib.stda_cfar(fake, 1, 12, 64, 2, 2, 4, 4, d(1e-3), fake, None, None, None) == -2  # window > map
+    assert lib.stda_evm(fake, fake, None, 1, 8, 8, fake, None) == -1
 
 
 def test_workspace_grows_with_batch(S):
