@@ -1,0 +1,107 @@
+// Output module (Conv3x3 p1, 16 -> 1, plus bias) and its adjoint on LDS tiles (gfx950).
+//
+// Forward: a block stages the 16-channel input of a TH x TW pixel tile plus a 1-pixel halo
+// (zeros off the map) and each thread forms one output pixel from the staged neighbourhood.
+// Adjoint: a block stages dz of the tile plus halo; thread items are (pixel, group of 4
+// channels) and compute dd[c](p) = sum_t dz(p - off_t) w[c][t] and accumulate the weight
+// gradient sum_p d[c](p) dz(p - off_t) (tap t = (ky, kx), off_t = (ky - 1, kx - 1)) and the bias
+// gradient sum_p dz(p); part[blk][10][16] holds the taps (rows 0..8) and the bias (row 9,
+// channel 0).  The grid loops over the tiles of all clips.
+#pragma once
+#include "stage1_tile.h"
+
+namespace stda {
+
+constexpr int kHeadTH = 8, kHeadTW = 32;
+
+template <class T>
+__global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, const float* __restrict__ w,
+                                                       const float* __restrict__ bias, float* __restrict__ z, int B,
+                                                       int H, int W) {
+  constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, PS = C + 4;
+  __shared__ float xt[(TH + 2) * RW * PS];
+  __shared__ float wt[9 * C];  // [tap][c]
+  for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) wt[q] = w[(q % C) * 9 + q / C];
+  const float b0 = bias[0];
+  const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int b, y0, x0;
+    tile_coords(tile, H, W, TH, TW, b, y0, x0);
+    __syncthreads();
+    load_tile<T, C, TH, TW, 1>(d, b, y0, x0, H, W, xt);
+    __syncthreads();
+    const int r = threadIdx.x / TW, cc = threadIdx.x % TW;  // one pixel per thread
+    const int y = y0 + r, x = x0 + cc;
+    if (y < H && x < W) {
+      float acc = b0;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const float* px = xt + ((r + t / 3) * RW + cc + t % 3) * PS;
+#pragma unroll
+        for (int c = 0; c < C; c += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(px + c);
+          acc += wt[t * C + c] * v.x + wt[t * C + c + 1] * v.y + wt[t * C + c + 2] * v.z + wt[t * C + c + 3] * v.w;
+        }
+      }
+      z[((int64_t)b * H + y) * W + x] = acc;
+    }
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__ dz, const float* __restrict__ w,
+                                                       const T* __restrict__ d, T* __restrict__ dd,
+                                                       float* __restrict__ part, int B, int H, int W) {
+  constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, G = 4, RW = TW + 2;
+  static_assert(TH * TW == STDA_BLOCK, "one pixel per thread and channel group pass");
+  __shared__ float zt[(TH + 2) * RW];
+  __shared__ float sm[4 * 10 * C];
+  __shared__ float red[10 * C];
+  const int c0 = (threadIdx.x % G) * 4;
+  float wr[9][4];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wr[t][j] = w[(c0 + j) * 9 + t];
+  float acc[10][4];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) zero4(acc[t]);
+  const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int b, y0, x0;
+    tile_coords(tile, H, W, TH, TW, b, y0, x0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < (TH + 2) * RW; q += STDA_BLOCK) {
+      const int y = y0 - 1 + q / RW, x = x0 - 1 + q % RW;
+      zt[q] = (y >= 0 && y < H && x >= 0 && x < W) ? dz[((int64_t)b * H + y) * W + x] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int e = threadIdx.x + k * STDA_BLOCK;
+      const int px = e / G, r = px / TW, cc = px % TW;
+      const int y = y0 + r, x = x0 + cc;
+      if (y >= H || x >= W) continue;
+      const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
+      float dv[4], o[4];
+      ld4(d + off, dv);
+      zero4(o);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        // dz at p - off_t = (y - ky + 1, x - kx + 1): tile position (r + 2 - ky, cc + 2 - kx)
+        const float g = zt[(r + 2 - t / 3) * RW + cc + 2 - t % 3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          o[j] += wr[t][j] * g;
+          acc[t][j] += dv[j] * g;
+        }
+      }
+      if (c0 == 0) acc[9][0] += zt[(r + 1) * RW + cc + 1];
+      st4(dd + off, o);
+    }
+  }
+  block_chan_reduce_shfl<G, 10>(acc, sm, red);
+  for (int q = threadIdx.x; q < 10 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 10 * C + q] = red[q];
+}
+
+}  // namespace stda

@@ -22,6 +22,7 @@
 #include "s2_tile.h"
 #include "stage1_tile.h"
 #include "stem_tile.h"
+#include "head_tile.h"
 
 using namespace stda;
 
@@ -492,13 +493,19 @@ int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const T* src,
 template <int C>
 int s1_grid(int n, int h, int w) {
   const int64_t tiles = (int64_t)n * ((h + S1Tile<C>::TH - 1) / S1Tile<C>::TH) * ((w + S1Tile<C>::TW - 1) / S1Tile<C>::TW);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
 }
 
-// Blocks of the tiled input-module kernels (8 x 32 pixel tiles), at most kMaxGrid.
+// Blocks of the tiled input-module kernels (8 x 32 pixel tiles), at most kTileGrid.
 int stem_grid(int n, int H, int W) {
   const int64_t tiles = (int64_t)n * ((H + 7) / 8) * ((W + 31) / 32);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+}
+
+// Blocks of the tiled output-module kernels, at most kTileGrid.
+int head_grid(int n, int H, int W) {
+  const int64_t tiles = (int64_t)n * ((H + kHeadTH - 1) / kHeadTH) * ((W + kHeadTW - 1) / kHeadTW);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
 }
 
 // Column sums of per-block BN partials followed by the statistics finalize.
@@ -619,8 +626,9 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
   if (int r = fwd_block<T, 32, 16, true>(c, 3, running)) return r;
-  KLAUNCH("head_fwd", k_head_fwd<T><<<grid_for(P), 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w, c.w + no.head_b,
-                                               z + S.z_off, S.n, S.H, S.W));
+  const int gz = head_grid(S.n, S.H, S.W);
+  KLAUNCH("head_fwd", k_head_fwd_tile<T><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
+                                                               c.w + no.head_b, z + S.z_off, S.n, S.H, S.W));
   return STDA_OK;
 }
 
@@ -915,9 +923,9 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   // output module
   {
     float* part = c.template scr<float>(c.P->ws_part);
-    const int gh = grid_for(P * 4);
-    KLAUNCH("head_bwd", k_head_bwd<T><<<gh, 256, 0, c.st>>>(dzs, c.w + no.head_w, c.template act<T>(S.blk[3].Xn), gb(0), part, S.n, S.H,
-                                        S.W));
+    const int gh = head_grid(S.n, S.H, S.W);
+    KLAUNCH("head_bwd", k_head_bwd_tile<T><<<gh, 256, 0, c.st>>>(dzs, c.w + no.head_w, c.template act<T>(S.blk[3].Xn),
+                                                                 gb(0), part, S.n, S.H, S.W));
     if (int r = colsum_to(c, part, gh, 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)

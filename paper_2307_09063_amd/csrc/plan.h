@@ -25,7 +25,8 @@ constexpr BlockCfg kBlocks[4] = {
 
 constexpr int kMaxSegs = 8;
 constexpr int kMaxGrid = 2048;       // blocks of per-pixel kernels (bounds partial buffers)
-constexpr int kMaxTiles = 64;        // blocks per clip of per-clip kernels
+constexpr int kTileGrid = 1024;      // blocks of the persistent LDS-tile kernels (4 per CU)
+constexpr int kMaxTiles = 16;        // blocks per clip of per-clip kernels
 constexpr int kMaxWgradGrid = 512;   // blocks of weight-gradient kernels
 constexpr int kNumGradBufs = 13;
 

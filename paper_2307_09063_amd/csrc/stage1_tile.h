@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 // LDS (never in HBM); the three pointwise products (p = x Wp, dP Wp^T, x^T dP) run on the matrix
 // cores, the last one accumulating in registers across tiles.
 template <class T, int C, bool DEC, bool SKIP>
-__global__ __launch_bounds__(256) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
+__global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
                                                       const T* __restrict__ dX1, const T* __restrict__ dXr,
                                                       const T* __restrict__ skip, const float* __restrict__ coef,
                                                       S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
