@@ -739,13 +739,6 @@ int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* d
   return STDA_OK;
 }
 
-template <class L>
-constexpr int pch_for() {
-  constexpr int per = (L::K + L::N) * 4;
-  constexpr int p = 40960 / per;
-  return p >= 64 ? 64 : p >= 32 ? 32 : p >= 16 ? 16 : p >= 8 ? 8 : 4;
-}
-
 // Weight gradient on the matrix cores; the pixel range is split so that about 1024 blocks run,
 // and the per-split partials are summed in FP64 into the destination.
 template <int D>

@@ -157,25 +157,6 @@ struct BnOut {
   float* stats[3];
   float* running[3];
 };
-__global__ void k_bn_stats_finalize(const double* __restrict__ sums, int NB, int C, double count,
-                                    BnOut out, int update_running) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NB * C) return;
-  const int i = t / C, c = t % C;
-  const double S = sums[(i * C + c) * 2], Q = sums[(i * C + c) * 2 + 1];
-  const double mean = S / count;
-  double var = Q / count - mean * mean;
-  if (var < 0.0) var = 0.0;
-  out.stats[i][c] = (float)mean;
-  out.stats[i][C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
-  if (update_running) {
-    float* r = out.running[i];
-    const double unb = count > 1.0 ? var * count / (count - 1.0) : var;
-    r[c] = (float)(0.9 * (double)r[c] + 0.1 * mean);
-    r[C + c] = (float)(0.9 * (double)r[C + c] + 0.1 * unb);
-  }
-}
-
 // Cross-block FP64 reduction of batch-norm statistics partials fused with their finalize.
 // part[blk][NB][C][2]: (sum, sum of squares) per BN layer and channel.  Block = 4 channels of
 // one layer (8 columns) x 32 row groups; fixed summation order.
@@ -229,76 +210,6 @@ __global__ void k_eval_stats(const float* __restrict__ running, float* __restric
   }
 }
 
-// --------------------------------------------------------------------- input module
-// Conv3x3 p1, 3 -> 16 on the planar FP32 maps (channel concatenation of frames t, t-1, t-2).
-// Channels c0..c0+NCH-1 of pixel (b, y, x).
-template <int NCH>
-__device__ __forceinline__ void stem_conv(const float* __restrict__ x, const float* __restrict__ w, int b, int y,
-                                          int xx, int H, int W, int c0, float* acc) {
-#pragma unroll
-  for (int o = 0; o < NCH; ++o) acc[o] = 0.f;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int ky = 0; ky < 3; ++ky) {
-      const int iy = y + ky - 1;
-#pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const int ix = xx + kx - 1;
-        const float v = (iy >= 0 && iy < H && ix >= 0 && ix < W) ? x[(((int64_t)b * 3 + c) * H + iy) * W + ix] : 0.f;
-#pragma unroll
-        for (int o = 0; o < NCH; ++o) acc[o] += w[(c0 + o) * 27 + c * 9 + ky * 3 + kx] * v;
-      }
-    }
-}
-
-// MODE 0 (TRAIN statistics): per-block (sum, sum of squares) of the conv output, part[blk][16][2];
-// nothing is stored.  MODE 1: writes ReLU(BN(conv)) with the given statistics (batch or running).
-// The pre-BN output is never stored: it is recomputed (432 MACs per pixel) where needed.
-template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_stem_fwd(const float* __restrict__ x, const float* __restrict__ w,
-                                                  T* __restrict__ out, float* __restrict__ part,
-                                                  const float* __restrict__ stats, const float* __restrict__ gamma,
-                                                  const float* __restrict__ beta, int B, int H, int W) {
-  __shared__ float sm[MODE == 0 ? 32 * STDA_BLOCK : 1];
-  __shared__ float red[32];
-  const int64_t P = (int64_t)B * H * W;
-  float acc1[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) acc1[i] = 0.f;
-  float sc[16], sh[16];
-  if (MODE == 1) {
-#pragma unroll
-    for (int o = 0; o < 16; ++o) {
-      sc[o] = gamma[o] * stats[16 + o];
-      sh[o] = beta[o] - stats[o] * sc[o];
-    }
-  }
-  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
-    int b, y, xx;
-    pix3(p, H, W, b, y, xx);
-    float acc[16];
-    stem_conv<16>(x, w, b, y, xx, H, W, 0, acc);
-    if (MODE == 0) {
-#pragma unroll
-      for (int o = 0; o < 16; ++o) {
-        acc1[2 * o] += acc[o];
-        acc1[2 * o + 1] += acc[o] * acc[o];
-      }
-    } else {
-#pragma unroll
-      for (int o = 0; o < 16; ++o) acc[o] = fmaxf(acc[o] * sc[o] + sh[o], 0.f);
-      T* op = out + p * 16;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) st4(op + 4 * q, acc + 4 * q);
-    }
-  }
-  if (MODE == 0) {
-    block_vec_reduce<32>(acc1, sm, red);
-    if (threadIdx.x < 32) part[(int64_t)blockIdx.x * 32 + threadIdx.x] = red[threadIdx.x];
-  }
-}
-
 // --------------------------------------------------------------------- stage 1
 // Branches of stage 1 (mobile encoder / decoder block, first equation group): pointwise
 // (C x C), depthwise 3x3 and identity.  Weights staged in LDS:
@@ -320,43 +231,7 @@ __device__ __forceinline__ void stage1_load_weights(const float* __restrict__ wp
   __syncthreads();
 }
 
-template <class T, int C>
-__device__ __forceinline__ void stage1_branches(const T* __restrict__ X, int64_t p, int b, int y, int x, int h,
-                                                int w, int c0, const float* wp, const float* wd, float pv[4],
-                                                float dv[4], float xv[4]) {
-  zero4(pv);
-  zero4(dv);
-  const T* row = X + p * C;
-#pragma unroll 4
-  for (int c = 0; c < C; c += 4) {
-    float v[4];
-    ld4(row + c, v);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float4 wq = *reinterpret_cast<const float4*>(wp + (c + j) * C + c0);
-      pv[0] += wq.x * v[j];
-      pv[1] += wq.y * v[j];
-      pv[2] += wq.z * v[j];
-      pv[3] += wq.w * v[j];
-    }
-  }
-  ld4(row + c0, xv);
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-    if (yy < 0 || yy >= h || xx < 0 || xx >= w) continue;
-    float v[4];
-    ld4(X + (((int64_t)b * h + yy) * w + xx) * C + c0, v);
-    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
-    dv[0] += wq.x * v[0];
-    dv[1] += wq.y * v[1];
-    dv[2] += wq.z * v[2];
-    dv[3] += wq.w * v[3];
-  }
-}
-
-// MODE 0: per-block partials of (sum, sumsq) for the three BN inputs -> part[blk][3][C][2].
-// MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)).
+// Parameters of the stage-1 kernels (weights, batch statistics and affine of the three BNs).
 struct S1Params {
   const float* wpw;
   const float* wdw;
@@ -364,62 +239,8 @@ struct S1Params {
   const float* gamma[3];
   const float* beta[3];
 };
-template <class T, int C, bool DEC, int MODE>
-__global__ __launch_bounds__(256) void k_stage1(const T* __restrict__ X, T* __restrict__ X1, float* __restrict__ part,
-                                                S1Params prm, int B, int h, int w) {
-  constexpr int G = C / 4;
-  __shared__ float wp[C * C];
-  __shared__ float wd[9 * C];
-  __shared__ float sm[(MODE == 0 ? 6 : 1) * 4 * STDA_BLOCK];
-  __shared__ float red[6 * C];
-  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
-  const int64_t P = (int64_t)B * h * w;
-  const int64_t items = P * G;
-  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
-  const int c0 = (int)(i % G) * 4;
-  float acc[6][4];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) zero4(acc[s]);
-  float sc[3][4], sh[3][4];
-  if (MODE == 1)
-#pragma unroll
-    for (int k = 0; k < 3; ++k) bn_affine4(prm.stats[k], prm.gamma[k], prm.beta[k], C, c0, sc[k], sh[k]);
-  for (; i < items; i += stride) {
-    const int64_t p = i / G;
-    int b, y, x;
-    pix3(p, h, w, b, y, x);
-    float pv[4], dv[4], xv[4];
-    stage1_branches<T, C>(X, p, b, y, x, h, w, c0, wp, wd, pv, dv, xv);
-    if (MODE == 0) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[0][j] += pv[j];
-        acc[1][j] += pv[j] * pv[j];
-        acc[2][j] += dv[j];
-        acc[3][j] += dv[j] * dv[j];
-        acc[4][j] += xv[j];
-        acc[5][j] += xv[j] * xv[j];
-      }
-    } else {
-      float o[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        o[j] = fmaxf(pv[j] * sc[0][j] + sh[0][j] + dv[j] * sc[1][j] + sh[1][j] + xv[j] * sc[2][j] + sh[2][j], 0.f);
-      st4(X1 + p * C + c0, o);
-    }
-  }
-  if (MODE == 0) {
-    block_chan_reduce<G, 6>(acc, sm, red);
-    // red[s*C + c], s = 2k + m  ->  part[blk][k][c][m]
-    for (int q = threadIdx.x; q < 6 * C; q += STDA_BLOCK) {
-      const int s = q / C, c = q % C;
-      part[(int64_t)blockIdx.x * 6 * C + ((s >> 1) * C + c) * 2 + (s & 1)] = red[q];
-    }
-  }
-}
 
-// ---------------------------------------------------------- dense stride-2 layers (SIMT)
+// ---------------------------------------------------------- dense stride-2 layers: tap rules
 // out[p][n] = sum over taps and input channels of src[...][k] * wl[tap][k][n]:
 //   OP_ENC_FWD   Conv3x3-s2-p1, src grid 2h x 2w -> dst h x w, taps: sy = 2y - 1 + ky
 //   OP_DEC_DGRAD adjoint of DeConv4x4-s2-p1 (a Conv4x4-s2-p1), same tap rule with k = 4
@@ -433,75 +254,6 @@ template <int OP> struct OpGeo {
   static constexpr int KS = (OP == OP_ENC_FWD || OP == OP_ENC_DGRAD) ? 3 : 4;
   static constexpr bool DOWN = (OP == OP_ENC_FWD || OP == OP_DEC_DGRAD);
 };
-
-template <class T, int OP, int K, int N, bool STATS>
-__global__ __launch_bounds__(256) void k_dense_simt(const T* __restrict__ src, const float* __restrict__ wl,
-                                                    T* __restrict__ dst, float* __restrict__ part, int B, int hd,
-                                                    int wd) {
-  constexpr int G = N / 4;
-  constexpr int KS = OpGeo<OP>::KS;
-  __shared__ float sm[(STATS ? 2 : 1) * 4 * STDA_BLOCK];
-  __shared__ float red[2 * N];
-  const int hs = OpGeo<OP>::DOWN ? hd * 2 : hd / 2;
-  const int ws = OpGeo<OP>::DOWN ? wd * 2 : wd / 2;
-  const int64_t P = (int64_t)B * hd * wd;
-  const int64_t items = P * G;
-  const int64_t stride = (int64_t)gridDim.x * STDA_BLOCK;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
-  const int n0 = (int)(i % G) * 4;
-  float st[2][4];
-  zero4(st[0]);
-  zero4(st[1]);
-  for (; i < items; i += stride) {
-    const int64_t p = i / G;
-    int b, y, x;
-    pix3(p, hd, wd, b, y, x);
-    float acc[4];
-    zero4(acc);
-#pragma unroll
-    for (int a = 0; a < (OpGeo<OP>::DOWN ? KS : 2); ++a) {
-      const int ky = OpGeo<OP>::DOWN ? a : ((y + 1) & 1) + 2 * a;
-      const int sy = OpGeo<OP>::DOWN ? 2 * y - 1 + ky : (y + 1 - ky) / 2;
-      if (ky >= KS || sy < 0 || sy >= hs) continue;
-#pragma unroll
-      for (int c = 0; c < (OpGeo<OP>::DOWN ? KS : 2); ++c) {
-        const int kx = OpGeo<OP>::DOWN ? c : ((x + 1) & 1) + 2 * c;
-        const int sx = OpGeo<OP>::DOWN ? 2 * x - 1 + kx : (x + 1 - kx) / 2;
-        if (kx >= KS || sx < 0 || sx >= ws) continue;
-        const T* row = src + (((int64_t)b * hs + sy) * ws + sx) * K;
-        const float* wt = wl + (int64_t)(ky * KS + kx) * K * N + n0;
-#pragma unroll 4
-        for (int k = 0; k < K; k += 4) {
-          float v[4];
-          ld4(row + k, v);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float4 wq = *reinterpret_cast<const float4*>(wt + (k + j) * N);
-            acc[0] += wq.x * v[j];
-            acc[1] += wq.y * v[j];
-            acc[2] += wq.z * v[j];
-            acc[3] += wq.w * v[j];
-          }
-        }
-      }
-    }
-    st4(dst + p * N + n0, acc);
-    if (STATS) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        st[0][j] += acc[j];
-        st[1][j] += acc[j] * acc[j];
-      }
-    }
-  }
-  if (STATS) {
-    block_chan_reduce<G, 2>(st, sm, red);
-    for (int q = threadIdx.x; q < 2 * N; q += STDA_BLOCK) {
-      const int s = q / N, c = q % N;
-      part[(int64_t)blockIdx.x * 2 * N + c * 2 + s] = red[q];
-    }
-  }
-}
 
 // --------------------------------------------------------------- stage 2 apply + GAP
 // Y = ReLU(BN(T)) + R; per-(clip, tile) channel sums of Y for the ECA global average pool.
@@ -598,34 +350,6 @@ __global__ __launch_bounds__(256) void k_eca_next(const T* __restrict__ Y, const
       for (int j = 0; j < 4; ++j) o[j] += s[j];
     }
     st4(Xn + off, o);
-  }
-}
-
-// --------------------------------------------------------------------- output module
-// z = Conv3x3-p1(d, 16 -> 1) + bias, planar FP32 output.
-template <class T>
-__global__ __launch_bounds__(256) void k_head_fwd(const T* __restrict__ d, const float* __restrict__ w,
-                                                  const float* __restrict__ bias, float* __restrict__ z, int B,
-                                                  int H, int W) {
-  const int64_t P = (int64_t)B * H * W;
-  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
-    int b, y, x;
-    pix3(p, H, W, b, y, x);
-    float acc = bias[0];
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-      if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-      const T* row = d + (((int64_t)b * H + yy) * W + xx) * 16;
-#pragma unroll
-      for (int c = 0; c < 16; c += 4) {
-        float v[4];
-        ld4(row + c, v);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc += w[(c + j) * 9 + t] * v[j];
-      }
-    }
-    z[p] = acc;
   }
 }
 
