@@ -265,17 +265,26 @@ typedef struct {
 } rd_tone;
 
 /*
- * FMCW interferer of one frame after dechirping (Sec. III-A, Eq. (IF signal)): beat frequency
- * F(n, m) = 2 q n + f0 + m dl (signed, 2^-32 cycles/sample); the term
- * a exp(j 2 pi ((f0 + m dl) n + q n^2 + phi_m) / 2^32) is present while |F| < 2^31.
- * phi_m = word 0 of Philox4x32-10(counter = (m, i, frame, 1), key = (seed, clip)).
+ * FMCW interferer of one frame after dechirping (Sec. III-A, Eq. (IF signal)).  All frequencies
+ * are signed 2^-32 cycles/sample.  The start beat frequency of victim chirp m is
+ *   g(m) = f0 + m dl                          (wrap == 0)
+ *   g(m) = f0 + ((s0 + m dl) mod wrap)        (wrap > 0, the remainder in [0, wrap)): the
+ *          aggressor's own ramp, sampled at each victim chirp start, is a sawtooth of span wrap;
+ * the beat frequency is F(n, m) = 2 q n + g(m) and the term a exp(j 2 pi (g(m) n + q n^2 + phi_m)
+ * / 2^32) is present while |F| < 2^31 (an ideal IF low-pass at half the sampling rate).
+ * phi_m = word 0 of Philox4x32-10(counter = (m, i, frame, 1), key = (seed, clip)) when
+ * coherent == 0, else ph0 + m phd (mod 2^32; oscillators coherent from chirp to chirp).
  */
 typedef struct {
   int64_t q;
   int64_t f0;
   int64_t dl;
+  int64_t s0;
+  int64_t wrap;
+  uint32_t ph0;
+  uint32_t phd;
   float amp;
-  uint32_t pad;
+  uint32_t coherent;
 } rd_intf;
 
 typedef struct {

@@ -12,11 +12,14 @@ Normalised encoding of a scene (the scene table the generator hands over; see th
 `synth_clip`):
   * tone k of a frame: s(n, m) = a * exp(j 2 pi u / 2^32), u = (fr*n + fd*m + ph) mod 2^32,
     with fr, fd, ph unsigned 32-bit fixed-point cycles (per sample, per chirp, absolute).
-  * interferer i of a frame: instantaneous beat frequency F(n, m) = 2*q*n + f0 + m*dl (signed
-    fixed point, 2^-32 cycles/sample); the term a * exp(j 2 pi P / 2^32) with
-    P = (f0 + m*dl)*n + q*n^2 + phi_m mod 2^32 is kept only while |F| < 2^31 (an ideal IF
-    low-pass at half the sampling rate after dechirping); phi_m is word 0 of
-    Philox4x32-10(counter=(m, i, frame, 1), key=(seed, clip)).
+  * interferer i of a frame: start beat frequency of chirp m g(m) = f0 + m*dl, or, when
+    wrap > 0, g(m) = f0 + ((s0 + m*dl) mod wrap) (the aggressor's own ramp seen at each victim
+    chirp start: a sawtooth of span wrap); instantaneous beat frequency F(n, m) = 2*q*n + g(m)
+    (signed fixed point, 2^-32 cycles/sample); the term a * exp(j 2 pi P / 2^32) with
+    P = g(m)*n + q*n^2 + phi_m mod 2^32 is kept only while |F| < 2^31 (an ideal IF low-pass at
+    half the sampling rate after dechirping); phi_m is word 0 of
+    Philox4x32-10(counter=(m, i, frame, 1), key=(seed, clip)), or ph0 + m*phd mod 2^32 when
+    the record is marked coherent.
   * noise: Philox4x32-10(counter=(n, m, frame, 0), key=(seed, clip)) words 0, 1 -> two
     uniforms -> Box-Muller -> re, im, each scaled by sigma/sqrt(2).
   * periodic Hann window on both axes, 2-D DFT (0-based index; a 1-based index only rotates the
@@ -104,20 +107,31 @@ def beat_signal(scene, clip, frame, with_interference=True):
             q = int(scene['intf_q'][clip, frame, i])
             f0 = int(scene['intf_f0'][clip, frame, i])
             dl = int(scene['intf_dl'][clip, frame, i])
+            wrap = int(scene['intf_wrap'][clip, frame, i]) if 'intf_wrap' in scene else 0
+            s0 = int(scene['intf_s0'][clip, frame, i]) if 'intf_s0' in scene else 0
+            coherent = int(scene['intf_coherent'][clip, frame, i]) if 'intf_coherent' in scene else 0
             amp = float(scene['intf_amp'][clip, frame, i])
             mm = np.arange(M, dtype=np.int64)
-            phi = philox4x32_10(mm.astype(np.uint64), i, frame, 1, seed, clip)[0]
+            # start beat frequency of each victim chirp, exact integers (the aggressor's ramp
+            # sampled at the chirp starts is a sawtooth of span `wrap` when wrap > 0)
+            g = np.array([f0 + m * dl if wrap == 0 else f0 + (s0 + m * dl) % wrap for m in range(M)],
+                         dtype=np.int64)
+            if coherent:
+                ph0 = int(scene['intf_ph0'][clip, frame, i])
+                phd = int(scene['intf_phd'][clip, frame, i])
+                phi = np.array([(ph0 + m * phd) % 2 ** 32 for m in range(M)], dtype=np.uint64)
+            else:
+                phi = philox4x32_10(mm.astype(np.uint64), i, frame, 1, seed, clip)[0]
             nn = np.arange(N, dtype=np.int64)[:, None]
-            fi = 2 * q * nn + f0 + mm[None, :] * dl                 # exact int64
+            fi = 2 * q * nn + g[None, :]                            # exact int64
             keep = np.abs(fi) < 2 ** 31
             # phase mod 2^32: two's-complement uint64 arithmetic wraps mod 2^64, whose low
             # 32 bits are the value mod 2^32
             u64 = lambda v: np.uint64(v % 2 ** 64)
             nu = np.arange(N, dtype=np.uint64)[:, None]
-            mu = np.arange(M, dtype=np.uint64)[None, :]
+            gu = g.astype(np.uint64)[None, :]                      # two's complement: g mod 2^64
             with np.errstate(over='ignore'):
-                P = ((u64(f0) + mu * u64(dl)) * nu + u64(q) * (nu * nu) + phi[None, :]) \
-                    & np.uint64(MASK32)
+                P = (gu * nu + u64(q) * (nu * nu) + phi[None, :]) & np.uint64(MASK32)
             s += np.where(keep, amp * phase_to_unit(P), 0.0)
     seed = int(scene['seed'])
     nn = np.broadcast_to(np.arange(N, dtype=np.uint64)[:, None], (N, M))

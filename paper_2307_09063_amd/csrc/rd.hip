@@ -68,11 +68,18 @@ __device__ __forceinline__ float2 synth_sample(const rd_scene& sc, int frame, bo
     const int ni = sc.n_intf[frame];
     for (int i = 0; i < ni; ++i) {
       const rd_intf f = sc.intf[frame][i];
-      const int64_t F = 2 * f.q * n + f.f0 + (int64_t)m * f.dl;  // beat frequency, exact
-      if (F >= -2147483648LL && F < 2147483648LL && F != -2147483648LL) {
-        const uint32_t phi = philox((uint32_t)m, (uint32_t)i, (uint32_t)frame, 1u, seed, clip_id).x;
-        const uint64_t P = ((uint64_t)f.f0 + (uint64_t)m * (uint64_t)f.dl) * (uint64_t)n +
-                           (uint64_t)f.q * (uint64_t)((int64_t)n * n) + (uint64_t)phi;
+      // start beat frequency of chirp m: linear in m, or the aggressor's sawtooth (span wrap)
+      int64_t g = f.f0 + (int64_t)m * f.dl;
+      if (f.wrap > 0) {
+        int64_t r = (f.s0 + (int64_t)m * f.dl) % f.wrap;
+        if (r < 0) r += f.wrap;
+        g = f.f0 + r;
+      }
+      const int64_t F = 2 * f.q * n + g;  // beat frequency, exact
+      if (F > -2147483648LL && F < 2147483648LL) {
+        const uint32_t phi = f.coherent ? f.ph0 + (uint32_t)m * f.phd
+                                        : philox((uint32_t)m, (uint32_t)i, (uint32_t)frame, 1u, seed, clip_id).x;
+        const uint64_t P = (uint64_t)g * (uint64_t)n + (uint64_t)f.q * (uint64_t)((int64_t)n * n) + (uint64_t)phi;
         float c, s;
         cis_u32((uint32_t)P, c, s);
         re += f.amp * c;

@@ -38,8 +38,8 @@ RD_MAX_TONES = 48
 RD_MAX_INTF = 4
 
 TONE_DTYPE = np.dtype([('fr', '<u4'), ('fd', '<u4'), ('ph', '<u4'), ('amp', '<f4')], align=True)
-INTF_DTYPE = np.dtype([('q', '<i8'), ('f0', '<i8'), ('dl', '<i8'), ('amp', '<f4'), ('pad', '<u4')],
-                      align=True)
+INTF_DTYPE = np.dtype([('q', '<i8'), ('f0', '<i8'), ('dl', '<i8'), ('s0', '<i8'), ('wrap', '<i8'),
+                       ('ph0', '<u4'), ('phd', '<u4'), ('amp', '<f4'), ('coherent', '<u4')], align=True)
 SCENE_DTYPE = np.dtype([('n_tones', '<i4', (3,)), ('n_intf', '<i4', (3,)),
                         ('tone', TONE_DTYPE, (3, RD_MAX_TONES)),
                         ('intf', INTF_DTYPE, (3, RD_MAX_INTF))], align=True)
@@ -127,6 +127,98 @@ def make_scenes(n_clips, N, M, seed, targets=(1, 3), intf=(1, 1), inr=(20.0, 20.
     return tab, meta
 
 
+# --------------------------------------------------------------- physical-units interferers
+# Victim ramp (Table 3): 153.6 MHz swept over the N-sample ADC window at 12.5 MHz (30 MHz/us at
+# N = 64), carrier 77 GHz, one victim chirp every T_CHIRP.  An aggressor (Table 4, or the
+# ratio scenarios of Table 2) with carrier fc_i, sweep bandwidth B_i over duration T_i (ramps
+# back to back), one-way radial velocity v (negative: approaching) and a random ramp timing
+# t_off gives, per victim chirp m, the beat frequency (received minus victim, cycles/sample)
+#   F(n, m) = (fc_i - fc_v + f_D) / f_s + (S_i u_m) / f_s + (S_i - S_v) n / f_s^2,
+#   u_m = (m T_CHIRP - t_off) mod T_i,  S = sweep slope,  f_D = -v fc_i / c,
+# i.e. q = (S_i - S_v) / (2 f_s^2), f0 = (fc_i - fc_v + f_D) / f_s, dl = S_i T_CHIRP / f_s,
+# s0 = -S_i t_off / f_s, wrap = B_i / f_s, and the two carriers stay coherent from chirp to
+# chirp: the relative phase advances by (fc_i - fc_v + f_D) T_CHIRP cycles per victim chirp.
+# The aggressor's ramp is taken as continuing through the victim's sampling window (no reset
+# inside it).  The amplitude follows the signal-to-interference ratio per sample, relative to
+# the mean power of the clip's targets.
+F_S = 12.5e6
+B_VICTIM = 153.6e6
+FC_VICTIM = 77e9
+C_LIGHT = 299792458.0
+TABLE2 = {  # scenario: (ratio of sweep bandwidth, ratio of sweep duration, carrier offset in Hz)
+    1: (1.0, 1.0, 0.0), 2: (1.0, 1.1, 0.0), 3: (1.0, 2.0, 0.0), 4: (2.0, 1.0, 0.0),
+    5: (1.0, 1.0, -20e6), 6: (2.0, 1.1, 0.0), 7: (2.0, 2.0, 0.0),
+}
+T_SWEEP_VICTIM = 21.12e-6   # victim sweep duration (Table 3), the unit of the Table 2 ratios
+
+
+def aggressor_record(e, N, fc_i, b_i, t_i, v, t_off, ph0, amp):
+    """Fill one interferer record from physical aggressor parameters (SI units)."""
+    s_v = B_VICTIM * F_S / N
+    s_i = b_i / t_i
+    f_d = -v * fc_i / C_LIGHT
+    base = (fc_i - FC_VICTIM + f_d) / F_S
+    wrap = b_i / F_S
+    e['q'] = _fx_signed(0.5 * (s_i - s_v) / F_S ** 2)
+    e['f0'] = _fx_signed(base)
+    e['dl'] = _fx_signed(s_i * T_CHIRP / F_S)
+    e['wrap'] = _fx_signed(wrap)
+    e['s0'] = _fx_signed((-s_i * t_off / F_S) % wrap)
+    e['ph0'] = _fx(ph0)
+    e['phd'] = _fx((fc_i - FC_VICTIM + f_d) * T_CHIRP)
+    e['coherent'] = 1
+    e['amp'] = np.float32(amp)
+
+
+def make_scenes_table4(n_clips, N, M, seed, targets=(1, 3), clutter=False, snr_db=10.0, noise_sigma=1.0):
+    """Scenes with one aggressor per clip drawn from the intervals of Table 4: SIR level
+    U{-5, 0, ..., 25} dB, carrier U{76.8, 76.9, ..., 77.2} GHz, sweep bandwidth U[120, 400] MHz,
+    sweep duration U[4, 30] us, distance U[2, 63] m (recorded), radial velocity U[-23.05, 0] m/s;
+    the ramp timing is redrawn per frame.  Targets and clutter as in make_scenes.  meta['aggressor']
+    lists the draws."""
+    tab, meta = make_scenes(n_clips, N, M, seed, targets=targets, intf=(0, 0), clutter=clutter, snr_db=snr_db,
+                            noise_sigma=noise_sigma)
+    rng = np.random.default_rng([seed, 4])
+    draws = []
+    for b in range(n_clips):
+        sir = float(rng.choice(np.arange(-5, 30, 5)))
+        fc_i = 76.8e9 + 0.1e9 * int(rng.integers(0, 5))
+        b_i = rng.uniform(120e6, 400e6)
+        t_i = rng.uniform(4e-6, 30e-6)
+        dist = rng.uniform(2.0, 63.0)
+        v = rng.uniform(-23.05, 0.0)
+        nt = int(tab[b]['n_tones'][0])
+        p_sig = float(np.mean(tab[b]['tone'][0, :nt]['amp'].astype(np.float64) ** 2)) if nt else noise_sigma ** 2
+        amp = np.sqrt(p_sig / 10.0 ** (sir / 10.0))
+        for f in range(3):
+            aggressor_record(tab[b]['intf'][f, 0], N, fc_i, b_i, t_i, v, rng.uniform(0.0, t_i), rng.random(), amp)
+            tab[b]['n_intf'][f] = 1
+        draws.append(dict(sir_db=sir, fc=fc_i, bandwidth=b_i, duration=t_i, distance=dist, velocity=v))
+    meta['aggressor'] = draws
+    return tab, meta
+
+
+def table2_scene(scenario, N, M, seed, amp=3.0, beat0=None, noise_sigma=1.0):
+    """One clip with one target and the aggressor of Table 2 scenario 1..7 (ratios of sweep
+    bandwidth and duration to the victim's, carrier offset), stationary, every frame the same;
+    amp is the aggressor's amplitude per sample.
+    The ramp timing is random, or chosen so that the aggressor's ramp offset at the victim's chirp
+    start is beat0 cycles/sample (beat0 = s(0), the sawtooth value of chirp 0)."""
+    rb, rt, dfc = TABLE2[scenario]
+    t_i = rt * T_SWEEP_VICTIM
+    s_i = rb / rt * (B_VICTIM * F_S / N)    # the victim's slope times the ratio of slopes
+    b_i = s_i * t_i
+    wrap = b_i / F_S
+    tab, meta = make_scenes(1, N, M, seed, targets=(1, 1), intf=(0, 0), noise_sigma=noise_sigma)
+    rng = np.random.default_rng([seed, 2])
+    t_off = rng.uniform(0.0, t_i) if beat0 is None else ((wrap - beat0) % wrap) * F_S / s_i
+    for f in range(3):
+        aggressor_record(tab[0]["intf"][f, 0], N, FC_VICTIM + dfc, b_i, t_i, 0.0, t_off, 0.0, amp)
+        tab[0]['n_intf'][f] = 1
+    meta['aggressor'] = [dict(scenario=scenario, bandwidth=b_i, duration=t_i, t_off=t_off)]
+    return tab, meta
+
+
 def scene_dict(tab, meta):
     """The scene table as plain arrays (the form the oracle reads)."""
     return {
@@ -136,6 +228,8 @@ def scene_dict(tab, meta):
         'tone_fr': tab['tone']['fr'], 'tone_fd': tab['tone']['fd'], 'tone_ph': tab['tone']['ph'],
         'tone_amp': tab['tone']['amp'].astype(np.float64),
         'intf_q': tab['intf']['q'], 'intf_f0': tab['intf']['f0'], 'intf_dl': tab['intf']['dl'],
+        'intf_s0': tab['intf']['s0'], 'intf_wrap': tab['intf']['wrap'], 'intf_ph0': tab['intf']['ph0'],
+        'intf_phd': tab['intf']['phd'], 'intf_coherent': tab['intf']['coherent'],
         'intf_amp': tab['intf']['amp'].astype(np.float64),
     }
 

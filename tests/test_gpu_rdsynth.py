@@ -70,3 +70,31 @@ def test_sinr_kernel():
     mc = maps.cpu().numpy()
     ref = [rdsynth.sinr_db(mc[b], masks[b][0], masks[b][1]) for b in range(3)]
     np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-12)
+
+
+def _compare(stda, tab, meta, N, M):
+    x, clean = stda.synthesize(tab, meta)
+    torch.cuda.synchronize()
+    xr, cr = rdsynth.synth(inputs.scene_dict(tab, meta))
+    for got, ref in ((x.cpu().numpy(), xr), (clean.cpu().numpy(), cr)):
+        err = np.abs(got.astype(np.float64) - ref)
+        assert err.max() <= 2e-3, err.max()
+        assert err.reshape(-1, N * M).mean(axis=1).max() <= 2e-5
+
+
+@pytest.mark.parametrize('size', [(64, 128), (256, 128)])
+def test_rd_synth_table4_aggressors(size):
+    """Physical-units aggressors (Table 4 intervals): sawtooth start frequency, coherent phase."""
+    from paper_2307_09063_amd import stda
+    N, M = size
+    print('rd_synth table4', N, M, file=sys.stderr, flush=True)
+    tab, meta = inputs.make_scenes_table4(4, N, M, seed=N + 1, clutter=True)
+    _compare(stda, tab, meta, N, M)
+
+
+@pytest.mark.parametrize('scenario', range(1, 8))
+def test_rd_synth_table2_scenarios(scenario):
+    from paper_2307_09063_amd import stda
+    print('rd_synth table2', scenario, file=sys.stderr, flush=True)
+    tab, meta = inputs.table2_scene(scenario, 64, 128, seed=scenario, beat0=0.45 if scenario in (2, 3) else 0.2)
+    _compare(stda, tab, meta, 64, 128)

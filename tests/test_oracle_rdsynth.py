@@ -171,3 +171,90 @@ def test_sinr_and_evm_closed_form():
     assert abs(R.sinr_db(z, o, n) - 20 * np.log10(8.0)) < 1e-12
     clean = np.ones((8, 8))
     assert abs(R.evm(clean, z, o) - 0.2) < 1e-12
+
+
+# ------------------------------------------------ physical-units aggressors (Tables 2 and 4)
+def _aggressor_only(scenario, N, M, beat0):
+    tab, meta = inputs.table2_scene(scenario, N, M, seed=5, amp=1.0, beat0=beat0, noise_sigma=0.0)
+    tab[0]['tone']['amp'] = 0.0
+    sc = inputs.scene_dict(tab, meta)
+    s = R.beat_signal(sc, 0, 0)
+    Y = np.abs(R.rd_spectrum(s)) ** 2
+    return s, Y
+
+
+def test_sawtooth_and_coherent_phase_exact_integers():
+    """Sawtooth start frequency and coherent phase against unbounded-integer arithmetic."""
+    N, M = 16, 12
+    tab, meta = _empty_scene(1, N, M, seed=3)
+    e = tab[0]['intf'][0, 0]
+    e['q'], e['f0'], e['dl'] = -12345678, -3 * 2 ** 31, 7 * 2 ** 32 + 123457
+    e['s0'], e['wrap'] = 2 ** 32 + 99, 5 * 2 ** 31 + 17
+    e['ph0'], e['phd'], e['coherent'], e['amp'] = 4000000000, 3000000001, 1, 1.0
+    tab[0]['n_intf'][0] = 1
+    s = R.beat_signal(inputs.scene_dict(tab, meta), 0, 0)
+    hit = 0
+    for m in range(M):
+        g = int(e['f0']) + (int(e['s0']) + m * int(e['dl'])) % int(e['wrap'])
+        for n in range(N):
+            F = 2 * int(e['q']) * n + g
+            if abs(F) >= 2 ** 31:
+                assert s[n, m] == 0
+                continue
+            hit += 1
+            P = (g * n + int(e['q']) * n * n + int(e['ph0']) + m * int(e['phd'])) % 2 ** 32
+            ang = 2 * np.pi * ((P - 2 ** 32 if P >= 2 ** 31 else P) / 2 ** 32)
+            assert abs(s[n, m] - np.exp(1j * ang)) < 1e-12
+    assert 0 < hit < N * M
+
+
+@pytest.mark.parametrize('scenario', [1, 7])
+def test_table2_equal_slopes_give_a_zero_doppler_ghost(scenario):
+    # equal slopes with a sweep period that divides the chirp period: the same beat every chirp
+    N, M = 64, 32
+    _, Y = _aggressor_only(scenario, N, M, beat0=0.3125)
+    p0 = int(round(0.3125 * N))
+    assert Y[p0 - 1:p0 + 2, M // 2 - 1:M // 2 + 2].sum() > 0.99 * Y.sum()
+
+
+@pytest.mark.parametrize('scenario', [3, 4])
+def test_table2_repeated_sweep_gives_a_ridge(scenario):
+    # different slopes, the same crossing in every chirp: a ridge along range at zero Doppler
+    N, M = 64, 32
+    # falling beat (scenario 3) enters the band from above, rising beat (4) must start inside it
+    _, Y = _aggressor_only(scenario, N, M, beat0=0.45 if scenario == 3 else 0.1)
+    assert Y[:, M // 2 - 1:M // 2 + 2].sum() > 0.99 * Y.sum()
+    prof = Y.sum(axis=1)
+    assert prof.max() < 0.5 * prof.sum() and (prof > 0.01 * prof.max()).sum() >= N // 8
+
+
+@pytest.mark.parametrize('scenario', [2, 6])
+def test_table2_detuned_period_raises_the_floor(scenario):
+    # the crossing moves from chirp to chirp: energy leaves the zero-Doppler columns
+    N, M = 64, 128
+    s, Y = _aggressor_only(scenario, N, M, beat0=0.45 if scenario == 2 else 0.1)
+    assert Y.sum() > 0
+    assert Y[:, M // 2 - 1:M // 2 + 2].sum() < 0.5 * Y.sum()
+
+
+def test_table2_carrier_offset_moves_the_beat_out_of_band():
+    # scenario 5 with the ramp timing of the in-band ghost of scenario 1: the 20 MHz carrier
+    # offset (1.6 cycles/sample at 12.5 MHz) puts the beat outside the IF band at every sample
+    s1, _ = _aggressor_only(1, 64, 32, beat0=0.3125)
+    s5, _ = _aggressor_only(5, 64, 32, beat0=0.3125)
+    assert s1.any() and not s5.any()
+
+
+def test_table4_draws_and_amplitude():
+    tab, meta = inputs.make_scenes_table4(16, 64, 128, seed=9)
+    for b, a in enumerate(meta['aggressor']):
+        assert a['sir_db'] in range(-5, 30, 5)
+        assert 76.8e9 - 1 <= a['fc'] <= 77.2e9 + 1 and round((a['fc'] - 76.8e9) / 0.1e9, 6).is_integer()
+        assert 120e6 <= a['bandwidth'] <= 400e6 and 4e-6 <= a['duration'] <= 30e-6
+        assert 2 <= a['distance'] <= 63 and -23.05 <= a['velocity'] <= 0
+        nt = tab[b]['n_tones'][0]
+        p_sig = np.mean(tab[b]['tone'][0, :nt]['amp'].astype(np.float64) ** 2)
+        amp = float(tab[b]['intf'][0, 0]['amp'])
+        assert abs(amp ** 2 - p_sig / 10 ** (a['sir_db'] / 10)) <= 1e-6 * amp ** 2
+        e = tab[b]['intf'][0, 0]
+        assert e['coherent'] == 1 and abs(e['wrap'] / 2 ** 32 - a['bandwidth'] / inputs.F_S) < 1e-8
