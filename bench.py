@@ -307,6 +307,7 @@ def main():
         fwd_ms, Bf, det = eval_forward(stda, inputs, torch, tr.w, tr.running, dev)
         extra['fwd_eval_fp32_b32_256x128'] = {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)}
         extra['detect_b32_256x128'] = det
+        extra['rd_synth_table4_b256_64x128'] = rd_synth_table4(stda, inputs, torch, dev)
         lat = latency_b1(stda, inputs, torch, tr.w, tr.running, dev)
         extra['fwd_eval_fp32_b1_64x64_latency_ms'] = round(lat, 4)
         for other in ('train_bf16_b256_256x128', 'train_uneven_bf16_512'):
@@ -435,6 +436,27 @@ def eval_forward(stda, inputs, torch, w, running, dev):
                         'cfar': dict(stda.CFAR_DEFAULT), 'peaks_hit': int(c[:, 1].sum()),
                         'peaks': int(om.sum().item()), 'detections': int(c[:, 0].sum()),
                         'note': 'random-init weights: detection quality is not meaningful, only timing'}
+
+
+def rd_synth_table4(stda, inputs, torch, dev, n=256, N=64, M=128):
+    """rd_synth of the physical-units aggressor family (Table 4 intervals, one aggressor per clip)
+    at the paper's map size (64 range x 128 Doppler), ms per call for n clips (4 maps each)."""
+    tab, meta = inputs.make_scenes_table4(n, N, M, seed=44, clutter=True)
+    scenes = stda.upload_scenes(tab, dev)
+    rws = stda.alloc_bytes(stda.rd_synth_workspace_size(n, N, M), dev)
+    x = torch.empty((n, 3, N, M), device=dev)
+    y = torch.empty((n, 1, N, M), device=dev)
+    for _ in range(2):
+        stda.rd_synth(scenes, n, N, M, meta['seed'], meta['noise_sigma'], x, y, rws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        stda.rd_synth(scenes, n, N, M, meta['seed'], meta['noise_sigma'], x, y, rws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    return {'ms': round(ms, 4), 'clips_per_s': round(n / (ms / 1e3), 1), 'clips': n, 'map': [N, M]}
 
 
 def cpu_baseline(nclips, N, M, x, y, w, r):
