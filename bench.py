@@ -308,8 +308,8 @@ def main():
         extra['fwd_eval_fp32_b32_256x128'] = {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)}
         extra['detect_b32_256x128'] = det
         extra['rd_synth_table4_b256_64x128'] = rd_synth_table4(stda, inputs, torch, dev)
-        lat = latency_b1(stda, inputs, torch, tr.w, tr.running, dev)
-        extra['fwd_eval_fp32_b1_64x64_latency_ms'] = round(lat, 4)
+        extra['fwd_eval_fp32_b1_64x64'] = latency_b1(stda, inputs, torch, tr.w, tr.running, dev, 64, 64)
+        extra['fwd_eval_fp32_b1_128x64'] = latency_b1(stda, inputs, torch, tr.w, tr.running, dev, 128, 64)
         for other in ('train_bf16_b256_256x128', 'train_uneven_bf16_512'):
             if other == args.workload:
                 continue
@@ -361,16 +361,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def latency_b1(stda, inputs, torch, w, running, dev):
-    """EVAL forward of one clip of 3 x 64 x 64 (the small configuration), ms per call."""
+def latency_b1(stda, inputs, torch, w, running, dev, N=64, M=64):
+    """EVAL forward of one clip of 3 x N x M (64 x 64: the small configuration; 128 x 64: the
+    paper's own FPS setting, Table 7): per-clip time of back-to-back calls, eager and as a replayed
+    graph, and the wall time of one synchronised graph replay (host-measured, median of 50)."""
     rc = inputs.WORKLOADS['cfg1_fwd_64x64']
-    tab, meta = inputs.make_scenes(1, 64, 64, rc['seed'], targets=rc['targets'], intf=rc['intf'], inr=rc['inr'],
+    tab, meta = inputs.make_scenes(1, N, M, rc['seed'], targets=rc['targets'], intf=rc['intf'], inr=rc['inr'],
                                    clutter=rc['clutter'])
     x1, _ = stda.synthesize(tab, meta, dev, with_clean=False)
-    segs = stda.uniform_segments(1, 64, 64)
+    segs = stda.uniform_segments(1, N, M)
     _, wsb = stda.workspace_size(segs, stda.FP32, stda.EVAL)
     ws = stda.alloc_bytes(wsb, dev)
-    z = torch.empty((1, 1, 64, 64), device=dev)
+    z = torch.empty((1, 1, N, M), device=dev)
     for _ in range(5):
         stda.forward(segs, x1, w, running, z, None, ws, stda.FP32, stda.EVAL)
     torch.cuda.synchronize()
@@ -380,7 +382,27 @@ def latency_b1(stda, inputs, torch, w, running, dev):
         stda.forward(segs, x1, w, running, z, None, ws, stda.FP32, stda.EVAL)
     e1.record()
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 50
+    eager = e0.elapsed_time(e1) / 50
+    g = stda.ForwardGraph(segs, x1, w, running, z, ws)
+    for _ in range(5):
+        g.launch()
+    torch.cuda.synchronize()
+    e0.record(g.stream)
+    for _ in range(50):
+        g.launch()
+    e1.record(g.stream)
+    torch.cuda.synchronize()
+    graph = e0.elapsed_time(e1) / 50
+    walls = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        g.launch()
+        g.stream.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+    g.close()
+    wall = sorted(walls)[len(walls) // 2]
+    return {'ms_eager': round(eager, 4), 'ms_graph': round(graph, 4), 'ms_graph_sync_wall': round(wall, 4),
+            'fps_graph_sync': round(1e3 / wall, 1)}
 
 
 def eval_forward(stda, inputs, torch, w, running, dev):

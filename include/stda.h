@@ -203,6 +203,16 @@ int stda_train_step_graph_create(const stda_segment* segs /*host*/, int n_segs, 
                                  size_t saved_bytes, void* ws, size_t ws_bytes, int dtype,
                                  int recompute, float lr, float weight_decay, uint16_t* w_bf16,
                                  hipStream_t stream, stda_graph* graph /*host out*/);
+/*
+ * Inference form of the forward (Sec. IV; the paper reports throughput for one clip at a time):
+ * one EVAL (or TRAIN) forward captured into a graph on the caller's (non-null) stream, for
+ * replay with stda_graph_launch at low latency.  Arguments as stda_forward; the buffers are
+ * bound at capture time.
+ */
+int stda_forward_graph_create(const stda_segment* segs /*host*/, int n_segs, const float* x,
+                              const float* w, float* running, float* z, void* saved,
+                              size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int mode,
+                              hipStream_t stream, stda_graph* graph /*host out*/);
 int stda_graph_launch(stda_graph graph, hipStream_t stream);
 int stda_graph_destroy(stda_graph graph);
 

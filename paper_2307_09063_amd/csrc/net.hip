@@ -1016,6 +1016,69 @@ struct stda_graph_s {
   hipGraphExec_t exec = nullptr;
 };
 
+}  // extern "C"
+
+namespace {
+// Captures the work `enqueue` puts on `stream` into an instantiated graph.
+template <class F>
+int capture_graph(hipStream_t stream, F enqueue, stda_graph* out) {
+  {
+    Prof& p = prof();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (p.on) return STDA_E_INVALID;  // the timing hook records events; keep it out of graphs
+  }
+  HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  const int r = enqueue();
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(stream, &g);
+  if (r) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return STDA_E_HIP;
+  }
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e2 != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    g_last_hip = (int)e2;
+    return STDA_E_HIP;
+  }
+  stda_graph h = new (std::nothrow) stda_graph_s;
+  if (!h) {
+    (void)hipGraphExecDestroy(ex);
+    (void)hipGraphDestroy(g);
+    return STDA_E_INVALID;
+  }
+  h->graph = g;
+  h->exec = ex;
+  *out = h;
+  return STDA_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int stda_forward_graph_create(const stda_segment* segs, int n_segs, const float* x, const float* w, float* running,
+                              float* z, void* saved, size_t saved_bytes, void* ws, size_t ws_bytes, int dtype,
+                              int mode, hipStream_t stream, stda_graph* out) {
+  if (!out || !stream) return STDA_E_INVALID;
+  *out = nullptr;
+  size_t sv = 0, wb = 0;
+  if (int r = stda_workspace_size(segs, n_segs, dtype, mode, 0, &sv, &wb)) return r;
+  if (!x || !w || !running || !z || !ws || (mode == STDA_TRAIN && !saved)) return STDA_E_INVALID;
+  if (ws_bytes < wb || (mode == STDA_TRAIN && saved_bytes < sv)) return STDA_E_WORKSPACE;
+  return capture_graph(
+      stream,
+      [&]() {
+        return stda_forward(segs, n_segs, x, w, running, z, saved, saved_bytes, ws, ws_bytes, dtype, mode, 0,
+                            stream);
+      },
+      out);
+}
+
 int stda_train_step_graph_create(const stda_segment* segs, int n_segs, const float* x, const float* y, float* w,
                                  float* running, float* z, double* loss, float* dz, float* dw, void* saved,
                                  size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int recompute, float lr,
@@ -1027,46 +1090,19 @@ int stda_train_step_graph_create(const stda_segment* segs, int n_segs, const flo
   if (int r = stda_workspace_size(segs, n_segs, dtype, STDA_TRAIN, recompute, &sv, &wb)) return r;
   if (!x || !y || !w || !running || !z || !loss || !dz || !dw || !saved || !ws) return STDA_E_INVALID;
   if (saved_bytes < sv || ws_bytes < wb) return STDA_E_WORKSPACE;
-  {
-    Prof& p = prof();
-    std::lock_guard<std::mutex> lk(p.mu);
-    if (p.on) return STDA_E_INVALID;  // the timing hook records events; keep it out of graphs
-  }
-  HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  int r = stda_forward(segs, n_segs, x, w, running, z, saved, saved_bytes, ws, ws_bytes, dtype, STDA_TRAIN, recompute,
-                       stream);
-  if (!r) r = stda_mse_loss(segs, n_segs, z, y, loss, dz, ws, ws_bytes, stream);
-  if (!r)
-    r = stda_backward(segs, n_segs, x, dz, w, saved, saved_bytes, dw, nullptr, ws, ws_bytes, dtype, recompute,
-                      stream);
-  if (!r) r = stda_sgd_step(w, dw, (int64_t)stda_param_count(), lr, weight_decay, w_bf16, stream);
-  hipGraph_t g = nullptr;
-  const hipError_t e = hipStreamEndCapture(stream, &g);
-  if (r) {
-    if (g) hipGraphDestroy(g);
-    return r;
-  }
-  if (e != hipSuccess) {
-    g_last_hip = (int)e;
-    return STDA_E_HIP;
-  }
-  hipGraphExec_t ex = nullptr;
-  const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-  if (e2 != hipSuccess) {
-    hipGraphDestroy(g);
-    g_last_hip = (int)e2;
-    return STDA_E_HIP;
-  }
-  stda_graph h = new (std::nothrow) stda_graph_s;
-  if (!h) {
-    hipGraphExecDestroy(ex);
-    hipGraphDestroy(g);
-    return STDA_E_INVALID;
-  }
-  h->graph = g;
-  h->exec = ex;
-  *out = h;
-  return STDA_OK;
+  return capture_graph(
+      stream,
+      [&]() {
+        int r = stda_forward(segs, n_segs, x, w, running, z, saved, saved_bytes, ws, ws_bytes, dtype, STDA_TRAIN,
+                             recompute, stream);
+        if (!r) r = stda_mse_loss(segs, n_segs, z, y, loss, dz, ws, ws_bytes, stream);
+        if (!r)
+          r = stda_backward(segs, n_segs, x, dz, w, saved, saved_bytes, dw, nullptr, ws, ws_bytes, dtype, recompute,
+                            stream);
+        if (!r) r = stda_sgd_step(w, dw, (int64_t)stda_param_count(), lr, weight_decay, w_bf16, stream);
+        return r;
+      },
+      out);
 }
 
 int stda_graph_launch(stda_graph g, hipStream_t stream) {

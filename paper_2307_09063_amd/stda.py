@@ -55,6 +55,7 @@ def _load():
         'stda_train_step_graph_create': (I, [P, I, P, P, P, P, P, P, P, P, P, SZ, P, SZ, I, I, F, F, P, P,
                                              P]),
         'stda_graph_launch': (I, [P, P]),
+        'stda_forward_graph_create': (I, [P, I, P, P, P, P, P, SZ, P, SZ, I, I, P, P]),
         'stda_graph_destroy': (I, [P]),
         'stda_profile_select': (I, [ctypes.c_char_p]),
         'stda_profile_read': (I, [P, P]),
@@ -80,7 +81,7 @@ _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
            'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
-           'stda_graph_launch', 'stda_graph_destroy', 'stda_profile_select',
+           'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
            'stda_autotune', 'stda_cfar', 'stda_evm', 'stda_adamw_step', 'rd_synth_workspace_size', 'rd_synth')
 
@@ -261,6 +262,36 @@ class TrainStepGraph:
                 _ptr(loss), _ptr(dz), _ptr(dw), _ptr(saved), saved.numel(), _ptr(ws), ws.numel(), dtype, recompute,
                 lr, weight_decay, _ptr(w_bf16), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                 'stda_train_step_graph_create')
+        self.handle = h
+
+    def launch(self):
+        _check(_lib.stda_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)), 'stda_graph_launch')
+
+    def close(self):
+        if self.handle:
+            _lib.stda_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ForwardGraph:
+    """One captured forward (EVAL by default) replayed with launch(); buffers bound at capture."""
+
+    def __init__(self, segs, x, w, running, z, ws, dtype=FP32, mode=EVAL, saved=None, stream=None):
+        self.stream = stream or torch.cuda.Stream()
+        self._keep = (x, w, running, z, ws, saved)
+        arr = _seg_array(segs)
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(_lib.stda_forward_graph_create(
+                ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(w), _ptr(running), _ptr(z), _ptr(saved),
+                saved.numel() if saved is not None else 0, _ptr(ws), ws.numel(), dtype, mode,
+                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stda_forward_graph_create')
         self.handle = h
 
     def launch(self):

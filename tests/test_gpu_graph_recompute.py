@@ -100,3 +100,33 @@ def test_graph_replay_matches_eager(case):
         assert gb['loss'].item() == eager[k][2]
         del junk
     graph.close()
+
+
+@pytest.mark.parametrize('dtype', [0, 1], ids=['fp32', 'bf16'])
+def test_forward_graph_replays(dtype):
+    """A captured EVAL forward replays bit-identically to the eager call, and reads the bound
+    input buffer afresh on every replay."""
+    from paper_2307_09063_amd import stda as S
+    B, H, W = 1, 128, 64
+    _say('forward graph', dtype)
+    w, r = U.weights(), U.running()
+    segs = S.uniform_segments(B, H, W)
+    _, wsb = S.workspace_size(segs, dtype, S.EVAL)
+    xs = [U.maps(B, H, W, seed=40 + k)[0] for k in range(3)]
+    xd, wd, rd = U.dev(xs[0]), U.dev(w), U.dev(r.copy())
+    z_e = torch.empty((B, 1, H, W), device='cuda')
+    z_g = torch.empty_like(z_e)
+    ws_e, ws_g = S.alloc_bytes(wsb), S.alloc_bytes(wsb)
+    graph = S.ForwardGraph(segs, xd, wd, rd, z_g, ws_g, dtype)
+    for k in range(3):
+        xd.copy_(U.dev(xs[k]))
+        S.forward(segs, xd, wd, rd, z_e, None, ws_e, dtype, S.EVAL)
+        torch.cuda.synchronize()
+        graph.launch()
+        graph.stream.synchronize()
+        junk = torch.randn(1 << 16, device='cuda').sum()   # eager work between replays
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(z_g.cpu().numpy(), z_e.cpu().numpy())
+        del junk
+    np.testing.assert_array_equal(rd.cpu().numpy(), r)
+    graph.close()
