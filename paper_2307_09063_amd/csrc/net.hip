@@ -408,7 +408,7 @@ int tiles_for(int64_t hw, int G) {
 
 // Tiling variant of each dense stage-2 launch, [dtype][0 forward, 1 input gradient, 2 weight
 // gradient][block]: 0..2 the LDS-tiled kernels with the tilings listed in launch_s2_variant and
-// launch_wgrad_variant, 3 the register-gather kernels.  Set by stda_tune_set (the autotuner); 0 by
+// launch_wgrad, 3 the register-gather kernels.  Set by stda_tune_set (the autotuner); 0 by
 // default.
 constexpr int kS2Variants = 4;
 constexpr int kTuneKinds = 3;
@@ -778,6 +778,20 @@ int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const T* lo, const
   return colsum_to(c, wpart, (int)gx, (int)cols, dst, map, acc, "wgrad_sum" + tag.substr(5));
 }
 
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+int launch_wgrad_v(const Ctx<T>& c, const std::string& tag, const T* lo, const T* hi, int n, int h, int w, float* dst,
+                   ColMap map, int acc) {
+  typedef WgVCfg<T, DEC, CL, CH, TH, TW> Cfg;
+  const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
+  int64_t gx = std::min<int64_t>(ntiles, cols <= 8192 ? kMaxWgradGrid : kMaxWgradGrid / 2);
+  if (gx >= 64) gx &= ~(int64_t)7;
+  gx = std::max<int64_t>(gx, 1);
+  float* wpart = c.template scr<float>(c.P->ws_wpart);
+  KLAUNCH(tag, k_s2_wgrad_v<T, DEC, CL, CH, TH, TW><<<(unsigned)gx, 256, 0, c.st>>>(lo, hi, wpart, n, h, w));
+  return colsum_to(c, wpart, (int)gx, (int)cols, dst, map, acc, "wgrad_sum" + tag.substr(5));
+}
+
 template <class T, bool DEC, int CIN, int COUT>
 int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, const T* d, int n, int hin, int win,
                  float* dst, int acc) {
@@ -798,9 +812,12 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
       return run_wgrad(c, tag, ld, (int64_t)n * (hin / 2) * (win / 2), dst, map, acc);
     }
   }
-  if constexpr (SMALL) return v == 1 ? WGV(8, 8) : v == 2 ? WGV(16, 16) : WGV(8, 16);
-  else return v == 1 ? WGV(4, 16) : v == 2 ? WGV(8, 16) : WGV(8, 8);
+#define WGVV(TH_, TW_) launch_wgrad_v<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
+  // 0, 1: vector-operand kernel; 2: scalar-operand kernel
+  if constexpr (SMALL) return v == 1 ? WGVV(8, 8) : v == 2 ? WGV(8, 16) : WGVV(8, 16);
+  else return v == 1 ? WGVV(4, 8) : v == 2 ? WGV(8, 8) : WGVV(8, 8);
 #undef WGV
+#undef WGVV
 }
 
 template <class T>

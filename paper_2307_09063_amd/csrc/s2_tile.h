@@ -424,3 +424,213 @@ __global__ __launch_bounds__(256) void k_s2_wgrad(const T* __restrict__ lo, cons
 }
 
 }  // namespace stda
+
+namespace stda {
+
+// Weight gradients of the stage-2 dense layers, vector-operand form (same R and part layout as
+// k_s2_wgrad).  LDS holds the operands in the storage type: Lo as [cl][pixel] and the Hi
+// rectangle as parity planes [slot][ch][Y][X] where a slot is a plane (py, px) together with a
+// column shift s in {0, 1} (slot content at X = plane value at X + s).  Tap (ky, kx) reads slot
+// (ky & 1, kx & 1, kx >> 1) at (y + ky / 2, x): the 4 consecutive pixels a lane group feeds to
+// the matrix core are one aligned 8-byte (BF16) or 16-byte (FP32) read for both operands.  The
+// shifted copy exists only for the planes a tap with kx >> 1 = 1 reads (px = 0 when KS = 3).
+// Staging: a thread takes 4 channels x 4 consecutive pixels, issues the 4 loads, transposes in
+// registers and writes 4 aligned vectors.
+template <class T>
+struct WgVec;
+template <>
+struct WgVec<float> {
+  typedef float4 type;
+  typedef float elem;
+};
+template <>
+struct WgVec<bf16> {
+  typedef shortx4 type;
+  typedef unsigned short elem;
+};
+
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+struct WgVCfg {
+  static constexpr int KS = DEC ? 4 : 3, TAPS = KS * KS;
+  static constexpr int SH = 2 * TH + KS - 2, SW = 2 * TW + KS - 2;
+  static constexpr int PY = TH + 1;
+  static constexpr int CS = PY * TW + 4;         // channel stride of a slot (elements)
+  static constexpr int SLOTS = KS == 3 ? 6 : 8;  // 4 planes unshifted + the shifted ones read
+  static constexpr int LP = TH * TW + 4;         // Lo channel stride (elements)
+  static constexpr int MTC = CH / 16, NTC = CL / 16;
+  static constexpr int PAIRS = TAPS * MTC, PW_ = (PAIRS + 3) / 4;
+  static constexpr int ELEMS = CL * LP + SLOTS * CH * CS;
+  static constexpr int LDS_BYTES = ELEMS * (int)sizeof(T);
+  static_assert(TW % 4 == 0 && (TH * TW) % 16 == 0, "pixel groups of 4 inside a row, chunks of 16");
+  static_assert(CL % 4 == 0 && CH % 4 == 0, "channel quads");
+  static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
+  // slot of plane p = 2 py + px with shift s
+  __device__ static constexpr int slot(int p, int s) { return s == 0 ? p : 4 + (KS == 3 ? (p >> 1) : p); }
+};
+
+template <class T>
+__device__ __forceinline__ void wg_store4(T* dst, const float v[4]);
+template <>
+__device__ __forceinline__ void wg_store4<float>(float* dst, const float v[4]) {
+  *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <>
+__device__ __forceinline__ void wg_store4<bf16>(bf16* dst, const float v[4]) {
+  // values are BF16-exact (they were loaded from BF16), so truncation packs them exactly
+  const uint32_t lo = (__float_as_uint(v[0]) >> 16) | (__float_as_uint(v[1]) & 0xffff0000u);
+  const uint32_t hi = (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xffff0000u);
+  *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+}
+
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+__global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, const T* __restrict__ hi,
+                                                    float* __restrict__ part, int B, int h, int w) {
+  typedef WgVCfg<T, DEC, CL, CH, TH, TW> C;
+  typedef typename WgVec<T>::type V;
+  constexpr int KS = C::KS, PW_ = C::PW_, NTC = C::NTC, MTC = C::MTC, LP = C::LP, CS = C::CS, PY = C::PY;
+  constexpr bool BF = sizeof(T) == 2;
+  __shared__ __attribute__((aligned(16))) T lds[C::ELEMS];
+  T* const ls = lds;            // [CL][LP]
+  T* const hs = lds + CL * LP;  // [slot][CH][PY][TW] with channel stride CS
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
+  const int H2 = 2 * h, W2 = 2 * w;
+
+  floatx4 acc[PW_][NTC];
+#pragma unroll
+  for (int u = 0; u < PW_; ++u)
+#pragma unroll
+    for (int j = 0; j < NTC; ++j) acc[u][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int nty = (h + TH - 1) / TH, ntx = (w + TW - 1) / TW;
+  const int64_t ntiles = (int64_t)B * nty * ntx;
+  int64_t t_begin, t_end, t_step;
+  if ((gridDim.x & 7) == 0) {
+    const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3, per = gridDim.x >> 3;
+    const int64_t chunk = (ntiles + 7) / 8;
+    t_begin = xcd * chunk + l;
+    t_end = (xcd + 1) * chunk < ntiles ? (xcd + 1) * chunk : ntiles;
+    t_step = per;
+  } else {
+    t_begin = blockIdx.x;
+    t_end = ntiles;
+    t_step = gridDim.x;
+  }
+  for (int64_t t = t_begin; t < t_end; t += t_step) {
+    int b, y0, x0;
+    s2_tile_origin(t, nty, ntx, TH, TW, b, y0, x0);
+    __syncthreads();
+    // Staging: a unit is (4 channels, 4 consecutive pixels); every load of the thread's units is
+    // issued before the first transpose and LDS write, so their latencies overlap.
+    // Lo units: (channel quad, pixel quad of a tile row); Hi units: (slot, channel quad, plane row,
+    // quad of plane columns).
+    {
+      constexpr int LU = (CL / 4) * (TH * TW / 4), XQ = TW / 4, HU = C::SLOTS * (CH / 4) * PY * XQ;
+      constexpr int PL = (LU + STDA_BLOCK - 1) / STDA_BLOCK, PH = (HU + STDA_BLOCK - 1) / STDA_BLOCK;
+      float lv[PL][4][4], hv[PH][4][4];  // [unit][pixel][channel]
+#pragma unroll
+      for (int k = 0; k < PL; ++k) {
+        const int e = threadIdx.x + k * STDA_BLOCK;
+        const int cq = e % (CL / 4), p0 = 4 * (e / (CL / 4)), ty = p0 / TW, tx = p0 % TW, y = y0 + ty;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int x = x0 + tx + q;
+          if (e < LU && y < h && x < w) ld4(lo + (((int64_t)b * h + y) * w + x) * CL + 4 * cq, lv[k][q]);
+          else zero4(lv[k][q]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PH; ++k) {
+        const int e = threadIdx.x + k * STDA_BLOCK;
+        int r = e;
+        const int xq = r % XQ;
+        r /= XQ;
+        const int Y = r % PY;
+        r /= PY;
+        const int cq = r % (CH / 4), sl = r / (CH / 4);
+        const int s = sl < 4 ? 0 : 1;
+        const int p = sl < 4 ? sl : (KS == 3 ? 2 * (sl - 4) : sl - 4);
+        const int ly = 2 * Y + (p >> 1), sy = 2 * y0 - 1 + ly;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int lx = 2 * (4 * xq + q + s) + (p & 1), sx = 2 * x0 - 1 + lx;
+          if (e < HU && ly < C::SH && lx < C::SW && sy >= 0 && sy < H2 && sx >= 0 && sx < W2)
+            ld4(hi + (((int64_t)b * H2 + sy) * W2 + sx) * CH + 4 * cq, hv[k][q]);
+          else
+            zero4(hv[k][q]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PL; ++k) {
+        const int e = threadIdx.x + k * STDA_BLOCK;
+        if (e >= LU) continue;
+        const int cq = e % (CL / 4), p0 = 4 * (e / (CL / 4));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float col[4] = {lv[k][0][c], lv[k][1][c], lv[k][2][c], lv[k][3][c]};
+          wg_store4<T>(ls + (4 * cq + c) * LP + p0, col);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < PH; ++k) {
+        const int e = threadIdx.x + k * STDA_BLOCK;
+        if (e >= HU) continue;
+        int r = e;
+        const int xq = r % XQ;
+        r /= XQ;
+        const int Y = r % PY;
+        r /= PY;
+        const int cq = r % (CH / 4), sl = r / (CH / 4);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float col[4] = {hv[k][0][c], hv[k][1][c], hv[k][2][c], hv[k][3][c]};
+          wg_store4<T>(hs + (sl * CH + 4 * cq + c) * CS + Y * TW + 4 * xq, col);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c16 = 0; c16 < TH * TW / 16; ++c16) {
+      const int p0 = 16 * c16 + 4 * g, ty = p0 / TW, tx = p0 % TW;
+      V bq[NTC];
+#pragma unroll
+      for (int j = 0; j < NTC; ++j) bq[j] = *reinterpret_cast<const V*>(ls + (16 * j + i) * LP + p0);
+#pragma unroll
+      for (int u = 0; u < PW_; ++u) {
+        const int q = wave + 4 * u;
+        if (q >= C::PAIRS) continue;
+        const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
+        const int sl = C::slot((ky & 1) * 2 + (kx & 1), kx >> 1);
+        const V a = *reinterpret_cast<const V*>(hs + (sl * CH + 16 * mt + i) * CS + (ty + (ky >> 1)) * TW + tx);
+#pragma unroll
+        for (int j = 0; j < NTC; ++j) {
+          if constexpr (BF) {
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bq[j], acc[u][j], 0, 0, 0);
+          } else {
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bq[j].x, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bq[j].y, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bq[j].z, acc[u][j], 0, 0, 0);
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bq[j].w, acc[u][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  constexpr int NCOL = DEC ? C::TAPS * CH : CL;
+  float* out = part + (int64_t)blockIdx.x * C::TAPS * CH * CL;
+#pragma unroll
+  for (int u = 0; u < PW_; ++u) {
+    const int q = wave + 4 * u;
+    if (q >= C::PAIRS) continue;
+    const int tap = q / MTC, mt = q % MTC;
+#pragma unroll
+    for (int j = 0; j < NTC; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ch = 16 * mt + 4 * g + r, cl = 16 * j + i;
+        const int64_t idx = DEC ? (int64_t)cl * NCOL + tap * CH + ch : ((int64_t)tap * CH + ch) * NCOL + cl;
+        out[idx] = acc[u][j][r];
+      }
+  }
+}
+
+}  // namespace stda
