@@ -73,6 +73,22 @@ def kernel_work(tag, B, H, W, es):
     return table.get(kind)
 
 
+def stage2_layers(per_tag, groups, bf16):
+    """Roofline of every stage-2 dense launch (the layers holding most of the arithmetic) from one
+    profiled step, {tag: {us, bound, frac}}; None for batches of several map sizes."""
+    if len(groups) != 1:
+        return None
+    B, N, M = groups[0]
+    out = {}
+    for t, (cnt, tms) in sorted(per_tag.items()):
+        if t.split('.')[0] in ('dense_fwd_main', 'dense_fwd_res', 'dense_dgrad_main', 'dense_dgrad_res', 'wgrad_main',
+                               'wgrad_res'):
+            rl = roofline(t, tms / cnt, B, N, M, bf16)
+            if rl:
+                out[t] = {'us': rl['avg_us'], 'bound': rl['bound'], 'frac': rl['frac']}
+    return out or None
+
+
 def roofline(tag, avg_ms, B, H, W, dtype_bf16):
     es = 2 if dtype_bf16 else 4
     w = kernel_work(tag, B, H, W, es)
@@ -277,6 +293,9 @@ def main():
     per_tag = stda.profile_report()
     stda.profile_select(None)
     dominant = args.kernel or max(per_tag, key=lambda t: per_tag[t][1])
+    # roofline of every stage-2 dense launch (the layers that hold most of the arithmetic), from the
+    # same profiled step; algorithmic work as in kernel_work
+    layers = stage2_layers(per_tag, groups, stda.BF16 == dtype)
     tot_tagged = sum(v[1] for v in per_tag.values())
     for t, (n, tms) in sorted(per_tag.items(), key=lambda kv: -kv[1][1])[:40]:
         print(f'bench:   {t:28s} {n:3d} launches {tms:8.3f} ms ({100 * tms / tot_tagged:4.1f}%)', file=sys.stderr)
@@ -318,12 +337,19 @@ def main():
             t2 = Trainer(stda, inputs, torch, sg, xo, yo, stda.BF16 if dn == 'bf16' else stda.FP32, rec, dev)
             tiles2 = None if args.no_tune else t2.autotune()
             t2.step()
+            torch.cuda.synchronize()
+            stda.profile_select('*')
+            t2.step()
+            torch.cuda.synchronize()
+            layers2 = stage2_layers(stda.profile_report(), gr, dn == 'bf16')
+            stda.profile_select(None)
             t2.capture()
             t2.timed(2, True)
             m2 = t2.timed(max(3, args.steps // 2), True)
             n2 = sum(g[0] for g in gr)
             extra[other] = {'ms_per_step': round(m2, 4), 'clips_per_s': round(n2 / (m2 / 1e3), 1), 'dtype': dn,
-                            'recompute': rec, 'segments': [list(g) for g in gr], 'tiles': tiles2}
+                            'recompute': rec, 'segments': [list(g) for g in gr], 'tiles': tiles2,
+                            'roofline_stage2_layers': layers2}
             print(f'bench: {other}: {m2:.3f} ms/step ({n2 / (m2 / 1e3):.0f} clips/s)', file=sys.stderr, flush=True)
             t2.graph.close()
             del t2, xo, yo
@@ -355,6 +381,7 @@ def main():
         'ms_per_step_eager': round(ms_eager, 4),
         'rd_synth_ms': round(rd_ms, 4),
         'roofline': roof,
+        'roofline_stage2_layers': layers or None,
         'cpu_baseline': cpu,
     }
     out.update(extra)

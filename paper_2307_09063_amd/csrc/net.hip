@@ -764,13 +764,20 @@ int run_wgrad(const Ctx<T>& c, const std::string& tag, const L& ld, int64_t npix
 // Stage-2 weight gradient of block `blk` on LDS tiles (or, variant 3, the register-gather
 // kernel); encoder: Lo = output gradient on the hout x wout grid, Hi = layer input; decoder:
 // Lo = layer input on the hin x win grid, Hi = output gradient.
+// Workgroups of a tiled weight-gradient launch: enough to keep 4 per CU where the partial rows
+// (one per workgroup, `cols` floats each) fit the partial buffer, at least 256.
+int64_t wgrad_rows(int64_t cols) {
+  const int64_t fit = (int64_t)kMaxWgradGrid * 32768 / cols;
+  return std::max<int64_t>(256, std::min<int64_t>(1024, fit));
+}
+
 template <class T, bool DEC, int CL, int CH, int TH, int TW>
 int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const T* lo, const T* hi, int n, int h, int w,
                      float* dst, ColMap map, int acc) {
   typedef WgCfg<T, DEC, CL, CH, TH, TW> Cfg;
   const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = std::min<int64_t>(ntiles, cols <= 8192 ? kMaxWgradGrid : kMaxWgradGrid / 2);
+  int64_t gx = std::min<int64_t>(ntiles, wgrad_rows(cols));
   if (gx >= 64) gx &= ~(int64_t)7;
   gx = std::max<int64_t>(gx, 1);
   float* wpart = c.template scr<float>(c.P->ws_wpart);
@@ -784,7 +791,7 @@ int launch_wgrad_v(const Ctx<T>& c, const std::string& tag, const T* lo, const T
   typedef WgVCfg<T, DEC, CL, CH, TH, TW> Cfg;
   const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = std::min<int64_t>(ntiles, cols <= 8192 ? kMaxWgradGrid : kMaxWgradGrid / 2);
+  int64_t gx = std::min<int64_t>(ntiles, wgrad_rows(cols));
   if (gx >= 64) gx &= ~(int64_t)7;
   gx = std::max<int64_t>(gx, 1);
   float* wpart = c.template scr<float>(c.P->ws_wpart);
