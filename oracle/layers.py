@@ -86,15 +86,16 @@ def conv2d_grad_weight(x, dout, w_shape, stride=1, pad=0, groups=1):
     return dw
 
 
-def deconv2d(x, w, stride=1, pad=0, groups=1):
-    """Transposed convolution by its scatter definition, then crop `pad` on each side."""
+def deconv2d(x, w, stride=1, pad=0, groups=1, out_pad=0):
+    """Transposed convolution by its scatter definition, then crop `pad` on each side; out_pad
+    extra rows and columns are kept at the far end (zero where the scatter does not reach)."""
     B, C, H, W = x.shape
     Ci, Og, k, _ = w.shape
     assert Ci == C and C % groups == 0
     cg = C // groups
     Co = Og * groups
-    Hf = (H - 1) * stride + k
-    Wf = (W - 1) * stride + k
+    Hf = (H - 1) * stride + k + out_pad
+    Wf = (W - 1) * stride + k + out_pad
     full = np.zeros((B, Co, Hf, Wf))
     for ky in range(k):
         for kx in range(k):
@@ -103,18 +104,18 @@ def deconv2d(x, w, stride=1, pad=0, groups=1):
                 full[:, g * Og:(g + 1) * Og, ky:ky + stride * (H - 1) + 1:stride,
                      kx:kx + stride * (W - 1) + 1:stride] += np.einsum(
                          'co,bcij->boij', wt, x[:, g * cg:(g + 1) * cg])
-    Ho = (H - 1) * stride - 2 * pad + k
-    Wo = (W - 1) * stride - 2 * pad + k
+    Ho = (H - 1) * stride - 2 * pad + k + out_pad
+    Wo = (W - 1) * stride - 2 * pad + k + out_pad
     return full[:, :, pad:pad + Ho, pad:pad + Wo]
 
 
-def deconv2d_grad_input(dout, w, in_shape, stride=1, pad=0, groups=1):
+def deconv2d_grad_input(dout, w, in_shape, stride=1, pad=0, groups=1, out_pad=0):
     """Adjoint of deconv2d w.r.t. its input: gather dout (zero-extended by the crop) at every tap."""
     B, C, H, W = in_shape
     Ci, Og, k, _ = w.shape
     cg = C // groups
-    Hf = (H - 1) * stride + k
-    Wf = (W - 1) * stride + k
+    Hf = (H - 1) * stride + k + out_pad
+    Wf = (W - 1) * stride + k + out_pad
     full = np.zeros((B, dout.shape[1], Hf, Wf))
     full[:, :, pad:pad + dout.shape[2], pad:pad + dout.shape[3]] = dout
     dx = np.zeros(in_shape)
@@ -127,13 +128,13 @@ def deconv2d_grad_input(dout, w, in_shape, stride=1, pad=0, groups=1):
     return dx
 
 
-def deconv2d_grad_weight(x, dout, w_shape, stride=1, pad=0, groups=1):
+def deconv2d_grad_weight(x, dout, w_shape, stride=1, pad=0, groups=1, out_pad=0):
     """Adjoint of deconv2d w.r.t. its weight."""
     B, C, H, W = x.shape
     Ci, Og, k, _ = w_shape
     cg = C // groups
-    Hf = (H - 1) * stride + k
-    Wf = (W - 1) * stride + k
+    Hf = (H - 1) * stride + k + out_pad
+    Wf = (W - 1) * stride + k + out_pad
     full = np.zeros((B, dout.shape[1], Hf, Wf))
     full[:, :, pad:pad + dout.shape[2], pad:pad + dout.shape[3]] = dout
     dw = np.zeros(w_shape)

@@ -29,6 +29,17 @@ C0 = 16
 ENC_IN = (16, 32)      # encoder block input widths
 DEC_IN = (64, 32)      # decoder block input widths
 
+# Architecture readings (the main reading by default; the alternatives are ablations):
+#   res_k : kernel of the decoder long residual, 4 (DeConv4x4-s2-p1) or 3 (DeConv3x3-s2-p1 with
+#           one row and column of output padding, so that it also doubles the map)
+#   head  : 'identity' (z = Conv3x3(d1) + b) or 'sigmoid' (z = sigmoid of that)
+ARCH = {'res_k': 4, 'head': 'identity'}
+
+
+def set_arch(res_k=4, head='identity'):
+    assert res_k in (3, 4) and head in ('identity', 'sigmoid')
+    ARCH['res_k'], ARCH['head'] = res_k, head
+
 
 def param_specs():
     """Ordered (name, shape, fan_in) of every parameter of the flat FP32 master buffer."""
@@ -52,7 +63,8 @@ def param_specs():
         s.append((f'{name}.s2.main_bn.gamma', (co,), 0))
         s.append((f'{name}.s2.main_bn.beta', (co,), 0))
         if dec:
-            s.append((f'{name}.s2.res.w', (c, co, 4, 4), c * 16))
+            k = ARCH['res_k']
+            s.append((f'{name}.s2.res.w', (c, co, k, k), c * k * k))
         else:
             s.append((f'{name}.s2.res.w', (co, c, 3, 3), c * 9))
         s.append((f'{name}.eca.w', (3,), 3))
@@ -140,7 +152,7 @@ def _stage1(name, x, P, R, mode, newR, caches, dec):
 def _stage2(name, x, x1, P, R, mode, newR, caches, dec):
     if dec:
         t = L.deconv2d(x1, P[name + '.s2.main.w'], stride=2, pad=1)
-        r = L.deconv2d(x, P[name + '.s2.res.w'], stride=2, pad=1)
+        r = L.deconv2d(x, P[name + '.s2.res.w'], stride=2, pad=1, out_pad=4 - ARCH['res_k'])
     else:
         t = L.conv2d(x1, P[name + '.s2.main.w'], stride=2, pad=1)
         r = L.conv2d(x, P[name + '.s2.res.w'], stride=2, pad=1)
@@ -188,7 +200,10 @@ def forward(params, running, x, mode='train'):
         h = e + skips[name]
         acts[name + '.out'] = h
     z = L.conv2d(h, P['head.conv.w'], stride=1, pad=1) + P['head.conv.b'][0]
-    cache = {'P': P, 'caches': caches, 'acts': acts, 'mode': mode}
+    if ARCH['head'] == 'sigmoid':
+        z = L.sigmoid(z)
+    acts['z'] = z
+    cache = {'P': P, 'caches': caches, 'acts': acts, 'mode': mode, 'arch': dict(ARCH)}
     return z, flatten_running(newR), cache
 
 
@@ -202,8 +217,9 @@ def _stage2_backward(name, dy, x, x1, P, caches, acts, G, dec):
     if dec:
         dx1 = L.deconv2d_grad_input(dt, wm, x1.shape, stride=2, pad=1)
         G[name + '.s2.main.w'] = L.deconv2d_grad_weight(x1, dt, wm.shape, stride=2, pad=1)
-        dx = L.deconv2d_grad_input(dy, wr, x.shape, stride=2, pad=1)
-        G[name + '.s2.res.w'] = L.deconv2d_grad_weight(x, dy, wr.shape, stride=2, pad=1)
+        op = 4 - wr.shape[2]   # output padding of the DeConv3x3-s2 residual reading
+        dx = L.deconv2d_grad_input(dy, wr, x.shape, stride=2, pad=1, out_pad=op)
+        G[name + '.s2.res.w'] = L.deconv2d_grad_weight(x, dy, wr.shape, stride=2, pad=1, out_pad=op)
     else:
         dx1 = L.conv2d_grad_input(dt, wm, x1.shape, stride=2, pad=1)
         G[name + '.s2.main.w'] = L.conv2d_grad_weight(x1, dt, wm.shape, stride=2, pad=1)
@@ -244,6 +260,9 @@ def backward(dz, cache, want_dx=False):
     P, caches, acts = cache['P'], cache['caches'], cache['acts']
     G = {}
     dz = np.asarray(dz, dtype=np.float64)
+    if cache['arch']['head'] == 'sigmoid':
+        z = acts['z']
+        dz = dz * z * (1.0 - z)
     h = acts['dec1.out']
     G['head.conv.b'] = np.array([dz.sum()])
     G['head.conv.w'] = L.conv2d_grad_weight(h, dz, P['head.conv.w'].shape, stride=1, pad=1)

@@ -231,3 +231,31 @@ def test_eca_backward_finite_difference():
         wp[k] += h
         wm[k] -= h
         assert abs((f(y, wp) - f(y, wm)) / (2 * h) - dw[k]) < 1e-8
+
+
+def test_deconv_output_padding_and_adjoint():
+    """DeConv3x3-s2-p1 with output padding 1 (the alternative decoder residual): equals the
+    library's ConvTranspose, doubles the map, and is the adjoint of Conv3x3-s2-p1 with the same
+    weight (an inner-product identity)."""
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((2, 4, 5, 6))
+    w = rng.standard_normal((4, 3, 3, 3))
+    out = L.deconv2d(x, w, stride=2, pad=1, out_pad=1)
+    assert out.shape == (2, 3, 10, 12)
+    ref = torch.nn.functional.conv_transpose2d(torch.from_numpy(x), torch.from_numpy(w), stride=2, padding=1,
+                                               output_padding=1).numpy()
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12)
+    yb = rng.standard_normal((2, 3, 10, 12))
+    # <deconv(x), y> = <x, conv(y)> with conv weights [Cout=4, Cin=3] = w itself
+    lhs = (out * yb).sum()
+    rhs = (x * L.conv2d(yb, w, stride=2, pad=1)).sum()
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    dout = rng.standard_normal(out.shape)
+    gx = L.deconv2d_grad_input(dout, w, x.shape, stride=2, pad=1, out_pad=1)
+    gw = L.deconv2d_grad_weight(x, dout, w.shape, stride=2, pad=1, out_pad=1)
+    np.testing.assert_allclose(gx, L.conv2d(dout, w, stride=2, pad=1), rtol=1e-12, atol=1e-12)
+    eps = 1e-6
+    e = np.zeros_like(w)
+    e[1, 2, 0, 2] = eps
+    fd = ((L.deconv2d(x, w + e, 2, 1, out_pad=1) - L.deconv2d(x, w - e, 2, 1, out_pad=1)) * dout).sum() / (2 * eps)
+    assert abs(fd - gw[1, 2, 0, 2]) <= 1e-7 * max(1.0, abs(fd))

@@ -155,3 +155,54 @@ def test_eval_stage1_reparameterisation():
     wd2 = wd * sc[1][:, None, None, None]
     folded = L.conv2d(x, wp2) + L.conv2d(x, wd2, 1, 1, c) + bias[None, :, None, None]
     np.testing.assert_allclose(u, folded, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------- architecture ablations
+ARCHS = [(3, 'identity'), (4, 'sigmoid'), (3, 'sigmoid')]
+
+
+@pytest.fixture()
+def arch():
+    yield
+    net.set_arch(4, 'identity')
+
+
+@pytest.mark.parametrize('res_k,head', ARCHS)
+def test_ablation_param_count(arch, res_k, head):
+    net.set_arch(res_k, head)
+    # a 3 x 3 decoder residual has 7 of 16 taps fewer: (64*32 + 32*16) * 7 weights fewer
+    assert net.param_count() == 137469 - (res_k == 3) * (64 * 32 + 32 * 16) * 7
+
+
+@pytest.mark.parametrize('res_k,head', ARCHS)
+def test_ablation_forward_and_gradient_match_torch(arch, res_k, head):
+    net.set_arch(res_k, head)
+    w, r, x, y = _setup(B=2, H=16, W=12)
+    rng = np.random.default_rng(7)
+    w = w + 0.1 * rng.standard_normal(w.shape)
+    z, _, _ = net.forward(w, r, x, 'train')
+    P, R = _torch_params(w, r)
+    xt = torch.tensor(x, requires_grad=True)
+    zt, _ = torch_ref.forward(P, R, xt, train=True, res_k=res_k, head=head)
+    np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-11, atol=1e-12)
+    loss, g, dx, _, _ = net.loss_and_grad(w, r, x, y, want_dx=True)
+    lt = ((zt - torch.from_numpy(y)) ** 2).mean()
+    lt.backward()
+    gt = net.flatten({k: v.grad.numpy() for k, v in P.items()})
+    np.testing.assert_allclose(g, gt, rtol=1e-9, atol=1e-14 * np.abs(gt).max())
+    np.testing.assert_allclose(dx, xt.grad.numpy(), rtol=1e-9, atol=1e-14 * np.abs(dx).max())
+
+
+@pytest.mark.parametrize('res_k,head', ARCHS)
+def test_ablation_directional_finite_difference(arch, res_k, head):
+    net.set_arch(res_k, head)
+    w, r, x, y = _setup(B=2, H=16, W=16, seed=34)
+    _, g, _, _, _ = net.loss_and_grad(w, r, x, y)
+    f = lambda ww: net.mse_loss(net.forward(ww, r, x, 'train')[0], y)[0]
+    h = 1e-6
+    v = np.random.default_rng(34).standard_normal(w.shape)
+    v /= np.linalg.norm(v)
+    base = _kinks(w, r, x)
+    assert np.array_equal(base, _kinks(w + h * v, r, x)) and np.array_equal(base, _kinks(w - h * v, r, x))
+    fd = (f(w + h * v) - f(w - h * v)) / (2 * h)
+    assert abs(fd - g @ v) <= 1e-6 * abs(fd)

@@ -22,8 +22,10 @@ def _eca(y, w):
     return torch.sigmoid(s)[:, :, None, None] * y
 
 
-def forward(P, R, x, train=True):
-    """P: dict name -> float64 tensor, R: dict bn name -> (mean, var) tensors."""
+def forward(P, R, x, train=True, res_k=4, head='identity'):
+    """P: dict name -> float64 tensor, R: dict bn name -> (mean, var) tensors.  res_k = 3 takes
+    the decoder residual as ConvTranspose3x3-s2-p1 with output padding 1; head = 'sigmoid'
+    applies a logistic sigmoid to the output."""
     newR = {}
     t = F.conv2d(x, P['stem.conv.w'], padding=1)
     s0 = F.relu(_bn(t, P, R, 'stem.bn', train, newR))
@@ -42,7 +44,7 @@ def forward(P, R, x, train=True):
         x1 = F.relu(u)
         if dec:
             t = F.conv_transpose2d(x1, P[name + '.s2.main.w'], stride=2, padding=1)
-            r = F.conv_transpose2d(h, P[name + '.s2.res.w'], stride=2, padding=1)
+            r = F.conv_transpose2d(h, P[name + '.s2.res.w'], stride=2, padding=1, output_padding=4 - res_k)
         else:
             t = F.conv2d(x1, P[name + '.s2.main.w'], stride=2, padding=1)
             r = F.conv2d(h, P[name + '.s2.res.w'], stride=2, padding=1)
@@ -55,4 +57,6 @@ def forward(P, R, x, train=True):
         outs[name] = e
         h = e
     z = F.conv2d(h, P['head.conv.w'], bias=P['head.conv.b'], padding=1)
+    if head == 'sigmoid':
+        z = torch.sigmoid(z)
     return z, newR
