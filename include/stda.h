@@ -81,6 +81,24 @@ int stda_param_table(stda_param_desc* out, int cap);
 int stda_bn_layer_count(void);
 size_t stda_running_count(void);
 
+/* ------------------------------------------------------------------ architecture readings
+ * Two places where the text of Sec. IV-C leaves the network open are selectable, process-wide
+ * (the default, 0, is the network described above):
+ *   STDA_ARCH_RES3    decoder long residual of Eq. (mobile_decoder_stage2) as DeConv3x3-s2-p1
+ *                     with output padding 1 (weight [Cin][Cout][3][3]) instead of DeConv4x4-s2-p1;
+ *                     the parameter count drops to 119,549.
+ *   STDA_ARCH_SIGMOID logistic sigmoid on the output module: z = sigma(Conv3x3(d1) + b).  TRAIN
+ *                     saves a copy of z (4 bytes per pixel) for the backward.
+ * The setting is read by every call: the parameter table and count, workspace sizes, and the
+ * launches.  A parameter vector, `saved` buffer or captured graph made under one setting must not
+ * be used under another.  Not synchronised: change it only while no other thread is inside the
+ * library.  Returns STDA_E_INVALID for unknown bits.
+ */
+#define STDA_ARCH_RES3 1
+#define STDA_ARCH_SIGMOID 2
+int stda_set_arch(int flags);
+int stda_get_arch(void);
+
 /*
  * Byte sizes of `saved` (kept from a TRAIN forward to its backward) and `ws` (scratch of a
  * single call; one size serves forward, backward and loss).  `recompute` != 0 keeps only the

@@ -7,6 +7,8 @@
 // gradient sum_p d[c](p) dz(p - off_t) (tap t = (ky, kx), off_t = (ky - 1, kx - 1)) and the bias
 // gradient sum_p dz(p); part[blk][10][16] holds the taps (rows 0..8) and the bias (row 9,
 // channel 0).  The grid loops over the tiles of all clips.
+// SIG: logistic output z = 1 / (1 + exp(-(conv + b))); the forward also writes z to zs (when
+// not null) and the adjoint stages dz * z (1 - z) from that copy in place of dz.
 #pragma once
 #include "stage1_tile.h"
 
@@ -14,10 +16,10 @@ namespace stda {
 
 constexpr int kHeadTH = 8, kHeadTW = 32;
 
-template <class T>
+template <class T, bool SIG>
 __global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, const float* __restrict__ w,
-                                                       const float* __restrict__ bias, float* __restrict__ z, int B,
-                                                       int H, int W) {
+                                                       const float* __restrict__ bias, float* __restrict__ z,
+                                                       float* __restrict__ zs, int B, int H, int W) {
   constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, PS = C + 4;
   __shared__ float xt[(TH + 2) * RW * PS];
   __shared__ float wt[9 * C];  // [tap][c]
@@ -43,15 +45,21 @@ __global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, 
           acc += wt[t * C + c] * v.x + wt[t * C + c + 1] * v.y + wt[t * C + c + 2] * v.z + wt[t * C + c + 3] * v.w;
         }
       }
-      z[((int64_t)b * H + y) * W + x] = acc;
+      const int64_t o = ((int64_t)b * H + y) * W + x;
+      if constexpr (SIG) {
+        acc = 1.f / (1.f + expf(-acc));
+        if (zs) zs[o] = acc;
+      }
+      z[o] = acc;
     }
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__ dz, const float* __restrict__ w,
-                                                       const T* __restrict__ d, T* __restrict__ dd,
-                                                       float* __restrict__ part, int B, int H, int W) {
+template <class T, bool SIG>
+__global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__ dz, const float* __restrict__ zs,
+                                                       const float* __restrict__ w, const T* __restrict__ d,
+                                                       T* __restrict__ dd, float* __restrict__ part, int B, int H,
+                                                       int W) {
   constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, G = 4, RW = TW + 2;
   static_assert(TH * TW == STDA_BLOCK, "one pixel per thread and channel group pass");
   __shared__ float zt[(TH + 2) * RW];
@@ -73,7 +81,13 @@ __global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__
     __syncthreads();
     for (int q = threadIdx.x; q < (TH + 2) * RW; q += STDA_BLOCK) {
       const int y = y0 - 1 + q / RW, x = x0 - 1 + q % RW;
-      zt[q] = (y >= 0 && y < H && x >= 0 && x < W) ? dz[((int64_t)b * H + y) * W + x] : 0.f;
+      float g = 0.f;
+      if (y >= 0 && y < H && x >= 0 && x < W) {
+        const int64_t o = ((int64_t)b * H + y) * W + x;
+        g = dz[o];
+        if constexpr (SIG) g *= zs[o] * (1.f - zs[o]);
+      }
+      zt[q] = g;
     }
     __syncthreads();
 #pragma unroll

@@ -101,106 +101,117 @@ int grid_for(int64_t items, int cap = 2048) {
 namespace stda {
 
 // ------------------------------------------------------------------- parameter table
-const std::vector<ParamEntry>& param_table() {
-  static std::vector<ParamEntry> tab = [] {
-    std::vector<ParamEntry> t;
-    int64_t off = 0;
-    auto add = [&](const std::string& name, std::vector<int> shape, int fan_in) {
-      ParamEntry e{};
-      std::snprintf(e.name, sizeof(e.name), "%s", name.c_str());
-      e.offset = off;
-      e.ndim = (int)shape.size();
-      int64_t n = 1;
-      for (int i = 0; i < e.ndim; ++i) {
-        e.shape[i] = shape[i];
-        n *= shape[i];
-      }
-      e.fan_in = fan_in;
-      e.count = n;
-      off += n;
-      t.push_back(e);
-    };
-    add("stem.conv.w", {16, 3, 3, 3}, 27);
-    add("stem.bn.gamma", {16}, 0);
-    add("stem.bn.beta", {16}, 0);
-    const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
-    for (int k = 0; k < 4; ++k) {
-      const BlockCfg& b = kBlocks[k];
-      const int c = b.cin, co = b.cout;
-      const std::string n = names[k];
-      add(n + ".s1.pw.w", {c, c, 1, 1}, c);
-      add(n + ".s1.pw_bn.gamma", {c}, 0);
-      add(n + ".s1.pw_bn.beta", {c}, 0);
-      add(n + ".s1.dw.w", {c, 1, 3, 3}, 9);
-      add(n + ".s1.dw_bn.gamma", {c}, 0);
-      add(n + ".s1.dw_bn.beta", {c}, 0);
-      add(n + ".s1.id_bn.gamma", {c}, 0);
-      add(n + ".s1.id_bn.beta", {c}, 0);
-      if (b.dec)
-        add(n + ".s2.main.w", {c, co, 4, 4}, c * 16);
-      else
-        add(n + ".s2.main.w", {co, c, 3, 3}, c * 9);
-      add(n + ".s2.main_bn.gamma", {co}, 0);
-      add(n + ".s2.main_bn.beta", {co}, 0);
-      if (b.dec)
-        add(n + ".s2.res.w", {c, co, 4, 4}, c * 16);
-      else
-        add(n + ".s2.res.w", {co, c, 3, 3}, c * 9);
-      add(n + ".eca.w", {3}, 3);
+int g_arch = 0;  // STDA_ARCH_* bits, see stda_set_arch
+int current_arch() { return g_arch; }
+
+static std::vector<ParamEntry> build_param_table(int arch) {
+  std::vector<ParamEntry> t;
+  int64_t off = 0;
+  auto add = [&](const std::string& name, std::vector<int> shape, int fan_in) {
+    ParamEntry e{};
+    std::snprintf(e.name, sizeof(e.name), "%s", name.c_str());
+    e.offset = off;
+    e.ndim = (int)shape.size();
+    int64_t n = 1;
+    for (int i = 0; i < e.ndim; ++i) {
+      e.shape[i] = shape[i];
+      n *= shape[i];
     }
-    add("head.conv.w", {1, 16, 3, 3}, 144);
-    add("head.conv.b", {1}, 0);
-    return t;
-  }();
-  return tab;
+    e.fan_in = fan_in;
+    e.count = n;
+    off += n;
+    t.push_back(e);
+  };
+  const int rk = (arch & STDA_ARCH_RES3) ? 3 : 4;  // decoder long-residual kernel
+  add("stem.conv.w", {16, 3, 3, 3}, 27);
+  add("stem.bn.gamma", {16}, 0);
+  add("stem.bn.beta", {16}, 0);
+  const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
+  for (int k = 0; k < 4; ++k) {
+    const BlockCfg& b = kBlocks[k];
+    const int c = b.cin, co = b.cout;
+    const std::string n = names[k];
+    add(n + ".s1.pw.w", {c, c, 1, 1}, c);
+    add(n + ".s1.pw_bn.gamma", {c}, 0);
+    add(n + ".s1.pw_bn.beta", {c}, 0);
+    add(n + ".s1.dw.w", {c, 1, 3, 3}, 9);
+    add(n + ".s1.dw_bn.gamma", {c}, 0);
+    add(n + ".s1.dw_bn.beta", {c}, 0);
+    add(n + ".s1.id_bn.gamma", {c}, 0);
+    add(n + ".s1.id_bn.beta", {c}, 0);
+    if (b.dec)
+      add(n + ".s2.main.w", {c, co, 4, 4}, c * 16);
+    else
+      add(n + ".s2.main.w", {co, c, 3, 3}, c * 9);
+    add(n + ".s2.main_bn.gamma", {co}, 0);
+    add(n + ".s2.main_bn.beta", {co}, 0);
+    if (b.dec)
+      add(n + ".s2.res.w", {c, co, rk, rk}, c * rk * rk);
+    else
+      add(n + ".s2.res.w", {co, c, 3, 3}, c * 9);
+    add(n + ".eca.w", {3}, 3);
+  }
+  add("head.conv.w", {1, 16, 3, 3}, 144);
+  add("head.conv.b", {1}, 0);
+  return t;
 }
 
-int64_t param_offset(const char* name) {
-  for (const auto& e : param_table())
-    if (std::strcmp(e.name, name) == 0) return e.offset;
+// The residual reading changes the table; the output nonlinearity does not.
+const std::vector<ParamEntry>& param_table(int arch) {
+  static const std::vector<ParamEntry> tab[2] = {build_param_table(0), build_param_table(STDA_ARCH_RES3)};
+  return tab[(arch & STDA_ARCH_RES3) ? 1 : 0];
+}
+
+static int64_t param_offset(const std::vector<ParamEntry>& t, const std::string& name) {
+  for (const auto& e : t)
+    if (name == e.name) return e.offset;
   return -1;
 }
 
-const NetOffsets& net_offsets() {
-  static NetOffsets o = [] {
-    NetOffsets n{};
-    n.stem_w = param_offset("stem.conv.w");
-    n.stem_g = param_offset("stem.bn.gamma");
-    n.stem_b = param_offset("stem.bn.beta");
-    const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
-    int64_t run = 32;  // stem BN occupies running[0..32)
-    for (int k = 0; k < 4; ++k) {
-      const std::string p = names[k];
-      BlockOffsets& b = n.blk[k];
-      b.pw_w = param_offset((p + ".s1.pw.w").c_str());
-      b.pw_g = param_offset((p + ".s1.pw_bn.gamma").c_str());
-      b.pw_b = param_offset((p + ".s1.pw_bn.beta").c_str());
-      b.dw_w = param_offset((p + ".s1.dw.w").c_str());
-      b.dw_g = param_offset((p + ".s1.dw_bn.gamma").c_str());
-      b.dw_b = param_offset((p + ".s1.dw_bn.beta").c_str());
-      b.id_g = param_offset((p + ".s1.id_bn.gamma").c_str());
-      b.id_b = param_offset((p + ".s1.id_bn.beta").c_str());
-      b.main_w = param_offset((p + ".s2.main.w").c_str());
-      b.main_g = param_offset((p + ".s2.main_bn.gamma").c_str());
-      b.main_b = param_offset((p + ".s2.main_bn.beta").c_str());
-      b.res_w = param_offset((p + ".s2.res.w").c_str());
-      b.eca_w = param_offset((p + ".eca.w").c_str());
-      const int c = kBlocks[k].cin, co = kBlocks[k].cout;
-      b.bn_pw = run;
-      run += 2 * c;
-      b.bn_dw = run;
-      run += 2 * c;
-      b.bn_id = run;
-      run += 2 * c;
-      b.bn_main = run;
-      run += 2 * co;
-    }
-    n.head_w = param_offset("head.conv.w");
-    n.head_b = param_offset("head.conv.b");
-    n.running_count = run;
-    return n;
-  }();
-  return o;
+static NetOffsets build_net_offsets(int arch) {
+  const std::vector<ParamEntry>& t = param_table(arch);
+  NetOffsets n{};
+  n.stem_w = param_offset(t, "stem.conv.w");
+  n.stem_g = param_offset(t, "stem.bn.gamma");
+  n.stem_b = param_offset(t, "stem.bn.beta");
+  const char* names[4] = {"enc0", "enc1", "dec0", "dec1"};
+  int64_t run = 32;  // stem BN occupies running[0..32)
+  for (int k = 0; k < 4; ++k) {
+    const std::string p = names[k];
+    BlockOffsets& b = n.blk[k];
+    b.pw_w = param_offset(t, p + ".s1.pw.w");
+    b.pw_g = param_offset(t, p + ".s1.pw_bn.gamma");
+    b.pw_b = param_offset(t, p + ".s1.pw_bn.beta");
+    b.dw_w = param_offset(t, p + ".s1.dw.w");
+    b.dw_g = param_offset(t, p + ".s1.dw_bn.gamma");
+    b.dw_b = param_offset(t, p + ".s1.dw_bn.beta");
+    b.id_g = param_offset(t, p + ".s1.id_bn.gamma");
+    b.id_b = param_offset(t, p + ".s1.id_bn.beta");
+    b.main_w = param_offset(t, p + ".s2.main.w");
+    b.main_g = param_offset(t, p + ".s2.main_bn.gamma");
+    b.main_b = param_offset(t, p + ".s2.main_bn.beta");
+    b.res_w = param_offset(t, p + ".s2.res.w");
+    b.eca_w = param_offset(t, p + ".eca.w");
+    const int c = kBlocks[k].cin, co = kBlocks[k].cout;
+    b.bn_pw = run;
+    run += 2 * c;
+    b.bn_dw = run;
+    run += 2 * c;
+    b.bn_id = run;
+    run += 2 * c;
+    b.bn_main = run;
+    run += 2 * co;
+  }
+  n.head_w = param_offset(t, "head.conv.w");
+  n.head_b = param_offset(t, "head.conv.b");
+  n.running_count = run;
+  n.param_count = t.back().offset + t.back().count;
+  return n;
+}
+
+const NetOffsets& net_offsets(int arch) {
+  static const NetOffsets o[2] = {build_net_offsets(0), build_net_offsets(STDA_ARCH_RES3)};
+  return o[(arch & STDA_ARCH_RES3) ? 1 : 0];
 }
 
 }  // namespace stda
@@ -282,12 +293,14 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
   P.n_segs = n_segs;
   P.dtype = dtype;
   P.mode = mode;
+  P.arch = current_arch();
+  const bool sigmoid_save = (P.arch & STDA_ARCH_SIGMOID) && mode == STDA_TRAIN;
   const size_t es = dtype == STDA_BF16 ? 2 : 4;
   Bump sv, ws;
   const bool train = mode == STDA_TRAIN;
   Bump& acts = train ? sv : ws;
   // per-call scratch shared by all segments
-  P.ws_wk = ws.take(sizeof(float) * stda_param_count());
+  P.ws_wk = ws.take(sizeof(float) * net_offsets(P.arch).param_count);
   int64_t dense_elems = 0;
   for (int k = 0; k < 4; ++k) {
     const BlockCfg& b = kBlocks[k];
@@ -352,6 +365,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     const int64_t HW = H * W;
     S.stats = (train ? sv : ws).take(sizeof(float) * stda_running_count());
     S.s0 = acts.take(es * 16 * n * HW);
+    S.zs = sigmoid_save ? sv.take(sizeof(float) * n * HW) : 0;
     for (int k = 0; k < 4; ++k) {
       const BlockCfg& b = kBlocks[k];
       const int64_t hin = H >> b.lin, win = W >> b.lin, hout = H >> b.lout, wout = W >> b.lout;
@@ -526,7 +540,7 @@ int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* c
 template <class T, int CIN, int COUT, bool DEC>
 int fwd_block(const Ctx<T>& c, int k, float* running) {
   const BlockCfg& bc = kBlocks[k];
-  const BlockOffsets& bo = net_offsets().blk[k];
+  const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
   const SegPlan& S = *c.S;
   const BlockActs& A = S.blk[k];
   const int n = S.n;
@@ -578,8 +592,18 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
                                                        nullptr))
       return r;
   }
-  if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
-    return r;
+  bool res_done = false;
+  if constexpr (DEC) {
+    if (c.P->arch & STDA_ARCH_RES3) {
+      // DeConv3x3-s2-p1 (output padding 1): the input-gradient operator of a Conv3x3-s2-p1
+      if (int r = launch_dense<T, OP_ENC_DGRAD, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+        return r;
+      res_done = true;
+    }
+  }
+  if (!res_done)
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+      return r;
   // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
   const int hw = hout * wout;
   const int tiles = tiles_for(hw, COUT / 4);
@@ -608,7 +632,7 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
 template <class T>
 int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   const SegPlan& S = *c.S;
-  const NetOffsets& no = net_offsets();
+  const NetOffsets& no = net_offsets(c.P->arch);
   const int64_t P = (int64_t)S.n * S.H * S.W;
   const float* xs = x + S.x_off;
   float* part = c.template scr<float>(c.P->ws_part);
@@ -627,8 +651,15 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
   if (int r = fwd_block<T, 32, 16, true>(c, 3, running)) return r;
   const int gz = head_grid(S.n, S.H, S.W);
-  KLAUNCH("head_fwd", k_head_fwd_tile<T><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
-                                                               c.w + no.head_b, z + S.z_off, S.n, S.H, S.W));
+  if (c.P->arch & STDA_ARCH_SIGMOID) {
+    float* zs = S.zs ? c.template act<float>(S.zs) : nullptr;
+    KLAUNCH("head_fwd", k_head_fwd_tile<T, true><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
+                                                                     c.w + no.head_b, z + S.z_off, zs, S.n, S.H, S.W));
+  } else {
+    KLAUNCH("head_fwd", k_head_fwd_tile<T, false><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
+                                                                      c.w + no.head_b, z + S.z_off, nullptr, S.n, S.H,
+                                                                      S.W));
+  }
   return STDA_OK;
 }
 
@@ -645,11 +676,13 @@ int validate_segs(const stda_segment* segs, int n_segs) {
 // Per-call preparation: working weights and dense layouts.
 int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, const float** wk_out) {
   float* wk = reinterpret_cast<float*>(ws + P.ws_wk);
-  const int64_t np = (int64_t)stda_param_count();
+  const NetOffsets& no = net_offsets(P.arch);
+  const int64_t np = no.param_count;
+  const bool res3 = (P.arch & STDA_ARCH_RES3) != 0;
   const float* src = w;
   if (P.dtype == STDA_BF16) {
     RoundRanges rr{};
-    for (const auto& e : param_table()) {
+    for (const auto& e : param_table(P.arch)) {
       // only the weights the matrix cores consume (the stride-2 layers) are rounded; the
       // SIMT layers (input / output modules, pointwise, depthwise) keep FP32 weights
       const bool mfma_w = std::strstr(e.name, ".s2.main.w") != nullptr || std::strstr(e.name, ".s2.res.w") != nullptr;
@@ -665,23 +698,34 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
   }
   PrepJobs jobs{};
   jobs.bf16 = P.dtype == STDA_BF16;
-  const NetOffsets& no = net_offsets();
   for (int k = 0; k < 4; ++k)
     for (int m = 0; m < 2; ++m) {
       PrepJob& j = jobs.j[jobs.n++];
-      j.dec = kBlocks[k].dec;
-      j.cin = kBlocks[k].cin;
-      j.cout = kBlocks[k].cout;
       j.src = m == 0 ? no.blk[k].main_w : no.blk[k].res_w;
-      j.dst_f = P.dense_f[k][m];
-      j.dst_d = P.dense_d[k][m];
+      if (res3 && m == 1 && kBlocks[k].dec) {
+        // DeConv3x3-s2-p1 with output padding 1 is the adjoint of a Conv3x3-s2-p1 whose input
+        // is the residual's output (Cout channels) and whose output is its input (Cin): the
+        // same [Cin][Cout][3][3] array read as that conv's [out][in][3][3] weight.  Its
+        // forward layout is that conv's input-gradient layout and vice versa.
+        j.dec = 0;
+        j.cin = kBlocks[k].cout;
+        j.cout = kBlocks[k].cin;
+        j.dst_f = P.dense_d[k][m];
+        j.dst_d = P.dense_f[k][m];
+      } else {
+        j.dec = kBlocks[k].dec;
+        j.cin = kBlocks[k].cin;
+        j.cout = kBlocks[k].cout;
+        j.dst_f = P.dense_f[k][m];
+        j.dst_d = P.dense_d[k][m];
+      }
     }
   k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
   LAUNCH_CHECK();
   FragJobs fj{};
   for (int k = 0; k < 4; ++k)
     for (int m = 0; m < 2; ++m) {
-      const int taps = kBlocks[k].dec ? 16 : 9;
+      const int taps = kBlocks[k].dec && !(res3 && m == 1) ? 16 : 9;
       fj.j[fj.n++] = FragJob{P.dense_f[k][m], P.dense_f[k][m], taps, kBlocks[k].cin, kBlocks[k].cout};
       fj.j[fj.n++] = FragJob{P.dense_d[k][m], P.dense_d[k][m], taps, kBlocks[k].cout, kBlocks[k].cin};
     }
@@ -705,8 +749,6 @@ int forward_all(const Plan& P, const float* x, const float* w, float* running, f
     Ctx<T> c{&P, &P.seg[s], train ? saved : ws, ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, train};
     if (!train) {
       BnTable tab{};
-      const NetOffsets& no = net_offsets();
-      (void)no;
       int off = 0;
       tab.off[tab.n] = off;
       tab.C[tab.n++] = 16;
@@ -845,7 +887,7 @@ int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg,
 template <class T, int CIN, int COUT, bool DEC>
 int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, float* dw, int acc) {
   const BlockCfg& bc = kBlocks[k];
-  const BlockOffsets& bo = net_offsets().blk[k];
+  const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
   const SegPlan& S = *c.S;
   const BlockActs& A = S.blk[k];
   const int n = S.n;
@@ -884,13 +926,26 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   (void)gd;
   if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
     return r;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
-    return r;
+  const bool res3 = DEC && (c.P->arch & STDA_ARCH_RES3);
+  if constexpr (DEC) {
+    if (res3)  // adjoint of the DeConv3x3-s2-p1 residual: a Conv3x3-s2-p1 of dY
+      if (int r = launch_dense<T, OP_ENC_FWD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+        return r;
+  }
+  if (!res3)
+    if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+      return r;
   // dense weight gradients
   if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_main", k), X1, dT, n, hin, win, dw + bo.main_w, acc))
     return r;
-  if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_res", k), X, dY, n, hin, win, dw + bo.res_w, acc))
-    return r;
+  if constexpr (DEC) {
+    if (res3)  // the weight gradient of that Conv3x3-s2-p1 with input dY and output gradient X
+      if (int r = launch_wgrad<T, false, COUT, CIN>(c, k, tagk("wgrad_res", k), dY, X, n, hout, wout, dw + bo.res_w, acc))
+        return r;
+  }
+  if (!res3)
+    if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_res", k), X, dY, n, hin, win, dw + bo.res_w, acc))
+      return r;
   // stage 1
   S1Params sp{};
   sp.wpw = c.w + bo.pw_w;
@@ -933,7 +988,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
 template <class T>
 int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, float* dx, int acc) {
   const SegPlan& S = *c.S;
-  const NetOffsets& no = net_offsets();
+  const NetOffsets& no = net_offsets(c.P->arch);
   const int64_t P = (int64_t)S.n * S.H * S.W;
   auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
   const float* dzs = dz + S.z_off;
@@ -941,8 +996,15 @@ int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
   {
     float* part = c.template scr<float>(c.P->ws_part);
     const int gh = head_grid(S.n, S.H, S.W);
-    KLAUNCH("head_bwd", k_head_bwd_tile<T><<<gh, 256, 0, c.st>>>(dzs, c.w + no.head_w, c.template act<T>(S.blk[3].Xn),
-                                                                 gb(0), part, S.n, S.H, S.W));
+    if (c.P->arch & STDA_ARCH_SIGMOID) {
+      KLAUNCH("head_bwd", k_head_bwd_tile<T, true><<<gh, 256, 0, c.st>>>(dzs, c.template act<float>(S.zs), c.w + no.head_w,
+                                                                       c.template act<T>(S.blk[3].Xn), gb(0), part,
+                                                                       S.n, S.H, S.W));
+    } else {
+      KLAUNCH("head_bwd", k_head_bwd_tile<T, false><<<gh, 256, 0, c.st>>>(dzs, nullptr, c.w + no.head_w,
+                                                                        c.template act<T>(S.blk[3].Xn), gb(0), part,
+                                                                        S.n, S.H, S.W));
+    }
     if (int r = colsum_to(c, part, gh, 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
@@ -1015,13 +1077,10 @@ const char* stda_status_string(int s) {
 
 int stda_last_hip_error(void) { return g_last_hip; }
 
-size_t stda_param_count(void) {
-  const auto& t = param_table();
-  return (size_t)(t.back().offset + t.back().count);
-}
+size_t stda_param_count(void) { return (size_t)net_offsets(current_arch()).param_count; }
 
 int stda_param_table(stda_param_desc* out, int cap) {
-  const auto& t = param_table();
+  const auto& t = param_table(current_arch());
   if (out) {
     for (int i = 0; i < (int)t.size() && i < cap; ++i) {
       std::memset(&out[i], 0, sizeof(out[i]));
@@ -1309,7 +1368,15 @@ int stda_profile_report(char* buf, size_t cap, size_t* needed) {
 }
 
 int stda_bn_layer_count(void) { return 17; }
-size_t stda_running_count(void) { return (size_t)net_offsets().running_count; }
+size_t stda_running_count(void) { return (size_t)net_offsets(0).running_count; }
+
+int stda_set_arch(int flags) {
+  if (flags & ~(STDA_ARCH_RES3 | STDA_ARCH_SIGMOID)) return STDA_E_INVALID;
+  g_arch = flags;
+  return STDA_OK;
+}
+
+int stda_get_arch(void) { return g_arch; }
 
 int stda_workspace_size(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute,
                         size_t* saved_bytes, size_t* ws_bytes) {

@@ -46,11 +46,14 @@ struct BlockOffsets {
 struct NetOffsets {
   int64_t stem_w, stem_g, stem_b, head_w, head_b;
   BlockOffsets blk[4];
-  int64_t running_count;
+  int64_t running_count, param_count;
 };
 
-const std::vector<ParamEntry>& param_table();
-const NetOffsets& net_offsets();
+// Architecture readings (STDA_ARCH_* bits) set by stda_set_arch; a call reads them once into its
+// plan and passes that value on.
+int current_arch();
+const std::vector<ParamEntry>& param_table(int arch);
+const NetOffsets& net_offsets(int arch);
 
 // Byte offsets of one segment's activations (in `saved` for TRAIN, in `ws` for EVAL).
 struct BlockActs {
@@ -62,11 +65,12 @@ struct SegPlan {
   int64_t x_off, z_off;
   size_t stats;  // [mean C][invstd C] per BN layer, running-buffer layout
   size_t s0;
+  size_t zs;     // TRAIN with the sigmoid output: FP32 copy of z (in saved), else 0
   BlockActs blk[4];
 };
 
 struct Plan {
-  int n_segs, dtype, mode;
+  int n_segs, dtype, mode, arch;
   SegPlan seg[kMaxSegs];
   // ws regions (byte offsets)
   size_t ws_wk, ws_dense, ws_R, ws_part, ws_sums, ws_gap, ws_eval_stats, ws_loss;

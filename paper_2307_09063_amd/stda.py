@@ -46,6 +46,8 @@ def _load():
         'stda_param_table': (I, [P, I]),
         'stda_bn_layer_count': (I, []),
         'stda_running_count': (SZ, []),
+        'stda_set_arch': (I, [I]),
+        'stda_get_arch': (I, []),
         'stda_workspace_size': (I, [P, I, I, I, I, P, P]),
         'stda_forward': (I, [P, I, P, P, P, P, P, SZ, P, SZ, I, I, I, P]),
         'stda_backward': (I, [P, I, P, P, P, P, SZ, P, P, P, SZ, I, I, P]),
@@ -79,7 +81,7 @@ def _load():
 
 _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
-           'stda_bn_layer_count', 'stda_running_count', 'stda_workspace_size', 'stda_forward',
+           'stda_bn_layer_count', 'stda_running_count', 'stda_set_arch', 'stda_get_arch', 'stda_workspace_size', 'stda_forward',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
@@ -115,6 +117,25 @@ def _seg_array(segs):
 
 
 # ------------------------------------------------------------------------ tables
+ARCH_RES3, ARCH_SIGMOID = 1, 2
+
+
+def set_arch(res_k=4, head='identity'):
+    """Process-wide architecture reading: res_k = 3 takes the decoder long residual as
+    DeConv3x3-s2-p1 with output padding 1 (4: DeConv4x4-s2-p1), head = 'sigmoid' puts a logistic
+    sigmoid on the output.  Parameter vectors, saved buffers and graphs are tied to the setting
+    they were made under."""
+    if res_k not in (3, 4) or head not in ('identity', 'sigmoid'):
+        raise StdaError(f'unknown architecture res_k={res_k} head={head}')
+    flags = (ARCH_RES3 if res_k == 3 else 0) | (ARCH_SIGMOID if head == 'sigmoid' else 0)
+    _check(_lib.stda_set_arch(flags), 'stda_set_arch')
+
+
+def get_arch():
+    f = int(_lib.stda_get_arch())
+    return {'res_k': 3 if f & ARCH_RES3 else 4, 'head': 'sigmoid' if f & ARCH_SIGMOID else 'identity'}
+
+
 def param_count():
     return int(_lib.stda_param_count())
 

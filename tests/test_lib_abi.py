@@ -118,3 +118,39 @@ def test_workspace_grows_with_batch(S):
     assert ev[0] == 0
     bf = S.workspace_size(S.uniform_segments(2, 64, 64), S.BF16, S.TRAIN)
     assert bf[0] < a[0]
+
+
+@pytest.mark.parametrize('res_k,head', [(3, 'identity'), (4, 'sigmoid'), (3, 'sigmoid')])
+def test_architecture_readings_layout(S, res_k, head):
+    """The residual reading changes the parameter table exactly as in the oracle; the sigmoid
+    output adds one FP32 map per clip to the TRAIN saved buffer and nothing else."""
+    segs = S.uniform_segments(3, 32, 24)
+    sv0, ws0 = S.workspace_size(segs, S.FP32, S.TRAIN)
+    ev0 = S.workspace_size(segs, S.FP32, S.EVAL)
+    try:
+        S.set_arch(res_k, head)
+        net.set_arch(res_k, head)
+        assert S.get_arch() == {'res_k': res_k, 'head': head}
+        got = [(d['name'], d['shape'], d['fan_in']) for d in S.param_table()]
+        assert got == [(n, tuple(s), f) for n, s, f in net.param_specs()]
+        assert S.param_count() == net.param_count() == (119549 if res_k == 3 else 137469)
+        sv, ws = S.workspace_size(segs, S.FP32, S.TRAIN)
+        ev = S.workspace_size(segs, S.FP32, S.EVAL)
+        extra = -(-(3 * 32 * 24 * 4) // 256) * 256 if head == 'sigmoid' else 0
+        assert sv == sv0 + extra
+        assert ev[0] == ev0[0] == 0
+        # the working-weight copy in ws shrinks with the parameter count
+        assert ws <= ws0 and ev[1] <= ev0[1]
+    finally:
+        S.set_arch()
+        net.set_arch()
+    assert S.get_arch() == {'res_k': 4, 'head': 'identity'}
+    assert S.param_count() == 137469
+
+
+def test_set_arch_rejects_unknown_bits(S):
+    assert S._lib.stda_set_arch(4) == -1      # STDA_E_INVALID
+    assert S._lib.stda_set_arch(-1) == -1
+    assert S._lib.stda_get_arch() == 0
+    with pytest.raises(S.StdaError):
+        S.set_arch(5)
