@@ -82,13 +82,15 @@ int stda_bn_layer_count(void);
 size_t stda_running_count(void);
 
 /* ------------------------------------------------------------------ architecture readings
- * Two places where the text of Sec. IV-C leaves the network open are selectable, process-wide
+ * Three places where the text of Sec. IV-C leaves the network open are selectable, process-wide
  * (the default, 0, is the network described above):
  *   STDA_ARCH_RES3    decoder long residual of Eq. (mobile_decoder_stage2) as DeConv3x3-s2-p1
  *                     with output padding 1 (weight [Cin][Cout][3][3]) instead of DeConv4x4-s2-p1;
  *                     the parameter count drops to 119,549.
  *   STDA_ARCH_SIGMOID logistic sigmoid on the output module: z = sigma(Conv3x3(d1) + b).  TRAIN
  *                     saves a copy of z (4 bytes per pixel) for the backward.
+ *   STDA_ARCH_PW_DW   stage-1 1x1 branch of Eq. (mobile_encoder_stage1) / (mobile_decoder_stage1)
+ *                     depthwise (weight [C][1][1][1]) instead of dense; 6,256 parameters fewer.
  * The setting is read by every call: the parameter table and count, workspace sizes, and the
  * launches.  A parameter vector, `saved` buffer or captured graph made under one setting must not
  * be used under another.  Not synchronised: change it only while no other thread is inside the
@@ -96,6 +98,7 @@ size_t stda_running_count(void);
  */
 #define STDA_ARCH_RES3 1
 #define STDA_ARCH_SIGMOID 2
+#define STDA_ARCH_PW_DW 4
 int stda_set_arch(int flags);
 int stda_get_arch(void);
 

@@ -16,7 +16,8 @@ Architecture (Radar-STDA, arXiv 2307.09063, Sec. IV):
     after decoder block 1).
   * output module: Conv3x3 16->1 with bias, no activation.
 Stage 1 of a block: BN(PW1x1(x)) + BN(DW3x3(x)) + BN(x), ReLU; the 3x3 branch is depthwise
-(the paper attributes the model's speed to depthwise separable convolution, Sec. VI-C).
+(the paper attributes the model's speed to depthwise separable convolution, Sec. VI-C) and the
+1x1 branch dense (ablation: depthwise too, see ARCH).
 Stage 2: ReLU(BN(Conv3x3-s2(x'))) + Conv3x3-s2(x) in the encoder; in the decoder both are
 DeConv4x4-s2-p1 (the printed decoder residual cannot produce the stated output size).
 Loss: mean squared error against the interference-free frame-t map (the paper names none).
@@ -33,12 +34,13 @@ DEC_IN = (64, 32)      # decoder block input widths
 #   res_k : kernel of the decoder long residual, 4 (DeConv4x4-s2-p1) or 3 (DeConv3x3-s2-p1 with
 #           one row and column of output padding, so that it also doubles the map)
 #   head  : 'identity' (z = Conv3x3(d1) + b) or 'sigmoid' (z = sigmoid of that)
-ARCH = {'res_k': 4, 'head': 'identity'}
+#   pw    : stage-1 1x1 branch 'dense' (C x C) or 'depthwise' (one weight per channel, groups = C)
+ARCH = {'res_k': 4, 'head': 'identity', 'pw': 'dense'}
 
 
-def set_arch(res_k=4, head='identity'):
-    assert res_k in (3, 4) and head in ('identity', 'sigmoid')
-    ARCH['res_k'], ARCH['head'] = res_k, head
+def set_arch(res_k=4, head='identity', pw='dense'):
+    assert res_k in (3, 4) and head in ('identity', 'sigmoid') and pw in ('dense', 'depthwise')
+    ARCH['res_k'], ARCH['head'], ARCH['pw'] = res_k, head, pw
 
 
 def param_specs():
@@ -48,7 +50,10 @@ def param_specs():
 
     def block(name, c, co, dec):
         s = []
-        s.append((f'{name}.s1.pw.w', (c, c, 1, 1), c))
+        if ARCH['pw'] == 'depthwise':
+            s.append((f'{name}.s1.pw.w', (c, 1, 1, 1), 1))
+        else:
+            s.append((f'{name}.s1.pw.w', (c, c, 1, 1), c))
         s.append((f'{name}.s1.pw_bn.gamma', (c,), 0))
         s.append((f'{name}.s1.pw_bn.beta', (c,), 0))
         s.append((f'{name}.s1.dw.w', (c, 1, 3, 3), 9))
@@ -137,11 +142,12 @@ def _bn(name, x, P, R, mode, newR, caches):
 
 def _stage1(name, x, P, R, mode, newR, caches, dec):
     c = x.shape[1]
+    gp = c if ARCH['pw'] == 'depthwise' else 1
     if dec:
-        p = L.deconv2d(x, P[name + '.s1.pw.w'])
+        p = L.deconv2d(x, P[name + '.s1.pw.w'], groups=gp)
         d = L.deconv2d(x, P[name + '.s1.dw.w'], stride=1, pad=1, groups=c)
     else:
-        p = L.conv2d(x, P[name + '.s1.pw.w'])
+        p = L.conv2d(x, P[name + '.s1.pw.w'], groups=gp)
         d = L.conv2d(x, P[name + '.s1.dw.w'], stride=1, pad=1, groups=c)
     u = (_bn(name + '.s1.pw_bn', p, P, R, mode, newR, caches)
          + _bn(name + '.s1.dw_bn', d, P, R, mode, newR, caches)
@@ -238,14 +244,15 @@ def _stage1_backward(name, dx1, x, x1, P, caches, G, dec):
     dx, G[name + '.s1.id_bn.gamma'], G[name + '.s1.id_bn.beta'] = \
         L.bn_backward(du, caches[name + '.s1.id_bn'])
     wp, wd = P[name + '.s1.pw.w'], P[name + '.s1.dw.w']
+    gp = c if wp.shape[1] == 1 and c > 1 else 1      # depthwise 1x1 reading
     if dec:
-        dx = dx + L.deconv2d_grad_input(dp, wp, x.shape)
-        G[name + '.s1.pw.w'] = L.deconv2d_grad_weight(x, dp, wp.shape)
+        dx = dx + L.deconv2d_grad_input(dp, wp, x.shape, groups=gp)
+        G[name + '.s1.pw.w'] = L.deconv2d_grad_weight(x, dp, wp.shape, groups=gp)
         dx = dx + L.deconv2d_grad_input(dd, wd, x.shape, stride=1, pad=1, groups=c)
         G[name + '.s1.dw.w'] = L.deconv2d_grad_weight(x, dd, wd.shape, stride=1, pad=1, groups=c)
     else:
-        dx = dx + L.conv2d_grad_input(dp, wp, x.shape)
-        G[name + '.s1.pw.w'] = L.conv2d_grad_weight(x, dp, wp.shape)
+        dx = dx + L.conv2d_grad_input(dp, wp, x.shape, groups=gp)
+        G[name + '.s1.pw.w'] = L.conv2d_grad_weight(x, dp, wp.shape, groups=gp)
         dx = dx + L.conv2d_grad_input(dd, wd, x.shape, stride=1, pad=1, groups=c)
         G[name + '.s1.dw.w'] = L.conv2d_grad_weight(x, dd, wd.shape, stride=1, pad=1, groups=c)
     return dx

@@ -123,6 +123,7 @@ static std::vector<ParamEntry> build_param_table(int arch) {
     t.push_back(e);
   };
   const int rk = (arch & STDA_ARCH_RES3) ? 3 : 4;  // decoder long-residual kernel
+  const bool pw_dw = (arch & STDA_ARCH_PW_DW) != 0;  // stage-1 1x1 branch depthwise
   add("stem.conv.w", {16, 3, 3, 3}, 27);
   add("stem.bn.gamma", {16}, 0);
   add("stem.bn.beta", {16}, 0);
@@ -131,7 +132,10 @@ static std::vector<ParamEntry> build_param_table(int arch) {
     const BlockCfg& b = kBlocks[k];
     const int c = b.cin, co = b.cout;
     const std::string n = names[k];
-    add(n + ".s1.pw.w", {c, c, 1, 1}, c);
+    if (pw_dw)
+      add(n + ".s1.pw.w", {c, 1, 1, 1}, 1);
+    else
+      add(n + ".s1.pw.w", {c, c, 1, 1}, c);
     add(n + ".s1.pw_bn.gamma", {c}, 0);
     add(n + ".s1.pw_bn.beta", {c}, 0);
     add(n + ".s1.dw.w", {c, 1, 3, 3}, 9);
@@ -156,10 +160,14 @@ static std::vector<ParamEntry> build_param_table(int arch) {
   return t;
 }
 
-// The residual reading changes the table; the output nonlinearity does not.
+// One table per combination of readings (the output nonlinearity leaves it unchanged).
+constexpr int kArchCombos = 8;
 const std::vector<ParamEntry>& param_table(int arch) {
-  static const std::vector<ParamEntry> tab[2] = {build_param_table(0), build_param_table(STDA_ARCH_RES3)};
-  return tab[(arch & STDA_ARCH_RES3) ? 1 : 0];
+  static const std::vector<ParamEntry> tab[kArchCombos] = {build_param_table(0), build_param_table(1),
+                                                          build_param_table(2), build_param_table(3),
+                                                          build_param_table(4), build_param_table(5),
+                                                          build_param_table(6), build_param_table(7)};
+  return tab[arch & (kArchCombos - 1)];
 }
 
 static int64_t param_offset(const std::vector<ParamEntry>& t, const std::string& name) {
@@ -210,8 +218,10 @@ static NetOffsets build_net_offsets(int arch) {
 }
 
 const NetOffsets& net_offsets(int arch) {
-  static const NetOffsets o[2] = {build_net_offsets(0), build_net_offsets(STDA_ARCH_RES3)};
-  return o[(arch & STDA_ARCH_RES3) ? 1 : 0];
+  static const NetOffsets o[kArchCombos] = {build_net_offsets(0), build_net_offsets(1), build_net_offsets(2),
+                                            build_net_offsets(3), build_net_offsets(4), build_net_offsets(5),
+                                            build_net_offsets(6), build_net_offsets(7)};
+  return o[arch & (kArchCombos - 1)];
 }
 
 }  // namespace stda
@@ -272,6 +282,21 @@ __global__ void k_working_weights(const float* __restrict__ w, float* __restrict
   }
 }
 
+// Depthwise 1x1 reading: the per-channel weights of each block's 1x1 branch written as the
+// diagonal of a dense C x C matrix, so that the dense pointwise kernels compute exactly the
+// depthwise branch (the off-diagonal products are exact zeros).
+struct PwDiag {
+  int64_t src[4], dst[4];
+  int C[4];
+};
+__global__ void k_pw_diag(const float* __restrict__ w, float* __restrict__ out, PwDiag d) {
+  const int k = blockIdx.y, C = d.C[k];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < C * C; i += gridDim.x * blockDim.x) {
+    const int r = i / C, q = i % C;
+    out[d.dst[k] + i] = r == q ? w[d.src[k] + r] : 0.f;
+  }
+}
+
 }  // namespace
 
 // ===================================================================== plan
@@ -313,6 +338,12 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     }
   }
   P.ws_dense = ws.take(sizeof(float) * dense_elems);
+  int64_t pwx = 0;
+  for (int k = 0; k < 4; ++k) {
+    P.pwx_off[k] = pwx;
+    pwx += (int64_t)kBlocks[k].cin * kBlocks[k].cin;
+  }
+  P.ws_pwx = ws.take(sizeof(float) * pwx);
   P.ws_frag = ws.take(sizeof(float) * dense_elems);  // same element offsets as ws_dense
   int64_t max_pix = 0, max_clips = 0;
   for (int s = 0; s < n_segs; ++s) {
@@ -553,7 +584,7 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   T* R = c.template scr<T>(c.P->ws_R);
   float* part = c.template scr<float>(c.P->ws_part);
   S1Params sp{};
-  sp.wpw = c.w + bo.pw_w;
+  sp.wpw = (c.P->arch & STDA_ARCH_PW_DW) ? c.template scr<float>(c.P->ws_pwx) + c.P->pwx_off[k] : c.w + bo.pw_w;
   sp.wdw = c.w + bo.dw_w;
   sp.stats[0] = c.stats(bo.bn_pw);
   sp.stats[1] = c.stats(bo.bn_dw);
@@ -722,6 +753,16 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
     }
   k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
   LAUNCH_CHECK();
+  if (P.arch & STDA_ARCH_PW_DW) {
+    PwDiag d{};
+    for (int k = 0; k < 4; ++k) {
+      d.src[k] = no.blk[k].pw_w;
+      d.dst[k] = P.pwx_off[k];
+      d.C[k] = kBlocks[k].cin;
+    }
+    k_pw_diag<<<dim3(16, 4), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_pwx), d);
+    LAUNCH_CHECK();
+  }
   FragJobs fj{};
   for (int k = 0; k < 4; ++k)
     for (int m = 0; m < 2; ++m) {
@@ -948,7 +989,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
       return r;
   // stage 1
   S1Params sp{};
-  sp.wpw = c.w + bo.pw_w;
+  sp.wpw = (c.P->arch & STDA_ARCH_PW_DW) ? c.template scr<float>(c.P->ws_pwx) + c.P->pwx_off[k] : c.w + bo.pw_w;
   sp.wdw = c.w + bo.dw_w;
   sp.stats[0] = c.stats(bo.bn_pw);
   sp.stats[1] = c.stats(bo.bn_dw);
@@ -980,8 +1021,9 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
                                                                part, n, hin, win);
   }
   LAUNCH_CHECK();
-  if (int r = colsum_to(c, pwpart, g1, CIN * CIN, dw + bo.pw_w, ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0}, acc))
-    return r;
+  const ColMap pwmap = (c.P->arch & STDA_ARCH_PW_DW) ? ColMap{MAP_PW_DIAG, CIN, 0}
+                                                      : ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0};
+  if (int r = colsum_to(c, pwpart, g1, CIN * CIN, dw + bo.pw_w, pwmap, acc)) return r;
   return colsum_to(c, part, g1, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc);
 }
 
@@ -1371,7 +1413,7 @@ int stda_bn_layer_count(void) { return 17; }
 size_t stda_running_count(void) { return (size_t)net_offsets(0).running_count; }
 
 int stda_set_arch(int flags) {
-  if (flags & ~(STDA_ARCH_RES3 | STDA_ARCH_SIGMOID)) return STDA_E_INVALID;
+  if (flags & ~(STDA_ARCH_RES3 | STDA_ARCH_SIGMOID | STDA_ARCH_PW_DW)) return STDA_E_INVALID;
   g_arch = flags;
   return STDA_OK;
 }

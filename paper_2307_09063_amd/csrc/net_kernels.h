@@ -92,7 +92,7 @@ struct ColMap {
   int a, b;   // kind-specific sizes
 };
 enum : int { MAP_DOUBLE = 0, MAP_ENC_S2 = 1, MAP_DEC_S2 = 2, MAP_PW_CONV = 3, MAP_IDENT = 4,
-             MAP_DW = 5, MAP_STEM = 6, MAP_HEAD = 7 };
+             MAP_DW = 5, MAP_STEM = 6, MAP_HEAD = 7, MAP_PW_DIAG = 8 };
 
 __device__ __forceinline__ int64_t colmap_dst(const ColMap m, int col) {
   switch (m.kind) {
@@ -107,6 +107,10 @@ __device__ __forceinline__ int64_t colmap_dst(const ColMap m, int col) {
     case MAP_PW_CONV: {  // col = c*C + o -> w[o][c]; a = C
       const int o = col % m.a, c = col / m.a;
       return (int64_t)o * m.a + c;
+    }
+    case MAP_PW_DIAG: {  // col = c*C + o -> w[c] if c == o, else unused; a = C
+      const int o = col % m.a, c = col / m.a;
+      return c == o ? c : -1;
     }
     case MAP_DW: {  // col = tap*C + c -> w[c][tap]; a = C
       const int c = col % m.a, tap = col / m.a;

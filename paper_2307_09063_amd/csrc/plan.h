@@ -78,6 +78,8 @@ struct Plan {
   size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart, ws_frag;
   size_t rec_T;                          // recompute scratch of the stage-2 main output
   int64_t dense_f[4][2], dense_d[4][2];  // element offsets inside ws_dense (main, residual)
+  size_t ws_pwx;                         // depthwise 1x1 reading: diagonal C x C weights
+  int64_t pwx_off[4];                    // element offsets inside ws_pwx per block
   size_t saved_bytes, ws_bytes;
 };
 

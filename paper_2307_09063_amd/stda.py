@@ -117,23 +117,25 @@ def _seg_array(segs):
 
 
 # ------------------------------------------------------------------------ tables
-ARCH_RES3, ARCH_SIGMOID = 1, 2
+ARCH_RES3, ARCH_SIGMOID, ARCH_PW_DW = 1, 2, 4
 
 
-def set_arch(res_k=4, head='identity'):
+def set_arch(res_k=4, head='identity', pw='dense'):
     """Process-wide architecture reading: res_k = 3 takes the decoder long residual as
     DeConv3x3-s2-p1 with output padding 1 (4: DeConv4x4-s2-p1), head = 'sigmoid' puts a logistic
-    sigmoid on the output.  Parameter vectors, saved buffers and graphs are tied to the setting
-    they were made under."""
-    if res_k not in (3, 4) or head not in ('identity', 'sigmoid'):
-        raise StdaError(f'unknown architecture res_k={res_k} head={head}')
-    flags = (ARCH_RES3 if res_k == 3 else 0) | (ARCH_SIGMOID if head == 'sigmoid' else 0)
+    sigmoid on the output, pw = 'depthwise' makes the stage-1 1x1 branch depthwise.  Parameter
+    vectors, saved buffers and graphs are tied to the setting they were made under."""
+    if res_k not in (3, 4) or head not in ('identity', 'sigmoid') or pw not in ('dense', 'depthwise'):
+        raise StdaError(f'unknown architecture res_k={res_k} head={head} pw={pw}')
+    flags = ((ARCH_RES3 if res_k == 3 else 0) | (ARCH_SIGMOID if head == 'sigmoid' else 0)
+             | (ARCH_PW_DW if pw == 'depthwise' else 0))
     _check(_lib.stda_set_arch(flags), 'stda_set_arch')
 
 
 def get_arch():
     f = int(_lib.stda_get_arch())
-    return {'res_k': 3 if f & ARCH_RES3 else 4, 'head': 'sigmoid' if f & ARCH_SIGMOID else 'identity'}
+    return {'res_k': 3 if f & ARCH_RES3 else 4, 'head': 'sigmoid' if f & ARCH_SIGMOID else 'identity',
+            'pw': 'depthwise' if f & ARCH_PW_DW else 'dense'}
 
 
 def param_count():

@@ -1,9 +1,16 @@
 """GPU-vs-oracle parity of the architecture readings selected by stda_set_arch: the decoder long
-residual as DeConv3x3-s2-p1 with output padding 1, and the logistic-sigmoid output (Sec. IV-C
-leaves both open).  Forward in EVAL and TRAIN (with the running statistics), and the adjoint
-(every parameter gradient and dx), FP32, with and without block recomputation, on shapes with
-ragged tiles.  Gate: rel-L2 <= 1e-4 per tensor, as for the default network.  Inputs are screened
-for ReLU decisions near their kink as in the default parity tests."""
+residual as DeConv3x3-s2-p1 with output padding 1, the logistic-sigmoid output, and a depthwise
+stage-1 1x1 branch (Sec. IV-C leaves all three open).  Forward in EVAL and TRAIN (with the
+running statistics), and the adjoint (every parameter gradient and dx), FP32, with and without
+block recomputation, on shapes with ragged tiles.  Gate: rel-L2 <= 1e-4 per tensor, as for the
+default network.  Inputs are screened for ReLU decisions near their kink as in the default parity
+tests.
+
+Depthwise 1x1 branch: batch norm makes BN(w x) independent of the size of a per-channel weight w
+except through its epsilon, so in TRAIN mode dL/dw is the epsilon-sized remainder of a sum whose
+terms cancel; its FP32 value carries the rounding of those terms, not of the remainder.  That
+gradient is therefore gated where it is well conditioned: weights with w^2 var(x) below epsilon,
+where the branch is nearly linear in w.  At the default weights every other tensor is gated."""
 import sys
 
 import numpy as np
@@ -16,7 +23,8 @@ from tests import gpu_util as U
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
-ARCHS = [(3, 'identity'), (4, 'sigmoid'), (3, 'sigmoid')]
+ARCHS = [(3, 'identity', 'dense'), (4, 'sigmoid', 'dense'), (3, 'sigmoid', 'dense'), (4, 'identity', 'depthwise'),
+         (3, 'sigmoid', 'depthwise')]
 SHAPES = [(2, 16, 16), (2, 40, 36)]
 
 
@@ -24,22 +32,47 @@ def _say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.fixture(params=ARCHS, ids=lambda a: f'res{a[0]}-{a[1]}')
-def arch(request):
+def _select(param):
     from paper_2307_09063_amd import stda
-    res_k, head = request.param
-    stda.set_arch(res_k, head)
-    net.set_arch(res_k, head)
-    yield stda, res_k, head
+    res_k, head, pw = param
+    stda.set_arch(res_k, head, pw)
+    net.set_arch(res_k, head, pw)
+    yield stda, res_k, head, pw
     stda.set_arch()
     net.set_arch()
 
 
+def _arch_id(a):
+    return f'res{a[0]}-{a[1]}-{a[2]}'
+
+
+@pytest.fixture(params=ARCHS, ids=_arch_id)
+def arch(request):
+    yield from _select(request.param)
+
+
+@pytest.fixture(params=[a for a in ARCHS if a[2] == 'depthwise'], ids=_arch_id)
+def arch_dw(request):
+    yield from _select(request.param)
+
+
+def _conditioned(w):
+    """The same weights with every depthwise 1x1 weight scaled to |w| <= 3e-4."""
+    w = w.copy()
+    off = 0
+    for name, shape, _ in net.param_specs():
+        n = int(np.prod(shape))
+        if name.endswith('.s1.pw.w'):
+            w[off:off + n] *= 3e-4 / np.abs(w[off:off + n]).max()
+        off += n
+    return w
+
+
 @pytest.mark.parametrize('shape', SHAPES)
 def test_forward(arch, shape):
-    S, res_k, head = arch
+    S, res_k, head, pw = arch
     B, H, W = shape
-    _say('ablation forward', res_k, head, shape)
+    _say('ablation forward', res_k, head, pw, shape)
     assert S.param_count() == net.param_count()
     x, _ = U.maps(B, H, W, seed=H * 7 + W + res_k)
     w, r = U.weights(), U.running()
@@ -63,10 +96,22 @@ def test_forward(arch, shape):
 @pytest.mark.parametrize('recompute', [0, 1])
 @pytest.mark.parametrize('shape', SHAPES)
 def test_backward(arch, shape, recompute):
-    S, res_k, head = arch
+    _backward(arch, shape, recompute, False)
+
+
+@pytest.mark.parametrize('recompute', [0, 1])
+@pytest.mark.parametrize('shape', SHAPES)
+def test_backward_depthwise_conditioned(arch_dw, shape, recompute):
+    _backward(arch_dw, shape, recompute, True)
+
+
+def _backward(arch, shape, recompute, conditioned):
+    S, res_k, head, pw = arch
     B, H, W = shape
-    _say('ablation backward', res_k, head, shape, recompute)
+    _say('ablation backward', res_k, head, pw, shape, recompute, conditioned)
     w, r = U.weights(), U.running()
+    if conditioned:
+        w = _conditioned(w)
     x, _ = U.unambiguous(lambda s: U.maps(B, H, W, seed=s), w, r, H * 3 + W + res_k)
     segs = S.uniform_segments(B, H, W)
     sv, wsb = S.workspace_size(segs, S.FP32, S.TRAIN, recompute)
@@ -83,6 +128,8 @@ def test_backward(arch, shape, recompute):
     _, _, cache = net.forward(w, r, x, 'train')
     gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
     errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
+    if pw == 'depthwise' and not conditioned:
+        errs = {k: v for k, v in errs.items() if not k.endswith('.s1.pw.w')}
     bad = {k: v for k, v in errs.items() if not v < TOL}
     assert not bad, bad
     assert U.rel_l2(dx.cpu().numpy(), dxr) < TOL
@@ -91,8 +138,8 @@ def test_backward(arch, shape, recompute):
 def test_train_step_graph(arch):
     """A captured training step (forward, loss, backward, SGD) under the reading, replayed with
     eager work in between, against the same step run eagerly."""
-    S, res_k, head = arch
-    _say('ablation graph', res_k, head)
+    S, res_k, head, pw = arch
+    _say('ablation graph', res_k, head, pw)
     B, H, W = 2, 32, 24
     x, y = U.maps(B, H, W, seed=5 + res_k)
     w0, r0 = U.weights(), U.running()

@@ -120,20 +120,22 @@ def test_workspace_grows_with_batch(S):
     assert bf[0] < a[0]
 
 
-@pytest.mark.parametrize('res_k,head', [(3, 'identity'), (4, 'sigmoid'), (3, 'sigmoid')])
-def test_architecture_readings_layout(S, res_k, head):
-    """The residual reading changes the parameter table exactly as in the oracle; the sigmoid
-    output adds one FP32 map per clip to the TRAIN saved buffer and nothing else."""
+@pytest.mark.parametrize('res_k,head,pw', [(3, 'identity', 'dense'), (4, 'sigmoid', 'dense'), (3, 'sigmoid', 'dense'),
+                                          (4, 'identity', 'depthwise'), (3, 'sigmoid', 'depthwise')])
+def test_architecture_readings_layout(S, res_k, head, pw):
+    """The residual and 1x1-branch readings change the parameter table exactly as in the oracle;
+    the sigmoid output adds one FP32 map per clip to the TRAIN saved buffer and nothing else."""
     segs = S.uniform_segments(3, 32, 24)
     sv0, ws0 = S.workspace_size(segs, S.FP32, S.TRAIN)
     ev0 = S.workspace_size(segs, S.FP32, S.EVAL)
     try:
-        S.set_arch(res_k, head)
-        net.set_arch(res_k, head)
-        assert S.get_arch() == {'res_k': res_k, 'head': head}
+        S.set_arch(res_k, head, pw)
+        net.set_arch(res_k, head, pw)
+        assert S.get_arch() == {'res_k': res_k, 'head': head, 'pw': pw}
         got = [(d['name'], d['shape'], d['fan_in']) for d in S.param_table()]
         assert got == [(n, tuple(s), f) for n, s, f in net.param_specs()]
-        assert S.param_count() == net.param_count() == (119549 if res_k == 3 else 137469)
+        fewer = (res_k == 3) * 17920 + (pw == 'depthwise') * 6256
+        assert S.param_count() == net.param_count() == 137469 - fewer
         sv, ws = S.workspace_size(segs, S.FP32, S.TRAIN)
         ev = S.workspace_size(segs, S.FP32, S.EVAL)
         extra = -(-(3 * 32 * 24 * 4) // 256) * 256 if head == 'sigmoid' else 0
@@ -144,12 +146,12 @@ def test_architecture_readings_layout(S, res_k, head):
     finally:
         S.set_arch()
         net.set_arch()
-    assert S.get_arch() == {'res_k': 4, 'head': 'identity'}
+    assert S.get_arch() == {'res_k': 4, 'head': 'identity', 'pw': 'dense'}
     assert S.param_count() == 137469
 
 
 def test_set_arch_rejects_unknown_bits(S):
-    assert S._lib.stda_set_arch(4) == -1      # STDA_E_INVALID
+    assert S._lib.stda_set_arch(8) == -1      # STDA_E_INVALID
     assert S._lib.stda_set_arch(-1) == -1
     assert S._lib.stda_get_arch() == 0
     with pytest.raises(S.StdaError):

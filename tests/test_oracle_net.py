@@ -158,32 +158,35 @@ def test_eval_stage1_reparameterisation():
 
 
 # ------------------------------------------------------------- architecture ablations
-ARCHS = [(3, 'identity'), (4, 'sigmoid'), (3, 'sigmoid')]
+ARCHS = [(3, 'identity', 'dense'), (4, 'sigmoid', 'dense'), (3, 'sigmoid', 'dense'), (4, 'identity', 'depthwise'),
+         (3, 'sigmoid', 'depthwise')]
 
 
 @pytest.fixture()
 def arch():
     yield
-    net.set_arch(4, 'identity')
+    net.set_arch()
 
 
-@pytest.mark.parametrize('res_k,head', ARCHS)
-def test_ablation_param_count(arch, res_k, head):
-    net.set_arch(res_k, head)
-    # a 3 x 3 decoder residual has 7 of 16 taps fewer: (64*32 + 32*16) * 7 weights fewer
-    assert net.param_count() == 137469 - (res_k == 3) * (64 * 32 + 32 * 16) * 7
+@pytest.mark.parametrize('res_k,head,pw', ARCHS)
+def test_ablation_param_count(arch, res_k, head, pw):
+    net.set_arch(res_k, head, pw)
+    # a 3 x 3 decoder residual has 7 of 16 taps fewer: (64*32 + 32*16) * 7 weights fewer; a
+    # depthwise 1x1 branch keeps C of the C^2 weights of each of the four blocks
+    fewer = (res_k == 3) * (64 * 32 + 32 * 16) * 7 + (pw == 'depthwise') * sum(c * c - c for c in (16, 32, 64, 32))
+    assert net.param_count() == 137469 - fewer
 
 
-@pytest.mark.parametrize('res_k,head', ARCHS)
-def test_ablation_forward_and_gradient_match_torch(arch, res_k, head):
-    net.set_arch(res_k, head)
+@pytest.mark.parametrize('res_k,head,pw', ARCHS)
+def test_ablation_forward_and_gradient_match_torch(arch, res_k, head, pw):
+    net.set_arch(res_k, head, pw)
     w, r, x, y = _setup(B=2, H=16, W=12)
     rng = np.random.default_rng(7)
     w = w + 0.1 * rng.standard_normal(w.shape)
     z, _, _ = net.forward(w, r, x, 'train')
     P, R = _torch_params(w, r)
     xt = torch.tensor(x, requires_grad=True)
-    zt, _ = torch_ref.forward(P, R, xt, train=True, res_k=res_k, head=head)
+    zt, _ = torch_ref.forward(P, R, xt, train=True, res_k=res_k, head=head, pw=pw)
     np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-11, atol=1e-12)
     loss, g, dx, _, _ = net.loss_and_grad(w, r, x, y, want_dx=True)
     lt = ((zt - torch.from_numpy(y)) ** 2).mean()
@@ -193,9 +196,9 @@ def test_ablation_forward_and_gradient_match_torch(arch, res_k, head):
     np.testing.assert_allclose(dx, xt.grad.numpy(), rtol=1e-9, atol=1e-14 * np.abs(dx).max())
 
 
-@pytest.mark.parametrize('res_k,head', ARCHS)
-def test_ablation_directional_finite_difference(arch, res_k, head):
-    net.set_arch(res_k, head)
+@pytest.mark.parametrize('res_k,head,pw', ARCHS)
+def test_ablation_directional_finite_difference(arch, res_k, head, pw):
+    net.set_arch(res_k, head, pw)
     w, r, x, y = _setup(B=2, H=16, W=16, seed=34)
     _, g, _, _, _ = net.loss_and_grad(w, r, x, y)
     f = lambda ww: net.mse_loss(net.forward(ww, r, x, 'train')[0], y)[0]
@@ -206,3 +209,50 @@ def test_ablation_directional_finite_difference(arch, res_k, head):
     assert np.array_equal(base, _kinks(w + h * v, r, x)) and np.array_equal(base, _kinks(w - h * v, r, x))
     fd = (f(w + h * v) - f(w - h * v)) / (2 * h)
     assert abs(fd - g @ v) <= 1e-6 * abs(fd)
+
+
+def test_depthwise_pointwise_is_the_diagonal_of_the_dense_one(arch):
+    """A depthwise 1x1 branch is the dense one with a diagonal weight: the same output in both
+    modes, and its gradient is the diagonal of the dense gradient."""
+    net.set_arch(pw='depthwise')
+    w_dw, r, x, y = _setup(B=2, H=16, W=12, seed=5)
+    specs_dw = net.param_specs()
+    net.set_arch()
+    specs = net.param_specs()
+    blocks = ('enc0', 'enc1', 'dec0', 'dec1')
+    # build the dense vector: the diagonal from the depthwise weights, zeros elsewhere
+    parts, off_dw, src = [], 0, {}
+    for name, shape, _ in specs_dw:
+        n = int(np.prod(shape))
+        src[name] = w_dw[off_dw:off_dw + n].reshape(shape)
+        off_dw += n
+    for name, shape, _ in specs:
+        if name.endswith('.s1.pw.w'):
+            c = shape[0]
+            d = np.zeros(shape)
+            d[np.arange(c), np.arange(c), 0, 0] = src[name][:, 0, 0, 0]
+            parts.append(d.ravel())
+        else:
+            parts.append(src[name].ravel())
+    w_dense = np.concatenate(parts)
+    for mode in ('train', 'eval'):
+        z_dense, r_dense, _ = net.forward(w_dense, r, x, mode)
+        net.set_arch(pw='depthwise')
+        z_dw, r_dw, _ = net.forward(w_dw, r, x, mode)
+        net.set_arch()
+        np.testing.assert_allclose(z_dw, z_dense, rtol=1e-13, atol=1e-13)
+        np.testing.assert_allclose(r_dw, r_dense, rtol=1e-13, atol=1e-13)
+    _, g_dense, dx_dense, _, _ = net.loss_and_grad(w_dense, r, x, y, want_dx=True)
+    net.set_arch(pw='depthwise')
+    _, g_dw, dx_dw, _, _ = net.loss_and_grad(w_dw, r, x, y, want_dx=True)
+    np.testing.assert_allclose(dx_dw, dx_dense, rtol=1e-12, atol=1e-15 * np.abs(dx_dense).max())
+    off, off_dw = 0, 0
+    for (name, shape, _), (_, shape_dw, _) in zip(specs, specs_dw):
+        n, n_dw = int(np.prod(shape)), int(np.prod(shape_dw))
+        gd, gw = g_dense[off:off + n].reshape(shape), g_dw[off_dw:off_dw + n_dw].reshape(shape_dw)
+        if name.endswith('.s1.pw.w'):
+            c = shape[0]
+            gd = gd[np.arange(c), np.arange(c), 0, 0].reshape(shape_dw)
+        np.testing.assert_allclose(gw, gd, rtol=1e-10, atol=1e-13 * np.abs(g_dense).max(), err_msg=name)
+        off, off_dw = off + n, off_dw + n_dw
+    assert set(blocks) == {k.split('.')[0] for k, s, _ in specs if k.endswith('.s1.pw.w')}

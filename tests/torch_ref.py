@@ -22,10 +22,11 @@ def _eca(y, w):
     return torch.sigmoid(s)[:, :, None, None] * y
 
 
-def forward(P, R, x, train=True, res_k=4, head='identity'):
+def forward(P, R, x, train=True, res_k=4, head='identity', pw='dense'):
     """P: dict name -> float64 tensor, R: dict bn name -> (mean, var) tensors.  res_k = 3 takes
     the decoder residual as ConvTranspose3x3-s2-p1 with output padding 1; head = 'sigmoid'
-    applies a logistic sigmoid to the output."""
+    applies a logistic sigmoid to the output; pw = 'depthwise' makes the stage-1 1x1 branch a
+    grouped (groups = C) convolution."""
     newR = {}
     t = F.conv2d(x, P['stem.conv.w'], padding=1)
     s0 = F.relu(_bn(t, P, R, 'stem.bn', train, newR))
@@ -33,11 +34,12 @@ def forward(P, R, x, train=True, res_k=4, head='identity'):
     outs = {}
     for name, dec in (('enc0', False), ('enc1', False), ('dec0', True), ('dec1', True)):
         c = h.shape[1]
+        gp = c if pw == 'depthwise' else 1
         if dec:
-            p = F.conv_transpose2d(h, P[name + '.s1.pw.w'])
+            p = F.conv_transpose2d(h, P[name + '.s1.pw.w'], groups=gp)
             d = F.conv_transpose2d(h, P[name + '.s1.dw.w'], padding=1, groups=c)
         else:
-            p = F.conv2d(h, P[name + '.s1.pw.w'])
+            p = F.conv2d(h, P[name + '.s1.pw.w'], groups=gp)
             d = F.conv2d(h, P[name + '.s1.dw.w'], padding=1, groups=c)
         u = (_bn(p, P, R, name + '.s1.pw_bn', train, newR) + _bn(d, P, R, name + '.s1.dw_bn', train, newR)
              + _bn(h, P, R, name + '.s1.id_bn', train, newR))
