@@ -200,7 +200,7 @@ class Trainer:
         res = self.stda.autotune(self.segs, self.x, self.y, self.w, scratch, self.z, self.loss, self.dz, self.dw,
                                  self.saved, self.ws, self.dtype, self.recompute, reps)
         self.torch.cuda.synchronize()
-        names = {0: 'fwd', 1: 'dgrad', 2: 'wgrad'}
+        names = {0: 'fwd', 1: 'dgrad', 2: 'wgrad', 3: 's1_bwd'}
         return {f'{names[k]}.{("enc0", "enc1", "dec0", "dec1")[b]}': v[0] for (k, b), v in sorted(res.items())}
 
     def capture(self):

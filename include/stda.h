@@ -256,11 +256,12 @@ int stda_profile_read(double* total_ms /*host out*/, int* count /*host out*/);
 int stda_profile_report(char* buf /*host out*/, size_t cap, size_t* needed /*host out*/);
 
 /* ------------------------------------------------------------------ tile-shape autotuning
- * The stage-2 dense layers (Conv3x3-s2 / DeConv4x4-s2 and their input gradients) have several
- * tilings each.  A tunable launch is (kind, dtype, block): kind 0 = stage-2 forward (main and
- * residual convolution), 1 = stage-2 input gradient (both); block 0..3 = encoder 0, encoder 1,
- * decoder 0, decoder 1.  The choice is process-wide and read when a launch is enqueued (a
- * captured graph keeps the choice it was captured with).
+ * The stage-2 dense layers (Conv3x3-s2 / DeConv4x4-s2, their input and weight gradients) and the
+ * fused stage-1 adjoint have several tilings each.  A tunable launch is (kind, dtype, block):
+ * kind 0 = stage-2 forward (main and residual convolution), 1 = stage-2 input gradient (both),
+ * 2 = stage-2 weight gradient (both), 3 = stage-1 adjoint (tile shape and registers per thread);
+ * block 0..3 = encoder 0, encoder 1, decoder 0, decoder 1.  The choice is process-wide and read
+ * when a launch is enqueued (a captured graph keeps the choice it was captured with).
  */
 int stda_tune_count(int kind);  /* number of variants of `kind`, or a negative status */
 int stda_tune_set(int kind, int dtype, int block, int variant);

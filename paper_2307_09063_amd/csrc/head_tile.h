@@ -20,8 +20,8 @@ template <class T, bool SIG>
 __global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, const float* __restrict__ w,
                                                        const float* __restrict__ bias, float* __restrict__ z,
                                                        float* __restrict__ zs, int B, int H, int W) {
-  constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, PS = C + 4;
-  __shared__ float xt[(TH + 2) * RW * PS];
+  constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, XN = (TH + 2) * RW;
+  __shared__ float xt[S1Lds<C, XN>::SIZE];
   __shared__ float wt[9 * C];  // [tap][c]
   for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) wt[q] = w[(q % C) * 9 + q / C];
   const float b0 = bias[0];
@@ -38,10 +38,10 @@ __global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, 
       float acc = b0;
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
-        const float* px = xt + ((r + t / 3) * RW + cc + t % 3) * PS;
+        const int px = (r + t / 3) * RW + cc + t % 3;
 #pragma unroll
         for (int c = 0; c < C; c += 4) {
-          const float4 v = *reinterpret_cast<const float4*>(px + c);
+          const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(px, c >> 2));
           acc += wt[t * C + c] * v.x + wt[t * C + c + 1] * v.y + wt[t * C + c + 2] * v.z + wt[t * C + c + 3] * v.w;
         }
       }

@@ -451,12 +451,13 @@ int tiles_for(int64_t hw, int G) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
 }
 
-// Tiling variant of each dense stage-2 launch, [dtype][0 forward, 1 input gradient, 2 weight
-// gradient][block]: 0..2 the LDS-tiled kernels with the tilings listed in launch_s2_variant and
-// launch_wgrad, 3 the register-gather kernels.  Set by stda_tune_set (the autotuner); 0 by
+// Tiling variant of each tunable launch, [dtype][kind][block]: kinds 0 forward, 1 input gradient,
+// 2 weight gradient of the dense stage-2 layers (0..2 the LDS-tiled kernels with the tilings
+// listed in launch_s2_variant and launch_wgrad, 3 the register-gather kernels), 3 the fused
+// stage-1 adjoint (tilings listed in launch_s1b).  Set by stda_tune_set (the autotuner); 0 by
 // default.
 constexpr int kS2Variants = 4;
-constexpr int kTuneKinds = 3;
+constexpr int kTuneKinds = 4;
 int g_s2_variant[2][kTuneKinds][4] = {};
 
 template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
@@ -910,6 +911,32 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
 #undef WGVV
 }
 
+// Fused stage-1 adjoint of block `blk` with the tiling chosen for it (tuning kind 3): TH x TW
+// pixel tiles, MINW waves per SIMD; *rows = workgroups = rows of weight-gradient partials.
+template <class T, int C, bool DEC, int TH, int TW, int MINW>
+int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, const T* dXr, const T* skipg,
+                   const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
+  const int64_t tiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  const int g = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+  const float* coef = c.template scr<float>(c.P->ws_coef);
+  KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW><<<g, 256, 0, c.st>>>(
+                                         X, X1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
+  *rows = g;
+  return STDA_OK;
+}
+
+template <class T, int C, bool DEC>
+int launch_s1b(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, const T* dXr, const T* skipg,
+               const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
+  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
+#define S1B(TH_, TW_, W_) \
+  launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, X1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
+  if constexpr (C == 16) return v == 1 ? S1B(8, 8, 3) : v == 2 ? S1B(4, 16, 3) : v == 3 ? S1B(8, 8, 2) : S1B(8, 16, 2);
+  else if constexpr (C == 32) return v == 1 ? S1B(4, 8, 3) : v == 2 ? S1B(8, 4, 3) : v == 3 ? S1B(4, 8, 2) : S1B(8, 8, 2);
+  else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1B(8, 2, 2) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
+#undef S1B
+}
+
 template <class T>
 int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg, float* const* db, int acc) {
   float* part = c.template scr<float>(c.P->ws_part);
@@ -1008,23 +1035,16 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
     float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
     if (int r = bn_bwd(c, g1, 4, CIN, (double)Pin, dg, db, acc)) return r;
   }
+  // the encoder blocks receive a skip gradient (from the decoder), the decoder blocks none
+  if ((skipg != nullptr) != !DEC) return STDA_E_INVALID;
   float* pwpart = c.template scr<float>(c.P->ws_wpart);
-  {
-    ProfScope ps_(tagk("s1_bwd_fused", k), c.st);
-    if (skipg)
-      k_s1_bwd_fused<T, CIN, DEC, true><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, skipg,
-                                                              c.template scr<float>(c.P->ws_coef), sp, dXout, pwpart,
-                                                              part, n, hin, win);
-    else
-      k_s1_bwd_fused<T, CIN, DEC, false><<<g1, 256, 0, c.st>>>(X, X1, dX1, dXr, nullptr,
-                                                               c.template scr<float>(c.P->ws_coef), sp, dXout, pwpart,
-                                                               part, n, hin, win);
-  }
-  LAUNCH_CHECK();
+  int rows = 0;
+  if (int r = launch_s1b<T, CIN, DEC>(c, k, X, X1, dX1, dXr, skipg, sp, dXout, pwpart, part, n, hin, win, &rows))
+    return r;
   const ColMap pwmap = (c.P->arch & STDA_ARCH_PW_DW) ? ColMap{MAP_PW_DIAG, CIN, 0}
                                                       : ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0};
-  if (int r = colsum_to(c, pwpart, g1, CIN * CIN, dw + bo.pw_w, pwmap, acc)) return r;
-  return colsum_to(c, part, g1, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc);
+  if (int r = colsum_to(c, pwpart, rows, CIN * CIN, dw + bo.pw_w, pwmap, acc, tagk("s1_bwd_fused_sum", k))) return r;
+  return colsum_to(c, part, rows, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc, tagk("s1_bwd_fused_sum", k));
 }
 
 template <class T>
@@ -1341,6 +1361,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
       const int kind = t.rfind("dense_fwd_", 0) == 0     ? 0
                        : t.rfind("dense_dgrad_", 0) == 0 ? 1
                        : t.rfind("wgrad_", 0) == 0       ? 2
+                       : t.rfind("s1_bwd_fused", 0) == 0 ? 3
                                                          : -1;
       if (kind < 0) continue;
       for (int b = 0; b < 4; ++b)

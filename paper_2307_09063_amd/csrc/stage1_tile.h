@@ -6,7 +6,7 @@
 // LDS with coalesced 16-byte loads (zeros outside the map) and computes every pixel of the tile
 // from LDS; the grid loops over the tiles of all clips.  Thread mapping inside a tile: item =
 // (pixel, group of 4 channels), channel group fastest, so a thread keeps one channel group for
-// its whole life.  LDS tiles are [pixel][C] floats laid out by S1Lds (see there) so that both
+// its whole life.  LDS tiles are [pixel][C] floats laid out by S1Lds (see there) so that the
 // access patterns avoid bank conflicts: one thread per (pixel, chunk) reading float4s, and
 // matrix-core operands reading one channel of 16 consecutive pixels.
 #pragma once
@@ -34,24 +34,30 @@ struct S1Geo {
   static constexpr int TH = S1Tile<C>::TH, TW = S1Tile<C>::TW, G = C / 4;
 };
 
-// LDS layout of a [pixel][C] tile.  64 channels: rows of C floats whose 16-byte chunk q sits in
-// slot q ^ (px & 15), so that 16 consecutive pixels cover all 64 banks in both access patterns.
-// 16 and 32 channels: rows padded to C + 4 floats (linear addresses, which the compiler folds
-// into instruction offsets; the swizzle measured slower there).
-template <int C>
+// LDS layout of an NPIX-pixel [pixel][C] tile.  64 channels: rows of C floats whose 16-byte chunk
+// q sits in slot q ^ (px & 15), so that 16 consecutive pixels cover all 64 banks in both access
+// patterns.  16 and 32 channels: planar by 16-byte chunk, plane q holding chunk q of every pixel
+// (px * 4 floats into the plane), planes PL floats apart with PL = 16 (16 channels) or 8 (32
+// channels) modulo the 64 banks.  Then the quarter-wave of a 16-byte access (4 or 2 consecutive
+// pixels x all chunks), a matrix-core operand (one channel of 16 consecutive pixels) and a
+// weight-gradient operand (16 channels of 4 pixels) each touch distinct banks, and a tap's
+// offset stays a constant the compiler folds into the instruction.
+template <int C, int NPIX>
 struct S1Lds {
   static constexpr bool SWZ = C == 64;
-  static constexpr int PITCH = SWZ ? C : C + 4;
+  static constexpr int TGT = C == 16 ? 16 : 8;
+  static constexpr int PL = NPIX * 4 + (TGT - (NPIX * 4) % 64 + 64) % 64;
+  static constexpr int SIZE = SWZ ? NPIX * C : (C / 4) * PL;
 };
 // Float offset of chunk q (channels 4q .. 4q + 3) of LDS pixel px, and of channel c.
-template <int C>
+template <int C, int NPIX>
 __device__ __forceinline__ int s1c(int px, int q) {
-  if constexpr (S1Lds<C>::SWZ) return px * C + ((q ^ (px & (C / 4 - 1))) << 2);
-  else return px * S1Lds<C>::PITCH + (q << 2);
+  if constexpr (S1Lds<C, NPIX>::SWZ) return px * C + ((q ^ (px & (C / 4 - 1))) << 2);
+  else return q * S1Lds<C, NPIX>::PL + (px << 2);
 }
-template <int C>
+template <int C, int NPIX>
 __device__ __forceinline__ int s1e(int px, int c) {
-  return s1c<C>(px, c >> 2) + (c & 3);
+  return s1c<C, NPIX>(px, c >> 2) + (c & 3);
 }
 
 // Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds, pixel
@@ -67,7 +73,7 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0
       ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v);
     else
       zero4(v);
-    *reinterpret_cast<float4*>(lds + s1c<C>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
+    *reinterpret_cast<float4*>(lds + s1c<C, RH * RW>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -114,12 +120,12 @@ __device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
 }
 
 // Depthwise branch (4 channels) of the pixel at padded LDS position (r, c).
-template <int C>
+template <int C, int NPIX>
 __device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float* wd, float dv[4]) {
   zero4(dv);
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
+    const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C, NPIX>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
     const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
     dv[0] += wq.x * v.x;
     dv[1] += wq.y * v.y;
@@ -135,8 +141,9 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
                                                  S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
-  __shared__ float xt[(TH + 2) * RW * S1Lds<C>::PITCH];
-  __shared__ float pt[TH * TW * S1Lds<C>::PITCH];  // pointwise branch of the tile (matrix cores)
+  constexpr int XN = (TH + 2) * RW, PN = TH * TW;  // pixels of the x tile (halo 1) and of the tile
+  __shared__ float xt[S1Lds<C, XN>::SIZE];
+  __shared__ float pt[S1Lds<C, PN>::SIZE];  // pointwise branch of the tile (matrix cores)
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
   __shared__ float sm[MODE == 0 ? 4 * 6 * C : 1];
@@ -158,26 +165,26 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
     load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
     __syncthreads();
     // pt[p][o] = sum_c x[p][c] wp[c][o]; tile pixel p = r*TW + cc sits at padded (r + 1, cc + 1)
-    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C>((p / TW + 1) * RW + p % TW + 1, k)]; },
+    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
-                              [&](int p, int n, float v) { pt[s1e<C>(p, n)] = v; });
+                              [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
     __syncthreads();
     for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
       if (y >= h || x >= w) continue;
       float pv[4], dv[4], xv[4];
-      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C>(px, c0 >> 2));
+      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C, PN>(px, c0 >> 2));
       pv[0] = pq.x;
       pv[1] = pq.y;
       pv[2] = pq.z;
       pv[3] = pq.w;
-      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 1) * RW + cc + 1, c0 >> 2));
+      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 1) * RW + cc + 1, c0 >> 2));
       xv[0] = xq.x;
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wd, dv);
       if (MODE == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -214,8 +221,9 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
                                                            S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
-  __shared__ float xt[(TH + 2) * RW * S1Lds<C>::PITCH];
-  __shared__ float pt[TH * TW * S1Lds<C>::PITCH];
+  constexpr int XN = (TH + 2) * RW, PN = TH * TW;
+  __shared__ float xt[S1Lds<C, XN>::SIZE];
+  __shared__ float pt[S1Lds<C, PN>::SIZE];
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
   __shared__ float sm[4 * 4 * C];
@@ -240,26 +248,26 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     __syncthreads();
     load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
     __syncthreads();
-    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C>((p / TW + 1) * RW + p % TW + 1, k)]; },
+    lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
-                              [&](int p, int n, float v) { pt[s1e<C>(p, n)] = v; });
+                              [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
     __syncthreads();
     for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
       if (y >= h || x >= w) continue;
       float pv[4], dv[4], xv[4], x1[4], g[4];
-      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C>(px, c0 >> 2));
+      const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C, PN>(px, c0 >> 2));
       pv[0] = pq.x;
       pv[1] = pq.y;
       pv[2] = pq.z;
       pv[3] = pq.w;
-      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 1) * RW + cc + 1, c0 >> 2));
+      const float4 xq = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 1) * RW + cc + 1, c0 >> 2));
       xv[0] = xq.x;
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wd, dv);
       const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
       ld4(X1 + off, x1);
       ld4(dX1 + off, g);
@@ -283,45 +291,54 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 //   dX = g_x is_x (du - k0 - xhat k3) + dXr + PW^T(dP) + DW^T(dD) (+ skip gradient),
 // plus the pointwise weight gradient sum_p x[c](p) dP[o](p) -> pwpart[blk][c][o] and the
 // depthwise one sum_p x[c](p + off_t) dD[c](p) -> dwpart[blk][tap][c] (the weight's own tap
-// index, flipped in the decoder).  Per tile: x on a 2-pixel halo, dD on a 1-pixel halo and dP in
-// LDS (never in HBM); the three pointwise products (p = x Wp, dP Wp^T, x^T dP) run on the matrix
-// cores, the last one accumulating in registers across tiles.
-template <class T, int C, bool DEC, bool SKIP>
-__global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
-                                                      const T* __restrict__ dX1, const T* __restrict__ dXr,
-                                                      const T* __restrict__ skip, const float* __restrict__ coef,
-                                                      S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
-                                                      float* __restrict__ dwpart, int B, int h, int w) {
-  typedef S1Geo<C> Gm;
-  constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, M = TH * TW;
+// index, flipped in the decoder).  Per tile: x on a 2-pixel halo, dD on a 1-pixel halo, dP and du
+// in LDS (never in HBM; du is formed once, with dD, and read back for dX); the three pointwise
+// products (p = x Wp, dP Wp^T, x^T dP) run on the matrix cores, the last one accumulating in
+// registers across tiles.  Tiles are TH x TW pixels; MINW waves per SIMD bound the registers.
+template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
+                                                         const T* __restrict__ dX1, const T* __restrict__ dXr,
+                                                         const T* __restrict__ skip, const float* __restrict__ coef,
+                                                         S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
+                                                         float* __restrict__ dwpart, int B, int h, int w) {
+  constexpr int G = C / 4, M = TH * TW;
+  static_assert(M % 16 == 0, "matrix-core row tiles of 16 pixels");
   constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
   constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
-  constexpr int XT = (TH + 4) * XW * S1Lds<C>::PITCH;
+  constexpr int XN = (TH + 4) * XW, DN = (TH + 2) * DWd;  // pixels of the x and dD tiles
+  constexpr int XT = S1Lds<C, XN>::SIZE;
   static_assert(XT >= 4 * 9 * C + 9 * C, "reduction scratch aliases the x tile");
   __shared__ float xt[XT];
-  __shared__ float ddt[(TH + 2) * DWd * S1Lds<C>::PITCH];
-  __shared__ float dpt[M * S1Lds<C>::PITCH];
-  __shared__ float qt[M * S1Lds<C>::PITCH];
+  __shared__ float ddt[S1Lds<C, DN>::SIZE];
+  __shared__ float dpt[S1Lds<C, M>::SIZE];
+  __shared__ float dut[S1Lds<C, M>::SIZE];
+  __shared__ float qt[S1Lds<C, M>::SIZE];
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
+  // the three BN adjoints as affine maps of (du, branch value): cf[3 s + 0/1/2][c] = a, b, e with
+  // grad = a du + b v + e, for s = 0 pointwise (v = p), 1 depthwise (v = d), 2 identity (v = x)
+  __shared__ float cf[9 * C];
   float* sm = xt;  // used only after the tile loop
   float* red = xt + 4 * 9 * C;
-  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
+  if (threadIdx.x < 3 * C) {
+    const int s = threadIdx.x / C, c = threadIdx.x % C;
+    const float mu = prm.stats[s][c], is = prm.stats[s][C + c], ga = prm.gamma[s][c];
+    const float k0 = coef[c], ks = coef[(s + 1) * C + c];
+    const float a = ga * is;
+    cf[(3 * s) * C + c] = a;
+    cf[(3 * s + 1) * C + c] = -a * is * ks;
+    cf[(3 * s + 2) * C + c] = a * (is * ks * mu - k0);
+  }
+  stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);  // ends with a barrier
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
   const int c0 = (threadIdx.x % G) * 4;
-  float mu[3][4], is[3][4], ga[3][4], k[4][4];
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      mu[q][j] = prm.stats[q][c0 + j];
-      is[q][j] = prm.stats[q][C + c0 + j];
-      ga[q][j] = prm.gamma[q][c0 + j];
-    }
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) k[q][j] = coef[q * C + c0 + j];
+  auto cfv = [&](int q, float v[4]) {
+    const float4 t = *reinterpret_cast<const float4*>(cf + q * C + c0);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+    v[3] = t.w;
+  };
   float dwacc[9][4];
 #pragma unroll
   for (int t = 0; t < 9; ++t) zero4(dwacc[t]);
@@ -338,48 +355,59 @@ __global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X
     load_tile<T, C, TH, TW, 2>(X, b, y0, x0, h, w, xt);
     __syncthreads();
     // A1: pointwise branch of the tile, qt = x Wp
-    lds_gemm_s<M, C, C>([&](int p, int kk) { return xt[s1e<C>(xpx(p), kk)]; },
+    lds_gemm_s<M, C, C>([&](int p, int kk) { return xt[s1e<C, XN>(xpx(p), kk)]; },
                         [&](int kk, int n) { return wp[kk * C + n]; },
-                        [&](int p, int n, float v) { qt[s1e<C>(p, n)] = v; });
+                        [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     __syncthreads();
     // A2: dD on the tile + halo 1, dP on the tile (zero off the map)
     for (int e = threadIdx.x; e < (TH + 2) * DWd * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / DWd, cc = px % DWd;  // position in the dD tile
       const int y = y0 - 1 + r, x = x0 - 1 + cc;
       const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
-      float od[4], op[4];
+      float od[4], op[4], uv[4];
       zero4(od);
       zero4(op);
+      zero4(uv);
       if (y >= 0 && y < h && x >= 0 && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         float x1[4], g[4], dv[4];
         ld4(X1 + off, x1);
         ld4(dX1 + off, g);
-        s1_dw_lds<C>(xt, XW, r + 1, cc + 1, c0, wd, dv);
+        s1_dw_lds<C, XN>(xt, XW, r + 1, cc + 1, c0, wd, dv);
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
-          const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C>((r - 1) * TW + cc - 1, c0 >> 2));
+          const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C, M>((r - 1) * TW + cc - 1, c0 >> 2));
           pv[0] = pq.x;
           pv[1] = pq.y;
           pv[2] = pq.z;
           pv[3] = pq.w;
         }
+        float pa[4], pb[4], pe[4], da[4], db[4], de[4];
+        cfv(0, pa);
+        cfv(1, pb);
+        cfv(2, pe);
+        cfv(3, da);
+        cfv(4, db);
+        cfv(5, de);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float du = x1[j] > 0.f ? g[j] : 0.f;
-          od[j] = ga[1][j] * is[1][j] * (du - k[0][j] - (dv[j] - mu[1][j]) * is[1][j] * k[2][j]);
-          op[j] = ga[0][j] * is[0][j] * (du - k[0][j] - (pv[j] - mu[0][j]) * is[0][j] * k[1][j]);
+          uv[j] = du;
+          od[j] = da[j] * du + db[j] * dv[j] + de[j];
+          op[j] = pa[j] * du + pb[j] * pv[j] + pe[j];
         }
       }
-      *reinterpret_cast<float4*>(ddt + s1c<C>(px, c0 >> 2)) = make_float4(od[0], od[1], od[2], od[3]);
-      if (center)
-        *reinterpret_cast<float4*>(dpt + s1c<C>((r - 1) * TW + cc - 1, c0 >> 2)) =
-            make_float4(op[0], op[1], op[2], op[3]);
+      *reinterpret_cast<float4*>(ddt + s1c<C, DN>(px, c0 >> 2)) = make_float4(od[0], od[1], od[2], od[3]);
+      if (center) {
+        const int cp = s1c<C, M>((r - 1) * TW + cc - 1, c0 >> 2);
+        *reinterpret_cast<float4*>(dpt + cp) = make_float4(op[0], op[1], op[2], op[3]);
+        *reinterpret_cast<float4*>(dut + cp) = make_float4(uv[0], uv[1], uv[2], uv[3]);
+      }
     }
     __syncthreads();
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
-    lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
-                        [&](int p, int n, float v) { qt[s1e<C>(p, n)] = v; });
+    lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
+                        [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles)
 #pragma unroll
     for (int u = 0; u < NTW; ++u) {
@@ -388,7 +416,7 @@ __global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X
         const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
 #pragma unroll 4
         for (int p = 0; p < M; p += 4)
-          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C>(xpx(p + lg), m0 + li)], dpt[s1e<C>(p + lg, n0 + li)],
+          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(p + lg), m0 + li)], dpt[s1e<C, M>(p + lg, n0 + li)],
                                                           pwacc[u], 0, 0, 0);
       }
     }
@@ -399,18 +427,18 @@ __global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X
       const int y = y0 + r, x = x0 + cc;
       if (y >= h || x >= w) continue;
       const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-      float x1[4], g[4], rr[4], acc[4];
-      ld4(X1 + off, x1);
-      ld4(dX1 + off, g);
+      float rr[4], acc[4];
       ld4(dXr + off, rr);
-      const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C>(xpx(px), c0 >> 2));
-      const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C>(px, c0 >> 2));
-      const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w};
+      const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px), c0 >> 2));
+      const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px, c0 >> 2));
+      const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px, c0 >> 2));
+      const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
+      float xa[4], xb[4], xe[4];
+      cfv(6, xa);
+      cfv(7, xb);
+      cfv(8, xe);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const float du = x1[j] > 0.f ? g[j] : 0.f;
-        acc[j] = ga[2][j] * is[2][j] * (du - k[0][j] - (xv[j] - mu[2][j]) * is[2][j] * k[3][j]) + rr[j] + qv[j];
-      }
+      for (int j = 0; j < 4; ++j) acc[j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
       if (SKIP) {
         float sv[4];
         ld4(skip + off, sv);
@@ -418,19 +446,19 @@ __global__ __launch_bounds__(256, 2) void k_s1_bwd_fused(const T* __restrict__ X
         for (int j = 0; j < 4; ++j) acc[j] += sv[j];
       }
       // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map
-      const float4 ddc = *reinterpret_cast<const float4*>(ddt + s1c<C>((r + 1) * DWd + cc + 1, c0 >> 2));
+      const float4 ddc = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1) * DWd + cc + 1, c0 >> 2));
       const float ddv[4] = {ddc.x, ddc.y, ddc.z, ddc.w};
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
+        const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
         const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
         acc[0] += wq.x * v.x;
         acc[1] += wq.y * v.y;
         acc[2] += wq.z * v.z;
         acc[3] += wq.w * v.w;
         // depthwise weight gradient: x(q + off_t) * dD(q)
-        const float4 xn = *reinterpret_cast<const float4*>(xt + s1c<C>((r + 2 + dy) * XW + cc + 2 + dx, c0 >> 2));
+        const float4 xn = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 2 + dy) * XW + cc + 2 + dx, c0 >> 2));
         dwacc[t][0] += xn.x * ddv[0];
         dwacc[t][1] += xn.y * ddv[1];
         dwacc[t][2] += xn.z * ddv[2];

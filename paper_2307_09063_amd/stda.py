@@ -357,8 +357,8 @@ def profile_report():
 
 
 # ------------------------------------------------------------------------ tile-shape autotuning
-TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD = 0, 1, 2
-TUNE_KINDS = (TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD)
+TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD, TUNE_S1_BWD = 0, 1, 2, 3
+TUNE_KINDS = (TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD, TUNE_S1_BWD)
 
 
 def tune_count(kind):

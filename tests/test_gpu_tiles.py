@@ -1,5 +1,5 @@
-"""The tiling variants of the stage-2 dense layers and of their weight gradients (the autotuner's
-candidates), through the C ABI.
+"""The tiling variants of the stage-2 dense layers, of their weight gradients and of the fused
+stage-1 adjoint (the autotuner's candidates), through the C ABI.
 
 * EVAL forward: every variant gives bit-identical z (each output element sums its taps and
   channels in the same order whatever the tiling), on shapes whose maps leave ragged tiles at
@@ -169,3 +169,32 @@ def test_wgrad_variants_agree(S, dtype):
             else:
                 np.testing.assert_array_equal(a, b)
             off += n
+
+
+@pytest.mark.parametrize('dtype', [0, 1], ids=['fp32', 'bf16'])
+def test_stage1_adjoint_variants_agree(S, dtype):
+    """Only the stage-1 adjoint tiling changes.  Each pixel's input gradient is the same expression
+    in every variant, but each instantiation is compiled on its own (tile shape, register budget)
+    and may fuse its multiply-adds differently, so dx and the gradients upstream of it agree to
+    FP32 rounding rather than bitwise; the stage-1 weight gradients (summed per tile) also differ
+    by the order of their pixel sums.  Each variant also meets the oracle gate
+    (test_variant_fp32_train_backward)."""
+    B, H, W = SHAPES[1]
+    x, _ = U.maps(B, H, W, seed=41)
+    w, r = U.weights(), U.running()
+    g = np.random.default_rng(4).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
+    res = []
+    for v in range(S.tune_count(S.TUNE_S1_BWD)):
+        _say('stage-1 adjoint variant', dtype, v)
+        for b in range(4):
+            S.tune_set(S.TUNE_S1_BWD, dtype, b, v)
+        z, _, (segs, xd, wd, saved, ws) = _forward(S, x, w, r, S.TRAIN, dtype)
+        dw = torch.full((net.param_count(),), float('nan'), device='cuda')
+        dx = torch.empty_like(xd)
+        S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws, dtype)
+        torch.cuda.synchronize()
+        res.append((dw.cpu().numpy(), dx.cpu().numpy()))
+    for v in range(1, len(res)):
+        assert U.rel_l2(res[v][1], res[0][1]) < 1e-6, v
+        bad = {k: e for k, e in U.per_tensor_errors(res[v][0], res[0][0]).items() if not e < 1e-5}
+        assert not bad, (v, bad)
