@@ -41,7 +41,8 @@ def kernel_work(tag, B, H, W, es):
         hin, hout = hw0 // 4 ** lin, hw0 // 4 ** lout
         s1_flops = 2.0 * B * hin * (cin * cin + 9 * cin)
         dense_macs = B * hout * (4 if dec else 9) * cin * cout
-        skip = 1 if blk in ('dec0', 'dec1') else 0
+        skip = 1 if blk in ('dec0', 'dec1') else 0      # decoder outputs add an encoder feature
+        skip_g = 1 - skip                                # encoder inputs receive its gradient back
         table = {
             'dense_fwd_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
             'dense_fwd_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
@@ -58,8 +59,9 @@ def kernel_work(tag, B, H, W, es):
             's2_bwd_apply': (10.0 * B * hout * cout, B * hout * cout * (4 * es + 0.25), 'alu'),
             's1_bwd_stats': (s1_flops, 3.0 * B * cin * hin * es, 'alu'),
             # three pointwise products (recompute, transpose, weight gradient) and three depthwise
-            # ones (recompute, transpose, weight gradient); reads x, x1, dx1, dxr (+ skip), writes dx
-            's1_bwd_fused': (2.0 * B * hin * (3 * cin * cin + 27 * cin), (5 + skip) * B * cin * hin * es, 'alu'),
+            # ones (recompute, transpose, weight gradient); reads x, x1, dx1, dxr (+ the skip
+            # gradient in the encoder), writes dx
+            's1_bwd_fused': (2.0 * B * hin * (3 * cin * cin + 27 * cin), (5 + skip_g) * B * cin * hin * es, 'alu'),
         }
         return table.get(kind)
     table = {

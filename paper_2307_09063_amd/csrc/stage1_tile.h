@@ -121,16 +121,30 @@ __device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
 
 // Depthwise branch (4 channels) of the pixel at padded LDS position (r, c).
 template <int C, int NPIX>
-__device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float* wd, float dv[4]) {
+// wr: this thread's 4 channels of the 9 taps, held in registers.
+__device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float (&wr)[9][4],
+                                          float dv[4]) {
   zero4(dv);
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
     const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C, NPIX>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
-    const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
-    dv[0] += wq.x * v.x;
-    dv[1] += wq.y * v.y;
-    dv[2] += wq.z * v.z;
-    dv[3] += wq.w * v.w;
+    dv[0] += wr[t][0] * v.x;
+    dv[1] += wr[t][1] * v.y;
+    dv[2] += wr[t][2] * v.z;
+    dv[3] += wr[t][3] * v.w;
+  }
+}
+
+// Channels c0 .. c0 + 3 of the 9 depthwise taps, from LDS into registers.
+template <int C>
+__device__ __forceinline__ void s1_dw_regs(const float* wd, int c0, float (&wr)[9][4]) {
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const float4 q = *reinterpret_cast<const float4*>(wd + t * C + c0);
+    wr[t][0] = q.x;
+    wr[t][1] = q.y;
+    wr[t][2] = q.z;
+    wr[t][3] = q.w;
   }
 }
 
@@ -150,6 +164,8 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
   __shared__ float red[6 * C];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
+  float wr[9][4];
+  s1_dw_regs<C>(wd, c0, wr);
   float acc[6][4];
 #pragma unroll
   for (int s = 0; s < 6; ++s) zero4(acc[s]);
@@ -184,7 +200,7 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
       if (MODE == 0) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -230,6 +246,8 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
   __shared__ float red[4 * C];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
+  float wr[9][4];
+  s1_dw_regs<C>(wd, c0, wr);
   float mu[3][4], is[3][4];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -267,7 +285,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wd, dv);
+      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
       const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
       ld4(X1 + off, x1);
       ld4(dX1 + off, g);
@@ -332,6 +350,8 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);  // ends with a barrier
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
   const int c0 = (threadIdx.x % G) * 4;
+  float wr[9][4];
+  s1_dw_regs<C>(wd, c0, wr);
   auto cfv = [&](int q, float v[4]) {
     const float4 t = *reinterpret_cast<const float4*>(cf + q * C + c0);
     v[0] = t.x;
@@ -373,7 +393,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         float x1[4], g[4], dv[4];
         ld4(X1 + off, x1);
         ld4(dX1 + off, g);
-        s1_dw_lds<C, XN>(xt, XW, r + 1, cc + 1, c0, wd, dv);
+        s1_dw_lds<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv);
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
           const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C, M>((r - 1) * TW + cc - 1, c0 >> 2));
@@ -452,11 +472,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
         const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
-        const float4 wq = *reinterpret_cast<const float4*>(wd + t * C + c0);
-        acc[0] += wq.x * v.x;
-        acc[1] += wq.y * v.y;
-        acc[2] += wq.z * v.z;
-        acc[3] += wq.w * v.w;
+        acc[0] += wr[t][0] * v.x;
+        acc[1] += wr[t][1] * v.y;
+        acc[2] += wr[t][2] * v.z;
+        acc[3] += wr[t][3] * v.w;
         // depthwise weight gradient: x(q + off_t) * dD(q)
         const float4 xn = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 2 + dy) * XW + cc + 2 + dx, c0 >> 2));
         dwacc[t][0] += xn.x * ddv[0];
