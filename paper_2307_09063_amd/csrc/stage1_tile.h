@@ -135,6 +135,21 @@ __device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c,
   }
 }
 
+// The same, also returning the 9 neighbourhood values it read.
+template <int C, int NPIX>
+__device__ __forceinline__ void s1_dw_lds_keep(const float* xt, int RW, int r, int c, int c0, const float (&wr)[9][4],
+                                               float dv[4], float4 (&xn)[9]) {
+  zero4(dv);
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    xn[t] = *reinterpret_cast<const float4*>(xt + s1c<C, NPIX>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
+    dv[0] += wr[t][0] * xn[t].x;
+    dv[1] += wr[t][1] * xn[t].y;
+    dv[2] += wr[t][2] * xn[t].z;
+    dv[3] += wr[t][3] * xn[t].w;
+  }
+}
+
 // Channels c0 .. c0 + 3 of the 9 depthwise taps, from LDS into registers.
 template <int C>
 __device__ __forceinline__ void s1_dw_regs(const float* wd, int c0, float (&wr)[9][4]) {
@@ -309,8 +324,10 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 //   dX = g_x is_x (du - k0 - xhat k3) + dXr + PW^T(dP) + DW^T(dD) (+ skip gradient),
 // plus the pointwise weight gradient sum_p x[c](p) dP[o](p) -> pwpart[blk][c][o] and the
 // depthwise one sum_p x[c](p + off_t) dD[c](p) -> dwpart[blk][tap][c] (the weight's own tap
-// index, flipped in the decoder).  Per tile: x on a 2-pixel halo, dD on a 1-pixel halo, dP and du
-// in LDS (never in HBM; du is formed once, with dD, and read back for dX); the three pointwise
+// index, flipped in the decoder; accumulated as each tile pixel's dD is formed, from the 3x3
+// neighbourhood of x that its depthwise recompute has just read).  Per tile: x on a 2-pixel halo,
+// dD on a 1-pixel halo, dP and du in LDS (never in HBM; du is formed once, with dD, and read back
+// for dX); the three pointwise
 // products (p = x Wp, dP Wp^T, x^T dP) run on the matrix cores, the last one accumulating in
 // registers across tiles.  Tiles are TH x TW pixels; MINW waves per SIMD bound the registers.
 template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW>
@@ -391,9 +408,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       if (y >= 0 && y < h && x >= 0 && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         float x1[4], g[4], dv[4];
+        float4 xn[9];
         ld4(X1 + off, x1);
         ld4(dX1 + off, g);
-        s1_dw_lds<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv);
+        s1_dw_lds_keep<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv, xn);
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
           const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C, M>((r - 1) * TW + cc - 1, c0 >> 2));
@@ -416,6 +434,14 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
           od[j] = da[j] * du + db[j] * dv[j] + de[j];
           op[j] = pa[j] * du + pb[j] * pv[j] + pe[j];
         }
+        if (center)  // depthwise weight gradient: x(q + off_t) dD(q) over the tile's pixels q
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            dwacc[t][0] += xn[t].x * od[0];
+            dwacc[t][1] += xn[t].y * od[1];
+            dwacc[t][2] += xn[t].z * od[2];
+            dwacc[t][3] += xn[t].w * od[3];
+          }
       }
       *reinterpret_cast<float4*>(ddt + s1c<C, DN>(px, c0 >> 2)) = make_float4(od[0], od[1], od[2], od[3]);
       if (center) {
@@ -466,8 +492,6 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         for (int j = 0; j < 4; ++j) acc[j] += sv[j];
       }
       // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map
-      const float4 ddc = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1) * DWd + cc + 1, c0 >> 2));
-      const float ddv[4] = {ddc.x, ddc.y, ddc.z, ddc.w};
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int dy = t / 3 - 1, dx = t % 3 - 1;
@@ -476,12 +500,6 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         acc[1] += wr[t][1] * v.y;
         acc[2] += wr[t][2] * v.z;
         acc[3] += wr[t][3] * v.w;
-        // depthwise weight gradient: x(q + off_t) * dD(q)
-        const float4 xn = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 2 + dy) * XW + cc + 2 + dx, c0 >> 2));
-        dwacc[t][0] += xn.x * ddv[0];
-        dwacc[t][1] += xn.y * ddv[1];
-        dwacc[t][2] += xn.z * ddv[2];
-        dwacc[t][3] += xn.w * ddv[3];
       }
       st4(dX + off, acc);
     }
