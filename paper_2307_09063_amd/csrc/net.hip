@@ -931,8 +931,8 @@ int launch_s1b(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, 
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
 #define S1B(TH_, TW_, W_) \
   launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, X1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
-  if constexpr (C == 16) return v == 1 ? S1B(8, 8, 3) : v == 2 ? S1B(4, 16, 3) : v == 3 ? S1B(8, 8, 2) : S1B(8, 16, 2);
-  else if constexpr (C == 32) return v == 1 ? S1B(4, 8, 3) : v == 2 ? S1B(8, 4, 3) : v == 3 ? S1B(4, 8, 2) : S1B(8, 8, 2);
+  if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1B(8, 8, 2) : S1B(8, 16, 2);
+  else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1B(4, 8, 2) : S1B(8, 8, 2);
   else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1B(8, 2, 2) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
 #undef S1B
 }

@@ -369,13 +369,15 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   const int c0 = (threadIdx.x % G) * 4;
   float wr[9][4];
   s1_dw_regs<C>(wd, c0, wr);
-  auto cfv = [&](int q, float v[4]) {
+  float cfr[9][4];  // this thread's 4 channels of the 9 coefficient rows
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
     const float4 t = *reinterpret_cast<const float4*>(cf + q * C + c0);
-    v[0] = t.x;
-    v[1] = t.y;
-    v[2] = t.z;
-    v[3] = t.w;
-  };
+    cfr[q][0] = t.x;
+    cfr[q][1] = t.y;
+    cfr[q][2] = t.z;
+    cfr[q][3] = t.w;
+  }
   float dwacc[9][4];
 #pragma unroll
   for (int t = 0; t < 9; ++t) zero4(dwacc[t]);
@@ -420,13 +422,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
           pv[2] = pq.z;
           pv[3] = pq.w;
         }
-        float pa[4], pb[4], pe[4], da[4], db[4], de[4];
-        cfv(0, pa);
-        cfv(1, pb);
-        cfv(2, pe);
-        cfv(3, da);
-        cfv(4, db);
-        cfv(5, de);
+        const float *pa = cfr[0], *pb = cfr[1], *pe = cfr[2], *da = cfr[3], *db = cfr[4], *de = cfr[5];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float du = x1[j] > 0.f ? g[j] : 0.f;
@@ -479,10 +475,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px, c0 >> 2));
       const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px, c0 >> 2));
       const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
-      float xa[4], xb[4], xe[4];
-      cfv(6, xa);
-      cfv(7, xb);
-      cfv(8, xe);
+      const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
       if (SKIP) {
