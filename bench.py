@@ -241,9 +241,17 @@ def source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
+def tile_key(tag):
+    """Key of config.tiles that selects the tiling of the tagged launch, or None if untuned."""
+    kind, _, blk = tag.partition('.')
+    k = {'dense_fwd_main': 'fwd', 'dense_fwd_res': 'fwd', 'dense_dgrad_main': 'dgrad', 'dense_dgrad_res': 'dgrad',
+         'wgrad_main': 'wgrad', 'wgrad_res': 'wgrad', 's1_bwd_fused': 's1_bwd'}.get(kind)
+    return f'{k}.{blk}' if k else None
+
+
+def measured_traffic(kernel, workload, tiles):
     """HBM bytes per launch of `kernel` in `workload` from the committed counter summary, or
-    None when the summary is missing, covers another kernel or workload, or was taken on
+    None when the summary is missing, covers another kernel, workload or tiling, or was taken on
     different sources."""
     path = os.path.join(ROOT, 'profiles', 'traffic.json')
     if not os.path.exists(path):
@@ -251,6 +259,9 @@ def measured_traffic(kernel, workload):
     with open(path) as f:
         t = json.load(f)
     if t.get('source_sha256') != source_hash() or t.get('kernel_tag') != kernel or t.get('workload') != workload:
+        return None
+    key = tile_key(kernel)
+    if key is not None and (tiles or {}).get(key, 0) != t.get('tile_variant'):
         return None
     return t.get('hbm_bytes_per_launch')
 
@@ -319,7 +330,7 @@ def main():
     stda.profile_select(None)
     roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16) if len(groups) == 1 else None
     if roof is not None:
-        roof['traffic'] = measured_traffic(dominant, args.workload)
+        roof['traffic'] = measured_traffic(dominant, args.workload, tiles)
     print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), eager {ms_eager:.3f} ms, wall {wall:.2f}s, '
           f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)
 

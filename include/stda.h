@@ -270,7 +270,8 @@ int stda_tune_get(int kind, int dtype, int block, int* variant /*host out*/);
 /*
  * Autotuner: for every variant v, sets all tunable launches of `dtype` to v, runs one untimed
  * training forward + loss + backward on the given buffers and then `reps` timed ones (HIP events
- * around each tunable launch), and finally sets every tunable launch to its fastest variant.
+ * around each tunable launch), and finally sets every tunable launch to its fastest variant
+ * (variant 0, the default, unless another is at least 3 % faster).
  * Arguments are those of stda_forward / stda_mse_loss / stda_backward; `running` is updated by
  * every trial step (pass a scratch copy), w is not modified, z / loss / dz / dw are overwritten.
  * The per-variant times and the choice are written as text lines

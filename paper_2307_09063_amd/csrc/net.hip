@@ -458,6 +458,7 @@ int tiles_for(int64_t hw, int G) {
 // default.
 constexpr int kS2Variants = 4;
 constexpr int kTuneKinds = 4;
+constexpr double kTuneMargin = 0.03;
 int g_s2_variant[2][kTuneKinds][4] = {};
 
 template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
@@ -1375,9 +1376,12 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
   char line[256];
   for (int kind = 0; kind < kTuneKinds; ++kind)
     for (int b = 0; b < 4; ++b) {
+      // another tiling replaces the default only when it is faster by kTuneMargin, so that
+      // near-ties do not flip with timing noise
       int best = 0;
       for (int v = 1; v < kS2Variants; ++v)
-        if (cost[kind][b][v] < cost[kind][b][best]) best = v;
+        if (cost[kind][b][v] < cost[kind][b][best] && cost[kind][b][v] < (1.0 - kTuneMargin) * cost[kind][b][0])
+          best = v;
       g_s2_variant[dtype][kind][b] = best;
       int n = std::snprintf(line, sizeof(line), "%d\t%d", kind, b);
       for (int v = 0; v < kS2Variants; ++v)

@@ -4,13 +4,14 @@
         per-kernel dispatch count, total and average duration, VGPRs and LDS of a
         ``--kernel-trace`` run
     python -m paper_2307_09063_amd.profsum traffic --fetch DIR --write DIR \
-            --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel NAME --tag TAG --workload NAME [--out FILE]
+            --copy-fetch DIR --copy-write DIR --copy-bytes N --kernel NAME --tag TAG --workload NAME \
+            --bench-log FETCH_LOG --bench-log WRITE_LOG [--out FILE]
         HBM bytes per dispatch of one kernel from a ``--pmc FETCH_SIZE`` run and a
         ``--pmc WRITE_SIZE`` run, each scaled by the factor that makes the same counter read
         exactly N bytes for a plain device copy of N bytes (``bench.py --copy-calib``)
 
-The traffic summary carries the SHA-256 of the library sources it was taken on; bench.py
-reports it only while the sources are unchanged."""
+The traffic summary carries the SHA-256 of the library sources it was taken on and the tiling
+variant the autotuner chose for the kernel; bench.py reports it only while both still hold."""
 import argparse
 import glob
 import json
@@ -72,7 +73,19 @@ def cmd_traffic(a):
     hbm = fetch * 1024.0 * f_fac + write * 1024.0 * w_fac
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
+    # the tiling the autotuner chose for this kernel in the counter runs (their bench.py logs)
+    key = bench.tile_key(a.tag)
+    chosen = set()
+    for log in a.bench_log:
+        with open(log) as f:
+            lines = [ln for ln in f if ln.startswith('{')]
+        if not lines:
+            raise SystemExit(f'no bench.py result line in {log}')
+        chosen.add((json.loads(lines[-1])['config'].get('tiles') or {}).get(key, 0))
+    if len(chosen) != 1:
+        raise SystemExit(f'the counter runs chose different tilings for {key}: {sorted(chosen)}')
     out = {'kernel_tag': a.tag, 'workload': a.workload, 'kernel': a.kernel, 'source_sha256': bench.source_hash(),
+           'tile_key': key, 'tile_variant': chosen.pop(),
            'fetch_kib_per_dispatch': round(fetch, 1), 'write_kib_per_dispatch': round(write, 1),
            'dispatches': [nf, nw], 'copy_bytes': a.copy_bytes,
            'copy_fetch_kib': round(cf, 1), 'copy_write_kib': round(cw, 1),
@@ -102,6 +115,8 @@ def main(argv=None):
     r.add_argument('--kernel', required=True, help='short kernel name as the trace summary prints it')
     r.add_argument('--tag', required=True, help='the profiling tag bench.py uses for that kernel')
     r.add_argument('--workload', required=True, help='bench.py workload the counters were taken on')
+    r.add_argument('--bench-log', action='append', required=True,
+                   help='output of a bench.py counter run (give both); their tiling choice is recorded')
     r.add_argument('--out', default=None)
     r.set_defaults(fn=cmd_traffic)
     a = ap.parse_args(argv)
