@@ -7,7 +7,8 @@
 // sub-pixel phases of it for the up-sampling operators) and NB of the N output channels; it
 //   1. copies its NB-column slice of the weights, already in MFMA fragment order, into LDS once;
 //   2. per tile, copies the source rectangle the tile reads (tile plus halo, zeros off the map)
-//      into LDS with 16-byte loads, channels innermost, rows padded against bank conflicts;
+//      into LDS with 16-byte loads, channels innermost, rows padded against bank conflicts; the
+//      next tile's rectangle is loaded into registers while this tile's GEMM runs;
 //   3. runs the GEMM: wave w takes row tiles w*R .. w*R+R-1 (16 output pixels each) of every
 //      phase, all NB/16 column tiles, A fragments and B fragments both read from LDS;
 //   4. writes the FP32 accumulators, rounded to the storage type, into an LDS staging tile that
@@ -110,39 +111,46 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     t_step = gridDim.x;
   }
 
+  // 2. source rectangle of tile t, HBM -> registers; the next tile's is loaded while this tile's
+  // GEMM runs (software pipelining: the loads stay in flight across the LDS-only barriers)
+  constexpr int CH = K / VE;  // 16-byte chunks per pixel
+  constexpr int TOTAL = SH * SW * CH;
+  constexpr int PER = (TOTAL + STDA_BLOCK - 1) / STDA_BLOCK;
+  uint4 v[PER];
+  auto load_src = [&](int64_t tt) {
+    int lb, ly0, lx0;
+    s2_tile_origin(tt, nty, ntx, TH, TW, lb, ly0, lx0);
+    const int sy0 = C::DOWN ? 2 * ly0 - 1 : ly0 / 2 - C::SOFF;
+    const int sx0 = C::DOWN ? 2 * lx0 - 1 : lx0 / 2 - C::SOFF;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * STDA_BLOCK;
+      v[i] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < TOTAL) {
+        const int c = e % CH, px = e / CH;
+        const int sy = sy0 + px / SW, sx = sx0 + px % SW;
+        if (sy >= 0 && sy < hs && sx >= 0 && sx < ws)
+          v[i] = *reinterpret_cast<const uint4*>(src + (((int64_t)lb * hs + sy) * ws + sx) * K + c * VE);
+      }
+    }
+  };
+  if (t_begin < t_end) load_src(t_begin);
+
   for (int64_t t = t_begin; t < t_end; t += t_step) {
     int b, y0, x0;
     s2_tile_origin(t, nty, ntx, TH, TW, b, y0, x0);
-    const int sy0 = C::DOWN ? 2 * y0 - 1 : y0 / 2 - C::SOFF;
-    const int sx0 = C::DOWN ? 2 * x0 - 1 : x0 / 2 - C::SOFF;
     __syncthreads();  // previous tile's staging reads are done (and the weights are in LDS)
-    // 2. source rectangle -> LDS
-    {
-      constexpr int CH = K / VE;  // 16-byte chunks per pixel
-      constexpr int TOTAL = SH * SW * CH;
-      constexpr int PER = (TOTAL + STDA_BLOCK - 1) / STDA_BLOCK;
-      uint4 v[PER];
+    // registers -> LDS
 #pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int e = threadIdx.x + i * STDA_BLOCK;
-        v[i] = make_uint4(0u, 0u, 0u, 0u);
-        if (e < TOTAL) {
-          const int c = e % CH, px = e / CH;
-          const int sy = sy0 + px / SW, sx = sx0 + px % SW;
-          if (sy >= 0 && sy < hs && sx >= 0 && sx < ws)
-            v[i] = *reinterpret_cast<const uint4*>(src + (((int64_t)b * hs + sy) * ws + sx) * K + c * VE);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < PER; ++i) {
-        const int e = threadIdx.x + i * STDA_BLOCK;
-        if (e < TOTAL) {
-          const int c = e % CH, px = e / CH;
-          *reinterpret_cast<uint4*>(tile_lds + px * KP + c * VE) = v[i];
-        }
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * STDA_BLOCK;
+      if (e < TOTAL) {
+        const int c = e % CH, px = e / CH;
+        *reinterpret_cast<uint4*>(tile_lds + px * KP + c * VE) = v[i];
       }
     }
     __syncthreads();
+    if (t + t_step < t_end) load_src(t + t_step);
     // 3. GEMM: every phase, R row tiles per wave, NTB column tiles
     floatx4 acc[PH][R][NTB];
 #pragma unroll
