@@ -461,17 +461,17 @@ constexpr int kTuneKinds = 4;
 constexpr double kTuneMargin = 0.03;
 int g_s2_variant[2][kTuneKinds][4] = {};
 
-template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
+template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS, int WV = 4>
 int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
                   int hd, int wd, int* nblk) {
-  typedef S2Cfg<T, OP, K, N, NB, TH, TW> C;
+  typedef S2Cfg<T, OP, K, N, NB, TH, TW, WV> C;
   const int64_t ntiles = (int64_t)n * ((hd + TH - 1) / TH) * ((wd + TW - 1) / TW);
   const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / C::LDS_BYTES);
   int64_t gx = std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid));
   if (gx >= 64) gx &= ~(int64_t)7;  // whole XCD groups: tiles are handed out XCD by XCD
   gx = std::max<int64_t>(gx, 1);
-  KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS><<<dim3((unsigned)gx, N / NB), 256, 0, c.st>>>(src, frag, dst,
-                                                                                                   part, n, hd, wd));
+  KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS, WV><<<dim3((unsigned)gx, N / NB), C::BLK, 0, c.st>>>(
+                    src, frag, dst, part, n, hd, wd));
   if (nblk) *nblk = (int)gx;
   return STDA_OK;
 }
@@ -497,33 +497,37 @@ int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* s
                       float* part, int n, int hd, int wd, int* nblk) {
   constexpr bool BF = sizeof(T) == 2;
 #define S2V(NB_, TH_, TW_) launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk)
+  // 8 waves per workgroup: tilings whose LDS leaves room for one workgroup per CU
+#define S2W(NB_, TH_, TW_) \
+  launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS, 8>(c, tag, src, frag, dst, part, n, hd, wd, nblk)
   if (v == 3) return launch_gather<T, OP, K, N, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk);
   if constexpr (OP == OP_ENC_FWD && K == 16) {
-    if constexpr (BF) return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2V(32, 16, 16) : S2V(32, 8, 32);
+    if constexpr (BF) return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2W(32, 16, 16) : S2V(32, 8, 32);
     else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 16);
   } else if constexpr (OP == OP_ENC_FWD) {
-    if constexpr (BF) return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2V(32, 8, 16) : S2V(64, 8, 16);
-    else return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 8);
+    if constexpr (BF) return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2W(32, 8, 16) : S2V(64, 8, 16);
+    else return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2W(16, 8, 16) : S2V(32, 8, 8);
   } else if constexpr (OP == OP_DEC_FWD && K == 64) {
-    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(32, 16, 32) : S2V(32, 16, 16);
-    else return v == 1 ? S2V(16, 32, 16) : v == 2 ? S2V(16, 16, 32) : S2V(16, 16, 16);
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2W(32, 16, 32) : S2V(32, 16, 16);
+    else return v == 1 ? S2V(16, 32, 16) : v == 2 ? S2W(16, 16, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_DEC_FWD) {
-    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 32);
-    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 16);
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2W(16, 32, 32) : S2V(16, 16, 32);
+    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2W(16, 32, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_ENC_DGRAD && K == 32) {
-    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 32);
-    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2V(16, 32, 32) : S2V(16, 16, 16);
+    if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2W(16, 32, 32) : S2V(16, 16, 32);
+    else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2W(16, 32, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_ENC_DGRAD) {
     if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(32, 16, 32) : S2V(32, 16, 16);
     else return v == 1 ? S2V(32, 16, 16) : v == 2 ? S2V(16, 16, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_DEC_DGRAD && K == 32) {
     if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(32, 8, 16) : S2V(64, 8, 8);
-    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(16, 8, 8);
+    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2W(16, 8, 16) : S2V(16, 8, 8);
   } else {
-    if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(32, 16, 16) : S2V(32, 8, 16);
-    else return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 8);
+    if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2W(32, 16, 16) : S2V(32, 8, 16);
+    else return v == 1 ? S2W(32, 8, 16) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 8);
   }
 #undef S2V
+#undef S2W
 }
 
 // Dense stride-2 layer of block `blk` on the matrix cores; *nblk = rows of BN partials written.

@@ -9,7 +9,8 @@
 //   2. per tile, copies the source rectangle the tile reads (tile plus halo, zeros off the map)
 //      into LDS with 16-byte loads, channels innermost, rows padded against bank conflicts; the
 //      next tile's rectangle is loaded into registers while this tile's GEMM runs;
-//   3. runs the GEMM: wave w takes row tiles w*R .. w*R+R-1 (16 output pixels each) of every
+//   3. runs the GEMM (4 or 8 waves per workgroup; 8 where the LDS allows one workgroup per CU, so
+//      that two waves share each SIMD): wave w takes row tiles w*R .. w*R+R-1 (16 output pixels each) of every
 //      phase, all NB/16 column tiles, A fragments and B fragments both read from LDS;
 //   4. writes the FP32 accumulators, rounded to the storage type, into an LDS staging tile that
 //      aliases the source rectangle, and stores it with 16-byte writes, contiguous along a row;
@@ -26,7 +27,7 @@ template <class T> struct S2Pad;
 template <> struct S2Pad<float> { static constexpr int v = 4; };  // 16 bytes per padded row end
 template <> struct S2Pad<bf16> { static constexpr int v = 8; };
 
-template <class T, int OP, int K, int N, int NB, int TH, int TW>
+template <class T, int OP, int K, int N, int NB, int TH, int TW, int WV = 4>
 struct S2Cfg {
   static constexpr int KS = OpGeo<OP>::KS;
   static constexpr bool DOWN = OpGeo<OP>::DOWN;
@@ -39,7 +40,8 @@ struct S2Cfg {
   static constexpr int PH = DOWN ? 1 : 4;                     // sub-pixel phases per tile
   static constexpr int PW = DOWN ? TW : TW / 2;               // width of one phase's pixel grid
   static constexpr int MT = (DOWN ? TH * TW : TH * TW / 4) / 16;  // 16-row tiles per phase
-  static constexpr int R = MT / 4;                            // row tiles per wave per phase
+  static constexpr int R = MT / WV;                           // row tiles per wave per phase
+  static constexpr int BLK = 64 * WV;                         // threads per workgroup
   static constexpr int KC = K / 16, NT = N / 16, NTB = NB / 16;
   static constexpr int TAPS = KS * KS;
   static constexpr int SRC_ELEMS = SH * SW * KP;
@@ -48,7 +50,7 @@ struct S2Cfg {
   static constexpr int W_ELEMS = TAPS * K * NB;
   static constexpr int LDS_BYTES = (TILE_ELEMS + W_ELEMS) * ES;
   static_assert(K % 16 == 0 && N % NB == 0 && NB % 16 == 0, "channel counts");
-  static_assert(MT % 4 == 0 && R >= 1, "each wave needs whole row tiles of every phase");
+  static_assert(MT % WV == 0 && R >= 1, "each wave needs whole row tiles of every phase");
   static_assert(DOWN || (TH % 2 == 0 && TW % 2 == 0), "up-sampling tiles cover whole phase pairs");
   static_assert(LDS_BYTES <= 160 * 1024, "LDS of one workgroup");
 };
@@ -62,11 +64,12 @@ __device__ __forceinline__ void s2_tile_origin(int64_t t, int nty, int ntx, int 
   x0 = (r % ntx) * TW;
 }
 
-template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS>
-__global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, const T* __restrict__ wfrag,
-                                                 T* __restrict__ dst, float* __restrict__ part, int B, int hd,
-                                                 int wd) {
-  typedef S2Cfg<T, OP, K, N, NB, TH, TW> C;
+template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, const T* __restrict__ wfrag,
+                                                     T* __restrict__ dst, float* __restrict__ part, int B, int hd,
+                                                     int wd) {
+  typedef S2Cfg<T, OP, K, N, NB, TH, TW, WV> C;
+  constexpr int BLK = C::BLK;
   typedef typename FragT<T>::type F;
   constexpr int KS = C::KS, KP = C::KP, SW = C::SW, SH = C::SH, R = C::R, NTB = C::NTB, KC = C::KC;
   constexpr int PH = C::PH, PW = C::PW;
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     const F* wf = reinterpret_cast<const F*>(wfrag);
     F* wl = reinterpret_cast<F*>(w_lds);
     constexpr int UNITS = C::TAPS * KC * NTB * 64;
-    for (int u = threadIdx.x; u < UNITS; u += STDA_BLOCK) {
+    for (int u = threadIdx.x; u < UNITS; u += BLK) {
       const int ln = u & 63, q = u >> 6;
       const int ntb = q % NTB, ts = q / NTB;  // ts = tap * KC + s
       wl[u] = wf[((int64_t)ts * C::NT + cb * NTB + ntb) * 64 + ln];
@@ -115,7 +118,7 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
   // GEMM runs (software pipelining: the loads stay in flight across the LDS-only barriers)
   constexpr int CH = K / VE;  // 16-byte chunks per pixel
   constexpr int TOTAL = SH * SW * CH;
-  constexpr int PER = (TOTAL + STDA_BLOCK - 1) / STDA_BLOCK;
+  constexpr int PER = (TOTAL + BLK - 1) / BLK;
   uint4 v[PER];
   auto load_src = [&](int64_t tt) {
     int lb, ly0, lx0;
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     const int sx0 = C::DOWN ? 2 * lx0 - 1 : lx0 / 2 - C::SOFF;
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + i * STDA_BLOCK;
+      const int e = threadIdx.x + i * BLK;
       v[i] = make_uint4(0u, 0u, 0u, 0u);
       if (e < TOTAL) {
         const int c = e % CH, px = e / CH;
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     // registers -> LDS
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-      const int e = threadIdx.x + i * STDA_BLOCK;
+      const int e = threadIdx.x + i * BLK;
       if (e < TOTAL) {
         const int c = e % CH, px = e / CH;
         *reinterpret_cast<uint4*>(tile_lds + px * KP + c * VE) = v[i];
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     {
       constexpr int CH = NB / VE;
       constexpr int TOTAL = TH * TW * CH;
-      for (int e = threadIdx.x; e < TOTAL; e += STDA_BLOCK) {
+      for (int e = threadIdx.x; e < TOTAL; e += BLK) {
         const int c = e % CH, p = e / CH;
         const int ty = p / TW, tx = p % TW;
         const int y = y0 + ty, x = x0 + tx;
@@ -239,10 +242,10 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
     }
   }
   if (STATS) {
-    // part[blockIdx.x][n][2] (n = cb * NB + column): reduce over the 4 lane groups, then the 4
+    // part[blockIdx.x][n][2] (n = cb * NB + column): reduce over the 4 lane groups, then the WV
     // waves, in a fixed order
     __syncthreads();
-    float* sm = reinterpret_cast<float*>(lds);  // 4 x 2 x NB floats, the tile is no longer needed
+    float* sm = reinterpret_cast<float*>(lds);  // WV x 2 x NB floats, the tile is no longer needed
 #pragma unroll
     for (int j = 0; j < NTB; ++j) {
       float a1 = st1[j], a2 = st2[j];
@@ -256,10 +259,12 @@ __global__ __launch_bounds__(256) void k_s2_tile(const T* __restrict__ src, cons
       }
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < 2 * NB; q += STDA_BLOCK) {
+    for (int q = threadIdx.x; q < 2 * NB; q += BLK) {
       const int c = q >> 1, s = q & 1;
-      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2 + s] =
-          sm[(0 * 2 + s) * NB + c] + sm[(1 * 2 + s) * NB + c] + sm[(2 * 2 + s) * NB + c] + sm[(3 * 2 + s) * NB + c];
+      float acc = sm[s * NB + c];
+#pragma unroll
+      for (int wv = 1; wv < WV; ++wv) acc += sm[(wv * 2 + s) * NB + c];
+      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2 + s] = acc;
     }
   }
 }
