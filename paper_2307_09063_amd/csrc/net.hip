@@ -824,7 +824,11 @@ namespace {
 template <class T>
 int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc,
               const std::string& tag = "colsum") {
-  KLAUNCH(tag, k_colsum<<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
+  if (ncols >= 4096) {
+    KLAUNCH(tag, k_colsum<64><<<(ncols + 63) / 64, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
+  } else {
+    KLAUNCH(tag, k_colsum<16><<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
+  }
   return STDA_OK;
 }
 

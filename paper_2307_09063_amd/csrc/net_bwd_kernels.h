@@ -179,11 +179,7 @@ __global__ __launch_bounds__(256) void k_bn_bwd_reduce(const float* __restrict__
   const int col = threadIdx.x % cols, rg = threadIdx.x / cols;
   const int c0 = blockIdx.x * 4;
   const int s = col / 4, c = c0 + col % 4;
-  double acc = 0.0;
-  if (rg < groups) {
-#pragma unroll 4
-    for (int r = rg; r < nrows; r += groups) acc += (double)part[(int64_t)r * NS * C + s * C + c];
-  }
+  const double acc = rg < groups ? strided_sum(part, rg, groups, nrows, (int64_t)NS * C, s * C + c) : 0.0;
   sm[threadIdx.x] = acc;
   __syncthreads();
   if (threadIdx.x < cols) {

@@ -130,22 +130,40 @@ __device__ __forceinline__ int64_t colmap_dst(const ColMap m, int col) {
   }
 }
 
+// acc += part[r * stride + off] for r = r0, r0 + step, ... < nrows, in that order; 16 loads are
+// issued before their adds so that their latencies overlap.
+__device__ __forceinline__ double strided_sum(const float* __restrict__ part, int r0, int step, int nrows, int64_t stride,
+                                              int64_t off) {
+  double acc = 0.0;
+  int r = r0;
+  for (; r + 15 * step < nrows; r += 16 * step) {
+    float v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = part[(int64_t)(r + k * step) * stride + off];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += (double)v[k];
+  }
+  for (; r < nrows; r += step) acc += (double)part[(int64_t)r * stride + off];
+  return acc;
+}
+
+// Column sums of part[nrows][ncols] in FP64 (fixed order): a block takes CW consecutive columns
+// and 256 / CW row groups; wide partial arrays use CW = 64 (a wave reads 256 contiguous bytes of
+// a row), narrow ones CW = 16 (more row groups in flight per column).
+template <int CW>
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, int nrows, int ncols,
                                                 double* __restrict__ dout, float* __restrict__ fout,
                                                 ColMap map, int accumulate) {
-  __shared__ double sm[16][17];
-  const int cl = threadIdx.x & 15, rg = threadIdx.x >> 4;
-  const int col = blockIdx.x * 16 + cl;
-  double acc = 0.0;
-  if (col < ncols) {
-#pragma unroll 8
-    for (int r = rg; r < nrows; r += 16) acc += (double)part[(int64_t)r * ncols + col];
-  }
+  constexpr int RG = 256 / CW;
+  __shared__ double sm[RG][CW];
+  const int cl = threadIdx.x % CW, rg = threadIdx.x / CW;
+  const int col = blockIdx.x * CW + cl;
+  const double acc = col < ncols ? strided_sum(part, rg, RG, nrows, ncols, col) : 0.0;
   sm[rg][cl] = acc;
   __syncthreads();
   if (rg == 0 && col < ncols) {
     double s = 0.0;
-    for (int i = 0; i < 16; ++i) s += sm[i][cl];
+    for (int i = 0; i < RG; ++i) s += sm[i][cl];
     if (map.kind == MAP_DOUBLE) {
       dout[col] = accumulate ? dout[col] + s : s;
     } else {
@@ -171,9 +189,7 @@ __global__ __launch_bounds__(256) void k_bn_stats_reduce(const float* __restrict
   const int i = (blockIdx.x * 4) / C, c0 = (blockIdx.x * 4) % C;
   const int ncols = NB * C * 2;
   const int gcol = (i * C + c0) * 2 + col;
-  double acc = 0.0;
-#pragma unroll 4
-  for (int r = rg; r < nrows; r += 32) acc += (double)part[(int64_t)r * ncols + gcol];
+  const double acc = strided_sum(part, rg, 32, nrows, ncols, gcol);
   sm[rg][col] = acc;
   __syncthreads();
   if (threadIdx.x < 4) {
