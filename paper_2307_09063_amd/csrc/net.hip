@@ -1393,7 +1393,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
       g_s2_variant[dtype][kind][b] = best;
       int n = std::snprintf(line, sizeof(line), "%d\t%d", kind, b);
       for (int v = 0; v < kS2Variants; ++v)
-        n += std::snprintf(line + n, sizeof(line) - n, "\t%.4f", cost[kind][b][v] / reps);
+        n += std::snprintf(line + n, sizeof(line) - n, "\t%.6f", cost[kind][b][v] / reps);
       std::snprintf(line + n, sizeof(line) - n, "\t%d\n", best);
       out += line;
     }

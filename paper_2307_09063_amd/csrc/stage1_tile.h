@@ -62,18 +62,41 @@ __device__ __forceinline__ int s1e(int px, int c) {
 
 // Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds, pixel
 // (row, col) of the haloed tile at LDS pixel row * (TW + 2 HALO) + col.
-template <class T, int C, int TH, int TW, int HALO>
+// BATCH: every load of the thread is issued before the first LDS write, so that their latencies
+// overlap (at the cost of the registers holding them; measured per kernel, see the callers).
+template <class T, int C, int TH, int TW, int HALO, bool BATCH = true>
 __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0, int x0, int h, int w, float* lds) {
-  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4;
-  for (int e = threadIdx.x; e < RH * RW * G; e += STDA_BLOCK) {
+  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4, N = RH * RW * G;
+  if constexpr (!BATCH) {
+    for (int e = threadIdx.x; e < N; e += STDA_BLOCK) {
+      const int q = e % G, px = e / G;
+      const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
+      float v[4];
+      if (y >= 0 && y < h && x >= 0 && x < w)
+        ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v);
+      else
+        zero4(v);
+      *reinterpret_cast<float4*>(lds + s1c<C, RH * RW>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+    return;
+  }
+  constexpr int K = (N + STDA_BLOCK - 1) / STDA_BLOCK;
+  float v[K][4];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * STDA_BLOCK;
     const int q = e % G, px = e / G;
     const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
-    float v[4];
-    if (y >= 0 && y < h && x >= 0 && x < w)
-      ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v);
+    if (e < N && y >= 0 && y < h && x >= 0 && x < w)
+      ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v[k]);
     else
-      zero4(v);
-    *reinterpret_cast<float4*>(lds + s1c<C, RH * RW>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
+      zero4(v[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = threadIdx.x + k * STDA_BLOCK;
+    if (e < N)
+      *reinterpret_cast<float4*>(lds + s1c<C, RH * RW>(e / G, e % G)) = make_float4(v[k][0], v[k][1], v[k][2], v[k][3]);
   }
 }
 
@@ -193,7 +216,7 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     __syncthreads();
-    load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
+    load_tile<T, C, TH, TW, 1, C != 32>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
     __syncthreads();
     // pt[p][o] = sum_c x[p][c] wp[c][o]; tile pixel p = r*TW + cc sits at padded (r + 1, cc + 1)
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
@@ -279,7 +302,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     __syncthreads();
-    load_tile<T, C, TH, TW, 1>(X, b, y0, x0, h, w, xt);
+    load_tile<T, C, TH, TW, 1, C != 16>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
     __syncthreads();
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },

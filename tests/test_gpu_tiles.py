@@ -129,8 +129,9 @@ def test_autotune(S, dtype):
     for (kind, b), (choice, ms) in res.items():
         assert 0 <= choice < n and len(ms) == n and all(t > 0 for t in ms)
         # the fastest, except that the default stays unless another is 3 % faster
-        assert ms[choice] == min(ms) or (choice == 0 and min(ms) >= 0.97 * ms[0])
-        assert choice == 0 or ms[choice] < 0.97 * ms[0]
+        # (times are printed to 1e-6 ms, hence the slack)
+        assert ms[choice] == min(ms) or (choice == 0 and min(ms) >= 0.97 * ms[0] - 1e-6)
+        assert choice == 0 or ms[choice] <= 0.97 * ms[0] + 1e-6
         assert S.tune_get(kind, dtype, b) == choice
     np.testing.assert_array_equal(wd.cpu().numpy(), w0)
     zt, _, _ = _forward(S, x, w0, r, S.EVAL, dtype)
