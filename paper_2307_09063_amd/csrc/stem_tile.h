@@ -70,16 +70,50 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
+    // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
+    // their latency overlaps them
+    constexpr int KI = (M * G + STDA_BLOCK - 1) / STDA_BLOCK;
+    float pg[KI][4], ps[KI][4];
+    if constexpr (MODE >= 2) {
+#pragma unroll
+      for (int k = 0; k < KI; ++k) {
+        const int e = threadIdx.x + k * STDA_BLOCK;
+        const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
+        if (e < M * G && y < H && x < W) {
+          const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
+          ld4(dS + off, pg[k]);
+          ld4(S + off, ps[k]);
+        } else {
+          zero4(pg[k]);
+          zero4(ps[k]);
+        }
+      }
+    }
     __syncthreads();
-    for (int q = threadIdx.x; q < 3 * XR * XC; q += STDA_BLOCK) {
-      const int c = q / (XR * XC), r = (q / XC) % XR, cc = q % XC;
-      const int y = y0 - 1 + r, x = x0 - 1 + cc;
-      xs[q] = (y >= 0 && y < H && x >= 0 && x < W) ? a.x[(((int64_t)b * 3 + c) * H + y) * W + x] : 0.f;
+    {
+      // the three planes of the tile plus halo; all loads issued before the LDS writes
+      constexpr int NX = 3 * XR * XC, KX = (NX + STDA_BLOCK - 1) / STDA_BLOCK;
+      float xv[KX];
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        const int q = threadIdx.x + k * STDA_BLOCK;
+        const int c = q / (XR * XC), r = (q / XC) % XR, cc = q % XC;
+        const int y = y0 - 1 + r, x = x0 - 1 + cc;
+        xv[k] = (q < NX && y >= 0 && y < H && x >= 0 && x < W) ? a.x[(((int64_t)b * 3 + c) * H + y) * W + x] : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < KX; ++k) {
+        const int q = threadIdx.x + k * STDA_BLOCK;
+        if (q < NX) xs[q] = xv[k];
+      }
     }
     __syncthreads();
     lds_gemm<M, C, 28>(im2col, [&](int kk, int n) { return wk[n * 28 + kk]; }, tt, PS);
     __syncthreads();
-    for (int e = threadIdx.x; e < M * G; e += STDA_BLOCK) {
+#pragma unroll
+    for (int k = 0; k < KI; ++k) {
+      const int e = threadIdx.x + k * STDA_BLOCK;
+      if (e >= M * G) break;
       const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
       const bool in = y < H && x < W;
       const float4 tq = *reinterpret_cast<const float4*>(tt + px * PS + c0);
@@ -99,14 +133,9 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
         for (int j = 0; j < 4; ++j) o[j] = fmaxf(t[j] * sc[j] + sh[j], 0.f);
         st4(out + off, o);
       } else {
-        float g[4], s[4], o[4];
-        if (in) {
-          ld4(dS + off, g);
-          ld4(S + off, s);
-        } else {
-          zero4(g);
-          zero4(s);
-        }
+        const float* g = pg[k];
+        const float* s = ps[k];
+        float o[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float dm = s[j] > 0.f ? g[j] : 0.f;
