@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
   constexpr int XN = (TH + 4) * XW, DN = (TH + 2) * DWd;  // pixels of the x and dD tiles
   constexpr int XT = S1Lds<C, XN>::SIZE;
-  static_assert(XT >= 4 * 9 * C + 9 * C, "reduction scratch aliases the x tile");
+  static_assert(XT >= 4 * 9 * C + 9 * C && XT >= 4 * 256, "reduction scratch aliases the x tile");
   __shared__ float xt[XT];
   __shared__ float ddt[S1Lds<C, DN>::SIZE];
   __shared__ float dpt[S1Lds<C, M>::SIZE];
@@ -473,16 +473,26 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
     lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
-    // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles)
-#pragma unroll
-    for (int u = 0; u < NTW; ++u) {
-      const int t = wave + 4 * u;
-      if (t < NT) {
-        const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
+    // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles);
+    // with a single 16 x 16 tile (16 channels) the 4 waves take a quarter of the pixels each
+    if constexpr (NT == 1) {
+      constexpr int MQ = M / 4;
+      const int pb = wave * MQ;
 #pragma unroll 4
-        for (int p = 0; p < M; p += 4)
-          pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(p + lg), m0 + li)], dpt[s1e<C, M>(p + lg, n0 + li)],
-                                                          pwacc[u], 0, 0, 0);
+      for (int p = 0; p < MQ; p += 4)
+        pwacc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(pb + p + lg), li)], dpt[s1e<C, M>(pb + p + lg, li)],
+                                                        pwacc[0], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int u = 0; u < NTW; ++u) {
+        const int t = wave + 4 * u;
+        if (t < NT) {
+          const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
+#pragma unroll 4
+          for (int p = 0; p < M; p += 4)
+            pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(p + lg), m0 + li)],
+                                                            dpt[s1e<C, M>(p + lg, n0 + li)], pwacc[u], 0, 0, 0);
+        }
       }
     }
     __syncthreads();
@@ -529,6 +539,16 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   }
   // pointwise gradient tile (m0, n0): lane holds D[4 lg + r][li] -> (c = m0 + 4 lg + r, o = n0 + li)
   float* pw = pwpart + (int64_t)blockIdx.x * C * C;
+  if constexpr (NT == 1) {
+    // the four waves' partial tiles, summed in wave order
+    __syncthreads();  // the reduction scratch above is no longer read
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sm[wave * 256 + (4 * lg + r) * 16 + li] = pwacc[0][r];
+    __syncthreads();
+    const int q = threadIdx.x;  // 256 = 16 x 16 entries
+    pw[q] = ((sm[q] + sm[256 + q]) + sm[512 + q]) + sm[768 + q];
+    return;
+  }
   for (int t = 0; t < NT; ++t) {
     const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
 #pragma unroll
