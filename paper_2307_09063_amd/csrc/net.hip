@@ -503,7 +503,7 @@ int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* s
   if (v == 3) return launch_gather<T, OP, K, N, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk);
   if constexpr (OP == OP_ENC_FWD && K == 16) {
     if constexpr (BF) return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2W(32, 16, 16) : S2V(32, 8, 32);
-    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(16, 8, 16) : S2V(32, 8, 16);
+    else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2W(32, 8, 16) : S2V(32, 8, 16);
   } else if constexpr (OP == OP_ENC_FWD) {
     if constexpr (BF) return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2W(32, 8, 16) : S2V(64, 8, 16);
     else return v == 1 ? S2V(64, 8, 8) : v == 2 ? S2W(16, 8, 16) : S2V(32, 8, 8);
@@ -518,7 +518,7 @@ int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* s
     else return v == 1 ? S2V(16, 16, 32) : v == 2 ? S2W(16, 32, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_ENC_DGRAD) {
     if constexpr (BF) return v == 1 ? S2V(16, 16, 16) : v == 2 ? S2V(32, 16, 32) : S2V(32, 16, 16);
-    else return v == 1 ? S2V(32, 16, 16) : v == 2 ? S2V(16, 16, 32) : S2V(16, 16, 16);
+    else return v == 1 ? S2V(32, 16, 16) : v == 2 ? S2W(16, 16, 32) : S2V(16, 16, 16);
   } else if constexpr (OP == OP_DEC_DGRAD && K == 32) {
     if constexpr (BF) return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2V(32, 8, 16) : S2V(64, 8, 8);
     else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2W(16, 8, 16) : S2V(16, 8, 8);
