@@ -235,6 +235,8 @@ int stda_forward_graph_create(const stda_segment* segs /*host*/, int n_segs, con
                               size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int mode,
                               hipStream_t stream, stda_graph* graph /*host out*/);
 int stda_graph_launch(stda_graph graph, hipStream_t stream);
+/* Frees the graph and its handle (NULL is a no-op); STDA_E_HIP if HIP reports an error, the
+ * handle is freed in any case. */
 int stda_graph_destroy(stda_graph graph);
 
 /* ------------------------------------------------------------------ measurement hooks */

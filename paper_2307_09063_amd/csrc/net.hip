@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -74,10 +75,11 @@ struct ProfScope {
     p.used += 2;
     if (p.evtag.size() < p.used / 2) p.evtag.resize(p.used / 2);
     p.evtag[idx / 2] = tag;
-    hipEventRecord(p.ev[idx], st);
+    // a failed record only leaves this measurement out (stda_profile_read reports the error)
+    (void)hipEventRecord(p.ev[idx], st);
   }
   ~ProfScope() {
-    if (idx >= 0) hipEventRecord(prof().ev[idx + 1], st);
+    if (idx >= 0) (void)hipEventRecord(prof().ev[idx + 1], st);
   }
 };
 const char* const kBlockName[4] = {"enc0", "enc1", "dec0", "dec1"};
@@ -101,8 +103,8 @@ int grid_for(int64_t items, int cap = 2048) {
 namespace stda {
 
 // ------------------------------------------------------------------- parameter table
-int g_arch = 0;  // STDA_ARCH_* bits, see stda_set_arch
-int current_arch() { return g_arch; }
+std::atomic<int> g_arch{0};  // STDA_ARCH_* bits, see stda_set_arch
+int current_arch() { return g_arch.load(std::memory_order_relaxed); }
 
 static std::vector<ParamEntry> build_param_table(int arch) {
   std::vector<ParamEntry> t;
@@ -562,8 +564,7 @@ int head_grid(int n, int H, int W) {
 // Column sums of per-block BN partials followed by the statistics finalize.
 template <class T>
 int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* const* stats_out,
-                float* const* running, float* running_base) {
-  (void)running_base;
+                float* const* running) {
   float* part = c.template scr<float>(c.P->ws_part);
   BnOut o{};
   for (int i = 0; i < NB; ++i) {
@@ -608,22 +609,18 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
     KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
-    if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro, running)) return r;
+    if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro)) return r;
   }
   KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win));
   // stage 2: main (with statistics) and residual
-  const float* dl = c.dl;
-  const int g2 = grid_for(Pout * (COUT / 4));
   constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
-  (void)dl;
-  (void)g2;
   if (stats_pass) {
     int nb = 0;
     if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
       return r;
     float* so[1] = {c.stats(bo.bn_main)};
     float* ro[1] = {running + bo.bn_main};
-    if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro, running)) return r;
+    if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro)) return r;
   } else {
     if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
                                                        nullptr))
@@ -680,7 +677,7 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
     KLAUNCH("stem_stats", k_stem_tile<T, 0><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, nullptr, S.n, S.H, S.W));
     float* so[1] = {c.stats(0)};
     float* ro[1] = {running};
-    if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro, running)) return r;
+    if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro)) return r;
   }
   KLAUNCH("stem_apply", k_stem_tile<T, 1><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
@@ -999,8 +996,6 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
                                                             c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw));
   // dense adjoints: dX1 from dT, dXr from dY
   constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
-  const int gd = grid_for(Pin * (CIN / 4));
-  (void)gd;
   if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
     return r;
   const bool res3 = DEC && (c.P->arch & STDA_ARCH_RES3);
@@ -1267,9 +1262,17 @@ int stda_graph_launch(stda_graph g, hipStream_t stream) {
 
 int stda_graph_destroy(stda_graph g) {
   if (!g) return STDA_OK;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->graph) hipGraphDestroy(g->graph);
+  hipError_t e = hipSuccess;
+  if (g->exec) e = hipGraphExecDestroy(g->exec);
+  if (g->graph) {
+    const hipError_t e2 = hipGraphDestroy(g->graph);
+    if (e == hipSuccess) e = e2;
+  }
   delete g;
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return STDA_E_HIP;
+  }
   return STDA_OK;
 }
 
@@ -1447,11 +1450,11 @@ size_t stda_running_count(void) { return (size_t)net_offsets(0).running_count; }
 
 int stda_set_arch(int flags) {
   if (flags & ~(STDA_ARCH_RES3 | STDA_ARCH_SIGMOID | STDA_ARCH_PW_DW)) return STDA_E_INVALID;
-  g_arch = flags;
+  g_arch.store(flags, std::memory_order_relaxed);
   return STDA_OK;
 }
 
-int stda_get_arch(void) { return g_arch; }
+int stda_get_arch(void) { return current_arch(); }
 
 int stda_workspace_size(const stda_segment* segs, int n_segs, int dtype, int mode, int recompute,
                         size_t* saved_bytes, size_t* ws_bytes) {

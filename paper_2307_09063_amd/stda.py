@@ -292,8 +292,8 @@ class TrainStepGraph:
 
     def close(self):
         if self.handle:
-            _lib.stda_graph_destroy(self.handle)
-            self.handle = None
+            h, self.handle = self.handle, None
+            _check(_lib.stda_graph_destroy(h), 'stda_graph_destroy')
 
     def __del__(self):
         try:
@@ -322,8 +322,8 @@ class ForwardGraph:
 
     def close(self):
         if self.handle:
-            _lib.stda_graph_destroy(self.handle)
-            self.handle = None
+            h, self.handle = self.handle, None
+            _check(_lib.stda_graph_destroy(h), 'stda_graph_destroy')
 
     def __del__(self):
         try:
