@@ -52,10 +52,16 @@ def test_bf16_train_forward_backward(case):
     assert U.rel_l2(rd_.cpu().numpy(), rr) < TOL
     errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
     flat = U.rel_l2(dw.cpu().numpy(), gr)
-    print(f'bf16 {case}: z {U.rel_l2(zc, zr):.2e} grad flat {flat:.2e} dx {U.rel_l2(dx.cpu().numpy(), dxr):.2e} '
+    print(f'bf16 {case}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e}; grad flat {flat:.2e} '
+          f'dx {U.rel_l2(dx.cpu().numpy(), dxr):.2e} '
           f'worst ' + ' '.join(f'{k}:{v:.1e}' for k, v in sorted(errs.items(), key=lambda t: -t[1])[:4]),
           file=sys.stderr, flush=True)
     assert flat < 0.25
+
+
+def _maxabs(a, b):
+    """max |a - b| / max |b| (reported next to rel-L2)."""
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 def _sinr_deltas(zc, zr, meta, H, W):
@@ -86,7 +92,8 @@ def test_bf16_sinr_delta(mode):
     zr, _, _ = net.forward(w, r, x, mode)
     zc = z.cpu().numpy()
     ds = _sinr_deltas(zc, zr, meta, H, W)
-    print(f'bf16 {mode}: z {U.rel_l2(zc, zr):.2e} delta SINR dB ' + ' '.join(f'{d:+.4f}' for d in ds),
+    print(f'bf16 {mode}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e}; mean |delta SINR| '
+          f'{np.mean(np.abs(ds)):.4f} dB; per clip ' + ' '.join(f'{d:+.4f}' for d in ds),
           file=sys.stderr, flush=True)
     assert U.rel_l2(zc, zr) < TOL
     assert np.mean(np.abs(ds)) <= 0.05, ds
