@@ -910,9 +910,17 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
     }
   }
 #define WGVV(TH_, TW_) launch_wgrad_v<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
-  // 0, 1: vector-operand kernel; 2: scalar-operand kernel
-  if constexpr (SMALL) return v == 1 ? WGVV(8, 8) : v == 2 ? WGV(8, 16) : WGVV(8, 16);
-  else return v == 1 ? WGVV(4, 8) : v == 2 ? WGV(8, 8) : WGVV(8, 8);
+  // 0, 1: vector-operand kernel; 2: scalar-operand kernel (BF16) or the vector-operand kernel on
+  // smaller tiles (FP32)
+  constexpr bool BF = sizeof(T) == 2;
+  if (v == 2) {
+    if constexpr (BF && SMALL) return WGV(8, 16);
+    else if constexpr (BF) return WGV(8, 8);
+    else if constexpr (SMALL) return WGVV(4, 8);
+    else return WGVV(4, 4);
+  }
+  if constexpr (SMALL) return v == 1 ? WGVV(8, 8) : WGVV(8, 16);
+  else return v == 1 ? WGVV(4, 8) : WGVV(8, 8);
 #undef WGV
 #undef WGVV
 }
