@@ -204,96 +204,4 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
 
 }  // namespace stda
 
-namespace stda {
 
-// Weight gradients on the matrix cores: dW[k][n] = sum over pixels p of A(p)[k] * B(p)[n], the
-// reduction over pixels being the MFMA's inner dimension.  A block covers one (16 TK) x (16 TN)
-// block of dW for one contiguous range of pixels (grid.y splits the pixels); its 4 waves take
-// quarters of that range and are summed in LDS in a fixed order.  Lane (i, g): row TK*i + t of
-// the block is row i of 16-row tile t (t < TK), read from the 4-aligned group the loader returns
-// (likewise columns with TN), so with TK = 4 one 16-byte load feeds four tiles.  FP32: one pixel
-// per lane group per MFMA (16x16x4).  BF16: four pixels per lane group per MFMA (16x16x16),
-// transposed in registers.  part[split][k * N + n] holds the real (unpadded) k < K, n < N.
-template <class L, bool BF, int TK, int TN>
-__global__ __launch_bounds__(256) void k_wgrad_mfma(L ld, float* __restrict__ part) {
-  constexpr int K = L::K, N = L::N;
-  constexpr int BK = 16 * TK, BN = 16 * TN;
-  constexpr int NB = (N + BN - 1) / BN;
-  constexpr int PS = BF ? 16 : 4;  // pixels per MFMA step
-  __shared__ float red[BK * BN];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i = lane & 15, g = lane >> 4;
-  const int kb = blockIdx.x / NB, nb = blockIdx.x % NB;
-  const int kr = kb * BK + TK * i, nr = nb * BN + TN * i;  // first row / column of this lane
-  const int kq = kr & ~3, ke = kr & 3, nq = nr & ~3, ne = nr & 3;
-  const bool kv = kr < K, nv = nr < N;
-  const int64_t P = ld.npix();
-  const int64_t nsplit = (int64_t)gridDim.y * 4;
-  const int64_t steps = (P + PS - 1) / PS;
-  const int64_t per = (steps + nsplit - 1) / nsplit;
-  const int64_t s0 = ((int64_t)blockIdx.y * 4 + wave) * per;
-  const int64_t s1 = s0 + per < steps ? s0 + per : steps;
-  floatx4 acc[TK][TN];
-#pragma unroll
-  for (int t = 0; t < TK; ++t)
-#pragma unroll
-    for (int u = 0; u < TN; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t st = s0; st < s1; ++st) {
-    if (!BF) {
-      const int64_t p = st * 4 + g;
-      float a[4], b[4];
-      if (p < P && kv) ld.a4(p, kq, a); else zero4(a);
-      if (p < P && nv) ld.b4(p, nq, b); else zero4(b);
-#pragma unroll
-      for (int t = 0; t < TK; ++t)
-#pragma unroll
-        for (int u = 0; u < TN; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ke + t], b[ne + u], acc[t][u], 0, 0, 0);
-    } else {
-      // pixels st*16 + 4g + e, e = 0..3; values are BF16-exact, so truncation packs them exactly
-      float a[4][4], b[4][4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t p = st * 16 + 4 * g + e;
-        if (p < P && kv) ld.a4(p, kq, a[e]); else zero4(a[e]);
-        if (p < P && nv) ld.b4(p, nq, b[e]); else zero4(b[e]);
-      }
-      shortx4 av[TK], bv[TN];
-#pragma unroll
-      for (int t = 0; t < TK; ++t)
-        av[t] = shortx4{(short)(__float_as_uint(a[0][ke + t]) >> 16), (short)(__float_as_uint(a[1][ke + t]) >> 16),
-                        (short)(__float_as_uint(a[2][ke + t]) >> 16), (short)(__float_as_uint(a[3][ke + t]) >> 16)};
-#pragma unroll
-      for (int u = 0; u < TN; ++u)
-        bv[u] = shortx4{(short)(__float_as_uint(b[0][ne + u]) >> 16), (short)(__float_as_uint(b[1][ne + u]) >> 16),
-                        (short)(__float_as_uint(b[2][ne + u]) >> 16), (short)(__float_as_uint(b[3][ne + u]) >> 16)};
-#pragma unroll
-      for (int t = 0; t < TK; ++t)
-#pragma unroll
-        for (int u = 0; u < TN; ++u)
-          acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[t], bv[u], acc[t][u], 0, 0, 0);
-    }
-  }
-  // tile (t, u), lane (i', g'): D[4g' + r][i'] -> block row TK (4g' + r) + t, column TN i' + u
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int t = 0; t < TK; ++t)
-#pragma unroll
-        for (int u = 0; u < TN; ++u)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = TK * (4 * g + r) + t, col = TN * i + u;
-            const float v = acc[t][u][r];
-            red[row * BN + col] = w == 0 ? v : red[row * BN + col] + v;
-          }
-    }
-    __syncthreads();
-  }
-  for (int q = threadIdx.x; q < BK * BN; q += STDA_BLOCK) {
-    const int row = q / BN, col = q % BN;
-    const int k = kb * BK + row, n = nb * BN + col;
-    if (k < K && n < N) part[(int64_t)blockIdx.y * K * N + (int64_t)k * N + n] = red[q];
-  }
-}
-
-}  // namespace stda

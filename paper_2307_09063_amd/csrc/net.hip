@@ -453,11 +453,11 @@ int tiles_for(int64_t hw, int G) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
 }
 
-// Tiling variant of each tunable launch, [dtype][kind][block]: kinds 0 forward, 1 input gradient,
-// 2 weight gradient of the dense stage-2 layers (0..2 the LDS-tiled kernels with the tilings
-// listed in launch_s2_variant and launch_wgrad, 3 the register-gather kernels), 3 the fused
-// stage-1 adjoint (tilings listed in launch_s1b).  Set by stda_tune_set (the autotuner); 0 by
-// default.
+// Tiling variant of each tunable launch, [dtype][kind][block]: kinds 0 forward, 1 input gradient
+// of the dense stage-2 layers (0..2 the LDS-tiled kernel with the tilings listed in
+// launch_s2_variant, 3 the register-gather kernel), 2 their weight gradient (tilings listed in
+// launch_wgrad), 3 the fused stage-1 adjoint (tilings listed in launch_s1b).  Set by
+// stda_tune_set (the autotuner); 0 by default.
 constexpr int kS2Variants = 4;
 constexpr int kTuneKinds = 4;
 constexpr double kTuneMargin = 0.03;
@@ -829,31 +829,9 @@ int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* d
   return STDA_OK;
 }
 
-// Weight gradient on the matrix cores; the pixel range is split so that about 1024 blocks run,
-// and the per-split partials are summed in FP64 into the destination.
-template <int D>
-constexpr int wg_tiles() {
-  return D >= 64 ? 4 : D >= 32 ? 2 : 1;
-}
-
-template <class T, class L>
-int run_wgrad(const Ctx<T>& c, const std::string& tag, const L& ld, int64_t npix, float* dst, ColMap map, int acc) {
-  constexpr int TK = wg_tiles<L::K>(), TN = wg_tiles<L::N>();
-  constexpr int KB = (L::K + 16 * TK - 1) / (16 * TK), NB = (L::N + 16 * TN - 1) / (16 * TN);
-  constexpr bool BF = L::kBF16Operands;
-  float* wpart = c.template scr<float>(c.P->ws_wpart);
-  const int64_t steps = (npix + (BF ? 15 : 3)) / (BF ? 16 : 4);
-  int64_t splits = std::max<int64_t>(1, 1024 / (KB * NB));
-  splits = std::min<int64_t>(splits, std::max<int64_t>(1, steps / 64));  // >= 16 steps per wave
-  splits = std::min<int64_t>(splits, kMaxWgradGrid);
-  KLAUNCH(tag, k_wgrad_mfma<L, BF, TK, TN><<<dim3(KB * NB, (int)splits), 256, 0, c.st>>>(ld, wpart));
-  return colsum_to(c, wpart, (int)splits, L::K * L::N, dst, map, acc,
-                   tag.rfind("wgrad_", 0) == 0 ? "wgrad_sum" + tag.substr(5) : std::string("colsum"));
-}
-
-// Stage-2 weight gradient of block `blk` on LDS tiles (or, variant 3, the register-gather
-// kernel); encoder: Lo = output gradient on the hout x wout grid, Hi = layer input; decoder:
-// Lo = layer input on the hin x win grid, Hi = output gradient.
+// Stage-2 weight gradient of block `blk` on LDS tiles; encoder: Lo = output gradient on the
+// hout x wout grid, Hi = layer input; decoder: Lo = layer input on the hin x win grid, Hi = output
+// gradient.
 // Workgroups of a tiled weight-gradient launch: enough to keep 4 per CU where the partial rows
 // (one per workgroup, `cols` floats each) fit the partial buffer, at least 256.
 int64_t wgrad_rows(int64_t cols) {
@@ -900,19 +878,14 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
   const ColMap map{DEC ? MAP_DEC_S2 : MAP_ENC_S2, CIN, COUT};
   constexpr bool SMALL = CL * CH <= 512;  // 16 x 32 channel pairs: larger tiles fit
 #define WGV(TH_, TW_) launch_wgrad_cfg<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
-  if (v == 3) {
-    if constexpr (DEC) {
-      WgDecS2<T, CIN, COUT> ld{x, d, n, hin, win};
-      return run_wgrad(c, tag, ld, (int64_t)n * hin * win, dst, map, acc);
-    } else {
-      WgEncS2<T, CIN, COUT> ld{x, d, n, hin / 2, win / 2};
-      return run_wgrad(c, tag, ld, (int64_t)n * (hin / 2) * (win / 2), dst, map, acc);
-    }
-  }
 #define WGVV(TH_, TW_) launch_wgrad_v<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
-  // 0, 1: vector-operand kernel; 2: scalar-operand kernel (BF16) or the vector-operand kernel on
+  // 0, 1, 3: vector-operand kernel; 2: scalar-operand kernel (BF16) or the vector-operand kernel on
   // smaller tiles (FP32)
   constexpr bool BF = sizeof(T) == 2;
+  if (v == 3) {
+    if constexpr (BF) return WGVV(4, 8);
+    else return WGVV(2, 8);
+  }
   if (v == 2) {
     if constexpr (BF && SMALL) return WGV(8, 16);
     else if constexpr (BF) return WGV(8, 8);

@@ -6,50 +6,6 @@
 
 namespace stda {
 
-// ------------------------------------------------ stage-2 weight-gradient operand loaders
-// (register-gather weight-gradient kernel k_wgrad_mfma, the autotuner's fourth candidate)
-// Conv3x3-s2-p1 weight gradient: p over output pixels (ho x wo); A = im2col of the input
-// (k = tap*CIN + c), B = output gradient (n = o).
-template <class T, int CIN, int COUT>
-struct WgEncS2 {
-  static constexpr int K = 9 * CIN, N = COUT;
-  static constexpr bool kBF16Operands = std::is_same<T, bf16>::value;
-  const T* X;
-  const T* D;
-  int B, ho, wo;
-  __device__ int64_t npix() const { return (int64_t)B * ho * wo; }
-  __device__ void a4(int64_t p, int k, float v[4]) const {
-    int b, y, x;
-    pix3(p, ho, wo, b, y, x);
-    const int tap = k / CIN, c = k % CIN;
-    const int iy = 2 * y - 1 + tap / 3, ix = 2 * x - 1 + tap % 3;
-    if (iy < 0 || iy >= 2 * ho || ix < 0 || ix >= 2 * wo) { zero4(v); return; }
-    ld4(X + (((int64_t)b * 2 * ho + iy) * 2 * wo + ix) * CIN + c, v);
-  }
-  __device__ void b4(int64_t p, int n, float v[4]) const { ld4(D + p * COUT + n, v); }
-};
-
-// DeConv4x4-s2-p1 weight gradient: p over input pixels (hi x wi); A = input (k = c),
-// B = gathered output gradient (n = tap*COUT + o) at (2i - 1 + ky, 2j - 1 + kx).
-template <class T, int CIN, int COUT>
-struct WgDecS2 {
-  static constexpr int K = CIN, N = 16 * COUT;
-  static constexpr bool kBF16Operands = std::is_same<T, bf16>::value;
-  const T* X;
-  const T* D;
-  int B, hi, wi;
-  __device__ int64_t npix() const { return (int64_t)B * hi * wi; }
-  __device__ void a4(int64_t p, int k, float v[4]) const { ld4(X + p * CIN + k, v); }
-  __device__ void b4(int64_t p, int n, float v[4]) const {
-    int b, i, j;
-    pix3(p, hi, wi, b, i, j);
-    const int tap = n / COUT, o = n % COUT;
-    const int yy = 2 * i - 1 + tap / 4, xx = 2 * j - 1 + tap % 4;
-    if (yy < 0 || yy >= 2 * hi || xx < 0 || xx >= 2 * wi) { zero4(v); return; }
-    ld4(D + (((int64_t)b * 2 * hi + yy) * 2 * wi + xx) * COUT + o, v);
-  }
-};
-
 // --------------------------------------------------------------------- ECA adjoint
 // gap-like partials of sum_hw G * Y per (clip, tile, channel).
 template <class T, int C>
