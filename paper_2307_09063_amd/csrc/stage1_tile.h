@@ -496,64 +496,100 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       }
     }
     __syncthreads();
-    // B2: dX on the tile, two horizontally adjacent pixels per item (their 3 x 3 neighbourhoods
-    // of dD share 6 of the 12 values read)
-    static_assert(TW % 2 == 0, "pixel pairs inside a tile row");
-    for (int e = threadIdx.x; e < (M / 2) * G; e += STDA_BLOCK) {
-      const int px = 2 * (e / G), r = px / TW, cc = px % TW;  // pixels px, px + 1 of tile row r
-      const int y = y0 + r, x = x0 + cc;
-      if (y >= h || x >= w) continue;
-      const bool second = x + 1 < w;
-      const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-      float acc[2][4];
-      const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
+    // B2: dX on the tile.  C < 64: two horizontally adjacent pixels per item, whose 3 x 3
+    // neighbourhoods of dD share 6 of the 12 values read; C = 64 keeps one pixel per item, since the
+    // pair does not fit its register budget.
+    if constexpr (C < 64) {
+      static_assert(TW % 2 == 0, "pixel pairs inside a tile row");
+      for (int e = threadIdx.x; e < (M / 2) * G; e += STDA_BLOCK) {
+        const int px = 2 * (e / G), r = px / TW, cc = px % TW;  // pixels px, px + 1 of tile row r
+        const int y = y0 + r, x = x0 + cc;
+        if (y >= h || x >= w) continue;
+        const bool second = x + 1 < w;
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        float acc[2][4];
+        const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        if (s == 1 && !second) break;
-        float rr[4];
-        ld4(dXr + off + s * C, rr);
-        const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px + s), c0 >> 2));
-        const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px + s, c0 >> 2));
-        const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px + s, c0 >> 2));
+        for (int s = 0; s < 2; ++s) {
+          if (s == 1 && !second) break;
+          float rr[4];
+          ld4(dXr + off + s * C, rr);
+          const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px + s), c0 >> 2));
+          const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px + s, c0 >> 2));
+          const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px + s, c0 >> 2));
+          const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[s][j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
+          if (SKIP) {
+            float sv[4];
+            ld4(skip + off + s * C, sv);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[s][j] += sv[j];
+          }
+        }
+        // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map.
+        // Row dy of the pair reads dD tile columns cc .. cc + 3 (k = 0..3); the first pixel takes
+        // column k with tap dx = 1 - k, the second with dx = 2 - k (taps in the order t = 0..8).
+#pragma unroll
+        for (int dyi = 0; dyi < 3; ++dyi) {
+          const int dy = dyi - 1;
+          float4 col[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            col[k] = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + k, c0 >> 2));
+#pragma unroll
+          for (int k = 2; k >= 0; --k) {
+            const int t = dyi * 3 + 2 - k;
+            acc[0][0] += wr[t][0] * col[k].x;
+            acc[0][1] += wr[t][1] * col[k].y;
+            acc[0][2] += wr[t][2] * col[k].z;
+            acc[0][3] += wr[t][3] * col[k].w;
+          }
+#pragma unroll
+          for (int k = 3; k >= 1; --k) {
+            const int t = dyi * 3 + 3 - k;
+            acc[1][0] += wr[t][0] * col[k].x;
+            acc[1][1] += wr[t][1] * col[k].y;
+            acc[1][2] += wr[t][2] * col[k].z;
+            acc[1][3] += wr[t][3] * col[k].w;
+          }
+        }
+        st4(dX + off, acc[0]);
+        if (second) st4(dX + off + C, acc[1]);
+      }
+    } else {
+      for (int e = threadIdx.x; e < M * G; e += STDA_BLOCK) {
+        const int px = e / G, r = px / TW, cc = px % TW;
+        const int y = y0 + r, x = x0 + cc;
+        if (y >= h || x >= w) continue;
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        float rr[4], acc[4];
+        ld4(dXr + off, rr);
+        const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px), c0 >> 2));
+        const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px, c0 >> 2));
+        const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px, c0 >> 2));
         const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
+        const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[s][j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
+        for (int j = 0; j < 4; ++j) acc[j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
         if (SKIP) {
           float sv[4];
-          ld4(skip + off + s * C, sv);
+          ld4(skip + off, sv);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[s][j] += sv[j];
+          for (int j = 0; j < 4; ++j) acc[j] += sv[j];
         }
+        // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          const int dy = t / 3 - 1, dx = t % 3 - 1;
+          const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
+          acc[0] += wr[t][0] * v.x;
+          acc[1] += wr[t][1] * v.y;
+          acc[2] += wr[t][2] * v.z;
+          acc[3] += wr[t][3] * v.w;
+        }
+        st4(dX + off, acc);
       }
-      // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map.
-      // Row dy of the pair reads dD tile columns cc .. cc + 3 (k = 0..3); the first pixel takes
-      // column k with tap dx = 1 - k, the second with dx = 2 - k (taps in the order t = 0..8).
-#pragma unroll
-      for (int dyi = 0; dyi < 3; ++dyi) {
-        const int dy = dyi - 1;
-        float4 col[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          col[k] = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + k, c0 >> 2));
-#pragma unroll
-        for (int k = 2; k >= 0; --k) {
-          const int t = dyi * 3 + 2 - k;
-          acc[0][0] += wr[t][0] * col[k].x;
-          acc[0][1] += wr[t][1] * col[k].y;
-          acc[0][2] += wr[t][2] * col[k].z;
-          acc[0][3] += wr[t][3] * col[k].w;
-        }
-#pragma unroll
-        for (int k = 3; k >= 1; --k) {
-          const int t = dyi * 3 + 3 - k;
-          acc[1][0] += wr[t][0] * col[k].x;
-          acc[1][1] += wr[t][1] * col[k].y;
-          acc[1][2] += wr[t][2] * col[k].z;
-          acc[1][3] += wr[t][3] * col[k].w;
-        }
-      }
-      st4(dX + off, acc[0]);
-      if (second) st4(dX + off + C, acc[1]);
     }
   }
   __syncthreads();
