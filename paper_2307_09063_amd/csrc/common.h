@@ -18,12 +18,15 @@ __device__ __forceinline__ float to_f(bf16 x) { return __uint_as_float((uint32_t
 
 template <class T> __device__ __forceinline__ T from_f(float x);
 template <> __device__ __forceinline__ float from_f<float>(float x) { return x; }
-// Round to nearest even; NaN stays a quiet NaN.
-template <> __device__ __forceinline__ bf16 from_f<bf16>(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)0x7fc0};
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return bf16{(uint16_t)(u >> 16)};
+// Round to nearest even; NaN stays a quiet NaN.  gfx950 converts in hardware (v_cvt_pk_bf16_f32,
+// two values per instruction); its results equal the bitwise round-to-nearest-even on every
+// non-NaN FP32 pattern.
+typedef __bf16 bf16x2_hw __attribute__((ext_vector_type(2)));
+typedef float f32x2_hw __attribute__((ext_vector_type(2)));
+template <> __device__ __forceinline__ bf16 from_f<bf16>(float x) { return bf16{__builtin_bit_cast(uint16_t, (__bf16)x)}; }
+// a in the low half, b in the high half
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_hw{a, b}, bf16x2_hw));
 }
 __device__ __forceinline__ float round_bf16(float x) { return to_f(from_f<bf16>(x)); }
 // The value a store of type T keeps.
@@ -46,8 +49,8 @@ __device__ __forceinline__ void st4(float* p, const float v[4]) {
 }
 __device__ __forceinline__ void st4(bf16* p, const float v[4]) {
   uint2 q;
-  q.x = (uint32_t)from_f<bf16>(v[0]).v | ((uint32_t)from_f<bf16>(v[1]).v << 16);
-  q.y = (uint32_t)from_f<bf16>(v[2]).v | ((uint32_t)from_f<bf16>(v[3]).v << 16);
+  q.x = pack_bf16x2(v[0], v[1]);
+  q.y = pack_bf16x2(v[2], v[3]);
   *reinterpret_cast<uint2*>(p) = q;
 }
 __device__ __forceinline__ void zero4(float v[4]) { v[0] = v[1] = v[2] = v[3] = 0.f; }
