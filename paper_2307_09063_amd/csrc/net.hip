@@ -821,8 +821,10 @@ namespace {
 template <class T>
 int colsum_to(const Ctx<T>& c, const float* part, int nrows, int ncols, float* dst, ColMap map, int acc,
               const std::string& tag = "colsum") {
-  if (ncols >= 4096) {
+  if (ncols >= 16384) {
     KLAUNCH(tag, k_colsum<64><<<(ncols + 63) / 64, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
+  } else if (ncols >= 4096) {  // too few 64-column blocks to fill the chip: more row groups each
+    KLAUNCH(tag, k_colsum<64, 1024><<<(ncols + 63) / 64, 1024, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
   } else {
     KLAUNCH(tag, k_colsum<16><<<(ncols + 15) / 16, 256, 0, c.st>>>(part, nrows, ncols, nullptr, dst, map, acc));
   }
@@ -1028,8 +1030,11 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
     return r;
   const ColMap pwmap = (c.P->arch & STDA_ARCH_PW_DW) ? ColMap{MAP_PW_DIAG, CIN, 0}
                                                       : ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0};
-  if (int r = colsum_to(c, pwpart, rows, CIN * CIN, dw + bo.pw_w, pwmap, acc, tagk("s1_bwd_fused_sum", k))) return r;
-  return colsum_to(c, part, rows, 9 * CIN, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, acc, tagk("s1_bwd_fused_sum", k));
+  // both weight gradients of stage 1 (pointwise, depthwise) in one reduction launch
+  const ColJob ja{pwpart, dw + bo.pw_w, pwmap, rows, CIN * CIN, (CIN * CIN + 15) / 16};
+  const ColJob jb{part, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, rows, 9 * CIN, (9 * CIN + 15) / 16};
+  KLAUNCH(tagk("s1_bwd_fused_sum", k), k_colsum2<<<ja.nblk + jb.nblk, 256, 0, c.st>>>(ja, jb, acc));
+  return STDA_OK;
 }
 
 template <class T>

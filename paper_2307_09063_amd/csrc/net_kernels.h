@@ -147,17 +147,19 @@ __device__ __forceinline__ double strided_sum(const float* __restrict__ part, in
   return acc;
 }
 
-// Column sums of part[nrows][ncols] in FP64 (fixed order): a block takes CW consecutive columns
-// and 256 / CW row groups; wide partial arrays use CW = 64 (a wave reads 256 contiguous bytes of
-// a row), narrow ones CW = 16 (more row groups in flight per column).
-template <int CW>
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, int nrows, int ncols,
-                                                double* __restrict__ dout, float* __restrict__ fout,
-                                                ColMap map, int accumulate) {
-  constexpr int RG = 256 / CW;
+// Column sums of part[nrows][ncols] in FP64 (fixed order): a block of NT threads takes CW
+// consecutive columns and NT / CW row groups; wide partial arrays use CW = 64 (a wave reads 256
+// contiguous bytes of a row), with NT = 1024 where there are few such blocks, so that a thread sums
+// one sixteenth of the rows in few dependent batches; narrow ones CW = 16 (more row groups in
+// flight per column).
+template <int CW, int NT>
+__device__ __forceinline__ void colsum_block(const float* __restrict__ part, int nrows, int ncols,
+                                             double* __restrict__ dout, float* __restrict__ fout, ColMap map,
+                                             int accumulate, int blk) {
+  constexpr int RG = NT / CW;
   __shared__ double sm[RG][CW];
   const int cl = threadIdx.x % CW, rg = threadIdx.x / CW;
-  const int col = blockIdx.x * CW + cl;
+  const int col = blk * CW + cl;
   const double acc = col < ncols ? strided_sum(part, rg, RG, nrows, ncols, col) : 0.0;
   sm[rg][cl] = acc;
   __syncthreads();
@@ -171,6 +173,26 @@ __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ part, 
       if (d >= 0) fout[d] = accumulate ? (float)((double)fout[d] + s) : (float)s;
     }
   }
+}
+template <int CW, int NT = 256>
+__global__ __launch_bounds__(NT) void k_colsum(const float* __restrict__ part, int nrows, int ncols,
+                                               double* __restrict__ dout, float* __restrict__ fout,
+                                               ColMap map, int accumulate) {
+  colsum_block<CW, NT>(part, nrows, ncols, dout, fout, map, accumulate, blockIdx.x);
+}
+// Two independent column sums into weight gradients in one launch: blocks [0, a.nblk) take job a,
+// the rest job b (CW = 16, 256 threads; the same per-column order as k_colsum<16>).
+struct ColJob {
+  const float* part;
+  float* fout;
+  ColMap map;
+  int nrows, ncols, nblk;
+};
+__global__ __launch_bounds__(256) void k_colsum2(ColJob a, ColJob b, int accumulate) {
+  if ((int)blockIdx.x < a.nblk)
+    colsum_block<16, 256>(a.part, a.nrows, a.ncols, nullptr, a.fout, a.map, accumulate, blockIdx.x);
+  else
+    colsum_block<16, 256>(b.part, b.nrows, b.ncols, nullptr, b.fout, b.map, accumulate, blockIdx.x - a.nblk);
 }
 
 // Batch statistics from column sums: sums[(i*C + c)*2 + {0,1}] = (sum, sum of squares) of
