@@ -10,6 +10,13 @@
         ``--pmc WRITE_SIZE`` run, each scaled by the factor that makes the same counter read
         exactly N bytes for a plain device copy of N bytes (``bench.py --copy-calib``)
 
+    python -m paper_2307_09063_amd.profsum counters --a DIR --b DIR [--top N]
+        per-kernel instruction mix and stall shares from two ``--pmc`` runs of the same command:
+        A = SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_MFMA SQ_INSTS_SALU
+            SQ_WAVE_CYCLES SQ_BUSY_CYCLES,
+        B = SQ_WAIT_INST_LDS SQ_WAIT_INST_ANY SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VALU
+            SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE SQ_INST_LEVEL_VMEM SQ_WAIT_ANY
+
 The traffic summary carries the SHA-256 of the library sources it was taken on and the tiling
 variant the autotuner chose for the kernel; bench.py reports it only while both still hold."""
 import argparse
@@ -100,6 +107,41 @@ def cmd_traffic(a):
     print(text)
 
 
+def counter_sums(d):
+    """{short kernel name: ({counter: sum over dispatches}, dispatches, summed duration ns)}."""
+    con = _db(d)
+    out, seen = {}, set()
+    for name, disp, cn, v, dur in con.execute(
+            'select kernel_name, dispatch_id, counter_name, value, duration from counters_collection'):
+        k = short_name(name)
+        c, n, t = out.get(k, ({}, 0, 0.0))
+        c[cn] = c.get(cn, 0.0) + v
+        if disp not in seen:
+            seen.add(disp)
+            n, t = n + 1, t + dur
+        out[k] = (c, n, t)
+    return out
+
+
+def cmd_counters(a):
+    A, B = counter_sums(a.a), counter_sums(a.b)
+    names = sorted(A, key=lambda k: -A[k][2])[:a.top]
+    print('per wave: instructions issued; wait / VALU: share of the wave-cycles (SQ_WAVE_CYCLES) spent '
+          'waiting on anything (SQ_WAIT_ANY), waiting on LDS (SQ_WAIT_INST_LDS) and issuing VALU '
+          '(SQ_ACTIVE_INST_VALU); us: mean dispatch duration in the counter run')
+    print(f'{"kernel":60s} {"n":>4s} {"us":>8s} {"VALU":>7s} {"MFMA":>6s} {"LDS":>6s} {"VMEM":>6s} '
+          f'{"wait%":>6s} {"wLDS%":>6s} {"VALU%":>6s}')
+    for k in names:
+        ca, n, t = A[k]
+        cb = B.get(k, ({}, 0, 0.0))[0]
+        w = max(ca.get('SQ_WAVES', 0.0), 1.0)
+        wc = max(ca.get('SQ_WAVE_CYCLES', 0.0), 1.0)
+        print(f'{k[:60]:60s} {n:4d} {t / n / 1e3:8.1f} {ca.get("SQ_INSTS_VALU", 0) / w:7.0f} '
+              f'{ca.get("SQ_INSTS_MFMA", 0) / w:6.0f} {ca.get("SQ_INSTS_LDS", 0) / w:6.0f} '
+              f'{ca.get("SQ_INSTS_VMEM_RD", 0) / w:6.0f} {100 * cb.get("SQ_WAIT_ANY", 0) / wc:6.1f} '
+              f'{100 * cb.get("SQ_WAIT_INST_LDS", 0) / wc:6.1f} {100 * cb.get("SQ_ACTIVE_INST_VALU", 0) / wc:6.1f}')
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog='profsum')
     sub = ap.add_subparsers(dest='cmd', required=True)
@@ -119,6 +161,11 @@ def main(argv=None):
                    help='output of a bench.py counter run (give both); their tiling choice is recorded')
     r.add_argument('--out', default=None)
     r.set_defaults(fn=cmd_traffic)
+    q = sub.add_parser('counters')
+    q.add_argument('--a', required=True, help='directory of the instruction-count run')
+    q.add_argument('--b', required=True, help='directory of the stall run')
+    q.add_argument('--top', type=int, default=30)
+    q.set_defaults(fn=cmd_counters)
     a = ap.parse_args(argv)
     a.fn(a)
 
