@@ -60,12 +60,16 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
   float acc[2][4];
   zero4(acc[0]);
   zero4(acc[1]);
-  floatx4_t wacc = {0.f, 0.f, 0.f, 0.f};  // MODE 3: waves 0, 1 own the 16 x 16 weight-gradient tiles
-  auto im2col = [&](int p, int kk) -> float {
-    if (kk >= 27) return 0.f;
-    const int c = kk / 9, t = kk % 9;
-    return xs[(c * XR + p / TW + t / 3) * XC + p % TW + t % 3];
-  };
+  // MODE 3: every wave accumulates the weight gradient of a quarter of each tile's pixels, columns
+  // k = 0..15 and 16..31 (two independent chains); the waves are summed at the end
+  floatx4_t wacc0 = {0.f, 0.f, 0.f, 0.f}, wacc1 = {0.f, 0.f, 0.f, 0.f};
+  // offset in xs of im2col column k (channel c = k / 9, tap t = k % 9) relative to the pixel's own
+  // top-left; -1 for the zero column k = 27
+  auto koff_of = [](int kk) { return kk < 27 ? ((kk / 9) * XR + (kk % 9) / 3) * XC + kk % 3 : -1; };
+  int koff[7];  // conv GEMM: column k = 4 s + lg of step s
+#pragma unroll
+  for (int s = 0; s < 7; ++s) koff[s] = koff_of(4 * s + lg);
+  const int wo0 = koff_of(li), wo1 = koff_of(16 + li);  // weight gradient: columns li, 16 + li
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
@@ -108,7 +112,34 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       }
     }
     __syncthreads();
-    lds_gemm<M, C, 28>(im2col, [&](int kk, int n) { return wk[n * 28 + kk]; }, tt, PS);
+    {
+      // conv GEMM tt[p][o] = sum_k im2col(p, k) w[o][k] on the matrix cores: wave w takes the
+      // 16-pixel row tiles w, w + 4, w + 8, w + 12, as NCH independent chains at a time (four in
+      // the forward modes; one in the adjoint modes, whose registers already hold dS and S)
+      constexpr int NCH = MODE < 2 ? 4 : 1;
+#pragma unroll 1
+      for (int t0 = wave; t0 < M / 16; t0 += 4 * NCH) {
+        floatx4_t cacc[NCH];
+        int pbase[NCH];
+#pragma unroll
+        for (int u = 0; u < NCH; ++u) {
+          const int p = 16 * (t0 + 4 * u) + li;
+          pbase[u] = (p / TW) * XC + p % TW;
+          cacc[u] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int s = 0; s < 7; ++s) {
+          const float bv = wk[li * 28 + 4 * s + lg];
+#pragma unroll
+          for (int u = 0; u < NCH; ++u)
+            cacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(koff[s] >= 0 ? xs[koff[s] + pbase[u]] : 0.f, bv, cacc[u], 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < NCH; ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tt[(16 * (t0 + 4 * u) + 4 * lg + r) * PS + li] = cacc[u][r];
+      }
+    }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
@@ -155,12 +186,14 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
     }
     if (MODE == 3) {
       __syncthreads();
-      // dW[o][k] += sum_p dTp[p][o] im2col(p, k): tile (o 0..15) x (k 0..15 | 16..31)
-      if (wave < 2) {
-        const int n0 = 16 * wave;
+      // dW[o][k] += sum_p dTp[p][o] im2col(p, k) over this wave's quarter of the pixels
+      const int pb = wave * (M / 4);
 #pragma unroll 4
-        for (int p = 0; p < M; p += 4)
-          wacc = __builtin_amdgcn_mfma_f32_16x16x4f32(tt[(p + lg) * PS + li], im2col(p + lg, n0 + li), wacc, 0, 0, 0);
+      for (int p = 0; p < M / 4; p += 4) {
+        const int q = pb + p + lg, qb = (q / TW) * XC + q % TW;
+        const float av = tt[q * PS + li];
+        wacc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xs[wo0 + qb], wacc0, 0, 0, 0);
+        wacc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av, wo1 >= 0 ? xs[wo1 + qb] : 0.f, wacc1, 0, 0, 0);
       }
     }
   }
@@ -172,12 +205,22 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       a.part[(int64_t)blockIdx.x * 2 * C + (MODE == 0 ? c * 2 + s : q)] = red[q];
     }
   }
-  if (MODE == 3 && wave < 2) {
-    // lane holds D[4 lg + r][li] = dW[o = 4 lg + r][k = 16 wave + li]
+  if (MODE == 3) {
+    // lane holds D[4 lg + r][li] = dW[o = 4 lg + r][k = li (wacc0) | 16 + li (wacc1)]; the four
+    // waves' tiles meet in LDS (aliasing tt) and are summed in wave order
+    static_assert(4 * 2 * 256 <= M * PS, "wave partials fit the tile buffer");
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int o = 4 * lg + r, kk = 16 * wave + li;
-      if (kk < 27) a.part[(int64_t)blockIdx.x * 27 * C + kk * C + o] = wacc[r];
+      tt[((wave * 2 + 0) * 16 + 4 * lg + r) * 16 + li] = wacc0[r];
+      tt[((wave * 2 + 1) * 16 + 4 * lg + r) * 16 + li] = wacc1[r];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * 256; q += STDA_BLOCK) {
+      const int hf = q / 256, o = (q / 16) % 16, ki = q % 16, kk = 16 * hf + ki;
+      auto wv = [&](int w) { return tt[((w * 2 + hf) * 16 + o) * 16 + ki]; };
+      const float v = ((wv(0) + wv(1)) + wv(2)) + wv(3);
+      if (kk < 27) a.part[(int64_t)blockIdx.x * 27 * C + kk * C + o] = v;
     }
   }
 }
