@@ -413,6 +413,24 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    // x1 and dx1 of the thread's next dD-phase item (zero off the map), one item ahead: the first
+    // item's loads overlap the staging and the first product, each later one the previous item.
+    // Not at 64 channels, whose tiles have no registers to spare: there each item loads its own.
+    constexpr int NA = (TH + 2) * DWd * G;
+    constexpr bool PF = C < 64;
+    float nx1[4], ng[4];
+    auto a2_load = [&](int e) {
+      const int px = e / G, y = y0 - 1 + px / DWd, x = x0 - 1 + px % DWd;
+      if (e < NA && y >= 0 && y < h && x >= 0 && x < w) {
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        ld4(X1 + off, nx1);
+        ld4(dX1 + off, ng);
+      } else {
+        zero4(nx1);
+        zero4(ng);
+      }
+    };
+    if constexpr (PF) a2_load(threadIdx.x);
     __syncthreads();
     load_tile<T, C, TH, TW, 2>(X, b, y0, x0, h, w, xt);
     __syncthreads();
@@ -422,20 +440,31 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     __syncthreads();
     // A2: dD on the tile + halo 1, dP on the tile (zero off the map)
-    for (int e = threadIdx.x; e < (TH + 2) * DWd * G; e += STDA_BLOCK) {
+    for (int e = threadIdx.x; e < NA; e += STDA_BLOCK) {
       const int px = e / G, r = px / DWd, cc = px % DWd;  // position in the dD tile
       const int y = y0 - 1 + r, x = x0 - 1 + cc;
       const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
+      float x1[4], g[4];
+      if constexpr (PF) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          x1[j] = nx1[j];
+          g[j] = ng[j];
+        }
+        if (e + STDA_BLOCK < NA) a2_load(e + STDA_BLOCK);
+      }
       float od[4], op[4], uv[4];
       zero4(od);
       zero4(op);
       zero4(uv);
       if (y >= 0 && y < h && x >= 0 && x < w) {
-        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        float x1[4], g[4], dv[4];
+        if constexpr (!PF) {
+          const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+          ld4(X1 + off, x1);
+          ld4(dX1 + off, g);
+        }
+        float dv[4];
         float4 xn[9];
-        ld4(X1 + off, x1);
-        ld4(dX1 + off, g);
         s1_dw_lds_keep<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv, xn);
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
@@ -469,6 +498,24 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         *reinterpret_cast<float4*>(dut + cp) = make_float4(uv[0], uv[1], uv[2], uv[3]);
       }
     }
+    // dXr and the skip gradient of the thread's next dX-phase pixel pair (below 64 channels), one
+    // pair ahead: the first pair's loads overlap the two products that follow
+    constexpr int NB2 = (M / 2) * G;
+    float nr[2][4], ns[2][4];
+    auto b2_load = [&](int e) {
+      const int px = 2 * (e / G), y = y0 + px / TW, x = x0 + px % TW;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        zero4(nr[s]);
+        zero4(ns[s]);
+        if (e < NB2 && y < h && x + s < w) {
+          const int64_t off = (((int64_t)b * h + y) * w + x + s) * C + c0;
+          ld4(dXr + off, nr[s]);
+          if (SKIP) ld4(skip + off, ns[s]);
+        }
+      }
+    };
+    if constexpr (PF) b2_load(threadIdx.x);
     __syncthreads();
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
     lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
@@ -501,9 +548,18 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     // pair does not fit its register budget.
     if constexpr (C < 64) {
       static_assert(TW % 2 == 0, "pixel pairs inside a tile row");
-      for (int e = threadIdx.x; e < (M / 2) * G; e += STDA_BLOCK) {
+      for (int e = threadIdx.x; e < NB2; e += STDA_BLOCK) {
         const int px = 2 * (e / G), r = px / TW, cc = px % TW;  // pixels px, px + 1 of tile row r
         const int y = y0 + r, x = x0 + cc;
+        float rp[2][4], sp2[2][4];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            rp[s][j] = nr[s][j];
+            sp2[s][j] = ns[s][j];
+          }
+        if (e + STDA_BLOCK < NB2) b2_load(e + STDA_BLOCK);
         if (y >= h || x >= w) continue;
         const bool second = x + 1 < w;
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
@@ -512,20 +568,16 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           if (s == 1 && !second) break;
-          float rr[4];
-          ld4(dXr + off + s * C, rr);
+          const float* rr = rp[s];
           const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px + s), c0 >> 2));
           const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px + s, c0 >> 2));
           const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px + s, c0 >> 2));
           const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[s][j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
-          if (SKIP) {
-            float sv[4];
-            ld4(skip + off + s * C, sv);
+          if (SKIP)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[s][j] += sv[j];
-          }
+            for (int j = 0; j < 4; ++j) acc[s][j] += sp2[s][j];
         }
         // depthwise transpose: dx[c](q) += sum_t dD[c](q - off_t) wd[t][c]; dD is 0 off the map.
         // Row dy of the pair reads dD tile columns cc .. cc + 3 (k = 0..3); the first pixel takes
