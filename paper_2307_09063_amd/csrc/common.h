@@ -55,6 +55,25 @@ __device__ __forceinline__ void st4(bf16* p, const float v[4]) {
 }
 __device__ __forceinline__ void zero4(float v[4]) { v[0] = v[1] = v[2] = v[3] = 0.f; }
 
+// Four channels held in their storage form (a load in flight is not waited for until raw_cvt4
+// converts it): float4 for FP32, the packed pairs for BF16.
+template <class T> struct Raw4;
+template <> struct Raw4<float> { typedef float4 type; };
+template <> struct Raw4<bf16> { typedef uint2 type; };
+__device__ __forceinline__ void raw_ld4(const float* p, float4& r) { r = *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ void raw_ld4(const bf16* p, uint2& r) { r = *reinterpret_cast<const uint2*>(p); }
+__device__ __forceinline__ void raw_zero4(float4& r) { r = make_float4(0.f, 0.f, 0.f, 0.f); }
+__device__ __forceinline__ void raw_zero4(uint2& r) { r = make_uint2(0u, 0u); }
+__device__ __forceinline__ void raw_cvt4(const float4& r, float v[4]) {
+  v[0] = r.x; v[1] = r.y; v[2] = r.z; v[3] = r.w;
+}
+__device__ __forceinline__ void raw_cvt4(const uint2& r, float v[4]) {
+  v[0] = __uint_as_float(r.x << 16);
+  v[1] = __uint_as_float(r.x & 0xffff0000u);
+  v[2] = __uint_as_float(r.y << 16);
+  v[3] = __uint_as_float(r.y & 0xffff0000u);
+}
+
 // Per-channel block reduction for the (pixel, channel-group) thread mapping: thread t owns
 // channels 4*(t % G) .. +3 of some pixel; NS statistics per channel.  Sums the NS*4 values
 // of all threads with the same channel group in a fixed order and writes

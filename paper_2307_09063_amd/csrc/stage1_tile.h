@@ -418,16 +418,17 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     // Not at 64 channels, whose tiles have no registers to spare: there each item loads its own.
     constexpr int NA = (TH + 2) * DWd * G;
     constexpr bool PF = C < 64;
-    float nx1[4], ng[4];
+    typedef typename Raw4<T>::type R4;  // held in storage form until used
+    R4 nx1, ng;
     auto a2_load = [&](int e) {
       const int px = e / G, y = y0 - 1 + px / DWd, x = x0 - 1 + px % DWd;
       if (e < NA && y >= 0 && y < h && x >= 0 && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        ld4(X1 + off, nx1);
-        ld4(dX1 + off, ng);
+        raw_ld4(X1 + off, nx1);
+        raw_ld4(dX1 + off, ng);
       } else {
-        zero4(nx1);
-        zero4(ng);
+        raw_zero4(nx1);
+        raw_zero4(ng);
       }
     };
     if constexpr (PF) a2_load(threadIdx.x);
@@ -446,11 +447,8 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
       float x1[4], g[4];
       if constexpr (PF) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          x1[j] = nx1[j];
-          g[j] = ng[j];
-        }
+        raw_cvt4(nx1, x1);
+        raw_cvt4(ng, g);
         if (e + STDA_BLOCK < NA) a2_load(e + STDA_BLOCK);
       }
       float od[4], op[4], uv[4];
@@ -501,17 +499,17 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     // dXr and the skip gradient of the thread's next dX-phase pixel pair (below 64 channels), one
     // pair ahead: the first pair's loads overlap the two products that follow
     constexpr int NB2 = (M / 2) * G;
-    float nr[2][4], ns[2][4];
+    R4 nr[2], ns[2];
     auto b2_load = [&](int e) {
       const int px = 2 * (e / G), y = y0 + px / TW, x = x0 + px % TW;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        zero4(nr[s]);
-        zero4(ns[s]);
+        raw_zero4(nr[s]);
+        raw_zero4(ns[s]);
         if (e < NB2 && y < h && x + s < w) {
           const int64_t off = (((int64_t)b * h + y) * w + x + s) * C + c0;
-          ld4(dXr + off, nr[s]);
-          if (SKIP) ld4(skip + off, ns[s]);
+          raw_ld4(dXr + off, nr[s]);
+          if (SKIP) raw_ld4(skip + off, ns[s]);
         }
       }
     };
@@ -553,12 +551,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         const int y = y0 + r, x = x0 + cc;
         float rp[2][4], sp2[2][4];
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            rp[s][j] = nr[s][j];
-            sp2[s][j] = ns[s][j];
-          }
+        for (int s = 0; s < 2; ++s) {
+          raw_cvt4(nr[s], rp[s]);
+          raw_cvt4(ns[s], sp2[s]);
+        }
         if (e + STDA_BLOCK < NB2) b2_load(e + STDA_BLOCK);
         if (y >= h || x >= w) continue;
         const bool second = x + 1 < w;
