@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
     // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
     // their latency overlaps them
     constexpr int KI = (M * G + STDA_BLOCK - 1) / STDA_BLOCK;
-    float pg[KI][4], ps[KI][4];
+    typename Raw4<T>::type pg[KI], ps[KI];  // storage form: converted where used
     if constexpr (MODE >= 2) {
 #pragma unroll
       for (int k = 0; k < KI; ++k) {
@@ -85,11 +85,11 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
         const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
         if (e < M * G && y < H && x < W) {
           const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
-          ld4(dS + off, pg[k]);
-          ld4(S + off, ps[k]);
+          raw_ld4(dS + off, pg[k]);
+          raw_ld4(S + off, ps[k]);
         } else {
-          zero4(pg[k]);
-          zero4(ps[k]);
+          raw_zero4(pg[k]);
+          raw_zero4(ps[k]);
         }
       }
     }
@@ -164,8 +164,9 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
         for (int j = 0; j < 4; ++j) o[j] = fmaxf(t[j] * sc[j] + sh[j], 0.f);
         st4(out + off, o);
       } else {
-        const float* g = pg[k];
-        const float* s = ps[k];
+        float g[4], s[4];
+        raw_cvt4(pg[k], g);
+        raw_cvt4(ps[k], s);
         float o[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
