@@ -301,6 +301,25 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    // BF16 above 16 channels: x1 and dx1 of the thread's next item loaded one item ahead, in
+    // storage form (the first item's loads overlap the staging and the product); otherwise each
+    // item loads its own in place (measured faster there: the 16-channel tiles lose a wave per SIMD)
+    constexpr int NI = TH * TW * G;
+    constexpr bool PF = sizeof(T) == 2 && C > 16;
+    typedef typename Raw4<T>::type R4;
+    R4 nx1, ng;
+    auto item_load = [&](int e) {
+      const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
+      if (e < NI && y < h && x < w) {
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        raw_ld4(X1 + off, nx1);
+        raw_ld4(dX1 + off, ng);
+      } else {
+        raw_zero4(nx1);
+        raw_zero4(ng);
+      }
+    };
+    if constexpr (PF) item_load(threadIdx.x);
     __syncthreads();
     load_tile<T, C, TH, TW, 1, C != 16>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
     __syncthreads();
@@ -308,11 +327,17 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
                               [&](int k, int n) { return wp[k * C + n]; },
                               [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
     __syncthreads();
-    for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
+    for (int e = threadIdx.x; e < NI; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
+      float x1[4], g[4];
+      if constexpr (PF) {
+        raw_cvt4(nx1, x1);
+        raw_cvt4(ng, g);
+        if (e + STDA_BLOCK < NI) item_load(e + STDA_BLOCK);
+      }
       if (y >= h || x >= w) continue;
-      float pv[4], dv[4], xv[4], x1[4], g[4];
+      float pv[4], dv[4], xv[4];
       const float4 pq = *reinterpret_cast<const float4*>(pt + s1c<C, PN>(px, c0 >> 2));
       pv[0] = pq.x;
       pv[1] = pq.y;
@@ -324,9 +349,11 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
       xv[2] = xq.z;
       xv[3] = xq.w;
       s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
-      const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-      ld4(X1 + off, x1);
-      ld4(dX1 + off, g);
+      if constexpr (!PF) {
+        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
+        ld4(X1 + off, x1);
+        ld4(dX1 + off, g);
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float du = x1[j] > 0.f ? g[j] : 0.f;
