@@ -21,7 +21,7 @@ from tests import gpu_util as U
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-2
-CASES = [(2, 32, 24, False), (2, 64, 64, True), (4, 128, 64, True)]
+CASES = [(2, 32, 24, False), (2, 40, 36, False), (2, 64, 64, True), (4, 128, 64, True)]
 
 
 @pytest.mark.parametrize('case', CASES, ids=lambda c: f'{c[0]}x{c[1]}x{c[2]}')
