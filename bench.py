@@ -521,23 +521,65 @@ def rd_synth_table4(stda, inputs, torch, dev, n=256, N=64, M=128):
     return {'ms': round(ms, 4), 'clips_per_s': round(n / (ms / 1e3), 1), 'clips': n, 'map': [N, M]}
 
 
-def cpu_baseline(nclips, N, M, x, y, w, r):
-    """The FP64 oracle's training step (forward, loss, backward, SGD) timed on the host."""
+def _oracle_step_worker(args):
+    """One FP64 oracle training step (forward, MSE, backward, SGD) on the sample; returns the
+    wall-clock interval of the step itself (process start-up and imports excluded)."""
+    x, y, w, r = args
     import numpy as np
-    import resource
 
     from oracle import net
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    loss, g, _, _, _ = net.loss_and_grad(w.astype(np.float64), r.astype(np.float64), x, y)
+    t0 = time.time()
+    _, g, _, _, _ = net.loss_and_grad(w.astype(np.float64), r.astype(np.float64), x, y)
     net.sgd_step(w, g, 1e-3, 5e-4)
-    wall = time.perf_counter() - t0
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    return {'value': round(nclips / wall, 4), 'unit': 'clips/s', 'cores': max(1, round(cpu_s / wall)),
-            'kind': 'oracle',
-            'sample': f'{nclips} clips of 3x{N}x{M}, one FP64 training step (forward, MSE, backward, SGD), '
-                      f'{wall:.1f} s wall'}
+    return t0, time.time()
+
+
+def host_cpu():
+    """(usable cores, CPU model name) of this host."""
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    model = 'unknown'
+    try:
+        with open('/proc/cpuinfo') as f:
+            for line in f:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline(nclips, N, M, x, y, w, r, max_workers=16):
+    """The FP64 oracle's training step timed on the host's cores: one single-threaded worker
+    process per core (at most max_workers, the host share of one GPU), each running the same
+    bounded sample, started together; throughput = all workers' clips over the span from the
+    first step's start to the last one's end.  The single-worker rate is reported beside it."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    cores, model = host_cpu()
+    workers = max(1, min(cores, max_workers))
+    env_keys = ('OMP_NUM_THREADS', 'OPENBLAS_NUM_THREADS', 'MKL_NUM_THREADS')
+    old = {k: os.environ.get(k) for k in env_keys}
+    for k in env_keys:
+        os.environ[k] = '1'  # one thread per worker: the workers are the parallelism
+    try:
+        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context('spawn')) as ex:
+            spans = list(ex.map(_oracle_step_worker, [(x, y, w, r)] * workers))
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    span = max(e for _, e in spans) - min(s for s, _ in spans)
+    one = sum(e - s for s, e in spans) / len(spans)
+    return {'value': round(workers * nclips / span, 4), 'unit': 'clips/s', 'cores': workers, 'kind': 'oracle',
+            'value_per_core': round(nclips / one, 4), 'host_cores': cores, 'cpu_model': model,
+            'sample': f'{workers} single-threaded workers, each one FP64 training step (forward, MSE, backward, '
+                      f'SGD) on the same {nclips} clips of 3x{N}x{M}; {span:.1f} s span, {one:.1f} s per step'}
 
 
 if __name__ == '__main__':

@@ -127,9 +127,12 @@ int stda_forward(const stda_segment* segs /*host*/, int n_segs, const float* x, 
 
 /*
  * Hand-written adjoint of the TRAIN forward that filled `saved` (same segs, x, w, dtype,
- * recompute; x is read again for the input-module weight gradient).  dz = dL/dz; writes dw (all 137,469 gradients, summed over segments; no zero
- * initialisation needed) and, if dx is not NULL, dL/dx.  Weight-gradient partials are reduced
- * across blocks in FP64.
+ * recompute; x is read again for the input-module weight gradient).  dz = dL/dz; writes dw (all
+ * 137,469 gradients, summed over segments; no zero initialisation needed) and, if dx is not NULL,
+ * dL/dx.  Weight-gradient partials are reduced across blocks in FP64.
+ * Every TRAIN forward records, on the host, the layout key of the `saved` it filled (segments,
+ * dtype, recompute, architecture reading); a `saved` that no TRAIN forward of this process filled
+ * under the same key is refused with STDA_E_INVALID (the layout would not match).
  */
 int stda_backward(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* dz,
                   const float* w, const void* saved, size_t saved_bytes, float* dw, float* dx,
@@ -268,6 +271,17 @@ int stda_profile_report(char* buf /*host out*/, size_t cap, size_t* needed /*hos
 int stda_tune_count(int kind);  /* number of variants of `kind`, or a negative status */
 int stda_tune_set(int kind, int dtype, int block, int variant);
 int stda_tune_get(int kind, int dtype, int block, int* variant /*host out*/);
+
+/*
+ * Upper bound on the workgroups of every tiled network kernel (0, the default, = no bound beyond
+ * the kernel's own).  Those kernels hand their tiles to a persistent grid and carry accumulators
+ * (batch-norm partial sums, weight-gradient products) from one tile to the next; a small bound
+ * makes a small batch take the same multi-tile paths a large one does.  A bound that is a multiple
+ * of 8 keeps the XCD-contiguous tile schedule, any other the plain grid stride.  Process-wide, read
+ * when a launch is enqueued (a captured graph keeps its grid).  Negative: STDA_E_INVALID.
+ */
+int stda_set_grid_cap(int cap);
+int stda_get_grid_cap(void);
 
 /*
  * Autotuner: for every variant v, sets all tunable launches of `dtype` to v, runs one untimed

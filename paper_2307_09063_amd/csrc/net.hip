@@ -98,6 +98,15 @@ int grid_for(int64_t items, int cap = 2048) {
   return (int)std::min<int64_t>(g, cap);
 }
 
+// Upper bound on the workgroups of the tiled network kernels (stda_set_grid_cap; 0 = none).  The
+// kernels walk their tiles with a grid-stride (or XCD-chunked) schedule and keep accumulators
+// across tiles, so a small cap makes every workgroup of a small batch take several tiles.
+std::atomic<int> g_grid_cap{0};
+int64_t capped(int64_t g) {
+  const int c = g_grid_cap.load(std::memory_order_relaxed);
+  return c > 0 ? std::min<int64_t>(g, c) : g;
+}
+
 }  // namespace
 
 namespace stda {
@@ -450,7 +459,7 @@ struct Ctx {
 
 int tiles_for(int64_t hw, int G) {
   const int64_t item_blocks = (hw * G + STDA_BLOCK - 1) / STDA_BLOCK;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4));
+  return (int)std::max<int64_t>(1, capped(std::min<int64_t>(kMaxTiles, (item_blocks + 3) / 4)));
 }
 
 // Tiling variant of each tunable launch, [dtype][kind][block]: kinds 0 forward, 1 input gradient
@@ -469,7 +478,7 @@ int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const T* src, const T
   typedef S2Cfg<T, OP, K, N, NB, TH, TW, WV> C;
   const int64_t ntiles = (int64_t)n * ((hd + TH - 1) / TH) * ((wd + TW - 1) / TW);
   const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / C::LDS_BYTES);
-  int64_t gx = std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid));
+  int64_t gx = capped(std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid)));
   if (gx >= 64) gx &= ~(int64_t)7;  // whole XCD groups: tiles are handed out XCD by XCD
   gx = std::max<int64_t>(gx, 1);
   KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS, WV><<<dim3((unsigned)gx, N / NB), C::BLK, 0, c.st>>>(
@@ -486,7 +495,7 @@ int launch_gather(const Ctx<T>& c, const std::string& tag, const T* src, const T
   const int64_t P = (int64_t)n * (down ? (int64_t)hd * wd : (int64_t)(hd / 2) * (wd / 2));
   const int phases = down ? 1 : 4;
   const int64_t tiles = (P + 64 * R - 1) / (64 * R);
-  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kMaxGrid / phases));
+  const int gx = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kMaxGrid / phases)));
   KLAUNCH(tag, k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd));
   if (nblk) *nblk = gx * phases;
   return STDA_OK;
@@ -546,19 +555,19 @@ int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const T* src,
 template <int C>
 int s1_grid(int n, int h, int w) {
   const int64_t tiles = (int64_t)n * ((h + S1Tile<C>::TH - 1) / S1Tile<C>::TH) * ((w + S1Tile<C>::TW - 1) / S1Tile<C>::TW);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+  return (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
 }
 
 // Blocks of the tiled input-module kernels (8 x 32 pixel tiles), at most kTileGrid.
 int stem_grid(int n, int H, int W) {
   const int64_t tiles = (int64_t)n * ((H + 7) / 8) * ((W + 31) / 32);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+  return (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
 }
 
 // Blocks of the tiled output-module kernels, at most kTileGrid.
 int head_grid(int n, int H, int W) {
   const int64_t tiles = (int64_t)n * ((H + kHeadTH - 1) / kHeadTH) * ((W + kHeadTW - 1) / kHeadTW);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+  return (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
 }
 
 // Column sums of per-block BN partials followed by the statistics finalize.
@@ -847,7 +856,7 @@ int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const T* lo, const
   typedef WgCfg<T, DEC, CL, CH, TH, TW> Cfg;
   const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = std::min<int64_t>(ntiles, wgrad_rows(cols));
+  int64_t gx = capped(std::min<int64_t>(ntiles, wgrad_rows(cols)));
   if (gx >= 64) gx &= ~(int64_t)7;
   gx = std::max<int64_t>(gx, 1);
   float* wpart = c.template scr<float>(c.P->ws_wpart);
@@ -861,7 +870,7 @@ int launch_wgrad_v(const Ctx<T>& c, const std::string& tag, const T* lo, const T
   typedef WgVCfg<T, DEC, CL, CH, TH, TW> Cfg;
   const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = std::min<int64_t>(ntiles, wgrad_rows(cols));
+  int64_t gx = capped(std::min<int64_t>(ntiles, wgrad_rows(cols)));
   if (gx >= 64) gx &= ~(int64_t)7;
   gx = std::max<int64_t>(gx, 1);
   float* wpart = c.template scr<float>(c.P->ws_wpart);
@@ -906,7 +915,7 @@ template <class T, int C, bool DEC, int TH, int TW, int MINW>
 int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, const T* dXr, const T* skipg,
                    const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
   const int64_t tiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  const int g = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, kTileGrid));
+  const int g = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
   const float* coef = c.template scr<float>(c.P->ws_coef);
   KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW><<<g, 256, 0, c.st>>>(
                                          X, X1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
@@ -1108,6 +1117,64 @@ int backward_all(const Plan& P, const float* dz, const float* x, const float* w,
     if (int r = backward_seg<T>(c, dz, x, dw, dx, s > 0 ? 1 : 0)) return r;
   }
   return STDA_OK;
+}
+
+}  // namespace
+
+// ===================================================================== saved-buffer records
+namespace {
+
+// The layout of `saved` follows from (segments, dtype, recompute, architecture reading).  Every
+// TRAIN forward records that key for its `saved` pointer on the host, and stda_backward accepts a
+// `saved` only under the key it was filled with, so that a backward with another dtype, recompute
+// flag, reading or segment list is refused instead of reading the buffer at the wrong offsets.
+// Host-side, so that neither call waits on the device (both stay capturable into graphs).
+uint64_t saved_key(const stda_segment* segs, int n_segs, int dtype, int recompute, int arch) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the fields
+  auto mix = [&h](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xffu;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)dtype);
+  mix((uint64_t)(recompute != 0));
+  mix((uint64_t)arch);
+  mix((uint64_t)n_segs);
+  for (int s = 0; s < n_segs; ++s) {
+    mix((uint64_t)segs[s].n);
+    mix((uint64_t)segs[s].H);
+    mix((uint64_t)segs[s].W);
+    mix((uint64_t)segs[s].x_off);
+    mix((uint64_t)segs[s].z_off);
+  }
+  return h;
+}
+
+struct SavedRec {
+  const void* ptr;
+  uint64_t key;
+};
+constexpr size_t kSavedRecs = 256;  // most recent TRAIN forwards remembered
+std::mutex g_saved_mu;
+std::vector<SavedRec> g_saved_recs;
+
+void saved_record(const void* p, uint64_t key) {
+  std::lock_guard<std::mutex> lk(g_saved_mu);
+  for (auto it = g_saved_recs.begin(); it != g_saved_recs.end(); ++it)
+    if (it->ptr == p) {
+      g_saved_recs.erase(it);
+      break;
+    }
+  if (g_saved_recs.size() >= kSavedRecs) g_saved_recs.erase(g_saved_recs.begin());
+  g_saved_recs.push_back(SavedRec{p, key});
+}
+
+bool saved_matches(const void* p, uint64_t key) {
+  std::lock_guard<std::mutex> lk(g_saved_mu);
+  for (const auto& r : g_saved_recs)
+    if (r.ptr == p) return r.key == key;
+  return false;
 }
 
 }  // namespace
@@ -1431,6 +1498,14 @@ int stda_profile_report(char* buf, size_t cap, size_t* needed) {
   return STDA_OK;
 }
 
+int stda_set_grid_cap(int cap) {
+  if (cap < 0) return STDA_E_INVALID;
+  g_grid_cap.store(cap, std::memory_order_relaxed);
+  return STDA_OK;
+}
+
+int stda_get_grid_cap(void) { return g_grid_cap.load(std::memory_order_relaxed); }
+
 int stda_bn_layer_count(void) { return 17; }
 size_t stda_running_count(void) { return (size_t)net_offsets(0).running_count; }
 
@@ -1464,9 +1539,10 @@ int stda_forward(const stda_segment* segs, int n_segs, const float* x, const flo
     build_plan(segs, n_segs, dtype, mode, recompute, P);
     if (ws_bytes < P.ws_bytes) return STDA_E_WORKSPACE;
     if (mode == STDA_TRAIN && (!saved || saved_bytes < P.saved_bytes)) return STDA_E_WORKSPACE;
-    if (dtype == STDA_BF16)
-      return forward_all<bf16>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
-    return forward_all<float>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
+    const int r = dtype == STDA_BF16 ? forward_all<bf16>(P, x, w, running, z, (char*)saved, (char*)ws, stream)
+                                     : forward_all<float>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
+    if (r == STDA_OK && mode == STDA_TRAIN) saved_record(saved, saved_key(segs, n_segs, dtype, recompute, P.arch));
+    return r;
   } catch (...) {
     return STDA_E_INVALID;
   }
@@ -1482,6 +1558,7 @@ int stda_backward(const stda_segment* segs, int n_segs, const float* x, const fl
     Plan P;
     build_plan(segs, n_segs, dtype, STDA_TRAIN, recompute, P);
     if (ws_bytes < P.ws_bytes || saved_bytes < P.saved_bytes) return STDA_E_WORKSPACE;
+    if (!saved_matches(saved, saved_key(segs, n_segs, dtype, recompute, P.arch))) return STDA_E_INVALID;
     if (dtype == STDA_BF16)
       return backward_all<bf16>(P, dz, x, w, (const char*)saved, dw, dx, (char*)ws, stream);
     return backward_all<float>(P, dz, x, w, (const char*)saved, dw, dx, (char*)ws, stream);

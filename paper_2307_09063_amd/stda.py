@@ -62,6 +62,8 @@ def _load():
         'stda_profile_select': (I, [ctypes.c_char_p]),
         'stda_profile_read': (I, [P, P]),
         'stda_profile_report': (I, [P, SZ, P]),
+        'stda_set_grid_cap': (I, [I]),
+        'stda_get_grid_cap': (I, []),
         'stda_tune_count': (I, [I]),
         'stda_tune_set': (I, [I, I, I, I]),
         'stda_tune_get': (I, [I, I, I, P]),
@@ -84,7 +86,7 @@ EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'std
            'stda_bn_layer_count', 'stda_running_count', 'stda_set_arch', 'stda_get_arch', 'stda_workspace_size', 'stda_forward',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
-           'stda_profile_read', 'stda_profile_report', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
+           'stda_profile_read', 'stda_profile_report', 'stda_set_grid_cap', 'stda_get_grid_cap', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
            'stda_autotune', 'stda_cfar', 'stda_evm', 'stda_adamw_step', 'rd_synth_workspace_size', 'rd_synth')
 
 
@@ -359,6 +361,16 @@ def profile_report():
 # ------------------------------------------------------------------------ tile-shape autotuning
 TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD, TUNE_S1_BWD = 0, 1, 2, 3
 TUNE_KINDS = (TUNE_FWD, TUNE_DGRAD, TUNE_WGRAD, TUNE_S1_BWD)
+
+
+def set_grid_cap(cap):
+    """Bound the workgroups of every tiled network kernel (0 = no bound), so that a small batch
+    walks several tiles per workgroup as a large one does."""
+    _check(_lib.stda_set_grid_cap(int(cap)), 'stda_set_grid_cap')
+
+
+def get_grid_cap():
+    return int(_lib.stda_get_grid_cap())
 
 
 def tune_count(kind):

@@ -88,3 +88,41 @@ def per_tensor_errors(g_gpu, g_ref):
         out[name] = rel_l2(g_gpu[off:off + n], g_ref[off:off + n])
         off += n
     return out
+
+
+def max_rel(a, b):
+    """max |a - b| / max |b|: the largest element error on the tensor's own scale (an error
+    confined to a few elements, e.g. tile borders, shows here long before it moves rel-L2)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return float(np.abs(a - b).max() / (mb if mb > 0 else 1.0)) if b.size else 0.0
+
+
+def elem_tol(rel):
+    """Element-wise gate that goes with a rel-L2 gate of `rel`."""
+    return 10.0 * rel
+
+
+def assert_close(a, b, rel, elem=None, what=''):
+    """rel-L2(a, b) < rel and max_rel(a, b) <= elem (default elem_tol(rel))."""
+    elem = elem_tol(rel) if elem is None else elem
+    e1, e2 = rel_l2(a, b), max_rel(a, b)
+    assert e1 < rel and e2 <= elem, f'{what} rel-L2 {e1:.3e} (gate {rel:.1e}), max-rel {e2:.3e} (gate {elem:.1e})'
+
+
+def grad_failures(g_gpu, g_ref, rel, elem=None, skip=()):
+    """{tensor: (rel-L2, max-rel)} of every parameter tensor that misses either gate."""
+    elem = elem_tol(rel) if elem is None else elem
+    bad = {}
+    off = 0
+    for name, shape, _ in net.param_specs():
+        n = int(np.prod(shape))
+        a, b = g_gpu[off:off + n], g_ref[off:off + n]
+        off += n
+        if name in skip or any(name.endswith(s) for s in skip):
+            continue
+        e1, e2 = rel_l2(a, b), max_rel(a, b)
+        if not (e1 < rel and e2 <= elem):
+            bad[name] = (e1, e2)
+    return bad

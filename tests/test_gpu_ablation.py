@@ -86,8 +86,8 @@ def test_forward(arch, shape):
         S.forward(segs, U.dev(x), U.dev(w), rd, z, saved, ws, S.FP32, mode)
         torch.cuda.synchronize()
         zr, rr, _ = net.forward(w, r, x, 'train' if mode == S.TRAIN else 'eval')
-        assert U.rel_l2(z.cpu().numpy(), zr) < TOL, mode
-        assert U.rel_l2(rd.cpu().numpy(), rr if mode == S.TRAIN else r) < TOL, mode
+        U.assert_close(z.cpu().numpy(), zr, TOL, what=f'z mode {mode}')
+        U.assert_close(rd.cpu().numpy(), rr if mode == S.TRAIN else r, TOL, what=f'running mode {mode}')
         if head == 'sigmoid':
             zz = z.cpu().numpy()
             assert zz.min() > 0 and zz.max() < 1
@@ -127,12 +127,10 @@ def _backward(arch, shape, recompute, conditioned):
     torch.cuda.synchronize()
     _, _, cache = net.forward(w, r, x, 'train')
     gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-    errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
-    if pw == 'depthwise' and not conditioned:
-        errs = {k: v for k, v in errs.items() if not k.endswith('.s1.pw.w')}
-    bad = {k: v for k, v in errs.items() if not v < TOL}
+    skip = ('.s1.pw.w',) if pw == 'depthwise' and not conditioned else ()
+    bad = U.grad_failures(dw.cpu().numpy(), gr, TOL, skip=skip)
     assert not bad, bad
-    assert U.rel_l2(dx.cpu().numpy(), dxr) < TOL
+    U.assert_close(dx.cpu().numpy(), dxr, TOL, what='dx')
 
 
 def test_train_step_graph(arch):

@@ -55,18 +55,18 @@ def test_maximum_extent(S, shape):
     w, r = U.weights(), U.running()
     z, r_out, _ = _forward(S, x, w, r, S.EVAL)
     zr, _, _ = net.forward(w, r, x, 'eval')
-    assert U.rel_l2(z, zr) < TOL
+    U.assert_close(z, zr, TOL, what='z')
     z, r_out, (segs, xd, wd, saved, ws) = _forward(S, x, w, r, S.TRAIN)
     zr, rr, cache = net.forward(w, r, x, 'train')
-    assert U.rel_l2(z, zr) < TOL
-    assert U.rel_l2(r_out, rr) < TOL
+    U.assert_close(z, zr, TOL, what='z')
+    U.assert_close(r_out, rr, TOL, what='running')
     g = np.random.default_rng(H * W).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
     dw = torch.empty(net.param_count(), device='cuda')
     dx = torch.empty_like(xd)
     S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws)
     torch.cuda.synchronize()
     _, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-    assert U.rel_l2(dx.cpu().numpy(), dxr) < TOL
+    U.assert_close(dx.cpu().numpy(), dxr, TOL, what='dx')
     assert np.isfinite(dw.cpu().numpy()).all()
 
 
@@ -96,6 +96,6 @@ def test_zero_input_gives_head_bias(S, mode, dtype):
         if dtype == 0:
             _, _, cache = net.forward(w, r, x, 'train')
             gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-            bad = {k: e for k, e in U.per_tensor_errors(got, gr).items() if not e < TOL}
+            bad = U.grad_failures(got, gr, TOL)
             assert not bad, bad
-            assert U.rel_l2(dx.cpu().numpy(), dxr) < TOL
+            U.assert_close(dx.cpu().numpy(), dxr, TOL, what='dx')

@@ -64,7 +64,7 @@ def test_eval_forward_b32_sampled(batch32):
     xc = x.cpu().numpy()
     for b in (0, 9, 31):
         zr, _, _ = net.forward(w, r, xc[b:b + 1], 'eval')
-        assert U.rel_l2(z[b:b + 1].cpu().numpy(), zr) < 1e-4
+        U.assert_close(z[b:b + 1].cpu().numpy(), zr, 1e-4, what=f'z clip {b}')
 
 
 def test_train_forward_b4_full_batch(batch32):
@@ -80,8 +80,8 @@ def test_train_forward_b4_full_batch(batch32):
     stda.forward(segs, xb, U.dev(w), rd, z, stda.alloc_bytes(sv), stda.alloc_bytes(wsb), stda.FP32, stda.TRAIN)
     torch.cuda.synchronize()
     zr, rr, _ = net.forward(w, r, xb.cpu().numpy(), 'train')
-    assert U.rel_l2(z.cpu().numpy(), zr) < 1e-4
-    assert U.rel_l2(rd.cpu().numpy(), rr) < 1e-4
+    U.assert_close(z.cpu().numpy(), zr, 1e-4, what='z')
+    U.assert_close(rd.cpu().numpy(), rr, 1e-4, what='running')
 
 
 def test_train_loss_b64_launch():
@@ -107,5 +107,5 @@ def test_train_loss_b64_launch():
     zc, yc = z.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
     lr_, dzr = net.mse_loss(zc, yc)
     assert abs(loss.item() - lr_) <= 1e-12 * lr_
-    assert U.rel_l2(dz.cpu().numpy(), dzr) < 1e-6
+    U.assert_close(dz.cpu().numpy(), dzr, 1e-6, what='dz')
     assert np.isfinite(dw.cpu().numpy()).all()

@@ -51,7 +51,7 @@ def test_forward_eval(S, shape):
     w, r = U.weights(), U.running()
     z, r_out, _ = _run_forward(S, x, w, r, S.EVAL)
     zr, _, _ = net.forward(w, r, x, 'eval')
-    assert U.rel_l2(z, zr) < TOL
+    U.assert_close(z, zr, TOL, what='z')
     np.testing.assert_array_equal(r_out, r)      # EVAL leaves the running buffer alone
 
 
@@ -63,8 +63,8 @@ def test_forward_train_and_running(S, shape):
     w, r = U.weights(), U.running()
     z, r_out, _ = _run_forward(S, x, w, r, S.TRAIN)
     zr, rr, _ = net.forward(w, r, x, 'train')
-    assert U.rel_l2(z, zr) < TOL
-    assert U.rel_l2(r_out, rr) < TOL
+    U.assert_close(z, zr, TOL, what='z')
+    U.assert_close(r_out, rr, TOL, what='running')
 
 
 @pytest.mark.parametrize('shape', SHAPES)
@@ -82,7 +82,7 @@ def test_backward(S, shape):
     torch.cuda.synchronize()
     lr_, dzr = net.mse_loss(z.astype(np.float64), y)
     assert abs(loss.item() - lr_) <= 1e-12 * abs(lr_) + 1e-300
-    assert U.rel_l2(dz.cpu().numpy(), dzr) < 1e-6
+    U.assert_close(dz.cpu().numpy(), dzr, 1e-6, what='dz')
     # the adjoint itself, on the same dz for both sides
     rng = np.random.default_rng(B * H * W)
     g = rng.standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
@@ -92,10 +92,9 @@ def test_backward(S, shape):
     torch.cuda.synchronize()
     _, _, cache = net.forward(w, r, x, 'train')
     gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-    errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
-    bad = {k: v for k, v in errs.items() if not v < TOL}
+    bad = U.grad_failures(dw.cpu().numpy(), gr, TOL)
     assert not bad, bad
-    assert U.rel_l2(dx.cpu().numpy(), dxr) < TOL
+    U.assert_close(dx.cpu().numpy(), dxr, TOL, what='dx')
 
 
 def test_sgd(S):
@@ -128,10 +127,10 @@ def test_autograd_function(S):
     loss.backward()
     torch.cuda.synchronize()
     lr_, gr, dxr, zr, _ = net.loss_and_grad(w, r, x, y, want_dx=True)
-    assert U.rel_l2(z.detach().cpu().numpy(), zr) < TOL
-    errs = U.per_tensor_errors(wd.grad.cpu().numpy(), gr)
-    assert max(errs.values()) < TOL, errs
-    assert U.rel_l2(xd.grad.cpu().numpy(), dxr) < TOL
+    U.assert_close(z.detach().cpu().numpy(), zr, TOL, what='z')
+    bad = U.grad_failures(wd.grad.cpu().numpy(), gr, TOL)
+    assert not bad, bad
+    U.assert_close(xd.grad.cpu().numpy(), dxr, TOL, what='dx')
 
 
 def test_uneven_segments(S):
@@ -160,16 +159,16 @@ def test_uneven_segments(S):
     off, lsum, gsum, rcur = 0, 0.0, 0.0, r.astype(np.float64)
     for (n, H, W), x, y in zip(parts, xs, ys):
         zr, rcur, cache = net.forward(w, rcur, x, 'train')
-        assert U.rel_l2(zc[off:off + n * H * W], zr.ravel()) < TOL
+        U.assert_close(zc[off:off + n * H * W], zr.ravel(), TOL, what=f'z {n}x{H}x{W}')
         l, d = net.mse_loss(zr, y)
         g, _ = net.backward(d, cache)
         lsum += l
         gsum = gsum + g
         off += n * H * W
     assert abs(loss.item() - lsum) < 1e-5 * lsum
-    assert U.rel_l2(rd.cpu().numpy(), rcur) < TOL
-    errs = U.per_tensor_errors(dw.cpu().numpy(), gsum)
-    assert max(errs.values()) < TOL, errs
+    U.assert_close(rd.cpu().numpy(), rcur, TOL, what='running')
+    bad = U.grad_failures(dw.cpu().numpy(), gsum, TOL)
+    assert not bad, bad
 
 
 def test_deterministic(S):
@@ -186,3 +185,34 @@ def test_deterministic(S):
         outs.append((z, dw.cpu().numpy()))
     np.testing.assert_array_equal(outs[0][0], outs[1][0])
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_backward_refuses_foreign_saved(S):
+    """A `saved` buffer is accepted only with the dtype, recompute flag and segments of the TRAIN
+    forward that filled it (its layout follows from them)."""
+    _say('saved key')
+    B, H, W = 2, 16, 16
+    x, _ = U.maps(B, H, W, seed=4)
+    w, r = U.weights(), U.running()
+    segs = S.uniform_segments(B, H, W)
+    sv0, ws0 = S.workspace_size(segs, S.FP32, S.TRAIN, 0)
+    sv1, ws1 = S.workspace_size(segs, S.FP32, S.TRAIN, 1)
+    svb, wsbb = S.workspace_size(segs, S.BF16, S.TRAIN, 0)
+    saved = S.alloc_bytes(max(sv0, sv1, svb))
+    ws = S.alloc_bytes(max(ws0, ws1, wsbb))
+    xd, wd = U.dev(x), U.dev(w)
+    z = torch.empty((B, 1, H, W), device='cuda')
+    S.forward(segs, xd, wd, U.dev(r.copy()), z, saved, ws, S.FP32, S.TRAIN, 0)
+    dz = torch.ones_like(z)
+    dw = torch.empty(net.param_count(), device='cuda')
+    for dtype, rec in ((S.FP32, 1), (S.BF16, 0)):
+        with pytest.raises(S.StdaError, match='invalid argument'):
+            S.backward(segs, xd, dz, wd, saved, dw, None, ws, dtype, rec)
+    with pytest.raises(S.StdaError, match='invalid argument'):
+        S.backward(S.uniform_segments(1, H, W), xd, dz, wd, saved, dw, None, ws, S.FP32, 0)
+    never_filled = S.alloc_bytes(sv0 + 256)[256:]  # an address no allocation has returned
+    with pytest.raises(S.StdaError, match='invalid argument'):
+        S.backward(segs, xd, dz, wd, never_filled, dw, None, ws, S.FP32, 0)
+    S.backward(segs, xd, dz, wd, saved, dw, None, ws, S.FP32, 0)  # the matching call runs
+    torch.cuda.synchronize()
+    assert np.isfinite(dw.cpu().numpy()).all()

@@ -70,7 +70,10 @@ def test_variants_eval_bitwise(S, dtype, shape):
     for v in range(1, len(outs)):
         np.testing.assert_array_equal(outs[v], outs[0])
     zr, _, _ = net.forward(w, r, x, 'eval')
-    assert U.rel_l2(outs[0], zr) < (1e-4 if dtype == 0 else 2e-2)
+    if dtype == 0:
+        U.assert_close(outs[0], zr, 1e-4, what='z')
+    else:
+        assert U.rel_l2(outs[0], zr) < 2e-2
 
 
 @pytest.mark.parametrize('v', [0, 1, 2, 3])
@@ -82,18 +85,17 @@ def test_variant_fp32_train_backward(S, v):
     x, _ = U.unambiguous(lambda s: U.maps(B, H, W, seed=s), w, r, 77)
     z, rd, (segs, xd, wd, saved, ws) = _forward(S, x, w, r, S.TRAIN, S.FP32)
     zr, rr, cache = net.forward(w, r, x, 'train')
-    assert U.rel_l2(z.cpu().numpy(), zr) < 1e-4
-    assert U.rel_l2(rd.cpu().numpy(), rr) < 1e-4
+    U.assert_close(z.cpu().numpy(), zr, 1e-4, what='z')
+    U.assert_close(rd.cpu().numpy(), rr, 1e-4, what='running')
     g = np.random.default_rng(v).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
     dw = torch.full((net.param_count(),), float('nan'), device='cuda')
     dx = torch.empty_like(xd)
     S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws)
     torch.cuda.synchronize()
     gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-    errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
-    bad = {k: e for k, e in errs.items() if not e < 1e-4}
+    bad = U.grad_failures(dw.cpu().numpy(), gr, 1e-4)
     assert not bad, bad
-    assert U.rel_l2(dx.cpu().numpy(), dxr) < 1e-4
+    U.assert_close(dx.cpu().numpy(), dxr, 1e-4, what='dx')
 
 
 @pytest.mark.parametrize('v', [0, 1, 2, 3])

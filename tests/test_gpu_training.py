@@ -53,5 +53,5 @@ def test_sgd_run_tracks_oracle(shape):
     np.testing.assert_allclose(losses, ref, rtol=1e-5)
     assert ref[-1] < ref[0]   # the run trains
     got = wd_.cpu().numpy().astype(np.float64)
-    assert U.rel_l2(got - w0, w - w0) < 1e-4
-    assert U.rel_l2(rd.cpu().numpy(), r) < 1e-4
+    U.assert_close(got - w0, w - w0, 1e-4, what='accumulated update')
+    U.assert_close(rd.cpu().numpy(), r, 1e-4, what='running')
