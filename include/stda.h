@@ -126,6 +126,24 @@ int stda_forward(const stda_segment* segs /*host*/, int n_segs, const float* x, 
                  size_t ws_bytes, int dtype, int mode, int recompute, hipStream_t stream);
 
 /*
+ * EVAL forward without a caller workspace, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same result as
+ * stda_forward in EVAL mode with the same arguments; the kernels' scratch is a library-owned
+ * static device array of STDA_NOALLOC_WS_MAX bytes (32 MiB) on each GPU the library runs on,
+ * held until the process ends.  The call allocates nothing.
+ *   segs, x, w, z, dtype: as stda_forward; running: read only (EVAL statistics).
+ *   stream: must belong to the current device (STDA_E_INVALID otherwise).
+ * Batches whose EVAL workspace (stda_workspace_size, mode EVAL) exceeds STDA_NOALLOC_WS_MAX are
+ * refused with STDA_E_WORKSPACE before anything is enqueued (one clip of 256 x 128 needs 29 MiB
+ * in FP32, 18 MiB in BF16; the paper's single 128 x 64 clip 13 MiB).  Every call on one GPU shares its array and nothing in it has to
+ * start at any value: calls that overlap on one GPU (other streams, other threads) race and must
+ * be serialised by the caller.  The first call on a device looks up the array's address there.
+ */
+#define STDA_NOALLOC_WS_MAX (32u << 20)
+int stda_forward_noalloc(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* w,
+                         const float* running, float* z, int dtype, hipStream_t stream);
+
+/*
  * Hand-written adjoint of the TRAIN forward that filled `saved` (same segs, x, w, dtype,
  * recompute; x is read again for the input-module weight gradient).  dz = dL/dz; writes dw (all
  * 137,469 gradients, summed over segments; no zero initialisation needed) and, if dx is not NULL,

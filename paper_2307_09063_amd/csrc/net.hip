@@ -107,6 +107,33 @@ int64_t capped(int64_t g) {
   return c > 0 ? std::min<int64_t>(g, c) : g;
 }
 
+// Workspace of stda_forward_noalloc: one array per GPU, resident until the process ends.  In host
+// code its name is only a stand-in; kernels get the device address that hipGetSymbolAddress
+// reports for the current device, looked up once per device and kept here.
+static __device__ __align__(256) unsigned char scratch[STDA_NOALLOC_WS_MAX];
+
+int noalloc_scratch(hipStream_t stream, char** out) {
+  static std::mutex mu;
+  static std::vector<char*> addr;  // per device ordinal
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (stream) {
+    hipDevice_t sdev = 0;
+    HIP_TRY(hipStreamGetDevice(stream, &sdev));
+    if ((int)sdev != dev) return STDA_E_INVALID;  // the stream must belong to the current device
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return STDA_E_HIP;
+    addr[dev] = static_cast<char*>(p);
+  }
+  *out = addr[dev];
+  return STDA_OK;
+}
+
 }  // namespace
 
 namespace stda {
@@ -1543,6 +1570,26 @@ int stda_forward(const stda_segment* segs, int n_segs, const float* x, const flo
                                      : forward_all<float>(P, x, w, running, z, (char*)saved, (char*)ws, stream);
     if (r == STDA_OK && mode == STDA_TRAIN) saved_record(saved, saved_key(segs, n_segs, dtype, recompute, P.arch));
     return r;
+  } catch (...) {
+    return STDA_E_INVALID;
+  }
+}
+
+int stda_forward_noalloc(const stda_segment* segs, int n_segs, const float* x, const float* w, const float* running,
+                         float* z, int dtype, hipStream_t stream) {
+  try {
+    if (int r = validate_segs(segs, n_segs)) return r;
+    if (dtype != STDA_FP32 && dtype != STDA_BF16) return STDA_E_INVALID;
+    if (!x || !w || !running || !z) return STDA_E_INVALID;
+    Plan P;
+    build_plan(segs, n_segs, dtype, STDA_EVAL, 0, P);
+    if (P.ws_bytes > STDA_NOALLOC_WS_MAX) return STDA_E_WORKSPACE;
+    char* ws = nullptr;
+    if (int r = noalloc_scratch(stream, &ws)) return r;
+    // EVAL reads the running statistics only
+    float* rn = const_cast<float*>(running);
+    return dtype == STDA_BF16 ? forward_all<bf16>(P, x, w, rn, z, nullptr, ws, stream)
+                              : forward_all<float>(P, x, w, rn, z, nullptr, ws, stream);
   } catch (...) {
     return STDA_E_INVALID;
   }

@@ -50,6 +50,7 @@ def _load():
         'stda_get_arch': (I, []),
         'stda_workspace_size': (I, [P, I, I, I, I, P, P]),
         'stda_forward': (I, [P, I, P, P, P, P, P, SZ, P, SZ, I, I, I, P]),
+        'stda_forward_noalloc': (I, [P, I, P, P, P, P, I, P]),
         'stda_backward': (I, [P, I, P, P, P, P, SZ, P, P, P, SZ, I, I, P]),
         'stda_mse_loss': (I, [P, I, P, P, P, P, P, SZ, P]),
         'stda_sgd_step': (I, [P, P, I64, F, F, P, P]),
@@ -84,6 +85,7 @@ def _load():
 _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
            'stda_bn_layer_count', 'stda_running_count', 'stda_set_arch', 'stda_get_arch', 'stda_workspace_size', 'stda_forward',
+           'stda_forward_noalloc',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_set_grid_cap', 'stda_get_grid_cap', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
@@ -201,6 +203,16 @@ def forward(segs, x, w, running, z, saved, ws, dtype=FP32, mode=EVAL, recompute=
     _check(_lib.stda_forward(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(w), _ptr(running),
                              _ptr(z), _ptr(saved), saved.numel() if saved is not None else 0, _ptr(ws),
                              ws.numel(), dtype, mode, recompute, _stream()), 'stda_forward')
+
+
+NOALLOC_WS_MAX = 32 << 20
+
+
+def forward_noalloc(segs, x, w, running, z, dtype=FP32):
+    """EVAL forward on the library's own static device scratch (no workspace argument)."""
+    arr = _seg_array(segs)
+    _check(_lib.stda_forward_noalloc(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(w), _ptr(running),
+                                     _ptr(z), dtype, _stream()), 'stda_forward_noalloc')
 
 
 def backward(segs, x, dz, w, saved, dw, dx, ws, dtype=FP32, recompute=0):

@@ -94,6 +94,18 @@ def test_validation_before_launch(S):
     # null pointers
     assert lib.stda_forward(p, n, None, fake, fake, fake, fake, sv.value, fake, wb.value, 0, 1, 0, None) == -1
     assert lib.stda_sgd_step(None, fake, 10, ctypes.c_float(0.1), ctypes.c_float(0.0), None, None) == -1
+    # no-allocation EVAL forward: shape, dtype and pointer checks, and batches whose EVAL workspace
+    # exceeds the static scratch array, are refused before any device call
+    for shape, code in (((1, 10, 16, 0, 0), -2), ((0, 16, 16, 0, 0), -1)):
+        q, m = _segs(S, shape)
+        assert lib.stda_forward_noalloc(q, m, fake, fake, fake, fake, 0, None) == code
+    assert lib.stda_forward_noalloc(p, n, fake, fake, fake, fake, 3, None) == -1
+    assert lib.stda_forward_noalloc(p, n, None, fake, fake, fake, 0, None) == -1
+    for dt, clips in ((0, 2), (1, 3)):
+        q, m = _segs(S, (clips, 256, 128, 0, 0))
+        assert lib.stda_workspace_size(q, m, dt, 0, 0, ctypes.byref(sv), ctypes.byref(wb)) == 0
+        assert wb.value > S.NOALLOC_WS_MAX
+        assert lib.stda_forward_noalloc(q, m, fake, fake, fake, fake, dt, None) == -3
     # rd_synth: N and M powers of two in [8, 1024]
     big = 1 << 40
     assert lib.rd_synth(fake, 1, 48, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -2
