@@ -51,17 +51,20 @@ def kernel_work(tag, B, H, W, es):
             'wgrad_main': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
             'wgrad_res': (2.0 * dense_macs, B * (cin * hin + cout * hout) * es, 'mfma'),
             's1_stats': (s1_flops, B * cin * hin * es, 'alu'),
-            's1_apply': (s1_flops, 2.0 * B * cin * hin * es, 'alu'),
+            # writes x1 and, in TRAIN, its ReLU decisions (1 bit per element)
+            's1_apply': (s1_flops, 2.0 * B * cin * hin * es + B * cin * hin / 8.0, 'alu'),
             's2_apply': (4.0 * B * hout * cout, B * hout * cout * (3 * es + 0.25), 'alu'),
             'eca_next': (2.0 * B * hout * cout, B * hout * cout * es * (2 + skip), 'alu'),
             'eca_bwd': (2.0 * B * hout * cout, 2.0 * B * hout * cout * es, 'alu'),
             's2_bwd_stats': (8.0 * B * hout * cout, B * hout * cout * (2 * es + 0.25), 'alu'),
             's2_bwd_apply': (10.0 * B * hout * cout, B * hout * cout * (4 * es + 0.25), 'alu'),
-            's1_bwd_stats': (s1_flops, 3.0 * B * cin * hin * es, 'alu'),
+            # reads x, dx1 and the 1-bit ReLU decisions of x1
+            's1_bwd_stats': (s1_flops, B * cin * hin * (2 * es + 1 / 8.0), 'alu'),
             # three pointwise products (recompute, transpose, weight gradient) and three depthwise
-            # ones (recompute, transpose, weight gradient); reads x, x1, dx1, dxr (+ the skip
-            # gradient in the encoder), writes dx
-            's1_bwd_fused': (2.0 * B * hin * (3 * cin * cin + 27 * cin), (5 + skip_g) * B * cin * hin * es, 'alu'),
+            # ones (recompute, transpose, weight gradient); reads x, the 1-bit ReLU decisions of
+            # x1, dx1, dxr (+ the skip gradient in the encoder), writes dx
+            's1_bwd_fused': (2.0 * B * hin * (3 * cin * cin + 27 * cin),
+                             B * cin * hin * ((4 + skip_g) * es + 1 / 8.0), 'alu'),
         }
         return table.get(kind)
     table = {

@@ -406,7 +406,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     P.ws_wpart = ws.take(sizeof(float) * (size_t)kMaxWgradGrid * 32768);
   }
   // recompute: one scratch set of block internals in ws, shared by every block and segment
-  size_t rx1 = 0, rty = 0, rmask = 0;
+  size_t rx1 = 0, rty = 0, rmask = 0, rm1 = 0;
   const bool rec = train && recompute;
   if (rec) {
     size_t mx1 = 0, mty = 0;
@@ -418,6 +418,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
         mty = std::max(mty, (size_t)b.cout * n * (H >> b.lout) * (W >> b.lout));
       }
     rx1 = ws.take(es * mx1);
+    rm1 = ws.take(mx1 / 8);
     const size_t rt = ws.take(es * mty);
     rty = ws.take(es * mty);
     rmask = ws.take(mty / 4);
@@ -445,11 +446,13 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
         A.T = P.rec_T;
         A.Y = rty;
         A.mask = rmask;
+        A.m1 = rm1;
       } else {
         A.X1 = acts.take(es * b.cin * n * hin * win);
         A.T = acts.take(es * b.cout * n * hout * wout);
         A.Y = acts.take(es * b.cout * n * hout * wout);
         A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
+        A.m1 = train ? acts.take((size_t)b.cin * n * hin * win / 8) : 0;
       }
       A.Xn = acts.take(es * b.cout * n * hout * wout);
       A.a = acts.take(sizeof(float) * b.cout * n);
@@ -642,12 +645,13 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
   const int g1 = s1_grid<CIN>(n, hin, win);
   const bool stats_pass = c.train && !c.rec_pass;
   if (stats_pass) {
-    KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, part, sp, n, hin, win));
+    KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
     if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro)) return r;
   }
-  KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, nullptr, sp, n, hin, win));
+  uint8_t* m1 = c.train ? c.template inner<uint8_t>(A, A.m1) : nullptr;
+  KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, m1, nullptr, sp, n, hin, win));
   // stage 2: main (with statistics) and residual
   constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
   if (stats_pass) {
@@ -939,23 +943,23 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
 // Fused stage-1 adjoint of block `blk` with the tiling chosen for it (tuning kind 3): TH x TW
 // pixel tiles, MINW waves per SIMD; *rows = workgroups = rows of weight-gradient partials.
 template <class T, int C, bool DEC, int TH, int TW, int MINW>
-int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, const T* dXr, const T* skipg,
+int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T* dX1, const T* dXr, const T* skipg,
                    const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
   const int64_t tiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int g = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
   const float* coef = c.template scr<float>(c.P->ws_coef);
   KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW><<<g, 256, 0, c.st>>>(
-                                         X, X1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
+                                         X, M1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
   *rows = g;
   return STDA_OK;
 }
 
 template <class T, int C, bool DEC>
-int launch_s1b(const Ctx<T>& c, int blk, const T* X, const T* X1, const T* dX1, const T* dXr, const T* skipg,
+int launch_s1b(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T* dX1, const T* dXr, const T* skipg,
                const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
 #define S1B(TH_, TW_, W_) \
-  launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, X1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
+  launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
   if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1B(8, 8, 2) : S1B(8, 16, 2);
   else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1B(4, 8, 2) : S1B(8, 8, 2);
   else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1B(8, 2, 2) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
@@ -988,6 +992,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
   const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
   const T* X1 = c.template inner<T>(A, A.X1);
+  const uint8_t* M1 = c.template inner<uint8_t>(A, A.m1);
   const T* Tm = c.template inner<T>(A, A.T);
   const T* Y = c.template inner<T>(A, A.Y);
   auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
@@ -1052,7 +1057,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   sp.beta[2] = c.w + bo.id_b;
   const int g1 = s1_grid<CIN>(n, hin, win);
   KLAUNCH(tagk("s1_bwd_stats", k),
-          k_s1_bwd_stats_tile<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, X1, dX1, part, sp, n, hin, win));
+          k_s1_bwd_stats_tile<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, M1, dX1, part, sp, n, hin, win));
   {
     float* dg[3] = {dw + bo.pw_g, dw + bo.dw_g, dw + bo.id_g};
     float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
@@ -1062,7 +1067,7 @@ int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, flo
   if ((skipg != nullptr) != !DEC) return STDA_E_INVALID;
   float* pwpart = c.template scr<float>(c.P->ws_wpart);
   int rows = 0;
-  if (int r = launch_s1b<T, CIN, DEC>(c, k, X, X1, dX1, dXr, skipg, sp, dXout, pwpart, part, n, hin, win, &rows))
+  if (int r = launch_s1b<T, CIN, DEC>(c, k, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, part, n, hin, win, &rows))
     return r;
   const ColMap pwmap = (c.P->arch & STDA_ARCH_PW_DW) ? ColMap{MAP_PW_DIAG, CIN, 0}
                                                       : ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0};

@@ -58,7 +58,8 @@ const NetOffsets& net_offsets(int arch);
 // Byte offsets of one segment's activations (in `saved` for TRAIN, in `ws` for EVAL).
 struct BlockActs {
   size_t X1, T, Y, Xn, a, g, mask;  // mask: stage-2 ReLU decisions, 4 bits per byte
-  bool inner_in_ws;                 // X1, T, Y, mask live in ws (recomputed in the backward)
+  size_t m1;                        // stage-1 ReLU decisions (X1 > 0), 1 bit per element
+  bool inner_in_ws;                 // X1, T, Y, mask, m1 live in ws (recomputed in the backward)
 };
 struct SegPlan {
   int n, H, W;

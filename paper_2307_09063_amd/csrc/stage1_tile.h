@@ -187,10 +187,12 @@ __device__ __forceinline__ void s1_dw_regs(const float* wd, int c0, float (&wr)[
 }
 
 // Forward.  MODE 0: per-block partials of (sum, sumsq) of the three BN inputs,
-// part[blk][3][C][2].  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)).
+// part[blk][3][C][2].  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)) and, if M1 is not null, the
+// ReLU decisions X1 > 0 as one bit per element (M1[pixel][C / 8], channel c at byte c / 8, bit
+// c % 8), which is all the adjoint needs of X1.
 template <class T, int C, bool DEC, int MODE>
-__global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __restrict__ X1, float* __restrict__ part,
-                                                 S1Params prm, int B, int h, int w) {
+__global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __restrict__ X1, uint8_t* __restrict__ M1,
+                                                 float* __restrict__ part, S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
   constexpr int XN = (TH + 2) * RW, PN = TH * TW;  // pixels of the x tile (halo 1) and of the tile
@@ -254,7 +256,15 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           o[j] = fmaxf(pv[j] * sc[0][j] + sh[0][j] + dv[j] * sc[1][j] + sh[1][j] + xv[j] * sc[2][j] + sh[2][j], 0.f);
-        st4(X1 + (((int64_t)b * h + y) * w + x) * C + c0, o);
+        const int64_t pix = ((int64_t)b * h + y) * w + x;
+        st4(X1 + pix * C + c0, o);
+        if (M1) {
+          // this thread's 4 decisions; the neighbouring lane holds the other half of the byte (the
+          // two lanes share the pixel, so both are active here)
+          const int nib = (o[0] > 0.f) | ((o[1] > 0.f) << 1) | ((o[2] > 0.f) << 2) | ((o[3] > 0.f) << 3);
+          const int hi = __shfl_xor(nib, 1);
+          if (!(c0 & 4)) M1[pix * (C / 8) + (c0 >> 3)] = (uint8_t)(nib | (hi << 4));
+        }
       }
     }
   }
@@ -267,10 +277,11 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
   }
 }
 
-// Backward statistics: du = dX1 [X1 > 0]; part[blk][4][C] = sum du, sum du*phat, sum du*dhat,
-// sum du*xhat (branch outputs recomputed from the tile).
+// Backward statistics: du = dX1 [X1 > 0] (the decisions read from the bit mask M1 the forward
+// wrote); part[blk][4][C] = sum du, sum du*phat, sum du*dhat, sum du*xhat (branch outputs
+// recomputed from the tile).
 template <class T, int C, bool DEC>
-__global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__ X, const T* __restrict__ X1,
+__global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__ X, const uint8_t* __restrict__ M1,
                                                            const T* __restrict__ dX1, float* __restrict__ part,
                                                            S1Params prm, int B, int h, int w) {
   typedef S1Geo<C> Gm;
@@ -307,15 +318,16 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     constexpr int NI = TH * TW * G;
     constexpr bool PF = sizeof(T) == 2 && C > 16;
     typedef typename Raw4<T>::type R4;
-    R4 nx1, ng;
+    R4 ng;
+    uint32_t nm;  // the byte of M1 holding this thread's 4 decisions
     auto item_load = [&](int e) {
       const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
       if (e < NI && y < h && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        raw_ld4(X1 + off, nx1);
+        nm = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
         raw_ld4(dX1 + off, ng);
       } else {
-        raw_zero4(nx1);
+        nm = 0;
         raw_zero4(ng);
       }
     };
@@ -330,9 +342,10 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     for (int e = threadIdx.x; e < NI; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
-      float x1[4], g[4];
+      float g[4];
+      uint32_t m;
       if constexpr (PF) {
-        raw_cvt4(nx1, x1);
+        m = nm;
         raw_cvt4(ng, g);
         if (e + STDA_BLOCK < NI) item_load(e + STDA_BLOCK);
       }
@@ -351,12 +364,13 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
       s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
       if constexpr (!PF) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        ld4(X1 + off, x1);
+        m = M1[off >> 3];
         ld4(dX1 + off, g);
       }
+      m >>= (c0 & 4);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const float du = x1[j] > 0.f ? g[j] : 0.f;
+        const float du = (m >> j) & 1u ? g[j] : 0.f;
         acc[0][j] += du;
         acc[1][j] += du * (pv[j] - mu[0][j]) * is[0][j];
         acc[2][j] += du * (dv[j] - mu[1][j]) * is[1][j];
@@ -368,7 +382,8 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
   for (int q = threadIdx.x; q < 4 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 4 * C + q] = red[q];
 }
 
-// Fused backward of stage 1.  With du = dX1 [X1 > 0] and the BN adjoint coefficients
+// Fused backward of stage 1.  With du = dX1 [X1 > 0] (decisions from the bit mask M1 of the
+// forward) and the BN adjoint coefficients
 // k[s][c] = (sum du, sum du*phat, sum du*dhat, sum du*xhat) / n:
 //   dP = g_p is_p (du - k0 - phat k1), dD = g_d is_d (du - k0 - dhat k2),
 //   dX = g_x is_x (du - k0 - xhat k3) + dXr + PW^T(dP) + DW^T(dD) (+ skip gradient),
@@ -381,7 +396,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 // products (p = x Wp, dP Wp^T, x^T dP) run on the matrix cores, the last one accumulating in
 // registers across tiles.  Tiles are TH x TW pixels; MINW waves per SIMD bound the registers.
 template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW>
-__global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict__ X, const T* __restrict__ X1,
+__global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict__ X, const uint8_t* __restrict__ M1,
                                                          const T* __restrict__ dX1, const T* __restrict__ dXr,
                                                          const T* __restrict__ skip, const float* __restrict__ coef,
                                                          S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
@@ -440,21 +455,23 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
-    // x1 and dx1 of the thread's next dD-phase item (zero off the map), one item ahead: the first
-    // item's loads overlap the staging and the first product, each later one the previous item.
-    // Not at 64 channels, whose tiles have no registers to spare: there each item loads its own.
+    // the ReLU decisions and dx1 of the thread's next dD-phase item (zero off the map), one item
+    // ahead: the first item's loads overlap the staging and the first product, each later one the
+    // previous item.  Not at 64 channels, whose tiles have no registers to spare: there each item
+    // loads its own.
     constexpr int NA = (TH + 2) * DWd * G;
     constexpr bool PF = C < 64;
     typedef typename Raw4<T>::type R4;  // held in storage form until used
-    R4 nx1, ng;
+    R4 ng;
+    uint32_t nm;  // the byte of M1 holding this thread's 4 decisions
     auto a2_load = [&](int e) {
       const int px = e / G, y = y0 - 1 + px / DWd, x = x0 - 1 + px % DWd;
       if (e < NA && y >= 0 && y < h && x >= 0 && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        raw_ld4(X1 + off, nx1);
+        nm = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
         raw_ld4(dX1 + off, ng);
       } else {
-        raw_zero4(nx1);
+        nm = 0;
         raw_zero4(ng);
       }
     };
@@ -472,9 +489,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       const int px = e / G, r = px / DWd, cc = px % DWd;  // position in the dD tile
       const int y = y0 - 1 + r, x = x0 - 1 + cc;
       const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
-      float x1[4], g[4];
+      float g[4];
+      uint32_t m;
       if constexpr (PF) {
-        raw_cvt4(nx1, x1);
+        m = nm;
         raw_cvt4(ng, g);
         if (e + STDA_BLOCK < NA) a2_load(e + STDA_BLOCK);
       }
@@ -485,9 +503,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
       if (y >= 0 && y < h && x >= 0 && x < w) {
         if constexpr (!PF) {
           const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-          ld4(X1 + off, x1);
+          m = M1[off >> 3];
           ld4(dX1 + off, g);
         }
+        m >>= (c0 & 4);
         float dv[4];
         float4 xn[9];
         s1_dw_lds_keep<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv, xn);
@@ -502,7 +521,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         const float *pa = cfr[0], *pb = cfr[1], *pe = cfr[2], *da = cfr[3], *db = cfr[4], *de = cfr[5];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const float du = x1[j] > 0.f ? g[j] : 0.f;
+          const float du = (m >> j) & 1u ? g[j] : 0.f;
           uv[j] = du;
           od[j] = da[j] * du + db[j] * dv[j] + de[j];
           op[j] = pa[j] * du + pb[j] * pv[j] + pe[j];
