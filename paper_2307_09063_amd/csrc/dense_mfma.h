@@ -102,9 +102,10 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
   const int64_t P = (int64_t)B * hr * wr;
   const int64_t tiles = (P + 64 * R - 1) / (64 * R);
   const F* wf = reinterpret_cast<const F*>(wfrag);
-  float st1[NT], st2[NT];
+  float mn[NT], q2[NT];  // STATS: mean and m2 of this lane's columns 16 nt + m (Welford)
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) st1[nt] = st2[nt] = 0.f;
+  for (int nt = 0; nt < NT; ++nt) mn[nt] = q2[nt] = 0.f;
+  float cnt = 0.f;  // rows seen by this lane
 
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t pbase = (tile * 4 + wave) * 16 * R;
@@ -167,37 +168,53 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
           pix3(p, hr, wr, b, y, x);
           dp = ((int64_t)b * hd + 2 * y + py) * wd + 2 * x + px;
         }
+        float rk = 0.f;
+        if (STATS) {
+          cnt += 1.f;
+          rk = __builtin_amdgcn_rcpf(cnt);
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const float v = acc[r][nt][i];
           dst[dp * N + 16 * nt + m] = from_f<T>(v);
-          if (STATS) {
-            st1[nt] += v;
-            st2[nt] += v * v;
-          }
+          if (STATS) wf_add(mn[nt], q2[nt], v, rk);
         }
       }
   }
   if (STATS) {
-    __shared__ float sm[4][2][N];
-    // reduce over the 4 lane groups (same channel), then over the 4 waves, in a fixed order
+    // part[blk][N][2] = (mean, m2), the block's count at part[blocks * 2 N + blk]: merge over the
+    // 4 lane groups (same channel), then over the 4 waves, in a fixed order
+    __shared__ float sm[4][2 * N + 1];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      float a1 = st1[nt], a2 = st2[nt];
-      a1 += __shfl_xor(a1, 16);
-      a2 += __shfl_xor(a2, 16);
-      a1 += __shfl_xor(a1, 32);
-      a2 += __shfl_xor(a2, 32);
-      if (g == 0) {
-        sm[wave][0][16 * nt + m] = a1;
-        sm[wave][1][16 * nt + m] = a2;
+    for (int off = 16; off < 64; off <<= 1) {
+      const float nb = __shfl_xor(cnt, off);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const float mb = __shfl_xor(mn[nt], off), qb = __shfl_xor(q2[nt], off);
+        chan_merge(cnt, mn[nt], q2[nt], nb, mb, qb);
       }
+      cnt += nb;
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        sm[wave][16 * nt + m] = mn[nt];
+        sm[wave][N + 16 * nt + m] = q2[nt];
+      }
+      if (m == 0) sm[wave][2 * N] = cnt;
     }
     __syncthreads();
     const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    for (int q = threadIdx.x; q < 2 * N; q += STDA_BLOCK) {
-      const int c = q >> 1, s = q & 1;
-      part[blk * 2 * N + q] = sm[0][s][c] + sm[1][s][c] + sm[2][s][c] + sm[3][s][c];
+    for (int c = threadIdx.x; c < N; c += STDA_BLOCK) {
+      float na = sm[0][2 * N], ma = sm[0][c], qa = sm[0][N + c];
+#pragma unroll
+      for (int wv = 1; wv < 4; ++wv) {
+        chan_merge(na, ma, qa, sm[wv][2 * N], sm[wv][c], sm[wv][N + c]);
+        na += sm[wv][2 * N];
+      }
+      part[blk * 2 * N + 2 * c] = ma;
+      part[blk * 2 * N + 2 * c + 1] = qa;
+      if (c == 0) part[(int64_t)gridDim.x * gridDim.y * 2 * N + blk] = na;
     }
   }
 }

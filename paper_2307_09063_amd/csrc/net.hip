@@ -600,9 +600,9 @@ int head_grid(int n, int H, int W) {
   return (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
 }
 
-// Column sums of per-block BN partials followed by the statistics finalize.
+// FP64 merge of the per-block BN statistics (count, mean, m2) followed by the finalize.
 template <class T>
-int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* const* stats_out,
+int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, float* const* stats_out,
                 float* const* running) {
   float* part = c.template scr<float>(c.P->ws_part);
   BnOut o{};
@@ -610,7 +610,7 @@ int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, double count, float* c
     o.stats[i] = stats_out[i];
     o.running[i] = running ? running[i] : nullptr;
   }
-  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(part, nblk, NB, C, count, o, running ? 1 : 0));
+  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(part, nblk, NB, C, o, running ? 1 : 0));
   return STDA_OK;
 }
 
@@ -648,7 +648,7 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
     KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, nullptr, part, sp, n, hin, win));
     float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
     float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
-    if (int r = bn_finalize(c, g1, 3, CIN, (double)Pin, so, ro)) return r;
+    if (int r = bn_finalize(c, g1, 3, CIN, so, ro)) return r;
   }
   uint8_t* m1 = c.train ? c.template inner<uint8_t>(A, A.m1) : nullptr;
   KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, m1, nullptr, sp, n, hin, win));
@@ -660,7 +660,7 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
       return r;
     float* so[1] = {c.stats(bo.bn_main)};
     float* ro[1] = {running + bo.bn_main};
-    if (int r = bn_finalize(c, nb, 1, COUT, (double)Pout, so, ro)) return r;
+    if (int r = bn_finalize(c, nb, 1, COUT, so, ro)) return r;
   } else {
     if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
                                                        nullptr))
@@ -717,7 +717,7 @@ int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
     KLAUNCH("stem_stats", k_stem_tile<T, 0><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, nullptr, S.n, S.H, S.W));
     float* so[1] = {c.stats(0)};
     float* ro[1] = {running};
-    if (int r = bn_finalize(c, gs, 1, 16, (double)P, so, ro)) return r;
+    if (int r = bn_finalize(c, gs, 1, 16, so, ro)) return r;
   }
   KLAUNCH("stem_apply", k_stem_tile<T, 1><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;

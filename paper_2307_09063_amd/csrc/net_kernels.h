@@ -69,6 +69,74 @@ __device__ __forceinline__ void block_chan_reduce_shfl(float (&v)[NS][4], float*
   __syncthreads();
 }
 
+// ------------------------------------------------------------------ batch-norm statistics
+// A channel's statistics are kept as (count, mean, m2 = sum of squared deviations from the mean):
+// Welford's update adds one value, Chan, Golub and LeVeque's pairwise formula merges two partial
+// results.  No sum of squares about zero is formed, whose difference E[x^2] - E[x]^2 would lose
+// (mean / std)^2 of its precision.
+// Adds the k-th value v (rk = 1 / k, the hardware reciprocal: its rounding only perturbs the weight
+// of v in the running mean, which m2's update uses consistently) to (mean, m2).
+__device__ __forceinline__ void wf_add(float& mean, float& m2, float v, float rk) {
+  const float d = v - mean;
+  mean = fmaf(d, rk, mean);
+  m2 = fmaf(d, v - mean, m2);
+}
+// Merges (nb, mb, qb) into (ma, qa) of count na (the caller updates the count to na + nb).
+__device__ __forceinline__ void chan_merge(float na, float& ma, float& qa, float nb, float mb, float qb) {
+  if (nb > 0.f) {
+    const float f = nb / (na + nb), d = mb - ma;
+    ma = fmaf(d, f, ma);
+    qa = qa + qb + d * d * na * f;
+  }
+}
+
+// Block merge of per-thread statistics, channel-group layout of block_chan_reduce_shfl: thread
+// holds count n (the same for all its channels) and (m, q)[s][j] for channels 4 (lane % G) + j
+// of NS statistics sets.  Lanes of one channel group merge with shuffles, then the 4 waves
+// through LDS in a fixed order.  Result: red[s C + c] = mean, red[NS C + s C + c] = m2, and
+// red[2 NS C] = the block's count.  sm holds 4 (2 NS C + 1) floats.
+template <int G, int NS>
+__device__ __forceinline__ void block_chan_stats(float n, float (&m)[NS][4], float (&q)[NS][4], float* sm, float* red) {
+  constexpr int C = 4 * G, ROW = 2 * NS * C + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = G; off < 64; off <<= 1) {
+    const float nb = __shfl_xor(n, off);
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float mb = __shfl_xor(m[s][j], off), qb = __shfl_xor(q[s][j], off);
+        chan_merge(n, m[s][j], q[s][j], nb, mb, qb);
+      }
+    n += nb;
+  }
+  if (lane < G) {
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sm[wave * ROW + s * C + 4 * lane + j] = m[s][j];
+        sm[wave * ROW + NS * C + s * C + 4 * lane + j] = q[s][j];
+      }
+    if (lane == 0) sm[wave * ROW + 2 * NS * C] = n;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < NS * C; i += STDA_BLOCK) {
+    float na = sm[2 * NS * C], ma = sm[i], qa = sm[NS * C + i];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      const float nb = sm[w * ROW + 2 * NS * C];
+      chan_merge(na, ma, qa, nb, sm[w * ROW + i], sm[w * ROW + NS * C + i]);
+      na += nb;
+    }
+    red[i] = ma;
+    red[NS * C + i] = qa;
+    if (i == 0) red[2 * NS * C] = na;
+  }
+  __syncthreads();
+}
+
 // Sum over the block of NV values per thread (all threads hold the same quantities).
 template <int NV>
 __device__ __forceinline__ void block_vec_reduce(const float (&v)[NV], float* sm, float* red) {
@@ -195,41 +263,58 @@ __global__ __launch_bounds__(256) void k_colsum2(ColJob a, ColJob b, int accumul
     colsum_block<16, 256>(b.part, b.nrows, b.ncols, nullptr, b.fout, b.map, accumulate, blockIdx.x - a.nblk);
 }
 
-// Batch statistics from column sums: sums[(i*C + c)*2 + {0,1}] = (sum, sum of squares) of
-// BN layer i.  Writes stats_i = [mean C][invstd C]; updates the running buffer when asked.
+// Batch statistics of BN layers from per-block partials.
 struct BnOut {
   float* stats[3];
   float* running[3];
 };
-// Cross-block FP64 reduction of batch-norm statistics partials fused with their finalize.
-// part[blk][NB][C][2]: (sum, sum of squares) per BN layer and channel.  Block = 4 channels of
-// one layer (8 columns) x 32 row groups; fixed summation order.
+// Cross-block FP64 merge of batch-norm statistics partials fused with their finalize.
+// part[blk][NB][C][2] = (mean, m2) of the block's values per BN layer and channel, followed by
+// the blocks' counts cnt[blk] (floats) at part + nrows NB C 2.  In FP64, one pass in a fixed
+// order, about the first block's mean m0 (d_b = mean_b - m0): n = sum n_b, s = sum n_b d_b,
+// q = sum (m2_b + n_b d_b^2); mean = m0 + s / n, var = (q - s^2 / n) / n.  The block means lie
+// within a few standard deviations of each other, so nothing cancels beyond FP64's reach.
+// Writes stats_i = [mean C][invstd C]; updates the running buffer (momentum 0.1, unbiased
+// variance) when asked.  Block = 4 channels of one layer x 64 row groups.
 __global__ __launch_bounds__(256) void k_bn_stats_reduce(const float* __restrict__ part, int nrows, int NB, int C,
-                                                         double count, BnOut out, int update_running) {
-  __shared__ double sm[32][9];
-  const int col = threadIdx.x & 7, rg = threadIdx.x >> 3;
+                                                         BnOut out, int update_running) {
+  __shared__ double sm[64][4][3];
+  const int cl = threadIdx.x & 3, rg = threadIdx.x >> 2;
   const int i = (blockIdx.x * 4) / C, c0 = (blockIdx.x * 4) % C;
-  const int ncols = NB * C * 2;
-  const int gcol = (i * C + c0) * 2 + col;
-  const double acc = strided_sum(part, rg, 32, nrows, ncols, gcol);
-  sm[rg][col] = acc;
+  const int64_t ncols = (int64_t)NB * C * 2;
+  const int64_t col = (int64_t)(i * C + c0 + cl) * 2;
+  const float* __restrict__ cnt = part + (int64_t)nrows * ncols;
+  const double m0 = (double)part[col];
+  double n = 0.0, s = 0.0, q = 0.0;
+#pragma unroll 4
+  for (int r = rg; r < nrows; r += 64) {
+    const double nb = (double)cnt[r];
+    const double d = (double)part[(int64_t)r * ncols + col] - m0;
+    n += nb;
+    s += nb * d;
+    q += (double)part[(int64_t)r * ncols + col + 1] + nb * d * d;
+  }
+  sm[rg][cl][0] = n;
+  sm[rg][cl][1] = s;
+  sm[rg][cl][2] = q;
   __syncthreads();
   if (threadIdx.x < 4) {
     const int c = c0 + threadIdx.x;
-    double S = 0.0, Q = 0.0;
-    for (int k = 0; k < 32; ++k) {
-      S += sm[k][2 * threadIdx.x];
-      Q += sm[k][2 * threadIdx.x + 1];
+    double nt = 0.0, st = 0.0, qt = 0.0;
+    for (int k = 0; k < 64; ++k) {
+      nt += sm[k][threadIdx.x][0];
+      st += sm[k][threadIdx.x][1];
+      qt += sm[k][threadIdx.x][2];
     }
-    const double mean = S / count;
-    double var = Q / count - mean * mean;
+    const double mu = nt > 0.0 ? m0 + st / nt : 0.0;
+    double var = nt > 0.0 ? (qt - st * st / nt) / nt : 0.0;
     if (var < 0.0) var = 0.0;
-    out.stats[i][c] = (float)mean;
+    out.stats[i][c] = (float)mu;
     out.stats[i][C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
     if (update_running) {
       float* rn = out.running[i];
-      const double unb = count > 1.0 ? var * count / (count - 1.0) : var;
-      rn[c] = (float)(0.9 * (double)rn[c] + 0.1 * mean);
+      const double unb = nt > 1.0 ? var * nt / (nt - 1.0) : var;
+      rn[c] = (float)(0.9 * (double)rn[c] + 0.1 * mu);
       rn[C + c] = (float)(0.9 * (double)rn[C + c] + 0.1 * unb);
     }
   }

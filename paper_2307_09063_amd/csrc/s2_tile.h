@@ -14,7 +14,7 @@
 //      phase, all NB/16 column tiles, A fragments and B fragments both read from LDS;
 //   4. writes the FP32 accumulators, rounded to the storage type, into an LDS staging tile that
 //      aliases the source rectangle, and stores it with 16-byte writes, contiguous along a row;
-//   5. optionally accumulates BN partial sums (sum, sum of squares) of the FP32 results.
+//   5. optionally accumulates the BN statistics (count, mean, m2) of the FP32 results.
 // Tiles are handed out XCD by XCD: consecutive workgroup indices alternate over the 8 XCDs, so
 // workgroup b walks the tiles of the contiguous range owned by XCD b % 8, which keeps the halo
 // rows shared by neighbouring tiles inside one L2.
@@ -94,9 +94,10 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
     }
   }
 
-  float st1[NTB], st2[NTB];
+  float mn[NTB], q2[NTB];  // STATS: mean and m2 of this lane's columns 16 j + m (Welford)
 #pragma unroll
-  for (int j = 0; j < NTB; ++j) st1[j] = st2[j] = 0.f;
+  for (int j = 0; j < NTB; ++j) mn[j] = q2[j] = 0.f;
+  float cnt = 0.f;  // rows seen by this lane
 
   const int nty = (hd + TH - 1) / TH, ntx = (wd + TW - 1) / TW;
   const int64_t ntiles = (int64_t)B * nty * ntx;
@@ -215,14 +216,16 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
           const int ty = C::DOWN ? p / PW : 2 * (p / PW) + py;
           const int tx = C::DOWN ? p % PW : 2 * (p % PW) + px;
           const bool valid = y0 + ty < hd && x0 + tx < wd;
+          float rk = 0.f;
+          if (STATS && valid) {
+            cnt += 1.f;
+            rk = __builtin_amdgcn_rcpf(cnt);
+          }
 #pragma unroll
           for (int j = 0; j < NTB; ++j) {
             const float v = acc[ph][r][j][i];
             tile_lds[(ty * TW + tx) * C::OP_ + 16 * j + m] = from_f<T>(v);
-            if (STATS && valid) {
-              st1[j] += v;
-              st2[j] += v * v;
-            }
+            if (STATS && valid) wf_add(mn[j], q2[j], v, rk);
           }
         }
     }
@@ -242,29 +245,43 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
     }
   }
   if (STATS) {
-    // part[blockIdx.x][n][2] (n = cb * NB + column): reduce over the 4 lane groups, then the WV
-    // waves, in a fixed order
+    // part[blockIdx.x][n][2] = (mean, m2) (n = cb * NB + column), the block's count at
+    // part[gridDim.x * 2 N + blockIdx.x]: merge over the 4 lane groups, then the WV waves, in a
+    // fixed order
+    constexpr int ROW = 2 * NB + 1;
+    static_assert(WV * ROW * 4 <= (int)sizeof(lds), "statistics scratch fits the tile buffer");
     __syncthreads();
-    float* sm = reinterpret_cast<float*>(lds);  // WV x 2 x NB floats, the tile is no longer needed
+    float* sm = reinterpret_cast<float*>(lds);  // WV x ROW floats, the tile is no longer needed
 #pragma unroll
-    for (int j = 0; j < NTB; ++j) {
-      float a1 = st1[j], a2 = st2[j];
-      a1 += __shfl_xor(a1, 16);
-      a2 += __shfl_xor(a2, 16);
-      a1 += __shfl_xor(a1, 32);
-      a2 += __shfl_xor(a2, 32);
-      if (g == 0) {
-        sm[(wave * 2 + 0) * NB + 16 * j + m] = a1;
-        sm[(wave * 2 + 1) * NB + 16 * j + m] = a2;
+    for (int off = 16; off < 64; off <<= 1) {
+      const float nb = __shfl_xor(cnt, off);
+#pragma unroll
+      for (int j = 0; j < NTB; ++j) {
+        const float mb = __shfl_xor(mn[j], off), qb = __shfl_xor(q2[j], off);
+        chan_merge(cnt, mn[j], q2[j], nb, mb, qb);
       }
+      cnt += nb;
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int j = 0; j < NTB; ++j) {
+        sm[wave * ROW + 16 * j + m] = mn[j];
+        sm[wave * ROW + NB + 16 * j + m] = q2[j];
+      }
+      if (m == 0) sm[wave * ROW + 2 * NB] = cnt;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < 2 * NB; q += BLK) {
-      const int c = q >> 1, s = q & 1;
-      float acc = sm[s * NB + c];
+    for (int c = threadIdx.x; c < NB; c += BLK) {
+      float na = sm[2 * NB], ma = sm[c], qa = sm[NB + c];
 #pragma unroll
-      for (int wv = 1; wv < WV; ++wv) acc += sm[(wv * 2 + s) * NB + c];
-      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2 + s] = acc;
+      for (int wv = 1; wv < WV; ++wv) {
+        const float nb = sm[wv * ROW + 2 * NB];
+        chan_merge(na, ma, qa, nb, sm[wv * ROW + c], sm[wv * ROW + NB + c]);
+        na += nb;
+      }
+      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2] = ma;
+      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2 + 1] = qa;
+      if (cb == 0 && c == 0) part[(int64_t)gridDim.x * 2 * N + blockIdx.x] = na;
     }
   }
 }

@@ -186,8 +186,8 @@ __device__ __forceinline__ void s1_dw_regs(const float* wd, int c0, float (&wr)[
   }
 }
 
-// Forward.  MODE 0: per-block partials of (sum, sumsq) of the three BN inputs,
-// part[blk][3][C][2].  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)) and, if M1 is not null, the
+// Forward.  MODE 0: per-block (mean, m2) of the three BN inputs, part[blk][3][C][2], and the
+// block's count at part[gridDim.x * 6 C + blk] (see block_chan_stats).  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)) and, if M1 is not null, the
 // ReLU decisions X1 > 0 as one bit per element (M1[pixel][C / 8], channel c at byte c / 8, bit
 // c % 8), which is all the adjoint needs of X1.
 template <class T, int C, bool DEC, int MODE>
@@ -200,15 +200,19 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
   __shared__ float pt[S1Lds<C, PN>::SIZE];  // pointwise branch of the tile (matrix cores)
   __shared__ float wp[C * C];
   __shared__ float wd[9 * C];
-  __shared__ float sm[MODE == 0 ? 4 * 6 * C : 1];
-  __shared__ float red[6 * C];
+  __shared__ float sm[MODE == 0 ? 4 * (6 * C + 1) : 1];
+  __shared__ float red[MODE == 0 ? 6 * C + 1 : 1];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
   float wr[9][4];
   s1_dw_regs<C>(wd, c0, wr);
-  float acc[6][4];
+  float mn[3][4], q2[3][4];  // MODE 0: mean and m2 of the p, d, x branches (Welford)
 #pragma unroll
-  for (int s = 0; s < 6; ++s) zero4(acc[s]);
+  for (int s = 0; s < 3; ++s) {
+    zero4(mn[s]);
+    zero4(q2[s]);
+  }
+  float cnt = 0.f;  // pixels seen by this thread
   float sc[3][4], sh[3][4];
   if (MODE == 1)
 #pragma unroll
@@ -242,14 +246,13 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
       xv[3] = xq.w;
       s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
       if (MODE == 0) {
+        cnt += 1.f;
+        const float rk = __builtin_amdgcn_rcpf(cnt);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          acc[0][j] += pv[j];
-          acc[1][j] += pv[j] * pv[j];
-          acc[2][j] += dv[j];
-          acc[3][j] += dv[j] * dv[j];
-          acc[4][j] += xv[j];
-          acc[5][j] += xv[j] * xv[j];
+          wf_add(mn[0][j], q2[0][j], pv[j], rk);
+          wf_add(mn[1][j], q2[1][j], dv[j], rk);
+          wf_add(mn[2][j], q2[2][j], xv[j], rk);
         }
       } else {
         float o[4];
@@ -269,11 +272,12 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
     }
   }
   if (MODE == 0) {
-    block_chan_reduce_shfl<G, 6>(acc, sm, red);
-    for (int q = threadIdx.x; q < 6 * C; q += STDA_BLOCK) {
-      const int s = q / C, c = q % C;
-      part[(int64_t)blockIdx.x * 6 * C + ((s >> 1) * C + c) * 2 + (s & 1)] = red[q];
+    block_chan_stats<G, 3>(cnt, mn, q2, sm, red);
+    for (int q = threadIdx.x; q < 3 * C; q += STDA_BLOCK) {
+      part[(int64_t)blockIdx.x * 6 * C + 2 * q] = red[q];               // mean of (branch q / C, channel q % C)
+      part[(int64_t)blockIdx.x * 6 * C + 2 * q + 1] = red[3 * C + q];   // m2
     }
+    if (threadIdx.x == 0) part[(int64_t)gridDim.x * 6 * C + blockIdx.x] = red[6 * C];
   }
 }
 

@@ -5,7 +5,8 @@
 // the convolution is an M x 16 x 28 GEMM (M = tile pixels, k = c*9 + tap, k = 27 zero) on the
 // matrix cores, reading the im2col operand straight from the staged planes.  The pre-BN output
 // is never stored: every pass recomputes it.
-//   MODE 0  TRAIN statistics: part[blk][16][2] = (sum, sum of squares) of the conv output
+//   MODE 0  TRAIN statistics: part[blk][16][2] = (mean, m2) of the block's conv outputs and
+//           the block's count at part[gridDim.x * 32 + blk] (see block_chan_stats)
 //   MODE 1  s0 = ReLU(BN(conv)) with the given statistics
 //   MODE 2  adjoint statistics: dM = dS [S > 0]; part[blk][2][16] = sum dM, sum dM * that
 //   MODE 3  adjoint apply: dTp = gamma invstd (dM - k0 - that k1); weight gradient
@@ -32,8 +33,8 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
   __shared__ float xs[3 * XR * XC];
   __shared__ float wk[C * 28];
   __shared__ float tt[M * PS];   // conv output of the tile (then dTp in MODE 3)
-  __shared__ float sm[4 * 2 * C];
-  __shared__ float red[2 * C];
+  __shared__ float sm[4 * (2 * C + 1)];
+  __shared__ float red[2 * C + 1];
   for (int q = threadIdx.x; q < C * 28; q += STDA_BLOCK) {
     const int o = q / 28, kk = q % 28;
     wk[q] = kk < 27 ? a.w[o * 27 + kk] : 0.f;
@@ -57,9 +58,10 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       k1[j] = a.coef[C + c0 + j];
     }
   }
-  float acc[2][4];
+  float acc[2][4];  // MODE 2 sums; MODE 0: mean and m2 of channels c0 .. c0 + 3 (Welford)
   zero4(acc[0]);
   zero4(acc[1]);
+  float cnt = 0.f;  // MODE 0: pixels seen by this thread
   // MODE 3: every wave accumulates the weight gradient of a quarter of each tile's pixels, columns
   // k = 0..15 and 16..31 (two independent chains); the waves are summed at the end
   floatx4_t wacc0 = {0.f, 0.f, 0.f, 0.f}, wacc1 = {0.f, 0.f, 0.f, 0.f};
@@ -152,11 +154,10 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
       if (MODE == 0) {
         if (!in) continue;
+        cnt += 1.f;
+        const float rk = __builtin_amdgcn_rcpf(cnt);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[0][j] += t[j];
-          acc[1][j] += t[j] * t[j];
-        }
+        for (int j = 0; j < 4; ++j) wf_add(acc[0][j], acc[1][j], t[j], rk);
       } else if (MODE == 1) {
         if (!in) continue;
         float o[4];
@@ -198,13 +199,23 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       }
     }
   }
-  if (MODE == 0 || MODE == 2) {
-    block_chan_reduce_shfl<G, 2>(acc, sm, red);
-    for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) {
-      // MODE 0: [16][2] (sum, sumsq per channel); MODE 2: [2][16]
-      const int s = q / C, c = q % C;
-      a.part[(int64_t)blockIdx.x * 2 * C + (MODE == 0 ? c * 2 + s : q)] = red[q];
+  if (MODE == 0) {
+    float mn[1][4], q2[1][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      mn[0][j] = acc[0][j];
+      q2[0][j] = acc[1][j];
     }
+    block_chan_stats<G, 1>(cnt, mn, q2, sm, red);
+    for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) {
+      const int s = q / C, c = q % C;  // red: [mean 16][m2 16] -> part [16][2]
+      a.part[(int64_t)blockIdx.x * 2 * C + c * 2 + s] = red[q];
+    }
+    if (threadIdx.x == 0) a.part[(int64_t)gridDim.x * 2 * C + blockIdx.x] = red[2 * C];
+  }
+  if (MODE == 2) {
+    block_chan_reduce_shfl<G, 2>(acc, sm, red);
+    for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) a.part[(int64_t)blockIdx.x * 2 * C + q] = red[q];  // [2][16]
   }
   if (MODE == 3) {
     // lane holds D[4 lg + r][li] = dW[o = 4 lg + r][k = li (wacc0) | 16 + li (wacc1)]; the four
