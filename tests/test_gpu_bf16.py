@@ -1,13 +1,29 @@
-"""BF16 path (BF16 activations, gradients and convolution weights, FP32 accumulation, FP32
-master weights) against the FP64 oracle run on the FP32 master weights.
+"""BF16 path (BF16 activations, activation gradients and stage-2 convolution weights, FP32
+arithmetic, FP32 master weights) against the FP64 oracle and against the BF16 storage model of
+tests/bf16_model.py (the oracle's layers in FP64 with BF16 rounding exactly where the path
+stores; its backward is the oracle's adjoint on the model's cache).
 
-Gates: rel-L2 <= 2e-2 for z and the running statistics; mean |delta SINR| <= 0.05 dB over an
-8-clip batch on z, with the target and noise cells of the scene that produced the input.  Gradients: with activations
-rounded to 8 significant bits, ReLU pre-activations within about 2^-9 of their layer's scale of
-the kink take the other decision than in FP64 (a few per thousand sites); each flip moves a
-batch-norm shift gradient (a sum of n terms of random sign) by about 1/sqrt(n), so per-tensor
-gradient errors of several percent against the FP64 oracle are the expected cost of the format.
-They are reported; the gate on the whole gradient vector is rel-L2 <= 0.25."""
+What the format allows.  Two equally valid BF16 computations, the storage model run twice with
+every stored value perturbed at the scale of FP32 arithmetic's own error (2^-20 relative, about
+what an FP32 sum of a few hundred products carries) before it is rounded, already differ by
+about 2e-3 in z and 3-6 % in the weight gradients: a value moved across a BF16 rounding boundary
+changes by a full BF16 step, the steps shift a few ReLU pre-activations per ten thousand across
+their kink, and every flipped site changes the gradient sums of all layers it feeds by a term of
+full size.  No BF16-storage
+computation of this network can therefore match another one, or the FP64 oracle, to 2e-2 per
+gradient tensor; the spread of those jittered runs (the envelope, computed on the CPU from the
+oracle and the rounding alone) is the format's own floor.
+
+Gates (per case):
+  z and the running statistics against the FP64 oracle: rel-L2 <= 2e-2;
+  z against the storage model: rel-L2 <= 3 x the envelope of z;
+  every parameter gradient tensor, the whole gradient and dx against the storage model's
+  gradient: rel-L2 <= 2e-2 + 2 x that tensor's envelope;
+  SINR (Sec. V-B, Eq. (19)) over 8 clips of the paper's 128 x 64 shape: mean |delta SINR| against
+  the oracle <= 0.05 dB, and per clip |delta SINR(GPU) - delta SINR(model)| <= 0.05 dB.  The
+  per-clip |delta SINR| against the oracle is reported, not gated: the storage model alone
+  reaches 0.10 dB on one clip of the TRAIN batch (the O set is 1-3 cells of a random-weight
+  output), so a per-clip 0.05 dB bound is beyond the format, whatever the kernels do."""
 import sys
 
 import numpy as np
@@ -16,52 +32,80 @@ import torch
 
 from oracle import net, rdsynth
 from paper_2307_09063_amd import inputs
+from tests import bf16_model as M
 from tests import gpu_util as U
 
 pytestmark = pytest.mark.gpu
 
 TOL = 2e-2
-CASES = [(2, 32, 24, False), (2, 40, 36, False), (2, 64, 64, True), (4, 128, 64, True)]
+JITTER = 2.0 ** -20
+# (clips, H, W, scene maps, recompute, jitter seeds); the last case is the 256 x 128 BF16 training
+# path with recomputation from stage checkpoints
+CASES = [(2, 32, 24, False, 0, (1, 2, 3)), (2, 64, 64, True, 0, (1, 2, 3)), (4, 128, 64, True, 0, (1, 2)),
+         (4, 256, 128, True, 1, (1,))]
 
 
-@pytest.mark.parametrize('case', CASES, ids=lambda c: f'{c[0]}x{c[1]}x{c[2]}')
-def test_bf16_train_forward_backward(case):
-    from paper_2307_09063_amd import stda
-    B, H, W, rd = case
-    print('bf16', case, file=sys.stderr, flush=True)
-    if rd:
-        x, y, tab, meta = U.rd_maps(B, H, W, seed=H + W, intf=(1, 2))
-    else:
-        x, y = U.maps(B, H, W, seed=3)
-    w, r = U.weights(), U.running()
-    segs = stda.uniform_segments(B, H, W)
-    sv, wsb = stda.workspace_size(segs, stda.BF16, stda.TRAIN)
-    saved, ws = stda.alloc_bytes(sv), stda.alloc_bytes(wsb)
-    xd, wd, rd_ = U.dev(x), U.dev(w), U.dev(r.copy())
-    z = torch.empty((B, 1, H, W), device='cuda')
-    stda.forward(segs, xd, wd, rd_, z, saved, ws, stda.BF16, stda.TRAIN)
-    g = np.random.default_rng(1).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
-    dw = torch.empty(net.param_count(), device='cuda')
-    dx = torch.empty_like(xd)
-    stda.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws, stda.BF16)
-    torch.cuda.synchronize()
-    zr, rr, cache = net.forward(w, r, x, 'train')
-    gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
-    zc = z.cpu().numpy()
-    assert U.rel_l2(zc, zr) < TOL
-    assert U.rel_l2(rd_.cpu().numpy(), rr) < TOL
-    errs = U.per_tensor_errors(dw.cpu().numpy(), gr)
-    flat = U.rel_l2(dw.cpu().numpy(), gr)
-    print(f'bf16 {case}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e}; grad flat {flat:.2e} '
-          f'dx {U.rel_l2(dx.cpu().numpy(), dxr):.2e} '
-          f'worst ' + ' '.join(f'{k}:{v:.1e}' for k, v in sorted(errs.items(), key=lambda t: -t[1])[:4]),
-          file=sys.stderr, flush=True)
-    assert flat < 0.25
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
 
 
 def _maxabs(a, b):
     """max |a - b| / max |b| (reported next to rel-L2)."""
     return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _envelope(w, r, x, g, seeds):
+    """Per-tensor rel-L2 spread between the storage model and its jittered runs (largest over the
+    seeds), with 'flat', 'dx' and 'z' entries; also returns the model's (z, running, grad, dx)."""
+    zm, cm = M.forward(w, r, x, 'train')
+    gm, dxm = net.backward(g, cm, want_dx=True)
+    env = {}
+    for s in seeds:
+        zj, cj = M.forward(w, r, x, 'train', jitter=(s, JITTER))
+        gj, dxj = net.backward(g, cj, want_dx=True)
+        e = U.per_tensor_errors(gj, gm)
+        e.update(flat=U.rel_l2(gj, gm), dx=U.rel_l2(dxj, dxm), z=U.rel_l2(zj, zm))
+        for k, v in e.items():
+            env[k] = max(env.get(k, 0.0), v)
+    return env, (zm, cm['running'], gm, dxm)
+
+
+@pytest.mark.parametrize('case', CASES, ids=lambda c: f'{c[0]}x{c[1]}x{c[2]}' + ('_recompute' if c[4] else ''))
+def test_bf16_train_forward_backward(case):
+    from paper_2307_09063_amd import stda
+    B, H, W, rd, rec, seeds = case
+    _say('bf16', case[:5])
+    if rd:
+        x, _, _, _ = U.rd_maps(B, H, W, seed=H + W, intf=(1, 2))
+    else:
+        x, _ = U.maps(B, H, W, seed=3)
+    w, r = U.weights(), U.running()
+    segs = stda.uniform_segments(B, H, W)
+    sv, wsb = stda.workspace_size(segs, stda.BF16, stda.TRAIN, rec)
+    saved, ws = stda.alloc_bytes(sv), stda.alloc_bytes(wsb)
+    xd, wd, rd_ = U.dev(x), U.dev(w), U.dev(r.copy())
+    z = torch.empty((B, 1, H, W), device='cuda')
+    stda.forward(segs, xd, wd, rd_, z, saved, ws, stda.BF16, stda.TRAIN, rec)
+    g = np.random.default_rng(1).standard_normal((B, 1, H, W)).astype(np.float32) / (B * H * W)
+    dw = torch.empty(net.param_count(), device='cuda')
+    dx = torch.empty_like(xd)
+    stda.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws, stda.BF16, rec)
+    torch.cuda.synchronize()
+    zc, rc, dwc, dxc = z.cpu().numpy(), rd_.cpu().numpy(), dw.cpu().numpy(), dx.cpu().numpy()
+    zr, rr, cache = net.forward(w, r, x, 'train')
+    gr, dxr = net.backward(g.astype(np.float64), cache, want_dx=True)
+    env, (zm, rm, gm, dxm) = _envelope(w, r, x, g.astype(np.float64), seeds)
+    em = U.per_tensor_errors(dwc, gm)
+    _say(f'bf16 {case[:5]}: vs oracle z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e}, grad {U.rel_l2(dwc, gr):.2e}, '
+         f'dx {U.rel_l2(dxc, dxr):.2e}; vs storage model z {U.rel_l2(zc, zm):.2e} (envelope {env["z"]:.2e}), grad '
+         f'{U.rel_l2(dwc, gm):.2e} (envelope {env["flat"]:.2e}), dx {U.rel_l2(dxc, dxm):.2e} (envelope {env["dx"]:.2e}); '
+         'tensors vs model / envelope: ' + ' '.join(f'{k}:{v:.1e}/{env[k]:.1e}' for k, v in sorted(em.items(), key=lambda t: -t[1])[:4]))
+    assert U.rel_l2(zc, zr) < TOL and U.rel_l2(rc, rr) < TOL
+    assert U.rel_l2(zc, zm) <= 3 * env['z']
+    bad = {k: (v, env[k]) for k, v in em.items() if v > TOL + 2 * env[k]}
+    assert not bad, bad
+    assert U.rel_l2(dwc, gm) <= TOL + 2 * env['flat']
+    assert U.rel_l2(dxc, dxm) <= TOL + 2 * env['dx']
 
 
 def _sinr_deltas(zc, zr, meta, H, W):
@@ -74,12 +118,11 @@ def _sinr_deltas(zc, zr, meta, H, W):
 
 @pytest.mark.parametrize('mode', ['eval', 'train'])
 def test_bf16_sinr_delta(mode):
-    """Mean |delta SINR| over 8 clips of the paper's map shape (128 range x 64 Doppler bins).
-    The O set is one cell per target, so one clip's delta is the error of 1-3 cells of a
-    random-weight output; the SINR of the paper is a mean over its test clips."""
+    """delta SINR over 8 clips of the paper's map shape (128 range x 64 Doppler bins), against the
+    oracle and against the storage model, clip by clip."""
     from paper_2307_09063_amd import stda
     B, H, W = 8, 128, 64
-    print('bf16 sinr', mode, file=sys.stderr, flush=True)
+    _say('bf16 sinr', mode)
     x, _, tab, meta = U.rd_maps(B, H, W, seed=77, intf=(1, 2))
     w, r = U.weights(), U.running()
     m = stda.TRAIN if mode == 'train' else stda.EVAL
@@ -90,13 +133,41 @@ def test_bf16_sinr_delta(mode):
     stda.forward(segs, U.dev(x), U.dev(w), U.dev(r.copy()), z, saved, stda.alloc_bytes(wsb), stda.BF16, m)
     torch.cuda.synchronize()
     zr, _, _ = net.forward(w, r, x, mode)
+    zm, _ = M.forward(w, r, x, mode)
     zc = z.cpu().numpy()
-    ds = _sinr_deltas(zc, zr, meta, H, W)
-    print(f'bf16 {mode}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e}; mean |delta SINR| '
-          f'{np.mean(np.abs(ds)):.4f} dB; per clip ' + ' '.join(f'{d:+.4f}' for d in ds),
-          file=sys.stderr, flush=True)
+    ds, dm = _sinr_deltas(zc, zr, meta, H, W), _sinr_deltas(zm, zr, meta, H, W)
+    _say(f'bf16 {mode}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e} (model {U.rel_l2(zm, zr):.2e}); '
+         f'|delta SINR| mean {np.mean(np.abs(ds)):.4f} max {np.max(np.abs(ds)):.4f} dB (model mean {np.mean(np.abs(dm)):.4f} '
+         f'max {np.max(np.abs(dm)):.4f}); per clip GPU ' + ' '.join(f'{d:+.4f}' for d in ds) + ' model '
+         + ' '.join(f'{d:+.4f}' for d in dm))
     assert U.rel_l2(zc, zr) < TOL
     assert np.mean(np.abs(ds)) <= 0.05, ds
+    assert np.max(np.abs(ds - dm)) <= 0.05, (ds, dm)
+
+
+def test_bf16_eval_sampled_clips_256x128():
+    """EVAL forward of a 64-clip BF16 batch at 256 x 128 (per-clip results are independent in
+    EVAL): four sampled clips against the oracle and the storage model."""
+    from paper_2307_09063_amd import stda
+    B, H, W = 64, 256, 128
+    _say('bf16 eval 64x256x128')
+    x, _, tab, meta = U.rd_maps(B, H, W, seed=41, intf=(0, 3))
+    w, r = U.weights(), U.running()
+    segs = stda.uniform_segments(B, H, W)
+    _, wsb = stda.workspace_size(segs, stda.BF16, stda.EVAL)
+    z = torch.empty((B, 1, H, W), device='cuda')
+    stda.forward(segs, U.dev(x), U.dev(w), U.dev(r.copy()), z, None, stda.alloc_bytes(wsb), stda.BF16, stda.EVAL)
+    torch.cuda.synchronize()
+    pick = [0, 21, 42, 63]
+    zc = z.cpu().numpy()[pick]
+    zr, _, _ = net.forward(w, r, x[pick], 'eval')
+    zm, _ = M.forward(w, r, x[pick], 'eval')
+    sub = {'peaks': [meta['peaks'][i] for i in pick]}
+    ds, dm = _sinr_deltas(zc, zr, sub, H, W), _sinr_deltas(zm, zr, sub, H, W)
+    _say(f'bf16 eval 256x128 clips {pick}: z rel-L2 {U.rel_l2(zc, zr):.2e} max-abs {_maxabs(zc, zr):.2e} (model '
+         f'{U.rel_l2(zm, zr):.2e}, GPU vs model {U.rel_l2(zc, zm):.2e}); delta SINR ' + ' '.join(f'{d:+.4f}' for d in ds))
+    assert U.rel_l2(zc, zr) < TOL
+    assert np.max(np.abs(ds - dm)) <= 0.05, (ds, dm)
 
 
 def test_bf16_eval_forward():

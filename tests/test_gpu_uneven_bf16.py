@@ -1,10 +1,11 @@
 """Uneven batching in BF16 against the per-size FP32 path: one captured training step (forward,
-loss, backward) over clips of three map sizes, each size its own batch-norm segment, against the
-FP32 path run on each size alone, in the same order, on the same weights and running buffer.
-z, the loss (the sum of the per-segment means), the running statistics and the gradient (the sum
-of the per-segment gradients) agree within the BF16 gates of the BF16 parity tests: rel-L2 2e-2
-on z, loss and running statistics, 0.25 on the whole gradient vector (ReLU decisions that BF16
-rounding takes the other way move batch-norm shift gradients; see the BF16 parity tests)."""
+loss, backward) over clips of the three map sizes of the uneven workload (128 x 64, 256 x 128,
+512 x 256), each size its own batch-norm segment, against the FP32 path run on each size alone,
+in the same order, on the same weights and running buffer.  z, the loss (the sum of the
+per-segment means) and the running statistics agree within the BF16 gate (rel-L2 2e-2).  The
+gradient (the sum of the per-segment gradients) is gated as in the BF16 parity tests, against
+the BF16 storage model's gradient of the same step: rel-L2 <= 2e-2 + 2 x the spread of a
+jittered run of the model (the format's own floor; see tests/test_gpu_bf16.py)."""
 import sys
 
 import numpy as np
@@ -12,6 +13,7 @@ import pytest
 import torch
 
 from oracle import net
+from tests import bf16_model as M
 from tests import gpu_util as U
 
 pytestmark = pytest.mark.gpu
@@ -20,7 +22,7 @@ pytestmark = pytest.mark.gpu
 def test_uneven_bf16_graph_matches_per_size_fp32():
     from paper_2307_09063_amd import stda as S
     print('uneven bf16 vs per-size fp32', file=sys.stderr, flush=True)
-    parts = [(3, 16, 16), (2, 32, 24), (2, 48, 32)]
+    parts = [(2, 128, 64), (1, 256, 128), (1, 512, 256)]
     xs, ys = zip(*(U.maps(n, H, W, seed=5 * n + H + W) for n, H, W in parts))
     w0, r0 = U.weights(), U.running()
     # the per-size FP32 path, size by size
@@ -67,5 +69,16 @@ def test_uneven_bf16_graph_matches_per_size_fp32():
         off += n * H * W
     assert abs(b['loss'].item() - loss_sum) <= 2e-2 * abs(loss_sum)
     assert U.rel_l2(b['running'].cpu().numpy(), r_ref) < 2e-2
-    assert U.rel_l2(b['dw'].cpu().numpy(), dw_sum) < 0.25
     np.testing.assert_array_equal(b['w'].cpu().numpy(), w0)   # lr 0, no decay
+    # the storage model's step (segments in order, each its own statistics) and a jittered run
+    gm, gj = np.zeros(net.param_count()), np.zeros(net.param_count())
+    for x_, y_ in zip(xs, ys):
+        for jit, acc in ((None, gm), ((1, 2.0 ** -20), gj)):
+            zm, cm = M.forward(w0, r0, x_, 'train', jitter=jit)
+            _, dzm = net.mse_loss(zm, y_)
+            acc += net.backward(dzm, cm)[0]
+    dwc = b['dw'].cpu().numpy()
+    env = U.rel_l2(gj, gm)
+    print(f'  gradient rel-L2 vs storage model {U.rel_l2(dwc, gm):.2e} (envelope {env:.2e}), vs per-size FP32 '
+          f'{U.rel_l2(dwc, dw_sum):.2e} (model vs FP32 {U.rel_l2(gm, dw_sum):.2e})', file=sys.stderr, flush=True)
+    assert U.rel_l2(dwc, gm) <= 2e-2 + 2 * env
