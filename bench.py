@@ -148,9 +148,11 @@ def make_batch(stda, inputs, torch, recipe_name, dev, rd_time=False):
     y = torch.empty(nx // 3, device=dev)
     rd_ms = 0.0
     xo = yo = 0
+    metas = []
     for gi, (n, H, W) in enumerate(groups):
         tab, meta = inputs.make_scenes(n, H, W, rc['seed'] + 101 * gi, targets=rc['targets'], intf=rc['intf'],
                                        inr=rc['inr'], clutter=rc['clutter'])
+        metas.append(meta)
         scenes = stda.upload_scenes(tab, dev)
         rws = stda.alloc_bytes(stda.rd_synth_workspace_size(n, H, W), dev)
         xv = x[xo:xo + 3 * n * H * W]
@@ -168,6 +170,7 @@ def make_batch(stda, inputs, torch, recipe_name, dev, rd_time=False):
         xo += 3 * n * H * W
         yo += n * H * W
     torch.cuda.synchronize()
+    make_batch.metas = metas  # per-group scene records (target peak cells), for the accuracy check
     return segs, groups, x, y, rd_ms
 
 
@@ -338,6 +341,9 @@ def main():
           f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)
 
     extra = {}
+    bf16_batches = {}
+    if dtype == stda.BF16:
+        bf16_batches[args.workload] = (segs, groups, x, make_batch.metas, tr.w, tr.running)
     if not args.train_only:
         fwd_ms, Bf, det = eval_forward(stda, inputs, torch, tr.w, tr.running, dev)
         extra['fwd_eval_fp32_b32_256x128'] = {'ms': round(fwd_ms, 4), 'clips_per_s': round(Bf / (fwd_ms / 1e3), 1)}
@@ -363,20 +369,31 @@ def main():
             t2.timed(2, True)
             m2 = t2.timed(max(3, args.steps // 2), True)
             n2 = sum(g[0] for g in gr)
+            bf16_batches[other] = (sg, gr, xo, make_batch.metas, t2.w, t2.running)
             extra[other] = {'ms_per_step': round(m2, 4), 'clips_per_s': round(n2 / (m2 / 1e3), 1), 'dtype': dn,
                             'recompute': rec, 'segments': [list(g) for g in gr], 'tiles': tiles2,
                             'roofline_stage2_layers': layers2}
             print(f'bench: {other}: {m2:.3f} ms/step ({n2 / (m2 / 1e3):.0f} clips/s)', file=sys.stderr, flush=True)
             t2.graph.close()
-            del t2, xo, yo
+            del t2, yo
             torch.cuda.empty_cache()
 
-    cpu = None
+    cpu = main_err = None
     if not args.no_cpu_baseline:
         k = args.cpu_sample_clips
         cpu = cpu_baseline(k, N, M, x[:3 * k * N * M].view(k, 3, N, M).cpu().numpy(),
                            y[:k * N * M].view(k, 1, N, M).cpu().numpy(), tr.w.cpu().numpy(),
                            tr.running.cpu().numpy())
+        # the oracle leg also checks the BF16 workloads' forward on sampled clips
+        for name, b in bf16_batches.items():
+            acc = bf16_error_vs_oracle(stda, torch, *b, dev)
+            if name == args.workload:
+                main_err = acc
+            else:
+                extra[name]['error_vs_oracle'] = acc
+            print(f'bench: {name}: BF16 error on sampled clips: max z rel-L2 {acc["max_z_rel_l2"]:.2e}, '
+                  f'max |delta SINR| {acc["max_abs_delta_sinr_db"]:.4f} dB', file=sys.stderr, flush=True)
+    bf16_batches.clear()
 
     out = {
         'metric': '3-frame RD clips/s, fwd+bwd training step',
@@ -400,8 +417,43 @@ def main():
         'roofline_stage2_layers': layers or None,
         'cpu_baseline': cpu,
     }
+    if main_err is not None:
+        out['error_vs_oracle'] = main_err
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def bf16_error_vs_oracle(stda, torch, segs, groups, x, metas, w, running, dev, per_group=2):
+    """Accuracy of a BF16 workload's forward on sampled clips (part of the oracle leg: run only
+    with the CPU baseline).  The workload's batch goes through the BF16 EVAL forward (per-clip
+    results are independent in EVAL); `per_group` clips of each map size are compared with the
+    FP64 oracle's EVAL forward of the same clips: rel-L2 and max |a - b| / max |b| of z, and the
+    SINR delta of Sec. V-B Eq. (19) per clip on the scene's target and noise cells."""
+    import numpy as np
+
+    from oracle import net, rdsynth
+    from paper_2307_09063_amd import inputs
+    _, wsb = stda.workspace_size(segs, stda.BF16, stda.EVAL)
+    z = torch.empty(sum(n * H * W for n, H, W in groups), device=dev)
+    stda.forward(segs, x, w, running, z, None, stda.alloc_bytes(wsb, dev), stda.BF16, stda.EVAL)
+    torch.cuda.synchronize()
+    wn, rn = w.cpu().numpy(), running.cpu().numpy()
+    res, xo, zo = [], 0, 0
+    for (n, H, W), meta in zip(groups, metas):
+        for c in np.linspace(0, n - 1, per_group).round().astype(int)[:n]:
+            xc = x[xo + 3 * c * H * W: xo + 3 * (c + 1) * H * W].view(1, 3, H, W).cpu().numpy()
+            zc = z[zo + c * H * W: zo + (c + 1) * H * W].view(1, 1, H, W).cpu().numpy().astype(np.float64)
+            zr, _, _ = net.forward(wn, rn, xc, 'eval')
+            o, nm = inputs.sinr_masks(meta['peaks'][c], H, W)
+            res.append({'map': [H, W], 'clip': int(c),
+                        'z_rel_l2': float(np.linalg.norm(zc - zr) / np.linalg.norm(zr)),
+                        'z_max_abs_rel': float(np.abs(zc - zr).max() / np.abs(zr).max()),
+                        'delta_sinr_db': float(rdsynth.sinr_db(zc[0, 0], o, nm) - rdsynth.sinr_db(zr[0, 0], o, nm))})
+        xo += 3 * n * H * W
+        zo += n * H * W
+    return {'mode': 'eval', 'clips': res,
+            'max_z_rel_l2': max(r['z_rel_l2'] for r in res),
+            'max_abs_delta_sinr_db': max(abs(r['delta_sinr_db']) for r in res)}
 
 
 def latency_b1(stda, inputs, torch, w, running, dev, N=64, M=64):
