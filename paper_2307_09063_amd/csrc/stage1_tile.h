@@ -100,6 +100,39 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0
   }
 }
 
+// The same tile in two halves, for software pipelining across a grid-stride tile loop: fetch()
+// issues this thread's loads into registers in storage form (they stay in flight until put()),
+// put() converts them and writes the LDS tile in load_tile's layout.
+template <class T, int C, int TH, int TW, int HALO>
+struct TileRegs {
+  static constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, G = C / 4, N = RH * RW * G;
+  static constexpr int K = (N + STDA_BLOCK - 1) / STDA_BLOCK;
+  typename Raw4<T>::type v[K];
+  __device__ __forceinline__ void fetch(const T* __restrict__ X, int b, int y0, int x0, int h, int w) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = threadIdx.x + k * STDA_BLOCK;
+      const int q = e % G, px = e / G;
+      const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
+      if (e < N && y >= 0 && y < h && x >= 0 && x < w)
+        raw_ld4(X + (((int64_t)b * h + y) * w + x) * C + 4 * q, v[k]);
+      else
+        raw_zero4(v[k]);
+    }
+  }
+  __device__ __forceinline__ void put(float* lds) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int e = threadIdx.x + k * STDA_BLOCK;
+      if (e < N) {
+        float f[4];
+        raw_cvt4(v[k], f);
+        *reinterpret_cast<float4*>(lds + s1c<C, RH * RW>(e / G, e % G)) = make_float4(f[0], f[1], f[2], f[3]);
+      }
+    }
+  }
+};
+
 __device__ __forceinline__ void tile_coords(int tile, int h, int w, int TH, int TW, int& b, int& y0, int& x0) {
   const int ty = (h + TH - 1) / TH, tx = (w + TW - 1) / TW;
   b = tile / (ty * tx);
@@ -218,12 +251,31 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
 #pragma unroll
     for (int k = 0; k < 3; ++k) bn_affine4(prm.stats[k], prm.gamma[k], prm.beta[k], C, c0, sc[k], sh[k]);
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  // PIPE: the x tile of the block's next tile is fetched while this one is computed.  It costs a
+  // wave per SIMD, which pays (measured) only for the BF16 16-channel statistics pass.
+  constexpr bool PIPE = MODE == 0 && C == 16 && sizeof(T) == 2;
+  TileRegs<T, C, TH, TW, 1> nx;
+  if (PIPE && blockIdx.x < ntiles) {
+    int b, y0, x0;
+    tile_coords(blockIdx.x, h, w, TH, TW, b, y0, x0);
+    nx.fetch(X, b, y0, x0, h, w);
+  }
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     __syncthreads();
-    load_tile<T, C, TH, TW, 1, C != 32>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
-    __syncthreads();
+    if constexpr (PIPE) {
+      nx.put(xt);
+      __syncthreads();
+      if (tile + (int)gridDim.x < ntiles) {
+        int nb, ny0, nx0;
+        tile_coords(tile + gridDim.x, h, w, TH, TW, nb, ny0, nx0);
+        nx.fetch(X, nb, ny0, nx0, h, w);
+      }
+    } else {
+      load_tile<T, C, TH, TW, 1, C != 32>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
+      __syncthreads();
+    }
     // pt[p][o] = sum_c x[p][c] wp[c][o]; tile pixel p = r*TW + cc sits at padded (r + 1, cc + 1)
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
@@ -313,6 +365,15 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 #pragma unroll
   for (int s = 0; s < 4; ++s) zero4(acc[s]);
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+  // PIPE: the x tile of the block's next tile is fetched while this one is computed (measured
+  // faster above 16 channels; at 16 it costs the kernel a wave per SIMD and time)
+  constexpr bool PIPE = C > 16;
+  TileRegs<T, C, TH, TW, 1> nx;
+  if (PIPE && blockIdx.x < ntiles) {
+    int b, y0, x0;
+    tile_coords(blockIdx.x, h, w, TH, TW, b, y0, x0);
+    nx.fetch(X, b, y0, x0, h, w);
+  }
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
@@ -337,8 +398,18 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     };
     if constexpr (PF) item_load(threadIdx.x);
     __syncthreads();
-    load_tile<T, C, TH, TW, 1, C != 16>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
-    __syncthreads();
+    if constexpr (PIPE) {
+      nx.put(xt);
+      __syncthreads();
+      if (tile + (int)gridDim.x < ntiles) {
+        int nb, ny0, nx0;
+        tile_coords(tile + gridDim.x, h, w, TH, TW, nb, ny0, nx0);
+        nx.fetch(X, nb, ny0, nx0, h, w);
+      }
+    } else {
+      load_tile<T, C, TH, TW, 1, C != 16>(X, b, y0, x0, h, w, xt);  // batched where it measured faster
+      __syncthreads();
+    }
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
                               [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
