@@ -47,6 +47,13 @@ __device__ __forceinline__ floatx4 mfma_chunk(const shortx4 a, const shortx4 b, 
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// Two 4-value BF16 operands as the 8 values one lane feeds v_mfma_f32_16x16x32_bf16 (gfx950).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 pack8(const shortx4 a, const shortx4 b) {
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 template <class F>
 __device__ __forceinline__ F frag_zero() {
   F z;

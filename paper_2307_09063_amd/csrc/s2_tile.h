@@ -545,18 +545,18 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
     t_end = ntiles;
     t_step = gridDim.x;
   }
-  for (int64_t t = t_begin; t < t_end; t += t_step) {
-    int b, y0, x0;
-    s2_tile_origin(t, nty, ntx, TH, TW, b, y0, x0);
-    __syncthreads();
-    // Staging: a unit is (4 channels, 4 consecutive pixels); every load of the thread's units is
-    // issued before the first transpose and LDS write, so their latencies overlap.
-    // Lo units: (channel quad, pixel quad of a tile row); Hi units: (slot, channel quad, plane row,
-    // quad of plane columns).
-    {
-      constexpr int LU = (CL / 4) * (TH * TW / 4), XQ = TW / 4, HU = C::SLOTS * (CH / 4) * PY * XQ;
-      constexpr int PL = (LU + STDA_BLOCK - 1) / STDA_BLOCK, PH = (HU + STDA_BLOCK - 1) / STDA_BLOCK;
-      float lv[PL][4][4], hv[PH][4][4];  // [unit][pixel][channel]
+  if constexpr (BF) {
+    // BF16: the operands stay packed from HBM to the matrix core.  The staging units of the next
+    // tile are loaded (4 channels of a pixel = one 8-byte load) while this tile's products run, the
+    // 4 x 4 transposes are byte permutes, and two 16-pixel chunks feed one
+    // v_mfma_f32_16x16x32_bf16 (lane group g: pixels 4g .. 4g + 3 of each chunk, the same
+    // reduction order for both operands).
+    constexpr int LU = (CL / 4) * (TH * TW / 4), XQ = TW / 4, HU = C::SLOTS * (CH / 4) * PY * XQ;
+    constexpr int PL = (LU + STDA_BLOCK - 1) / STDA_BLOCK, PH = (HU + STDA_BLOCK - 1) / STDA_BLOCK;
+    uint2 lv[PL][4], hv[PH][4];  // [unit][pixel]: channels 4 cq .. 4 cq + 3 packed
+    auto fetch = [&](int64_t tt) {
+      int b, y0, x0;
+      s2_tile_origin(tt, nty, ntx, TH, TW, b, y0, x0);
 #pragma unroll
       for (int k = 0; k < PL; ++k) {
         const int e = threadIdx.x + k * STDA_BLOCK;
@@ -564,8 +564,9 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int x = x0 + tx + q;
-          if (e < LU && y < h && x < w) ld4(lo + (((int64_t)b * h + y) * w + x) * CL + 4 * cq, lv[k][q]);
-          else zero4(lv[k][q]);
+          lv[k][q] = (e < LU && y < h && x < w)
+                         ? *reinterpret_cast<const uint2*>(lo + (((int64_t)b * h + y) * w + x) * CL + 4 * cq)
+                         : make_uint2(0u, 0u);
         }
       }
 #pragma unroll
@@ -578,27 +579,35 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
         r /= PY;
         const int cq = r % (CH / 4), sl = r / (CH / 4);
         const int s = sl < 4 ? 0 : 1;
-        const int p = sl < 4 ? sl : (KS == 3 ? 2 * (sl - 4) : sl - 4);
-        const int ly = 2 * Y + (p >> 1), sy = 2 * y0 - 1 + ly;
+        const int pp = sl < 4 ? sl : (KS == 3 ? 2 * (sl - 4) : sl - 4);
+        const int ly = 2 * Y + (pp >> 1), sy = 2 * y0 - 1 + ly;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int lx = 2 * (4 * xq + q + s) + (p & 1), sx = 2 * x0 - 1 + lx;
-          if (e < HU && ly < C::SH && lx < C::SW && sy >= 0 && sy < H2 && sx >= 0 && sx < W2)
-            ld4(hi + (((int64_t)b * H2 + sy) * W2 + sx) * CH + 4 * cq, hv[k][q]);
-          else
-            zero4(hv[k][q]);
+          const int lx = 2 * (4 * xq + q + s) + (pp & 1), sx = 2 * x0 - 1 + lx;
+          hv[k][q] = (e < HU && ly < C::SH && lx < C::SW && sy >= 0 && sy < H2 && sx >= 0 && sx < W2)
+                         ? *reinterpret_cast<const uint2*>(hi + (((int64_t)b * H2 + sy) * W2 + sx) * CH + 4 * cq)
+                         : make_uint2(0u, 0u);
         }
       }
+    };
+    // channel c of pixels 0..3 of a unit (u[q] holds channels 4 cq .. 4 cq + 3 of pixel q), as the
+    // four BF16 values of one 8-byte LDS row segment
+    auto column = [](const uint2 (&u)[4], int c) {
+      const uint32_t sel = (c & 1) ? 0x07060302u : 0x05040100u;
+      const uint32_t a0 = (c & 2) ? u[0].y : u[0].x, a1 = (c & 2) ? u[1].y : u[1].x;
+      const uint32_t a2 = (c & 2) ? u[2].y : u[2].x, a3 = (c & 2) ? u[3].y : u[3].x;
+      return make_uint2(__builtin_amdgcn_perm(a1, a0, sel), __builtin_amdgcn_perm(a3, a2, sel));
+    };
+    if (t_begin < t_end) fetch(t_begin);
+    for (int64_t t = t_begin; t < t_end; t += t_step) {
+      __syncthreads();  // the previous tile's products have read the LDS operands
 #pragma unroll
       for (int k = 0; k < PL; ++k) {
         const int e = threadIdx.x + k * STDA_BLOCK;
         if (e >= LU) continue;
         const int cq = e % (CL / 4), p0 = 4 * (e / (CL / 4));
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float col[4] = {lv[k][0][c], lv[k][1][c], lv[k][2][c], lv[k][3][c]};
-          wg_store4<T>(ls + (4 * cq + c) * LP + p0, col);
-        }
+        for (int c = 0; c < 4; ++c) *reinterpret_cast<uint2*>(ls + (4 * cq + c) * LP + p0) = column(lv[k], c);
       }
 #pragma unroll
       for (int k = 0; k < PH; ++k) {
@@ -611,35 +620,151 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
         r /= PY;
         const int cq = r % (CH / 4), sl = r / (CH / 4);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const float col[4] = {hv[k][0][c], hv[k][1][c], hv[k][2][c], hv[k][3][c]};
-          wg_store4<T>(hs + (sl * CH + 4 * cq + c) * CS + Y * TW + 4 * xq, col);
+        for (int c = 0; c < 4; ++c)
+          *reinterpret_cast<uint2*>(hs + (sl * CH + 4 * cq + c) * CS + Y * TW + 4 * xq) = column(hv[k], c);
+      }
+      __syncthreads();
+      if (t + t_step < t_end) fetch(t + t_step);
+      constexpr int NCH = TH * TW / 16;
+#pragma unroll 1
+      for (int c32 = 0; c32 < NCH / 2; ++c32) {
+        const int pa = 32 * c32 + 4 * g, pb = pa + 16;
+        const int tya = pa / TW, txa = pa % TW, tyb = pb / TW, txb = pb % TW;
+        bf16x8 bq[NTC];
+#pragma unroll
+        for (int j = 0; j < NTC; ++j)
+          bq[j] = pack8(*reinterpret_cast<const shortx4*>(ls + (16 * j + i) * LP + pa),
+                        *reinterpret_cast<const shortx4*>(ls + (16 * j + i) * LP + pb));
+#pragma unroll
+        for (int u = 0; u < PW_; ++u) {
+          const int q = wave + 4 * u;
+          if (q >= C::PAIRS) continue;
+          const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
+          const int sl = C::slot((ky & 1) * 2 + (kx & 1), kx >> 1);
+          const T* hb = hs + (sl * CH + 16 * mt + i) * CS + (ky >> 1) * TW;
+          const bf16x8 a = pack8(*reinterpret_cast<const shortx4*>(hb + tya * TW + txa),
+                                 *reinterpret_cast<const shortx4*>(hb + tyb * TW + txb));
+#pragma unroll
+          for (int j = 0; j < NTC; ++j)
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bq[j], acc[u][j], 0, 0, 0);
+        }
+      }
+      if constexpr (NCH % 2 == 1) {  // an odd last chunk on the 16-deep instruction
+        const int p0 = 16 * (NCH - 1) + 4 * g, ty = p0 / TW, tx = p0 % TW;
+        shortx4 bq[NTC];
+#pragma unroll
+        for (int j = 0; j < NTC; ++j) bq[j] = *reinterpret_cast<const shortx4*>(ls + (16 * j + i) * LP + p0);
+#pragma unroll
+        for (int u = 0; u < PW_; ++u) {
+          const int q = wave + 4 * u;
+          if (q >= C::PAIRS) continue;
+          const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
+          const int sl = C::slot((ky & 1) * 2 + (kx & 1), kx >> 1);
+          const shortx4 a =
+              *reinterpret_cast<const shortx4*>(hs + (sl * CH + 16 * mt + i) * CS + (ty + (ky >> 1)) * TW + tx);
+#pragma unroll
+          for (int j = 0; j < NTC; ++j)
+            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bq[j], acc[u][j], 0, 0, 0);
         }
       }
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int c16 = 0; c16 < TH * TW / 16; ++c16) {
-      const int p0 = 16 * c16 + 4 * g, ty = p0 / TW, tx = p0 % TW;
-      V bq[NTC];
-#pragma unroll
-      for (int j = 0; j < NTC; ++j) bq[j] = *reinterpret_cast<const V*>(ls + (16 * j + i) * LP + p0);
-#pragma unroll
-      for (int u = 0; u < PW_; ++u) {
-        const int q = wave + 4 * u;
-        if (q >= C::PAIRS) continue;
-        const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
-        const int sl = C::slot((ky & 1) * 2 + (kx & 1), kx >> 1);
-        const V a = *reinterpret_cast<const V*>(hs + (sl * CH + 16 * mt + i) * CS + (ty + (ky >> 1)) * TW + tx);
-#pragma unroll
-        for (int j = 0; j < NTC; ++j) {
-          if constexpr (BF) {
-            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bq[j], acc[u][j], 0, 0, 0);
-          } else {
-            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bq[j].x, acc[u][j], 0, 0, 0);
-            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bq[j].y, acc[u][j], 0, 0, 0);
-            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bq[j].z, acc[u][j], 0, 0, 0);
-            acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bq[j].w, acc[u][j], 0, 0, 0);
+  } else {
+    for (int64_t t = t_begin; t < t_end; t += t_step) {
+      int b, y0, x0;
+      s2_tile_origin(t, nty, ntx, TH, TW, b, y0, x0);
+      __syncthreads();
+      // Staging: a unit is (4 channels, 4 consecutive pixels); every load of the thread's units is
+      // issued before the first transpose and LDS write, so their latencies overlap.
+      // Lo units: (channel quad, pixel quad of a tile row); Hi units: (slot, channel quad, plane row,
+      // quad of plane columns).
+      {
+        constexpr int LU = (CL / 4) * (TH * TW / 4), XQ = TW / 4, HU = C::SLOTS * (CH / 4) * PY * XQ;
+        constexpr int PL = (LU + STDA_BLOCK - 1) / STDA_BLOCK, PH = (HU + STDA_BLOCK - 1) / STDA_BLOCK;
+        float lv[PL][4][4], hv[PH][4][4];  // [unit][pixel][channel]
+  #pragma unroll
+        for (int k = 0; k < PL; ++k) {
+          const int e = threadIdx.x + k * STDA_BLOCK;
+          const int cq = e % (CL / 4), p0 = 4 * (e / (CL / 4)), ty = p0 / TW, tx = p0 % TW, y = y0 + ty;
+  #pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int x = x0 + tx + q;
+            if (e < LU && y < h && x < w) ld4(lo + (((int64_t)b * h + y) * w + x) * CL + 4 * cq, lv[k][q]);
+            else zero4(lv[k][q]);
+          }
+        }
+  #pragma unroll
+        for (int k = 0; k < PH; ++k) {
+          const int e = threadIdx.x + k * STDA_BLOCK;
+          int r = e;
+          const int xq = r % XQ;
+          r /= XQ;
+          const int Y = r % PY;
+          r /= PY;
+          const int cq = r % (CH / 4), sl = r / (CH / 4);
+          const int s = sl < 4 ? 0 : 1;
+          const int p = sl < 4 ? sl : (KS == 3 ? 2 * (sl - 4) : sl - 4);
+          const int ly = 2 * Y + (p >> 1), sy = 2 * y0 - 1 + ly;
+  #pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int lx = 2 * (4 * xq + q + s) + (p & 1), sx = 2 * x0 - 1 + lx;
+            if (e < HU && ly < C::SH && lx < C::SW && sy >= 0 && sy < H2 && sx >= 0 && sx < W2)
+              ld4(hi + (((int64_t)b * H2 + sy) * W2 + sx) * CH + 4 * cq, hv[k][q]);
+            else
+              zero4(hv[k][q]);
+          }
+        }
+  #pragma unroll
+        for (int k = 0; k < PL; ++k) {
+          const int e = threadIdx.x + k * STDA_BLOCK;
+          if (e >= LU) continue;
+          const int cq = e % (CL / 4), p0 = 4 * (e / (CL / 4));
+  #pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float col[4] = {lv[k][0][c], lv[k][1][c], lv[k][2][c], lv[k][3][c]};
+            wg_store4<T>(ls + (4 * cq + c) * LP + p0, col);
+          }
+        }
+  #pragma unroll
+        for (int k = 0; k < PH; ++k) {
+          const int e = threadIdx.x + k * STDA_BLOCK;
+          if (e >= HU) continue;
+          int r = e;
+          const int xq = r % XQ;
+          r /= XQ;
+          const int Y = r % PY;
+          r /= PY;
+          const int cq = r % (CH / 4), sl = r / (CH / 4);
+  #pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const float col[4] = {hv[k][0][c], hv[k][1][c], hv[k][2][c], hv[k][3][c]};
+            wg_store4<T>(hs + (sl * CH + 4 * cq + c) * CS + Y * TW + 4 * xq, col);
+          }
+        }
+      }
+      __syncthreads();
+  #pragma unroll 1
+      for (int c16 = 0; c16 < TH * TW / 16; ++c16) {
+        const int p0 = 16 * c16 + 4 * g, ty = p0 / TW, tx = p0 % TW;
+        V bq[NTC];
+  #pragma unroll
+        for (int j = 0; j < NTC; ++j) bq[j] = *reinterpret_cast<const V*>(ls + (16 * j + i) * LP + p0);
+  #pragma unroll
+        for (int u = 0; u < PW_; ++u) {
+          const int q = wave + 4 * u;
+          if (q >= C::PAIRS) continue;
+          const int tap = q / MTC, mt = q % MTC, ky = tap / KS, kx = tap % KS;
+          const int sl = C::slot((ky & 1) * 2 + (kx & 1), kx >> 1);
+          const V a = *reinterpret_cast<const V*>(hs + (sl * CH + 16 * mt + i) * CS + (ty + (ky >> 1)) * TW + tx);
+  #pragma unroll
+          for (int j = 0; j < NTC; ++j) {
+            if constexpr (BF) {
+              acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bq[j], acc[u][j], 0, 0, 0);
+            } else {
+              acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, bq[j].x, acc[u][j], 0, 0, 0);
+              acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, bq[j].y, acc[u][j], 0, 0, 0);
+              acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, bq[j].z, acc[u][j], 0, 0, 0);
+              acc[u][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, bq[j].w, acc[u][j], 0, 0, 0);
+            }
           }
         }
       }
