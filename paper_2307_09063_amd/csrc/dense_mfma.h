@@ -10,8 +10,10 @@
 //
 // FP32: v_mfma_f32_16x16x4f32.  The four channels a lane holds feed four consecutive MFMAs
 // (k-index e of the lane group g is channel 4g + e): a fixed permutation of the reduction order
-// applied identically to A and B.  BF16: v_mfma_f32_16x16x16bf16_1k, lane group g supplying
-// channels 4g .. 4g + 3 of the 16-channel chunk.  Accumulation is FP32 in both cases.
+// applied identically to A and B.  BF16: lane group g supplies channels 4g .. 4g + 3 of a
+// 16-channel chunk; with 32 or more input channels two chunks of a tap feed one gfx950
+// v_mfma_f32_16x16x32_bf16, with 16 one chunk feeds v_mfma_f32_16x16x16bf16_1k.  Accumulation is
+// FP32 in both cases.
 //
 // Up-sampling operators (DeConv4x4-s2 forward, Conv3x3-s2 adjoint) run one output phase
 // (row parity, column parity) per grid.y so that all rows of a block share their taps.
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
   constexpr int KS = OpGeo<OP>::KS;
   constexpr bool DOWN = OpGeo<OP>::DOWN;
   constexpr int NT = N / 16, KC = K / 16;
+  constexpr bool PAIR2 = sizeof(T) == 2 && KC % 2 == 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, g = lane >> 4;
   const int py = DOWN ? 0 : (int)(blockIdx.y >> 1), px = DOWN ? 0 : (int)(blockIdx.y & 1);
   const int hr = DOWN ? hd : hd / 2, wr = DOWN ? wd : wd / 2;  // GEMM row grid
@@ -147,6 +150,24 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
           const bool ok = pv[r] && sy >= 0 && sy < hs && sx >= 0 && sx < ws;
           so[r] = ok ? (((int64_t)pb[r] * hs + sy) * ws + sx) * K + 4 * g : -1;
         }
+        if constexpr (PAIR2) {
+          // BF16, K a multiple of 32: chunks s and s + 1 of the tap feed one 16x16x32 product
+#pragma unroll
+          for (int s = 0; s < KC; s += 2) {
+            bf16x8 av[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              av[r] = so[r] >= 0 ? pack8(*reinterpret_cast<const F*>(src + so[r] + 16 * s),
+                                         *reinterpret_cast<const F*>(src + so[r] + 16 * s + 16))
+                                 : pack8(frag_zero<F>(), frag_zero<F>());
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+              const bf16x8 bv = pack8(wf[((tap * KC + s) * NT + nt) * 64 + lane], wf[((tap * KC + s + 1) * NT + nt) * 64 + lane]);
+#pragma unroll
+              for (int r = 0; r < R; ++r) acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][nt], 0, 0, 0);
+            }
+          }
+        } else
 #pragma unroll
         for (int s = 0; s < KC; ++s) {
           F av[R];

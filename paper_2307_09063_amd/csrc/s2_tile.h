@@ -11,7 +11,8 @@
 //      next tile's rectangle is loaded into registers while this tile's GEMM runs;
 //   3. runs the GEMM (4 or 8 waves per workgroup; 8 where the LDS allows one workgroup per CU, so
 //      that two waves share each SIMD): wave w takes row tiles w*R .. w*R+R-1 (16 output pixels each) of every
-//      phase, all NB/16 column tiles, A fragments and B fragments both read from LDS;
+//      phase, all NB/16 column tiles, A fragments and B fragments both read from LDS (BF16 with 32 or
+//      more input channels: two 16-channel chunks per gfx950 v_mfma_f32_16x16x32_bf16);
 //   4. writes the FP32 accumulators, rounded to the storage type, into an LDS staging tile that
 //      aliases the source rectangle, and stores it with 16-byte writes, contiguous along a row;
 //   5. optionally accumulates the BN statistics (count, mean, m2) of the FP32 results.
@@ -72,6 +73,7 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
   constexpr int BLK = C::BLK;
   typedef typename FragT<T>::type F;
   constexpr int KS = C::KS, KP = C::KP, SW = C::SW, SH = C::SH, R = C::R, NTB = C::NTB, KC = C::KC;
+  constexpr bool PAIR2 = sizeof(T) == 2 && KC % 2 == 0;  // BF16 on the 16x16x32 instruction
   constexpr int PH = C::PH, PW = C::PW;
   constexpr int VE = 16 / C::ES;  // elements per 16-byte vector
   __shared__ __attribute__((aligned(16))) T lds[C::TILE_ELEMS + C::W_ELEMS];
@@ -188,16 +190,35 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
             base[r] = (ly * SW + lx) * KP + 4 * g;
           }
           const F* wl = reinterpret_cast<const F*>(w_lds) + (tap * KC * NTB) * 64 + lane;
+          if constexpr (PAIR2) {
+            // BF16, K a multiple of 32: chunks s and s + 1 feed one 16x16x32 product
 #pragma unroll
-          for (int s = 0; s < KC; ++s) {
-            F av[R];
+            for (int s = 0; s < KC; s += 2) {
+              bf16x8 av[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) av[r] = *reinterpret_cast<const F*>(tile_lds + base[r] + 16 * s);
+              for (int r = 0; r < R; ++r)
+                av[r] = pack8(*reinterpret_cast<const F*>(tile_lds + base[r] + 16 * s),
+                              *reinterpret_cast<const F*>(tile_lds + base[r] + 16 * s + 16));
 #pragma unroll
-            for (int j = 0; j < NTB; ++j) {
-              const F bv = wl[(s * NTB + j) * 64];
+              for (int j = 0; j < NTB; ++j) {
+                const bf16x8 bv = pack8(wl[(s * NTB + j) * 64], wl[((s + 1) * NTB + j) * 64]);
 #pragma unroll
-              for (int r = 0; r < R; ++r) acc[ph][r][j] = mfma_chunk(av[r], bv, acc[ph][r][j]);
+                for (int r = 0; r < R; ++r)
+                  acc[ph][r][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[ph][r][j], 0, 0, 0);
+              }
+            }
+          } else {
+#pragma unroll
+            for (int s = 0; s < KC; ++s) {
+              F av[R];
+#pragma unroll
+              for (int r = 0; r < R; ++r) av[r] = *reinterpret_cast<const F*>(tile_lds + base[r] + 16 * s);
+#pragma unroll
+              for (int j = 0; j < NTB; ++j) {
+                const F bv = wl[(s * NTB + j) * 64];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[ph][r][j] = mfma_chunk(av[r], bv, acc[ph][r][j]);
+              }
             }
           }
         }
