@@ -67,3 +67,27 @@ def test_trace_rows(tmp_path):
     con.close()
     rows = profsum.trace_rows(d)
     assert rows[0] == ('k_x', 2, 40.0, 20.0, 40, 0) and rows[1][0] == 'k_y'
+
+
+def test_kernel_tag_mapping():
+    """Kernel names as rocprofv3 prints them map to bench.py's profiling tags (the block follows
+    from the template's channel counts), so per-kernel counters meet the algorithmic work."""
+    cases = {
+        'void k_s2_tile<float, 3, 32, 64, 16, 8, 8, false, 4>': 'dense_dgrad_main.dec0',
+        'void k_s2_tile<bf16, 0, 16, 32, 32, 8, 32, true, 4>': 'dense_fwd_main.enc0',
+        'void k_dense_mfma<float, 1, 64, 32, 4, true>': 'dense_fwd_main.dec0',
+        'void k_s2_wgrad_v<bf16, true, 32, 16, 8, 16>': 'wgrad_main.dec1',
+        'void k_s2_wgrad<float, false, 64, 32, 8, 8>': 'wgrad_main.enc1',
+        'void k_s1_bwd_fused<float, 16, false, true, 8, 16, 2>': 's1_bwd_fused.enc0',
+        'void k_s1_bwd_stats_tile<bf16, 64, true>': 's1_bwd_stats.dec0',
+        'void k_s1_tile<float, 32, true, 0>': 's1_stats.dec1',
+        'void k_s1_tile<float, 32, false, 1>': 's1_apply.enc1',
+        'void k_eca_next<float, 32, true>': 'eca_next.dec0',
+        'void k_eca_next<float, 32, false>': 'eca_next.enc0',
+        'void k_s2_bwd_apply<float, 16>': 's2_bwd_apply.dec1',
+        'void k_stem_tile<float, 2>': 'stem_bwd_stats',
+        'void k_head_fwd_tile<float, false>': 'head_fwd',
+        'k_bn_stats_reduce': None,
+    }
+    for name, tag in cases.items():
+        assert profsum.kernel_tag(name) == tag, name
