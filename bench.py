@@ -459,7 +459,9 @@ def bf16_error_vs_oracle(stda, torch, segs, groups, x, metas, w, running, dev, p
 def latency_b1(stda, inputs, torch, w, running, dev, N=64, M=64):
     """EVAL forward of one clip of 3 x N x M (64 x 64: the small configuration; 128 x 64: the
     paper's own FPS setting, Table 7): per-clip time of back-to-back calls, eager and as a replayed
-    graph, and the wall time of one synchronised graph replay (host-measured, median of 50)."""
+    graph, and the wall time of one synchronised graph replay (host-measured, median of 50); the
+    same for the folded-weight EVAL forward (stda_forward_folded, its graph), with the number of
+    tagged launches of one call of each."""
     rc = inputs.WORKLOADS['cfg1_fwd_64x64']
     tab, meta = inputs.make_scenes(1, N, M, rc['seed'], targets=rc['targets'], intf=rc['intf'], inr=rc['inr'],
                                    clutter=rc['clutter'])
@@ -496,8 +498,42 @@ def latency_b1(stda, inputs, torch, w, running, dev, N=64, M=64):
         walls.append((time.perf_counter() - t0) * 1e3)
     g.close()
     wall = sorted(walls)[len(walls) // 2]
+    # the folded-weight EVAL forward (batch norm folded into the weights once, stage 2 in one launch)
+    fb = stda.alloc_bytes(stda.eval_fold_size(stda.FP32), dev)
+    stda.eval_fold(w, running, fb, stda.FP32)
+    zf = torch.empty_like(z)
+    gf = stda.FoldedForwardGraph(segs, x1, fb, zf, ws)
+    for _ in range(5):
+        gf.launch()
+    torch.cuda.synchronize()
+    e0.record(gf.stream)
+    for _ in range(50):
+        gf.launch()
+    e1.record(gf.stream)
+    torch.cuda.synchronize()
+    graph_f = e0.elapsed_time(e1) / 50
+    walls = []
+    for _ in range(50):
+        t0 = time.perf_counter()
+        gf.launch()
+        gf.stream.synchronize()
+        walls.append((time.perf_counter() - t0) * 1e3)
+    gf.close()
+    wall_f = sorted(walls)[len(walls) // 2]
+    # launches per forward call, unfolded and folded (every tagged launch of one call)
+    stda.profile_select('*')
+    stda.forward(segs, x1, w, running, z, None, ws, stda.FP32, stda.EVAL)
+    torch.cuda.synchronize()
+    n_unf = sum(v[0] for v in stda.profile_report().values())
+    stda.profile_select('*')
+    stda.forward_folded(segs, x1, fb, zf, ws)
+    torch.cuda.synchronize()
+    n_fold = sum(v[0] for v in stda.profile_report().values())
+    stda.profile_select(None)
     return {'ms_eager': round(eager, 4), 'ms_graph': round(graph, 4), 'ms_graph_sync_wall': round(wall, 4),
-            'fps_graph_sync': round(1e3 / wall, 1)}
+            'fps_graph_sync': round(1e3 / wall, 1), 'tagged_launches': n_unf,
+            'folded': {'ms_graph': round(graph_f, 4), 'ms_graph_sync_wall': round(wall_f, 4),
+                       'fps_graph_sync': round(1e3 / wall_f, 1), 'tagged_launches': n_fold}}
 
 
 def eval_forward(stda, inputs, torch, w, running, dev):

@@ -143,6 +143,27 @@ int stda_forward(const stda_segment* segs /*host*/, int n_segs, const float* x, 
 int stda_forward_noalloc(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* w,
                          const float* running, float* z, int dtype, hipStream_t stream);
 
+/* ------------------------------------------------------------------ folded EVAL inference
+ * In EVAL mode every batch normalisation is a fixed per-channel affine map, which folds into the
+ * adjacent weights (the re-parameterisation the mobile block of Sec. IV-C takes from MobileOne):
+ * stage 1 becomes ReLU(PW'(x) + DW'(x) + b1) with the identity branch on the 1x1 weight's
+ * diagonal, stage 2 ReLU(conv'(x1) + b) + conv_res(x), the input module ReLU(conv'(x) + b').
+ * stda_eval_fold computes the folded parameters once, from the FP32 master parameters w and the
+ * running statistics, into the caller's device buffer `folded` (stda_eval_fold_size bytes; for
+ * `dtype`, whose stage-2 weights it also arranges for the matrix cores).  stda_forward_folded then
+ * runs the EVAL forward on it: per mobile block one stage-1 launch, one launch for all of stage 2
+ * (both convolutions, bias, ReLU and the residual sum) and one for ECA and the skip; z equals
+ * stda_forward's EVAL result up to rounding.  ws: stda_workspace_size's ws bytes for these
+ * segments in EVAL mode.  The main architecture reading and the sigmoid output are supported;
+ * STDA_ARCH_RES3 and STDA_ARCH_PW_DW give STDA_E_INVALID.  A folded buffer is valid until w or
+ * the running statistics change.
+ */
+int stda_eval_fold_size(int dtype, size_t* bytes /*host out*/);
+int stda_eval_fold(const float* w, const float* running, void* folded, size_t folded_bytes, int dtype,
+                   hipStream_t stream);
+int stda_forward_folded(const stda_segment* segs /*host*/, int n_segs, const float* x, const void* folded,
+                        size_t folded_bytes, float* z, void* ws, size_t ws_bytes, int dtype, hipStream_t stream);
+
 /*
  * Hand-written adjoint of the TRAIN forward that filled `saved` (same segs, x, w, dtype,
  * recompute; x is read again for the input-module weight gradient).  dz = dL/dz; writes dw (all
@@ -255,6 +276,11 @@ int stda_forward_graph_create(const stda_segment* segs /*host*/, int n_segs, con
                               const float* w, float* running, float* z, void* saved,
                               size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int mode,
                               hipStream_t stream, stda_graph* graph /*host out*/);
+/* The folded EVAL forward (stda_forward_folded) captured the same way. */
+int stda_forward_folded_graph_create(const stda_segment* segs /*host*/, int n_segs, const float* x,
+                                     const void* folded, size_t folded_bytes, float* z, void* ws,
+                                     size_t ws_bytes, int dtype, hipStream_t stream,
+                                     stda_graph* graph /*host out*/);
 int stda_graph_launch(stda_graph graph, hipStream_t stream);
 /* Frees the graph and its handle (NULL is a no-op); STDA_E_HIP if HIP reports an error, the
  * handle is freed in any case. */

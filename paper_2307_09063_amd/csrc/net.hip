@@ -24,6 +24,7 @@
 #include "stage1_tile.h"
 #include "stem_tile.h"
 #include "head_tile.h"
+#include "eval_folded.h"
 
 using namespace stda;
 
@@ -766,7 +767,10 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
         ++rr.n;
       }
     }
-    k_working_weights<<<grid_for(np, 256), 256, 0, st>>>(w, wk, np, rr);
+    {
+      ProfScope ps_("prep_weights", st);
+      k_working_weights<<<grid_for(np, 256), 256, 0, st>>>(w, wk, np, rr);
+    }
     LAUNCH_CHECK();
     src = wk;
   }
@@ -794,7 +798,10 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
         j.dst_d = P.dense_d[k][m];
       }
     }
-  k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
+  {
+    ProfScope ps_("prep_weights", st);
+    k_prep_dense<<<dim3(32, jobs.n), 256, 0, st>>>(w, reinterpret_cast<float*>(ws + P.ws_dense), jobs);
+  }
   LAUNCH_CHECK();
   if (P.arch & STDA_ARCH_PW_DW) {
     PwDiag d{};
@@ -814,10 +821,13 @@ int prepare_weights(const Plan& P, const float* w, char* ws, hipStream_t st, con
       fj.j[fj.n++] = FragJob{P.dense_d[k][m], P.dense_d[k][m], taps, kBlocks[k].cout, kBlocks[k].cin};
     }
   const float* dl = reinterpret_cast<const float*>(ws + P.ws_dense);
-  if (P.dtype == STDA_BF16)
-    k_prep_frag<bf16><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<bf16*>(ws + P.ws_frag), fj);
-  else
-    k_prep_frag<float><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<float*>(ws + P.ws_frag), fj);
+  {
+    ProfScope ps_("prep_weights", st);
+    if (P.dtype == STDA_BF16)
+      k_prep_frag<bf16><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<bf16*>(ws + P.ws_frag), fj);
+    else
+      k_prep_frag<float><<<dim3(16, fj.n), 256, 0, st>>>(dl, reinterpret_cast<float*>(ws + P.ws_frag), fj);
+  }
   LAUNCH_CHECK();
   *wk_out = src;
   return STDA_OK;
@@ -845,13 +855,121 @@ int forward_all(const Plan& P, const float* x, const float* w, float* running, f
           off += 2 * cs[q];
         }
       }
-      k_eval_stats<<<1, 256, 0, st>>>(running, c.stats(0), tab);
+      {
+        ProfScope ps_("eval_stats", st);
+        k_eval_stats<<<1, 256, 0, st>>>(running, c.stats(0), tab);
+      }
       LAUNCH_CHECK();
     }
     if (int r = forward_seg<T>(c, x, running, z)) return r;
   }
   return STDA_OK;
 }
+
+// ------------------------------------------------------------------ folded EVAL inference
+// Layout of the folded-parameter buffer: the weight regions of the per-call workspace (working
+// weights, dense and fragment-order layouts; their offsets do not depend on the batch), then the
+// folded parameter vector, then the identity statistics.
+struct FoldLayout {
+  Plan P;
+  size_t wf_off, bytes;
+};
+bool fold_arch_ok(int arch) { return (arch & (STDA_ARCH_RES3 | STDA_ARCH_PW_DW)) == 0; }
+FoldLayout fold_layout(int dtype) {
+  FoldLayout L;
+  const stda_segment one{1, 8, 8, 0, 0};
+  build_plan(&one, 1, dtype, STDA_EVAL, 0, L.P);
+  L.wf_off = L.P.ws_R;  // ws_wk, ws_dense, ws_pwx and ws_frag come first
+  L.bytes = align_up(L.wf_off + sizeof(float) * (net_offsets(L.P.arch).param_count + kFoldIds));
+  return L;
+}
+
+#define FLAUNCH(tag, ...)             \
+  do {                                \
+    ProfScope ps_((tag), st);         \
+    __VA_ARGS__;                      \
+  } while (0);                        \
+  LAUNCH_CHECK()
+
+template <class T, int CIN, int COUT, bool DEC>
+int folded_block(const Plan& P, const SegPlan& S, int k, const char* fold, const float* wk, const float* ids, char* ws,
+                 hipStream_t st) {
+  const BlockCfg& bc = kBlocks[k];
+  const BlockOffsets& bo = net_offsets(P.arch).blk[k];
+  const BlockActs& A = S.blk[k];
+  const int n = S.n;
+  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
+  const T* X = reinterpret_cast<const T*>(ws + (k == 0 ? S.s0 : S.blk[k - 1].Xn));
+  T* X1 = reinterpret_cast<T*>(ws + A.X1);
+  T* Y = reinterpret_cast<T*>(ws + A.Y);
+  T* Xn = reinterpret_cast<T*>(ws + A.Xn);
+  S1Params sp{};
+  sp.wpw = wk + bo.pw_w;
+  sp.wdw = wk + bo.dw_w;
+  for (int q = 0; q < 3; ++q) sp.stats[q] = ids + fold_ids_off(CIN);
+  sp.gamma[0] = wk + bo.pw_g;
+  sp.gamma[1] = wk + bo.dw_g;
+  sp.gamma[2] = wk + bo.id_g;
+  sp.beta[0] = wk + bo.pw_b;
+  sp.beta[1] = wk + bo.dw_b;
+  sp.beta[2] = wk + bo.id_b;
+  FLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<s1_grid<CIN>(n, hin, win), 256, 0, st>>>(X, X1, nullptr, nullptr, sp, n, hin, win));
+  constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD, PH = DEC ? 4 : 1, R = 1;
+  const int64_t rows = DEC ? (int64_t)(hout / 2) * (wout / 2) : (int64_t)hout * wout;  // one clip's phase grid
+  const int tx = (int)((rows + 64 * R - 1) / (64 * R));
+  const T* frag = reinterpret_cast<const T*>(fold + P.ws_frag);
+  float* gap = reinterpret_cast<float*>(ws + P.ws_R);  // the residual buffer is not needed here
+  FLAUNCH(tagk("s2_eval", k), k_s2_eval<T, OPF, CIN, COUT, R><<<dim3(tx, PH, n), 256, 0, st>>>(
+                                  X1, X, frag + P.dense_f[k][0], frag + P.dense_f[k][1], wk + bo.main_b, Y, gap, hout, wout));
+  const int hw = hout * wout;
+  const int tiles = tiles_for(hw, COUT / 4);
+  const T* skip = k == 2 ? reinterpret_cast<const T*>(ws + S.blk[0].Xn) : (k == 3 ? reinterpret_cast<const T*>(ws + S.s0) : nullptr);
+  float* g = reinterpret_cast<float*>(ws + A.g);
+  float* a = reinterpret_cast<float*>(ws + A.a);
+  if (skip) {
+    FLAUNCH(tagk("eca_next", k), k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, st>>>(Y, skip, Xn, gap, wk + bo.eca_w, g, a, hw, tx * PH));
+  } else {
+    FLAUNCH(tagk("eca_next", k), k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, st>>>(Y, nullptr, Xn, gap, wk + bo.eca_w, g, a, hw, tx * PH));
+  }
+  return STDA_OK;
+}
+
+template <class T>
+int forward_folded_all(const Plan& P, const FoldLayout& L, const float* x, const char* fold, float* z, char* ws,
+                       hipStream_t st) {
+  const NetOffsets& no = net_offsets(P.arch);
+  const float* wf = reinterpret_cast<const float*>(fold + L.wf_off);
+  const float* ids = wf + no.param_count;
+  // working weights: the folded vector (BF16: its copy with the stage-2 weights rounded)
+  const float* wk = P.dtype == STDA_BF16 ? reinterpret_cast<const float*>(fold + L.P.ws_wk) : wf;
+  for (int s = 0; s < P.n_segs; ++s) {
+    const SegPlan& S = P.seg[s];
+    // the per-(clip, phase, tile) ECA partial sums of every block fit the residual buffer
+    for (int k = 0; k < 4; ++k) {
+      const BlockCfg& b = kBlocks[k];
+      const int64_t ho = S.H >> b.lout, wo = S.W >> b.lout;
+      const int64_t rows = b.dec ? (ho / 2) * (wo / 2) : ho * wo;
+      const int64_t need = (int64_t)S.n * (b.dec ? 4 : 1) * ((rows + 63) / 64) * b.cout * (int64_t)sizeof(float);
+      if (need > (int64_t)(P.ws_part - P.ws_R)) return STDA_E_WORKSPACE;
+    }
+    T* s0 = reinterpret_cast<T*>(ws + S.s0);
+    StemArgs sa{x + S.x_off, wk + no.stem_w, ids + fold_ids_off(16), wk + no.stem_g, wk + no.stem_b, nullptr, nullptr};
+    FLAUNCH("stem_apply", k_stem_tile<T, 1><<<stem_grid(S.n, S.H, S.W), 256, 0, st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
+    if (int r = folded_block<T, 16, 32, false>(P, S, 0, fold, wk, ids, ws, st)) return r;
+    if (int r = folded_block<T, 32, 64, false>(P, S, 1, fold, wk, ids, ws, st)) return r;
+    if (int r = folded_block<T, 64, 32, true>(P, S, 2, fold, wk, ids, ws, st)) return r;
+    if (int r = folded_block<T, 32, 16, true>(P, S, 3, fold, wk, ids, ws, st)) return r;
+    const T* d1 = reinterpret_cast<const T*>(ws + S.blk[3].Xn);
+    const int gz = head_grid(S.n, S.H, S.W);
+    if (P.arch & STDA_ARCH_SIGMOID) {
+      FLAUNCH("head_fwd", k_head_fwd_tile<T, true><<<gz, 256, 0, st>>>(d1, wk + no.head_w, wk + no.head_b, z + S.z_off, nullptr, S.n, S.H, S.W));
+    } else {
+      FLAUNCH("head_fwd", k_head_fwd_tile<T, false><<<gz, 256, 0, st>>>(d1, wk + no.head_w, wk + no.head_b, z + S.z_off, nullptr, S.n, S.H, S.W));
+    }
+  }
+  return STDA_OK;
+}
+#undef FLAUNCH
 
 }  // namespace
 
@@ -1313,6 +1431,22 @@ int stda_forward_graph_create(const stda_segment* segs, int n_segs, const float*
       out);
 }
 
+int stda_forward_folded_graph_create(const stda_segment* segs, int n_segs, const float* x, const void* folded,
+                                     size_t folded_bytes, float* z, void* ws, size_t ws_bytes, int dtype,
+                                     hipStream_t stream, stda_graph* out) {
+  if (!out || !stream) return STDA_E_INVALID;
+  *out = nullptr;
+  if (int r = validate_segs(segs, n_segs)) return r;
+  if ((dtype != STDA_FP32 && dtype != STDA_BF16) || !x || !folded || !z || !ws) return STDA_E_INVALID;
+  if (!fold_arch_ok(current_arch())) return STDA_E_INVALID;
+  size_t sv = 0, wb = 0;
+  if (int r = stda_workspace_size(segs, n_segs, dtype, STDA_EVAL, 0, &sv, &wb)) return r;
+  if (ws_bytes < wb || folded_bytes < fold_layout(dtype).bytes) return STDA_E_WORKSPACE;
+  return capture_graph(
+      stream, [&]() { return stda_forward_folded(segs, n_segs, x, folded, folded_bytes, z, ws, ws_bytes, dtype, stream); },
+      out);
+}
+
 int stda_train_step_graph_create(const stda_segment* segs, int n_segs, const float* x, const float* y, float* w,
                                  float* running, float* z, double* loss, float* dz, float* dw, void* saved,
                                  size_t saved_bytes, void* ws, size_t ws_bytes, int dtype, int recompute, float lr,
@@ -1595,6 +1729,58 @@ int stda_forward_noalloc(const stda_segment* segs, int n_segs, const float* x, c
     float* rn = const_cast<float*>(running);
     return dtype == STDA_BF16 ? forward_all<bf16>(P, x, w, rn, z, nullptr, ws, stream)
                               : forward_all<float>(P, x, w, rn, z, nullptr, ws, stream);
+  } catch (...) {
+    return STDA_E_INVALID;
+  }
+}
+
+int stda_eval_fold_size(int dtype, size_t* bytes) {
+  if ((dtype != STDA_FP32 && dtype != STDA_BF16) || !bytes) return STDA_E_INVALID;
+  if (!fold_arch_ok(current_arch())) return STDA_E_INVALID;
+  *bytes = fold_layout(dtype).bytes;
+  return STDA_OK;
+}
+
+int stda_eval_fold(const float* w, const float* running, void* folded, size_t folded_bytes, int dtype,
+                   hipStream_t stream) {
+  try {
+    if ((dtype != STDA_FP32 && dtype != STDA_BF16) || !w || !running || !folded) return STDA_E_INVALID;
+    if (!fold_arch_ok(current_arch())) return STDA_E_INVALID;
+    const FoldLayout L = fold_layout(dtype);
+    if (folded_bytes < L.bytes) return STDA_E_WORKSPACE;
+    char* base = static_cast<char*>(folded);
+    float* wf = reinterpret_cast<float*>(base + L.wf_off);
+    const NetOffsets& no = net_offsets(L.P.arch);
+    HIP_TRY(hipMemcpyAsync(wf, w, sizeof(float) * no.param_count, hipMemcpyDeviceToDevice, stream));
+    FoldArgs fa{};
+    fa.no = no;
+    for (int k = 0; k < 4; ++k) {
+      fa.cin[k] = kBlocks[k].cin;
+      fa.cout[k] = kBlocks[k].cout;
+      fa.dec[k] = kBlocks[k].dec;
+    }
+    fa.ids = no.param_count;
+    k_fold_eval<<<10, 256, 0, stream>>>(w, running, wf, fa);
+    HIP_TRY(hipGetLastError());
+    const float* wk = nullptr;
+    return prepare_weights(L.P, wf, base, stream, &wk);
+  } catch (...) {
+    return STDA_E_INVALID;
+  }
+}
+
+int stda_forward_folded(const stda_segment* segs, int n_segs, const float* x, const void* folded, size_t folded_bytes,
+                        float* z, void* ws, size_t ws_bytes, int dtype, hipStream_t stream) {
+  try {
+    if (int r = validate_segs(segs, n_segs)) return r;
+    if ((dtype != STDA_FP32 && dtype != STDA_BF16) || !x || !folded || !z || !ws) return STDA_E_INVALID;
+    if (!fold_arch_ok(current_arch())) return STDA_E_INVALID;
+    const FoldLayout L = fold_layout(dtype);
+    Plan P;
+    build_plan(segs, n_segs, dtype, STDA_EVAL, 0, P);
+    if (folded_bytes < L.bytes || ws_bytes < P.ws_bytes) return STDA_E_WORKSPACE;
+    return dtype == STDA_BF16 ? forward_folded_all<bf16>(P, L, x, static_cast<const char*>(folded), z, (char*)ws, stream)
+                              : forward_folded_all<float>(P, L, x, static_cast<const char*>(folded), z, (char*)ws, stream);
   } catch (...) {
     return STDA_E_INVALID;
   }

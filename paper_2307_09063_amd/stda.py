@@ -51,6 +51,10 @@ def _load():
         'stda_workspace_size': (I, [P, I, I, I, I, P, P]),
         'stda_forward': (I, [P, I, P, P, P, P, P, SZ, P, SZ, I, I, I, P]),
         'stda_forward_noalloc': (I, [P, I, P, P, P, P, I, P]),
+        'stda_eval_fold_size': (I, [I, P]),
+        'stda_eval_fold': (I, [P, P, P, SZ, I, P]),
+        'stda_forward_folded': (I, [P, I, P, P, SZ, P, P, SZ, I, P]),
+        'stda_forward_folded_graph_create': (I, [P, I, P, P, SZ, P, P, SZ, I, P, P]),
         'stda_backward': (I, [P, I, P, P, P, P, SZ, P, P, P, SZ, I, I, P]),
         'stda_mse_loss': (I, [P, I, P, P, P, P, P, SZ, P]),
         'stda_sgd_step': (I, [P, P, I64, F, F, P, P]),
@@ -85,7 +89,8 @@ def _load():
 _lib = _load()
 EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'stda_param_table',
            'stda_bn_layer_count', 'stda_running_count', 'stda_set_arch', 'stda_get_arch', 'stda_workspace_size', 'stda_forward',
-           'stda_forward_noalloc',
+           'stda_forward_noalloc', 'stda_eval_fold_size', 'stda_eval_fold', 'stda_forward_folded',
+           'stda_forward_folded_graph_create',
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_set_grid_cap', 'stda_get_grid_cap', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
@@ -215,6 +220,25 @@ def forward_noalloc(segs, x, w, running, z, dtype=FP32):
                                      _ptr(z), dtype, _stream()), 'stda_forward_noalloc')
 
 
+def eval_fold_size(dtype=FP32):
+    n = ctypes.c_size_t()
+    _check(_lib.stda_eval_fold_size(dtype, ctypes.byref(n)), 'stda_eval_fold_size')
+    return n.value
+
+
+def eval_fold(w, running, folded, dtype=FP32):
+    """Folded EVAL parameters of (w, running) into the device byte buffer `folded`."""
+    _check(_lib.stda_eval_fold(_ptr(w), _ptr(running), _ptr(folded), folded.numel(), dtype, _stream()),
+           'stda_eval_fold')
+
+
+def forward_folded(segs, x, folded, z, ws, dtype=FP32):
+    arr = _seg_array(segs)
+    _check(_lib.stda_forward_folded(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(folded),
+                                    folded.numel(), _ptr(z), _ptr(ws), ws.numel(), dtype, _stream()),
+           'stda_forward_folded')
+
+
 def backward(segs, x, dz, w, saved, dw, dx, ws, dtype=FP32, recompute=0):
     arr = _seg_array(segs)
     _check(_lib.stda_backward(ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(dz), _ptr(w),
@@ -299,6 +323,37 @@ class TrainStepGraph:
                 _ptr(loss), _ptr(dz), _ptr(dw), _ptr(saved), saved.numel(), _ptr(ws), ws.numel(), dtype, recompute,
                 lr, weight_decay, _ptr(w_bf16), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
                 'stda_train_step_graph_create')
+        self.handle = h
+
+    def launch(self):
+        _check(_lib.stda_graph_launch(self.handle, ctypes.c_void_p(self.stream.cuda_stream)), 'stda_graph_launch')
+
+    def close(self):
+        if self.handle:
+            h, self.handle = self.handle, None
+            _check(_lib.stda_graph_destroy(h), 'stda_graph_destroy')
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FoldedForwardGraph:
+    """The folded EVAL forward captured into a graph and replayed with launch(); buffers bound at
+    capture."""
+
+    def __init__(self, segs, x, folded, z, ws, dtype=FP32, stream=None):
+        self.stream = stream or torch.cuda.Stream()
+        self._keep = (x, folded, z, ws)
+        arr = _seg_array(segs)
+        h = ctypes.c_void_p()
+        with torch.cuda.stream(self.stream):
+            _check(_lib.stda_forward_folded_graph_create(
+                ctypes.cast(arr, ctypes.c_void_p), len(segs), _ptr(x), _ptr(folded), folded.numel(), _ptr(z),
+                _ptr(ws), ws.numel(), dtype, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+                'stda_forward_folded_graph_create')
         self.handle = h
 
     def launch(self):

@@ -168,3 +168,29 @@ def test_set_arch_rejects_unknown_bits(S):
     assert S._lib.stda_get_arch() == 0
     with pytest.raises(S.StdaError):
         S.set_arch(5)
+
+
+def test_folded_eval_validation(S):
+    """The folded EVAL entry points: size query, refusal of the readings the fold does not cover
+    and argument checks before anything touches the device."""
+    assert S.eval_fold_size(0) > 4 * S.param_count() and S.eval_fold_size(1) > 4 * S.param_count()
+    for kw in ({'res_k': 3}, {'pw': 'depthwise'}):
+        S.set_arch(**kw)
+        try:
+            with pytest.raises(S.StdaError):
+                S.eval_fold_size(0)
+        finally:
+            S.set_arch()
+    lib, fake = S._lib, ctypes.c_void_p(16)
+    need = S.eval_fold_size(0)
+    assert lib.stda_eval_fold(fake, fake, fake, need - 1, 0, None) == -3
+    assert lib.stda_eval_fold(None, fake, fake, need, 0, None) == -1
+    assert lib.stda_eval_fold(fake, fake, fake, need, 5, None) == -1
+    p, n = _segs(S, (1, 16, 16, 0, 0))
+    sv, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.stda_workspace_size(p, n, 0, 0, 0, ctypes.byref(sv), ctypes.byref(wb)) == 0
+    assert lib.stda_forward_folded(p, n, fake, fake, need, fake, fake, wb.value - 1, 0, None) == -3
+    assert lib.stda_forward_folded(p, n, fake, fake, need - 1, fake, fake, wb.value, 0, None) == -3
+    assert lib.stda_forward_folded(p, n, None, fake, need, fake, fake, wb.value, 0, None) == -1
+    q, m = _segs(S, (1, 10, 16, 0, 0))
+    assert lib.stda_forward_folded(q, m, fake, fake, need, fake, fake, wb.value, 0, None) == -2
