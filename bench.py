@@ -80,39 +80,53 @@ def kernel_work(tag, B, H, W, es):
 
 def stage2_layers(per_tag, groups, bf16):
     """Roofline of every stage-2 dense launch (the layers holding most of the arithmetic) from one
-    profiled step, {tag: {us, bound, frac}}; None for batches of several map sizes."""
-    if len(groups) != 1:
-        return None
-    B, N, M = groups[0]
+    profiled step, {tag: {us, bound, frac}}; for a batch of several map sizes the work of every
+    segment's launch over the tag's summed time (us: mean per launch)."""
     out = {}
     for t, (cnt, tms) in sorted(per_tag.items()):
         if t.split('.')[0] in ('dense_fwd_main', 'dense_fwd_res', 'dense_dgrad_main', 'dense_dgrad_res', 'wgrad_main',
                                'wgrad_res'):
-            rl = roofline(t, tms / cnt, B, N, M, bf16)
+            rl = roofline_groups(t, tms, cnt, groups, bf16)
             if rl:
-                out[t] = {'us': rl['avg_us'], 'bound': rl['bound'], 'frac': rl['frac']}
+                out[t] = {'us': round(tms * 1e3 / cnt, 2), 'bound': rl['bound'], 'frac': rl['frac']}
     return out or None
 
 
 def roofline(tag, avg_ms, B, H, W, dtype_bf16):
+    return roofline_groups(tag, avg_ms, 1, [(B, H, W)], dtype_bf16)
+
+
+def roofline_groups(tag, total_ms, launches, groups, dtype_bf16):
+    """Roofline of `launches` launches of the tagged kernel taking total_ms together, spread evenly
+    over the segments `groups` [(clips, H, W)] (one launch per segment per step): algorithmic work
+    of all of them over their total time, against the engine's peak or HBM, whichever binds."""
     es = 2 if dtype_bf16 else 4
-    w = kernel_work(tag, B, H, W, es)
-    if w is None or avg_ms <= 0:
+    per = launches / len(groups)
+    flops = nbytes = 0.0
+    engine = None
+    for B, H, W in groups:
+        w = kernel_work(tag, B, H, W, es)
+        if w is None:
+            return None
+        flops += w[0] * per
+        nbytes += w[1] * per
+        engine = w[2]
+    if total_ms <= 0:
         return None
-    flops, nbytes, engine = w
     peak_c = PEAK['mfma_bf16' if dtype_bf16 else 'mfma_f32'] if engine == 'mfma' else PEAK['alu_f32']
     t_c = flops / (peak_c * 1e12)
     t_b = nbytes / (PEAK['hbm'] * 1e9)
-    sec = avg_ms / 1e3
+    sec = total_ms / 1e3
+    avg_us = round(total_ms * 1e3 / launches, 2)
     if t_c >= t_b:
         achieved = flops / sec / 1e12
         return {'bound': engine, 'achieved': round(achieved, 2), 'peak': peak_c, 'unit': 'TFLOP/s',
                 'frac': round(achieved / peak_c, 4), 'traffic': None, 'kernel': tag,
-                'avg_us': round(avg_ms * 1e3, 2), 'algorithmic_flops': flops, 'algorithmic_bytes': nbytes}
+                'avg_us': avg_us, 'algorithmic_flops': flops / launches, 'algorithmic_bytes': nbytes / launches}
     achieved = nbytes / sec / 1e9
     return {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': PEAK['hbm'], 'unit': 'GB/s',
             'frac': round(achieved / PEAK['hbm'], 4), 'traffic': None, 'kernel': tag,
-            'avg_us': round(avg_ms * 1e3, 2), 'algorithmic_flops': flops, 'algorithmic_bytes': nbytes}
+            'avg_us': avg_us, 'algorithmic_flops': flops / launches, 'algorithmic_bytes': nbytes / launches}
 
 
 def parse():
@@ -334,8 +348,8 @@ def main():
     ms_eager = tr.timed(args.steps, False)
     k_total, k_count = stda.profile_read()
     stda.profile_select(None)
-    roof = roofline(dominant, k_total / max(k_count, 1), B, N, M, dtype == stda.BF16) if len(groups) == 1 else None
-    if roof is not None:
+    roof = roofline_groups(dominant, k_total, max(k_count, 1), groups, dtype == stda.BF16)
+    if roof is not None and len(groups) == 1:
         roof['traffic'] = measured_traffic(dominant, args.workload, tiles)
     print(f'bench: {ms:.3f} ms/step ({clips_s:.0f} clips/s), eager {ms_eager:.3f} ms, wall {wall:.2f}s, '
           f'loss {tr.loss.item():.5f}', file=sys.stderr, flush=True)

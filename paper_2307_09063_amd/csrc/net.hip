@@ -1060,13 +1060,13 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
 
 // Fused stage-1 adjoint of block `blk` with the tiling chosen for it (tuning kind 3): TH x TW
 // pixel tiles, MINW waves per SIMD; *rows = workgroups = rows of weight-gradient partials.
-template <class T, int C, bool DEC, int TH, int TW, int MINW>
+template <class T, int C, bool DEC, int TH, int TW, int MINW, bool LC = false>
 int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T* dX1, const T* dXr, const T* skipg,
                    const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
   const int64_t tiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   const int g = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
   const float* coef = c.template scr<float>(c.P->ws_coef);
-  KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW><<<g, 256, 0, c.st>>>(
+  KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW, LC><<<g, 256, 0, c.st>>>(
                                          X, M1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
   *rows = g;
   return STDA_OK;
@@ -1078,10 +1078,14 @@ int launch_s1b(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T*
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
 #define S1B(TH_, TW_, W_) \
   launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
-  if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1B(8, 8, 2) : S1B(8, 16, 2);
-  else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1B(4, 8, 2) : S1B(8, 8, 2);
-  else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1B(8, 2, 2) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
+  // LC: depthwise taps and BN-adjoint coefficients read from LDS, three waves per SIMD
+#define S1L(TH_, TW_) \
+  launch_s1b_cfg<T, C, DEC, TH_, TW_, 3, true>(c, blk, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
+  if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1L(8, 16) : S1B(8, 16, 2);
+  else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1L(8, 8) : S1B(8, 8, 2);
+  else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1L(4, 4) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
 #undef S1B
+#undef S1L
 }
 
 template <class T>

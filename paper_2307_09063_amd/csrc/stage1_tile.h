@@ -47,7 +47,7 @@ struct S1Lds {
   static constexpr bool SWZ = C == 64;
   static constexpr int TGT = C == 16 ? 16 : 8;
   static constexpr int PL = NPIX * 4 + (TGT - (NPIX * 4) % 64 + 64) % 64;
-  static constexpr int SIZE = SWZ ? NPIX * C : (C / 4) * PL;
+  static constexpr int SIZE = SWZ ? NPIX * C : (C / 4 - 1) * PL + NPIX * 4;  // no pad after the last plane
 };
 // Float offset of chunk q (channels 4q .. 4q + 3) of LDS pixel px, and of channel c.
 template <int C, int NPIX>
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 // for dX); the three pointwise
 // products (p = x Wp, dP Wp^T, x^T dP) run on the matrix cores, the last one accumulating in
 // registers across tiles.  Tiles are TH x TW pixels; MINW waves per SIMD bound the registers.
-template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW>
+template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW, bool LC = false>
 __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict__ X, const uint8_t* __restrict__ M1,
                                                          const T* __restrict__ dX1, const T* __restrict__ dXr,
                                                          const T* __restrict__ skip, const float* __restrict__ coef,
@@ -507,17 +507,29 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);  // ends with a barrier
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
   const int c0 = (threadIdx.x % G) * 4;
-  float wr[9][4];
-  s1_dw_regs<C>(wd, c0, wr);
-  float cfr[9][4];  // this thread's 4 channels of the 9 coefficient rows
+  // LC: the depthwise taps and the BN-adjoint coefficients are read from LDS where they are used
+  // (72 registers fewer per thread, for a third wave per SIMD); otherwise held in registers
+  float wr[LC ? 1 : 9][4];
+  float cfr[LC ? 1 : 9][4];  // this thread's 4 channels of the 9 coefficient rows
+  if constexpr (!LC) {
+    s1_dw_regs<C>(wd, c0, wr);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    const float4 t = *reinterpret_cast<const float4*>(cf + q * C + c0);
-    cfr[q][0] = t.x;
-    cfr[q][1] = t.y;
-    cfr[q][2] = t.z;
-    cfr[q][3] = t.w;
+    for (int q = 0; q < 9; ++q) {
+      const float4 t = *reinterpret_cast<const float4*>(cf + q * C + c0);
+      cfr[q][0] = t.x;
+      cfr[q][1] = t.y;
+      cfr[q][2] = t.z;
+      cfr[q][3] = t.w;
+    }
   }
+  auto W4 = [&](int t) {
+    if constexpr (LC) return *reinterpret_cast<const float4*>(wd + t * C + c0);
+    else return make_float4(wr[t][0], wr[t][1], wr[t][2], wr[t][3]);
+  };
+  auto CF4 = [&](int q) {
+    if constexpr (LC) return *reinterpret_cast<const float4*>(cf + q * C + c0);
+    else return make_float4(cfr[q][0], cfr[q][1], cfr[q][2], cfr[q][3]);
+  };
   float dwacc[9][4];
 #pragma unroll
   for (int t = 0; t < 9; ++t) zero4(dwacc[t]);
@@ -535,7 +547,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     // previous item.  Not at 64 channels, whose tiles have no registers to spare: there each item
     // loads its own.
     constexpr int NA = (TH + 2) * DWd * G;
-    constexpr bool PF = C < 64;
+    constexpr bool PF = C < 64 && !LC;  // (LC: registers go to a third wave instead)
     typedef typename Raw4<T>::type R4;  // held in storage form until used
     R4 ng;
     uint32_t nm;  // the byte of M1 holding this thread's 4 decisions
@@ -552,7 +564,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
     };
     if constexpr (PF) a2_load(threadIdx.x);
     __syncthreads();
-    load_tile<T, C, TH, TW, 2>(X, b, y0, x0, h, w, xt);
+    load_tile<T, C, TH, TW, 2, !LC>(X, b, y0, x0, h, w, xt);  // LC: one load at a time (register peak)
     __syncthreads();
     // A1: pointwise branch of the tile, qt = x Wp
     lds_gemm_s<M, C, C>([&](int p, int kk) { return xt[s1e<C, XN>(xpx(p), kk)]; },
@@ -584,7 +596,16 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         m >>= (c0 & 4);
         float dv[4];
         float4 xn[9];
-        s1_dw_lds_keep<C, XN>(xt, XW, r + 1, cc + 1, c0, wr, dv, xn);
+        zero4(dv);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+          xn[t] = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 1 + t / 3 - 1) * XW + cc + 1 + t % 3 - 1, c0 >> 2));
+          const float4 w4 = W4(t);
+          dv[0] += w4.x * xn[t].x;
+          dv[1] += w4.y * xn[t].y;
+          dv[2] += w4.z * xn[t].z;
+          dv[3] += w4.w * xn[t].w;
+        }
         float pv[4] = {0.f, 0.f, 0.f, 0.f};
         if (center) {
           const float4 pq = *reinterpret_cast<const float4*>(qt + s1c<C, M>((r - 1) * TW + cc - 1, c0 >> 2));
@@ -593,7 +614,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
           pv[2] = pq.z;
           pv[3] = pq.w;
         }
-        const float *pa = cfr[0], *pb = cfr[1], *pe = cfr[2], *da = cfr[3], *db = cfr[4], *de = cfr[5];
+        const float4 pa4 = CF4(0), pb4 = CF4(1), pe4 = CF4(2), da4 = CF4(3), db4 = CF4(4), de4 = CF4(5);
+        const float pa[4] = {pa4.x, pa4.y, pa4.z, pa4.w}, pb[4] = {pb4.x, pb4.y, pb4.z, pb4.w};
+        const float pe[4] = {pe4.x, pe4.y, pe4.z, pe4.w}, da[4] = {da4.x, da4.y, da4.z, da4.w};
+        const float db[4] = {db4.x, db4.y, db4.z, db4.w}, de[4] = {de4.x, de4.y, de4.z, de4.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const float du = (m >> j) & 1u ? g[j] : 0.f;
@@ -634,7 +658,8 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         }
       }
     };
-    if constexpr (PF) b2_load(threadIdx.x);
+    constexpr bool PF2 = !LC;  // dX phase: load one pair ahead (else each pair loads its own)
+    if constexpr (C < 64 && PF2) b2_load(threadIdx.x);
     __syncthreads();
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
     lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
@@ -671,17 +696,21 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         const int px = 2 * (e / G), r = px / TW, cc = px % TW;  // pixels px, px + 1 of tile row r
         const int y = y0 + r, x = x0 + cc;
         float rp[2][4], sp2[2][4];
+        if constexpr (!PF2) b2_load(e);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           raw_cvt4(nr[s], rp[s]);
           raw_cvt4(ns[s], sp2[s]);
         }
-        if (e + STDA_BLOCK < NB2) b2_load(e + STDA_BLOCK);
+        if constexpr (PF2)
+          if (e + STDA_BLOCK < NB2) b2_load(e + STDA_BLOCK);
         if (y >= h || x >= w) continue;
         const bool second = x + 1 < w;
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         float acc[2][4];
-        const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
+        const float4 xa4 = CF4(6), xb4 = CF4(7), xe4 = CF4(8);
+        const float xa[4] = {xa4.x, xa4.y, xa4.z, xa4.w}, xb[4] = {xb4.x, xb4.y, xb4.z, xb4.w};
+        const float xe[4] = {xe4.x, xe4.y, xe4.z, xe4.w};
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           if (s == 1 && !second) break;
@@ -708,19 +737,19 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
             col[k] = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + k, c0 >> 2));
 #pragma unroll
           for (int k = 2; k >= 0; --k) {
-            const int t = dyi * 3 + 2 - k;
-            acc[0][0] += wr[t][0] * col[k].x;
-            acc[0][1] += wr[t][1] * col[k].y;
-            acc[0][2] += wr[t][2] * col[k].z;
-            acc[0][3] += wr[t][3] * col[k].w;
+            const float4 w4 = W4(dyi * 3 + 2 - k);
+            acc[0][0] += w4.x * col[k].x;
+            acc[0][1] += w4.y * col[k].y;
+            acc[0][2] += w4.z * col[k].z;
+            acc[0][3] += w4.w * col[k].w;
           }
 #pragma unroll
           for (int k = 3; k >= 1; --k) {
-            const int t = dyi * 3 + 3 - k;
-            acc[1][0] += wr[t][0] * col[k].x;
-            acc[1][1] += wr[t][1] * col[k].y;
-            acc[1][2] += wr[t][2] * col[k].z;
-            acc[1][3] += wr[t][3] * col[k].w;
+            const float4 w4 = W4(dyi * 3 + 3 - k);
+            acc[1][0] += w4.x * col[k].x;
+            acc[1][1] += w4.y * col[k].y;
+            acc[1][2] += w4.z * col[k].z;
+            acc[1][3] += w4.w * col[k].w;
           }
         }
         st4(dX + off, acc[0]);
@@ -738,7 +767,9 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px, c0 >> 2));
         const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px, c0 >> 2));
         const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
-        const float *xa = cfr[6], *xb = cfr[7], *xe = cfr[8];
+        const float4 xa4 = CF4(6), xb4 = CF4(7), xe4 = CF4(8);
+        const float xa[4] = {xa4.x, xa4.y, xa4.z, xa4.w}, xb[4] = {xb4.x, xb4.y, xb4.z, xb4.w};
+        const float xe[4] = {xe4.x, xe4.y, xe4.z, xe4.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
         if (SKIP) {
@@ -752,10 +783,11 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
         for (int t = 0; t < 9; ++t) {
           const int dy = t / 3 - 1, dx = t % 3 - 1;
           const float4 v = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + 1 - dx, c0 >> 2));
-          acc[0] += wr[t][0] * v.x;
-          acc[1] += wr[t][1] * v.y;
-          acc[2] += wr[t][2] * v.z;
-          acc[3] += wr[t][3] * v.w;
+          const float4 w4 = W4(t);
+          acc[0] += w4.x * v.x;
+          acc[1] += w4.y * v.y;
+          acc[2] += w4.z * v.z;
+          acc[3] += w4.w * v.w;
         }
         st4(dX + off, acc);
       }

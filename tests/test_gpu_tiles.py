@@ -182,8 +182,9 @@ def test_stage1_adjoint_variants_agree(S, dtype):
     in every variant, but each instantiation is compiled on its own (tile shape, register budget)
     and may fuse its multiply-adds differently, so dx and the gradients upstream of it agree to
     FP32 rounding rather than bitwise; the stage-1 weight gradients (summed per tile) also differ
-    by the order of their pixel sums.  Each variant also meets the oracle gate
-    (test_variant_fp32_train_backward)."""
+    by the order of their pixel sums (in BF16, where the adjoint stores its outputs in BF16, those
+    FP32 differences can move single elements by a BF16 step).  Each variant also meets the oracle
+    gate (test_variant_fp32_train_backward)."""
     B, H, W = SHAPES[1]
     x, _ = U.maps(B, H, W, seed=41)
     w, r = U.weights(), U.running()
@@ -199,7 +200,11 @@ def test_stage1_adjoint_variants_agree(S, dtype):
         S.backward(segs, xd, U.dev(g), wd, saved, dw, dx, ws, dtype)
         torch.cuda.synchronize()
         res.append((dw.cpu().numpy(), dx.cpu().numpy()))
+    # FP32: agreement to FP32 rounding.  BF16: the adjoint's outputs are stored in BF16, so an FP32
+    # difference that straddles a BF16 rounding boundary moves that element by a full BF16 step
+    # (2^-8 relative); a few such elements per ten thousand give rel-L2 of order 1e-4.
+    tol_dx, tol_w = (1e-6, 1e-5) if dtype == 0 else (2e-3, 2e-3)
     for v in range(1, len(res)):
-        assert U.rel_l2(res[v][1], res[0][1]) < 1e-6, v
-        bad = {k: e for k, e in U.per_tensor_errors(res[v][0], res[0][0]).items() if not e < 1e-5}
+        assert U.rel_l2(res[v][1], res[0][1]) < tol_dx, v
+        bad = {k: e for k, e in U.per_tensor_errors(res[v][0], res[0][0]).items() if not e < tol_w}
         assert not bad, (v, bad)
