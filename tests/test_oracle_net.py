@@ -1,6 +1,8 @@
 """Pins of the oracle network: parameter count, zero input, an independent torch.nn.functional
 re-expression (forward, running statistics, autograd gradient), FP64 central finite
 differences, the loss closed form, and the EVAL-mode re-parameterisation identity.  CPU only."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -81,10 +83,31 @@ def _kinks(w, r, x):
                           + [(a['s0'] > 0).ravel()])
 
 
+def _fd_coordinates(args):
+    """Central differences of the loss along single coordinates (worker of the FD test): for each
+    index, (True, None) if a step flips a ReLU, else (False, relative error against g)."""
+    w, r, x, y, g, idx, h = args
+    f = lambda ww: net.mse_loss(net.forward(ww, r, x, 'train')[0], y)[0]
+    base = _kinks(w, r, x)
+    out = []
+    for i in idx:
+        e = np.zeros_like(w)
+        e[i] = h
+        if not (np.array_equal(base, _kinks(w + e, r, x)) and np.array_equal(base, _kinks(w - e, r, x))):
+            out.append((True, None))
+            continue
+        fd = (f(w + e) - f(w - e)) / (2 * h)
+        out.append((False, abs(fd - g[i]) / max(abs(fd), 1e-3 * np.abs(g).max())))
+    return out
+
+
 def test_gradient_central_finite_differences():
     """One 3 x 16 x 16 clip (B = 2 for non-degenerate batch statistics), h = 1e-6: a random
-    direction over all parameters plus sampled coordinates; steps that flip a ReLU are counted
-    and skipped."""
+    direction over all parameters plus 2,000 sampled coordinates and one in every parameter tensor
+    (BN, ECA and the head bias included); steps that flip a ReLU are counted and skipped.  The
+    coordinates are spread over worker processes."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
     w, r, x, y = _setup(B=2, H=16, W=16, seed=33)
     loss, g, _, _, _ = net.loss_and_grad(w, r, x, y)
     f = lambda ww: net.mse_loss(net.forward(ww, r, x, 'train')[0], y)[0]
@@ -96,23 +119,20 @@ def test_gradient_central_finite_differences():
     assert np.array_equal(base, _kinks(w + h * v, r, x)) and np.array_equal(base, _kinks(w - h * v, r, x))
     fd = (f(w + h * v) - f(w - h * v)) / (2 * h)
     assert abs(fd - g @ v) <= 1e-6 * abs(fd)
-    idx = rng.choice(w.size, 150, replace=False)
-    # every small tensor (BN, ECA, head bias) is covered too
+    idx = rng.choice(w.size, 2000, replace=False)
     offs, o = [], 0
     for _, shape, _ in net.param_specs():
         n = int(np.prod(shape))
         offs.append(o + n // 2)
         o += n
     idx = np.unique(np.concatenate([idx, offs]))
-    flips, errs = 0, []
-    for i in idx:
-        e = np.zeros_like(w)
-        e[i] = h
-        if not (np.array_equal(base, _kinks(w + e, r, x)) and np.array_equal(base, _kinks(w - e, r, x))):
-            flips += 1
-            continue
-        fd = (f(w + e) - f(w - e)) / (2 * h)
-        errs.append(abs(fd - g[i]) / max(abs(fd), 1e-3 * np.abs(g).max()))
+    workers = max(1, min(8, os.cpu_count() or 1))
+    chunks = [(w, r, x, y, g, c, h) for c in np.array_split(idx, 4 * workers)]
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context('spawn')) as ex:
+        res = [t for part in ex.map(_fd_coordinates, chunks) for t in part]
+    flips = sum(1 for fl, _ in res if fl)
+    errs = [e for fl, e in res if not fl]
+    assert len(idx) >= 2000
     assert flips < len(idx) // 10
     assert max(errs) < 1e-5
 
