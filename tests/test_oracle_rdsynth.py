@@ -1,6 +1,7 @@
 """Pins of the oracle RD-map synthesizer and metrics: Philox known answers, Box-Muller moments,
-Parseval, closed-form Hann tone spectra, brute-force DFT, analytic peak positions, the ghost
-case of identical chirps, the IF gate, and the SINR / EVM closed forms.  CPU only."""
+Parseval, closed-form Hann tone spectra, brute-force DFT, analytic peak positions and their motion
+over the three frames, the ghost case of identical chirps, the IF gate, and the SINR / EVM closed
+forms.  CPU only."""
 import json
 import os
 
@@ -122,6 +123,35 @@ def test_target_peak_positions():
         p, q = np.unravel_index(np.argmax(Y), Y.shape)
         ep, eq = meta['peaks'][0][0]
         assert abs(((p - ep + 32) % 64) - 32) <= 1 and abs(((q - eq + 16) % 32) - 16) <= 1
+
+
+def test_target_motion_across_frames():
+    """A target of radial velocity v (in units of v_max, the sign of its Doppler bin offset) moves
+    v kappa_f range units per frame, kappa_f = v_max T_frame / R_max (Sec. V-A): the RD peak of
+    frame t - f sits at the range bin nearest (r - f v kappa_f) N, r = the frame-t range read back
+    from the tone table as f_r / 2^32 and v = 2 f_d / 2^32, and at the same Doppler bin in all
+    three frames.  At N = 256
+    a target at the velocity limit moves 2.5 bins a frame, so a dropped or reversed frame term
+    moves the peak by 2 bins or more."""
+    N, M = 256, 32
+    moved = 0
+    for trial in range(8):
+        tab, meta = inputs.make_scenes(1, N, M, seed=300 + trial, targets=(1, 1), intf=(0, 0))
+        sc = inputs.scene_dict(tab, meta)
+        sc['noise_sigma'] = 0.0
+        r = int(tab[0]['tone']['fr'][0, 0]) / 2.0 ** 32
+        fd = int(tab[0]['tone']['fd'][0, 0])
+        v = 2.0 * (fd - 2 ** 32 if fd >= 2 ** 31 else fd) / 2.0 ** 32
+        qs = set()
+        for f in range(3):
+            Y = np.abs(R.rd_spectrum(R.beat_signal(sc, 0, f)))
+            p, q = np.unravel_index(np.argmax(Y), Y.shape)
+            ep = (r - f * v * inputs.KAPPA_F) * N
+            assert abs(((p - ep + N / 2) % N) - N / 2) <= 0.5 + 1e-9, (trial, f, p, ep)
+            qs.add(int(q))
+        assert len(qs) == 1 and abs(((qs.pop() - meta['peaks'][0][0][1] + M // 2) % M) - M // 2) <= 1
+        moved += abs(v) * inputs.KAPPA_F * N > 1.0
+    assert moved >= 3
 
 
 def test_ghost_identical_chirps():
