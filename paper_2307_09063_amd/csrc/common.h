@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "seg.h"
+
 #define STDA_BLOCK 256
 
 namespace stda {

@@ -97,9 +97,29 @@ __global__ void k_prep_frag(const float* __restrict__ wl, T* __restrict__ frag, 
 }
 
 template <class T, int OP, int K, int N, int R, bool STATS>
-__global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, const T* __restrict__ wfrag,
-                                                    T* __restrict__ dst, float* __restrict__ part, int B, int hd,
-                                                    int wd) {
+struct k_dense_mfma_args {
+  const T* src;
+  const T* wfrag;
+  T* dst;
+  float* part;
+  int B;
+  int hd;
+  int wd;
+};
+template <class T, int OP, int K, int N, int R, bool STATS>
+__global__ __launch_bounds__(256) void k_dense_mfma(SegL<k_dense_mfma_args<T, OP, K, N, R, STATS>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_dense_mfma_args<T, OP, K, N, R, STATS>& a_ = L.a[sb.s];
+  const T* __restrict__ const src = a_.src;
+  const T* __restrict__ const wfrag = a_.wfrag;
+  T* __restrict__ const dst = a_.dst;
+  float* __restrict__ const part = a_.part;
+  const int B = a_.B;
+  const int hd = a_.hd;
+  const int wd = a_.wd;
   typedef typename FragT<T>::type F;
   constexpr int KS = OpGeo<OP>::KS;
   constexpr bool DOWN = OpGeo<OP>::DOWN;
@@ -112,12 +132,16 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
   const int64_t P = (int64_t)B * hr * wr;
   const int64_t tiles = (P + 64 * R - 1) / (64 * R);
   const F* wf = reinterpret_cast<const F*>(wfrag);
+  // the unrolled tap loop lets the compiler keep every weight fragment of the layer in registers
+  // across tiles; that pays while they fit (up to 256 dwords a lane)
+  constexpr int WDW = (DOWN ? KS * KS : 4) * KC * NT * (int)(sizeof(F) / 4);
+  constexpr bool HOIST_W = WDW <= 256;
   float mn[NT], q2[NT];  // STATS: mean and m2 of this lane's columns 16 nt + m (Welford)
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) mn[nt] = q2[nt] = 0.f;
   float cnt = 0.f;  // rows seen by this lane
 
-  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+  for (int64_t tile = bx; tile < tiles; tile += gx) {
     const int64_t pbase = (tile * 4 + wave) * 16 * R;
     int pb[R], prow[R], pcol[R];
     bool pv[R];
@@ -133,41 +157,35 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[r][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+    // one tap (ky, kx) of the GEMM's k loop
+    auto do_tap = [&](const int ky, const int kx) {
+      const int tap = ky * KS + kx;
+      int64_t so[R];
 #pragma unroll
-    for (int a = 0; a < (DOWN ? KS : 2); ++a) {
-      const int ky = DOWN ? a : ((py + 1) & 1) + 2 * a;
-      if (ky >= KS) continue;
+      for (int r = 0; r < R; ++r) {
+        const int sy = DOWN ? 2 * prow[r] - 1 + ky : (2 * prow[r] + py + 1 - ky) / 2;
+        const int sx = DOWN ? 2 * pcol[r] - 1 + kx : (2 * pcol[r] + px + 1 - kx) / 2;
+        const bool ok = pv[r] && sy >= 0 && sy < hs && sx >= 0 && sx < ws;
+        so[r] = ok ? (((int64_t)pb[r] * hs + sy) * ws + sx) * K + 4 * g : -1;
+      }
+      if constexpr (PAIR2) {
+        // BF16, K a multiple of 32: chunks s and s + 1 of the tap feed one 16x16x32 product
 #pragma unroll
-      for (int c = 0; c < (DOWN ? KS : 2); ++c) {
-        const int kx = DOWN ? c : ((px + 1) & 1) + 2 * c;
-        if (kx >= KS) continue;
-        const int tap = ky * KS + kx;
-        int64_t so[R];
+        for (int s = 0; s < KC; s += 2) {
+          bf16x8 av[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int sy = DOWN ? 2 * prow[r] - 1 + ky : (2 * prow[r] + py + 1 - ky) / 2;
-          const int sx = DOWN ? 2 * pcol[r] - 1 + kx : (2 * pcol[r] + px + 1 - kx) / 2;
-          const bool ok = pv[r] && sy >= 0 && sy < hs && sx >= 0 && sx < ws;
-          so[r] = ok ? (((int64_t)pb[r] * hs + sy) * ws + sx) * K + 4 * g : -1;
-        }
-        if constexpr (PAIR2) {
-          // BF16, K a multiple of 32: chunks s and s + 1 of the tap feed one 16x16x32 product
+          for (int r = 0; r < R; ++r)
+            av[r] = so[r] >= 0 ? pack8(*reinterpret_cast<const F*>(src + so[r] + 16 * s),
+                                       *reinterpret_cast<const F*>(src + so[r] + 16 * s + 16))
+                               : pack8(frag_zero<F>(), frag_zero<F>());
 #pragma unroll
-          for (int s = 0; s < KC; s += 2) {
-            bf16x8 av[R];
+          for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 bv = pack8(wf[((tap * KC + s) * NT + nt) * 64 + lane], wf[((tap * KC + s + 1) * NT + nt) * 64 + lane]);
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-              av[r] = so[r] >= 0 ? pack8(*reinterpret_cast<const F*>(src + so[r] + 16 * s),
-                                         *reinterpret_cast<const F*>(src + so[r] + 16 * s + 16))
-                                 : pack8(frag_zero<F>(), frag_zero<F>());
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-              const bf16x8 bv = pack8(wf[((tap * KC + s) * NT + nt) * 64 + lane], wf[((tap * KC + s + 1) * NT + nt) * 64 + lane]);
-#pragma unroll
-              for (int r = 0; r < R; ++r) acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][nt], 0, 0, 0);
-            }
+            for (int r = 0; r < R; ++r) acc[r][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[r], bv, acc[r][nt], 0, 0, 0);
           }
-        } else
+        }
+      } else {
 #pragma unroll
         for (int s = 0; s < KC; ++s) {
           F av[R];
@@ -181,6 +199,30 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
             for (int r = 0; r < R; ++r) acc[r][nt] = mfma_chunk(av[r], bv, acc[r][nt]);
           }
         }
+      }
+    };
+    // taps of this phase: KS x KS (stride-2 convolution) or 2 x 2 (one phase of a transposed one)
+    constexpr int NA = DOWN ? KS : 2;
+    if constexpr (HOIST_W) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        const int ky = DOWN ? a : ((py + 1) & 1) + 2 * a;
+        if (ky >= KS) continue;
+#pragma unroll
+        for (int c = 0; c < NA; ++c) {
+          const int kx = DOWN ? c : ((px + 1) & 1) + 2 * c;
+          if (kx >= KS) continue;
+          do_tap(ky, kx);
+        }
+      }
+    } else {
+      // a runtime tap loop: the weight fragments are read per tile (from cache) instead of being
+      // held across tiles, which for this many taps would not fit the registers
+#pragma unroll 1
+      for (int t = 0; t < NA * NA; ++t) {
+        const int a = t / NA, c = t % NA;
+        const int ky = DOWN ? a : ((py + 1) & 1) + 2 * a, kx = DOWN ? c : ((px + 1) & 1) + 2 * c;
+        if (ky < KS && kx < KS) do_tap(ky, kx);
       }
     }
     // epilogue: lane holds rows 4g + i of each 16-row sub-tile, channel 16 nt + m
@@ -232,7 +274,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
       if (m == 0) sm[wave][2 * N] = cnt;
     }
     __syncthreads();
-    const int64_t blk = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int64_t blk = (int64_t)blockIdx.y * gx + bx;
     for (int c = threadIdx.x; c < N; c += STDA_BLOCK) {
       float na = sm[0][2 * N], ma = sm[0][c], qa = sm[0][N + c];
 #pragma unroll
@@ -242,7 +284,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(const T* __restrict__ src, c
       }
       part[blk * 2 * N + 2 * c] = ma;
       part[blk * 2 * N + 2 * c + 1] = qa;
-      if (c == 0) part[(int64_t)gridDim.x * gridDim.y * 2 * N + blk] = na;
+      if (c == 0) part[(int64_t)gx * gridDim.y * 2 * N + blk] = na;
     }
   }
 }

@@ -111,16 +111,41 @@ constexpr int kFoldIds = 2 * (16 + 32 + 64);
 
 // Stage 2 of a folded mobile block:  y = ReLU(conv'(x1) + bias) + conv_res(x),  stored in the
 // storage type, and per (clip, phase, row tile) channel sums of the stored y for the ECA average:
-// gap[((clip * PH + phase) * gridDim.x + tile) * N + n].  The two convolutions have the same
+// gap[((clip * PH + phase) * tiles + tile) * N + n].  The two convolutions have the same
 // geometry (x1 and x have the same width and map size), so each tap's A-fragment address serves
 // both sources; the wave keeps two accumulator chains.  One wave computes 16 R rows of one clip's
-// output (phase) grid with all N output channels; grid (row tiles, phases, clips).  Weights in
+// output (phase) grid with all N output channels; grid (clips x row tiles, phases).  Weights in
 // MFMA fragment order as for k_dense_mfma.
 template <class T, int OP, int K, int N, int R>
-__global__ __launch_bounds__(256) void k_s2_eval(const T* __restrict__ x1, const T* __restrict__ x,
-                                                 const T* __restrict__ wmain, const T* __restrict__ wres,
-                                                 const float* __restrict__ bias, T* __restrict__ y,
-                                                 float* __restrict__ gap, int hd, int wd) {
+struct k_s2_eval_args {
+  const T* x1;
+  const T* x;
+  const T* wmain;
+  const T* wres;
+  const float* bias;
+  T* y;
+  float* gap;
+  int hd;
+  int wd;
+  int tiles;
+};
+template <class T, int OP, int K, int N, int R>
+__global__ __launch_bounds__(256) void k_s2_eval(SegL<k_s2_eval_args<T, OP, K, N, R>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_eval_args<T, OP, K, N, R>& a_ = L.a[sb.s];
+  const T* __restrict__ const x1 = a_.x1;
+  const T* __restrict__ const x = a_.x;
+  const T* __restrict__ const wmain = a_.wmain;
+  const T* __restrict__ const wres = a_.wres;
+  const float* __restrict__ const bias = a_.bias;
+  T* __restrict__ const y = a_.y;
+  float* __restrict__ const gap = a_.gap;
+  const int hd = a_.hd;
+  const int wd = a_.wd;
+  const int tiles = a_.tiles;
   typedef typename FragT<T>::type F;
   constexpr int KS = OpGeo<OP>::KS;
   constexpr bool DOWN = OpGeo<OP>::DOWN;
@@ -129,13 +154,13 @@ __global__ __launch_bounds__(256) void k_s2_eval(const T* __restrict__ x1, const
   __shared__ float sm[4][N];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, g = lane >> 4;
   const int ph = blockIdx.y, py = DOWN ? 0 : ph >> 1, px = DOWN ? 0 : ph & 1;
-  const int b = blockIdx.z;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, row tile of the clip
   const int hr = DOWN ? hd : hd / 2, wr = DOWN ? wd : wd / 2;  // the clip's GEMM row grid
   const int hs = DOWN ? 2 * hd : hd / 2, ws = DOWN ? 2 * wd : wd / 2;
   const int64_t Pc = (int64_t)hr * wr;
   const F* wm = reinterpret_cast<const F*>(wmain);
   const F* wq = reinterpret_cast<const F*>(wres);
-  const int64_t pbase = ((int64_t)blockIdx.x * 4 + wave) * 16 * R;
+  const int64_t pbase = ((int64_t)tx * 4 + wave) * 16 * R;
   int prow[R], pcol[R];
   bool pv[R];
 #pragma unroll
@@ -245,7 +270,7 @@ __global__ __launch_bounds__(256) void k_s2_eval(const T* __restrict__ x1, const
     if (g == 0) sm[wave][16 * nt + m] = s;
   }
   __syncthreads();
-  float* out = gap + (((int64_t)b * gridDim.y + ph) * gridDim.x + blockIdx.x) * N;
+  float* out = gap + (((int64_t)b * gridDim.y + ph) * tiles + tx) * N;
   for (int c = threadIdx.x; c < N; c += blockDim.x) out[c] = ((sm[0][c] + sm[1][c]) + sm[2][c]) + sm[3][c];
 }
 

@@ -17,16 +17,38 @@ namespace stda {
 constexpr int kHeadTH = 8, kHeadTW = 32;
 
 template <class T, bool SIG>
-__global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, const float* __restrict__ w,
-                                                       const float* __restrict__ bias, float* __restrict__ z,
-                                                       float* __restrict__ zs, int B, int H, int W) {
+struct k_head_fwd_tile_args {
+  const T* d;
+  const float* w;
+  const float* bias;
+  float* z;
+  float* zs;
+  int B;
+  int H;
+  int W;
+};
+template <class T, bool SIG>
+__global__ __launch_bounds__(256) void k_head_fwd_tile(SegL<k_head_fwd_tile_args<T, SIG>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_head_fwd_tile_args<T, SIG>& a_ = L.a[sb.s];
+  const T* __restrict__ const d = a_.d;
+  const float* __restrict__ const w = a_.w;
+  const float* __restrict__ const bias = a_.bias;
+  float* __restrict__ const z = a_.z;
+  float* __restrict__ const zs = a_.zs;
+  const int B = a_.B;
+  const int H = a_.H;
+  const int W = a_.W;
   constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, XN = (TH + 2) * RW;
   __shared__ float xt[S1Lds<C, XN>::SIZE];
   __shared__ float wt[9 * C];  // [tap][c]
   for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) wt[q] = w[(q % C) * 9 + q / C];
   const float b0 = bias[0];
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
     __syncthreads();
@@ -56,10 +78,33 @@ __global__ __launch_bounds__(256) void k_head_fwd_tile(const T* __restrict__ d, 
 }
 
 template <class T, bool SIG>
-__global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__ dz, const float* __restrict__ zs,
-                                                       const float* __restrict__ w, const T* __restrict__ d,
-                                                       T* __restrict__ dd, float* __restrict__ part, int B, int H,
-                                                       int W) {
+struct k_head_bwd_tile_args {
+  const float* dz;
+  const float* zs;
+  const float* w;
+  const T* d;
+  T* dd;
+  float* part;
+  int B;
+  int H;
+  int W;
+};
+template <class T, bool SIG>
+__global__ __launch_bounds__(256) void k_head_bwd_tile(SegL<k_head_bwd_tile_args<T, SIG>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_head_bwd_tile_args<T, SIG>& a_ = L.a[sb.s];
+  const float* __restrict__ const dz = a_.dz;
+  const float* __restrict__ const zs = a_.zs;
+  const float* __restrict__ const w = a_.w;
+  const T* __restrict__ const d = a_.d;
+  T* __restrict__ const dd = a_.dd;
+  float* __restrict__ const part = a_.part;
+  const int B = a_.B;
+  const int H = a_.H;
+  const int W = a_.W;
   constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, G = 4, RW = TW + 2;
   static_assert(TH * TW == STDA_BLOCK, "one pixel per thread and channel group pass");
   __shared__ float zt[(TH + 2) * RW];
@@ -75,7 +120,7 @@ __global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__
 #pragma unroll
   for (int t = 0; t < 10; ++t) zero4(acc[t]);
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
     __syncthreads();
@@ -115,7 +160,7 @@ __global__ __launch_bounds__(256) void k_head_bwd_tile(const float* __restrict__
     }
   }
   block_chan_reduce_shfl<G, 10>(acc, sm, red);
-  for (int q = threadIdx.x; q < 10 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 10 * C + q] = red[q];
+  for (int q = threadIdx.x; q < 10 * C; q += STDA_BLOCK) part[(int64_t)bx * 10 * C + q] = red[q];
 }
 
 }  // namespace stda

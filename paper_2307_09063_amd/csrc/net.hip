@@ -384,47 +384,38 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
   }
   P.ws_pwx = ws.take(sizeof(float) * pwx);
   P.ws_frag = ws.take(sizeof(float) * dense_elems);  // same element offsets as ws_dense
-  int64_t max_pix = 0, max_clips = 0;
+  // per-segment regions: full-resolution scratch by pixels, per-clip scratch by clips
+  int64_t tot_pix = 0, tot_clips = 0;
+  size_t part_cap = 0;
   for (int s = 0; s < n_segs; ++s) {
-    max_pix = std::max<int64_t>(max_pix, (int64_t)segs[s].n * segs[s].H * segs[s].W);
-    max_clips = std::max<int64_t>(max_clips, segs[s].n);
+    P.seg[s].scr = es * 16 * (size_t)tot_pix;
+    P.seg[s].clip0 = tot_clips;
+    tot_pix += (int64_t)segs[s].n * segs[s].H * segs[s].W;
+    tot_clips += segs[s].n;
+    // per-block partials: up to 9 x 64 floats (+ a count) per block of a per-pixel kernel, or
+    // 2 x 64 per (clip, tile) block of the per-clip stage-2 adjoint; regions with counts are
+    // aligned to 64 floats
+    part_cap += std::max<size_t>((size_t)kMaxGrid * (9 * 64 + 1), (size_t)segs[s].n * kMaxTiles * (2 * 64 + 1)) + 64;
   }
-  const size_t full16 = es * 16 * (size_t)max_pix;  // largest per-level activation
+  const size_t full16 = es * 16 * (size_t)tot_pix;  // largest per-level activation of all segments
   P.ws_R = ws.take(full16);
-  // per-block partials: up to 9 x 64 floats per block of a per-pixel kernel (depthwise weight
-  // gradient), or 2 x 64 per (clip, tile) block of the per-clip stage-2 adjoint
-  P.ws_part = ws.take(sizeof(float) * std::max<size_t>((size_t)kMaxGrid * 9 * 64,
-                                                       (size_t)max_clips * kMaxTiles * 2 * 64));
+  P.part_cap = part_cap;
+  P.ws_part = ws.take(sizeof(float) * part_cap);
   P.ws_sums = ws.take(sizeof(double) * 6 * 64);
-  P.ws_gap = ws.take(sizeof(float) * (size_t)max_clips * kMaxTiles * 64);
+  P.ws_gap = ws.take(sizeof(float) * (size_t)tot_clips * kMaxTiles * 64);
   P.ws_eval_stats = ws.take(sizeof(float) * stda_running_count());
   P.ws_loss = ws.take(sizeof(double) * kMaxGrid);
+  P.wpart_cap = 0;
   if (train) {
     for (int i = 0; i < kNumGradBufs; ++i) P.ws_g[i] = ws.take(full16);
-    P.ws_coef_e = ws.take(sizeof(float) * (size_t)max_clips * 64);
-    P.ws_coef = ws.take(sizeof(float) * 4 * 64);
-    P.ws_ecaw = ws.take(sizeof(float) * (size_t)max_clips * 3);
-    P.ws_wpart = ws.take(sizeof(float) * (size_t)kMaxWgradGrid * 32768);
+    P.ws_coef_e = ws.take(sizeof(float) * (size_t)tot_clips * 64);
+    P.ws_coef = ws.take(sizeof(float) * (size_t)n_segs * 4 * 64);
+    P.ws_ecaw = ws.take(sizeof(float) * (size_t)tot_clips * 3);
+    // weight-gradient partial rows of one launch: at most kMaxWgradGrid x 32768 floats a segment
+    P.wpart_cap = (size_t)n_segs * kMaxWgradGrid * 32768;
+    P.ws_wpart = ws.take(sizeof(float) * P.wpart_cap);
   }
-  // recompute: one scratch set of block internals in ws, shared by every block and segment
-  size_t rx1 = 0, rty = 0, rmask = 0, rm1 = 0;
   const bool rec = train && recompute;
-  if (rec) {
-    size_t mx1 = 0, mty = 0;
-    for (int s = 0; s < n_segs; ++s)
-      for (int k = 0; k < 4; ++k) {
-        const BlockCfg& b = kBlocks[k];
-        const size_t n = segs[s].n, H = segs[s].H, W = segs[s].W;
-        mx1 = std::max(mx1, (size_t)b.cin * n * (H >> b.lin) * (W >> b.lin));
-        mty = std::max(mty, (size_t)b.cout * n * (H >> b.lout) * (W >> b.lout));
-      }
-    rx1 = ws.take(es * mx1);
-    rm1 = ws.take(mx1 / 8);
-    const size_t rt = ws.take(es * mty);
-    rty = ws.take(es * mty);
-    rmask = ws.take(mty / 4);
-    P.rec_T = rt;
-  }
   for (int s = 0; s < n_segs; ++s) {
     SegPlan& S = P.seg[s];
     const int64_t n = segs[s].n, H = segs[s].H, W = segs[s].W;
@@ -437,6 +428,21 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     S.stats = (train ? sv : ws).take(sizeof(float) * stda_running_count());
     S.s0 = acts.take(es * 16 * n * HW);
     S.zs = sigmoid_save ? sv.take(sizeof(float) * n * HW) : 0;
+    // recompute: one scratch set of block internals in ws per segment, shared by its blocks
+    size_t rx1 = 0, rty = 0, rt = 0, rmask = 0, rm1 = 0;
+    if (rec) {
+      size_t mx1 = 0, mty = 0;
+      for (int k = 0; k < 4; ++k) {
+        const BlockCfg& b = kBlocks[k];
+        mx1 = std::max(mx1, (size_t)b.cin * n * (H >> b.lin) * (W >> b.lin));
+        mty = std::max(mty, (size_t)b.cout * n * (H >> b.lout) * (W >> b.lout));
+      }
+      rx1 = ws.take(es * mx1);
+      rm1 = ws.take(mx1 / 8);
+      rt = ws.take(es * mty);
+      rty = ws.take(es * mty);
+      rmask = ws.take(mty / 4);
+    }
     for (int k = 0; k < 4; ++k) {
       const BlockCfg& b = kBlocks[k];
       const int64_t hin = H >> b.lin, win = W >> b.lin, hout = H >> b.lout, wout = W >> b.lout;
@@ -444,7 +450,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
       A.inner_in_ws = rec;
       if (rec) {
         A.X1 = rx1;
-        A.T = P.rec_T;
+        A.T = rt;
         A.Y = rty;
         A.mask = rmask;
         A.m1 = rm1;
@@ -469,10 +475,56 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
 // ===================================================================== forward
 namespace {
 
+// Consecutive per-segment regions of a partial-sums buffer (one region per segment of a launch).
+// Regions without per-row counts follow each other with no gap, so a column sum over all rows
+// of all segments is one reduction; regions with counts start on 256-byte boundaries.
+struct Parts {
+  float* base;
+  size_t cap, used = 0;  // floats
+  int n = 0;
+  bool over = false;     // a region did not fit: nothing may be launched with these regions
+  float* p[kMaxSegs] = {};
+  int rows[kMaxSegs] = {};
+  Parts(float* b, size_t c) : base(b), cap(c) {}
+  // the next segment's region: r rows of `row` floats, followed (counts) by one count per row
+  float* take(int r, int64_t row, bool counts) {
+    if (counts) used = (used + 63) & ~(size_t)63;
+    const size_t need = (size_t)r * (size_t)row + (counts ? (size_t)r : 0);
+    if (n >= kMaxSegs || used + need > cap) {
+      over = true;
+      return base;
+    }
+    p[n] = base + used;
+    rows[n] = r;
+    used += need;
+    return p[n++];
+  }
+  int total_rows() const {
+    int t = 0;
+    for (int i = 0; i < n; ++i) t += rows[i];
+    return t;
+  }
+};
+
+// The arguments of one launch over all segments (see SegL): segment s's workgroups start at the
+// first multiple of 8 after the previous segment's.
+template <class A>
+struct Batch {
+  SegL<A> L{};
+  int end = 0;
+  void add(int grid, const A& a) {
+    const int s = L.n++;
+    L.base[s] = (end + 7) & ~7;
+    L.grid[s] = grid;
+    L.a[s] = a;
+    end = L.base[s] + grid;
+  }
+  unsigned blocks() const { return (unsigned)end; }
+};
+
 template <class T>
 struct Ctx {
   const Plan* P;
-  const SegPlan* S;
   char* sv;  // activations base (saved in TRAIN, ws in EVAL)
   char* ws;
   const float* w;   // working weights (rounded in BF16 mode)
@@ -480,12 +532,47 @@ struct Ctx {
   hipStream_t st;
   bool train;
   bool rec_pass = false;  // re-running a block's forward inside the backward (recompute mode)
+  int ns() const { return P->n_segs; }
+  const SegPlan& S(int s) const { return P->seg[s]; }
   template <class U> U* act(size_t off) const { return reinterpret_cast<U*>(sv + off); }
   template <class U> U* inner(const BlockActs& A, size_t off) const {
     return reinterpret_cast<U*>((A.inner_in_ws ? ws : sv) + off);
   }
   template <class U> U* scr(size_t off) const { return reinterpret_cast<U*>(ws + off); }
-  float* stats(int64_t bn_off) const { return reinterpret_cast<float*>((train ? sv : ws) + S->stats) + bn_off; }
+  float* stats(int s, int64_t bn_off) const {
+    return reinterpret_cast<float*>((train ? sv : ws) + P->seg[s].stats) + bn_off;
+  }
+  // segment s's regions of the per-call scratch
+  T* R(int s) const { return scr<T>(P->ws_R + P->seg[s].scr); }
+  T* grad(int s, int i) const { return scr<T>(P->ws_g[i] + P->seg[s].scr); }
+  float* gap(int s) const { return scr<float>(P->ws_gap) + P->seg[s].clip0 * kMaxTiles * 64; }
+  float* coef(int s) const { return scr<float>(P->ws_coef) + (size_t)s * 4 * 64; }
+  float* coef_e(int s) const { return scr<float>(P->ws_coef_e) + P->seg[s].clip0 * 64; }
+  float* ecaw(int s) const { return scr<float>(P->ws_ecaw) + P->seg[s].clip0 * 3; }
+  Parts part() const { return Parts(scr<float>(P->ws_part), P->part_cap); }
+  Parts wpart() const { return Parts(scr<float>(P->ws_wpart), P->wpart_cap); }
+  int clips() const {
+    int t = 0;
+    for (int s = 0; s < P->n_segs; ++s) t += P->seg[s].n;
+    return t;
+  }
+};
+
+// One segment's operands of a dense stage-2 launch.
+template <class T>
+struct DenseOps {
+  int n = 0;
+  const T* src[kMaxSegs];
+  T* dst[kMaxSegs];
+  int clips[kMaxSegs], hd[kMaxSegs], wd[kMaxSegs];
+  void add(const T* s, T* d, int b, int h, int w) {
+    src[n] = s;
+    dst[n] = d;
+    clips[n] = b;
+    hd[n] = h;
+    wd[n] = w;
+    ++n;
+  }
 };
 
 int tiles_for(int64_t hw, int G) {
@@ -503,46 +590,58 @@ constexpr int kTuneKinds = 4;
 constexpr double kTuneMargin = 0.03;
 int g_s2_variant[2][kTuneKinds][4] = {};
 
+// Dense stride-2 layer on LDS tiles over every segment; with STATS, each segment's BN partials
+// go to a region of *pm.
 template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS, int WV = 4>
-int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
-                  int hd, int wd, int* nblk) {
+int launch_s2_cfg(const Ctx<T>& c, const std::string& tag, const DenseOps<T>& D, const T* frag, Parts* pm) {
   typedef S2Cfg<T, OP, K, N, NB, TH, TW, WV> C;
-  const int64_t ntiles = (int64_t)n * ((hd + TH - 1) / TH) * ((wd + TW - 1) / TW);
   const int64_t per_cu = std::max<int64_t>(1, (160 * 1024) / C::LDS_BYTES);
-  int64_t gx = capped(std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid)));
-  if (gx >= 64) gx &= ~(int64_t)7;  // whole XCD groups: tiles are handed out XCD by XCD
-  gx = std::max<int64_t>(gx, 1);
-  KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS, WV><<<dim3((unsigned)gx, N / NB), C::BLK, 0, c.st>>>(
-                    src, frag, dst, part, n, hd, wd));
-  if (nblk) *nblk = (int)gx;
+  Batch<k_s2_tile_args<T, OP, K, N, NB, TH, TW, STATS, WV>> b;
+  for (int s = 0; s < D.n; ++s) {
+    const int64_t ntiles = (int64_t)D.clips[s] * ((D.hd[s] + TH - 1) / TH) * ((D.wd[s] + TW - 1) / TW);
+    int64_t gx = capped(std::min<int64_t>(ntiles, std::min<int64_t>(256 * per_cu * 2, kMaxGrid)));
+    if (gx >= 64) gx &= ~(int64_t)7;  // whole XCD groups: tiles are handed out XCD by XCD
+    gx = std::max<int64_t>(gx, 1);
+    float* part = nullptr;
+    if constexpr (STATS) part = pm->take((int)gx, 2 * N, true);
+    b.add((int)gx, {D.src[s], frag, D.dst[s], part, D.clips[s], D.hd[s], D.wd[s]});
+  }
+  if (STATS && pm->over) return STDA_E_WORKSPACE;
+  KLAUNCH(tag, k_s2_tile<T, OP, K, N, NB, TH, TW, STATS, WV><<<dim3(b.blocks(), N / NB), C::BLK, 0, c.st>>>(b.L));
   return STDA_OK;
 }
 
 template <class T, int OP, int K, int N, bool STATS>
-int launch_gather(const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst, float* part, int n,
-                  int hd, int wd, int* nblk) {
+int launch_gather(const Ctx<T>& c, const std::string& tag, const DenseOps<T>& D, const T* frag, Parts* pm) {
   constexpr int R = 4;
   constexpr bool down = OpGeo<OP>::DOWN;
-  const int64_t P = (int64_t)n * (down ? (int64_t)hd * wd : (int64_t)(hd / 2) * (wd / 2));
   const int phases = down ? 1 : 4;
-  const int64_t tiles = (P + 64 * R - 1) / (64 * R);
-  const int gx = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kMaxGrid / phases)));
-  KLAUNCH(tag, k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(gx, phases), 256, 0, c.st>>>(src, frag, dst, part, n, hd, wd));
-  if (nblk) *nblk = gx * phases;
+  Batch<k_dense_mfma_args<T, OP, K, N, R, STATS>> b;
+  for (int s = 0; s < D.n; ++s) {
+    const int64_t hd = D.hd[s], wd = D.wd[s];
+    const int64_t P = (int64_t)D.clips[s] * (down ? hd * wd : (hd / 2) * (wd / 2));
+    const int64_t tiles = (P + 64 * R - 1) / (64 * R);
+    const int gx = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kMaxGrid / phases)));
+    float* part = nullptr;
+    if constexpr (STATS) part = pm->take(gx * phases, 2 * N, true);
+    b.add(gx, {D.src[s], frag, D.dst[s], part, D.clips[s], D.hd[s], D.wd[s]});
+  }
+  if (STATS && pm->over) return STDA_E_WORKSPACE;
+  KLAUNCH(tag, k_dense_mfma<T, OP, K, N, R, STATS><<<dim3(b.blocks(), phases), 256, 0, c.st>>>(b.L));
   return STDA_OK;
 }
 
 // The candidate tilings (NB output channels per workgroup, TH x TW output pixels) of each
 // operator; all fit the 160 KB of LDS of a gfx950 workgroup (checked at compile time).
 template <class T, int OP, int K, int N, bool STATS>
-int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* src, const T* frag, T* dst,
-                      float* part, int n, int hd, int wd, int* nblk) {
+int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const DenseOps<T>& D, const T* frag,
+                      Parts* pm) {
   constexpr bool BF = sizeof(T) == 2;
-#define S2V(NB_, TH_, TW_) launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk)
+#define S2V(NB_, TH_, TW_) launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS>(c, tag, D, frag, pm)
   // 8 waves per workgroup: tilings whose LDS leaves room for one workgroup per CU
 #define S2W(NB_, TH_, TW_) \
-  launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS, 8>(c, tag, src, frag, dst, part, n, hd, wd, nblk)
-  if (v == 3) return launch_gather<T, OP, K, N, STATS>(c, tag, src, frag, dst, part, n, hd, wd, nblk);
+  launch_s2_cfg<T, OP, K, N, NB_, TH_, TW_, STATS, 8>(c, tag, D, frag, pm)
+  if (v == 3) return launch_gather<T, OP, K, N, STATS>(c, tag, D, frag, pm);
   if constexpr (OP == OP_ENC_FWD && K == 16) {
     if constexpr (BF) return v == 1 ? S2V(32, 8, 16) : v == 2 ? S2W(32, 16, 16) : S2V(32, 8, 32);
     else return v == 1 ? S2V(32, 8, 8) : v == 2 ? S2W(32, 8, 16) : S2V(32, 8, 16);
@@ -572,14 +671,14 @@ int launch_s2_variant(int v, const Ctx<T>& c, const std::string& tag, const T* s
 #undef S2W
 }
 
-// Dense stride-2 layer of block `blk` on the matrix cores; *nblk = rows of BN partials written.
+// Dense stride-2 layer of block `blk` on the matrix cores over every segment, with the tiling the
+// tuner chose for it; with STATS the BN partials go to *pm.
 template <class T, int OP, int K, int N, bool STATS>
-int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const T* src, int64_t frag_off, T* dst,
-                 float* part, int n, int hd, int wd, int* nblk) {
+int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const DenseOps<T>& D, int64_t frag_off, Parts* pm) {
   const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
   const bool dgrad = OP == OP_ENC_DGRAD || OP == OP_DEC_DGRAD;
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][dgrad ? 1 : 0][blk];
-  return launch_s2_variant<T, OP, K, N, STATS>(v, c, tag, src, frag, dst, part, n, hd, wd, nblk);
+  return launch_s2_variant<T, OP, K, N, STATS>(v, c, tag, D, frag, pm);
 }
 
 // Blocks of the tiled stage-1 kernels: one per tile, at most kMaxGrid (they loop over tiles).
@@ -601,141 +700,218 @@ int head_grid(int n, int H, int W) {
   return (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
 }
 
-// FP64 merge of the per-block BN statistics (count, mean, m2) followed by the finalize.
+// FP64 merge of the per-block BN statistics (count, mean, m2) followed by the finalize, for every
+// segment of the launch whose partials are in pm; NB layers of C channels at the given offsets
+// of the statistics layout.  `running` (null: no update) gets one update per segment.
 template <class T>
-int bn_finalize(const Ctx<T>& c, int nblk, int NB, int C, float* const* stats_out,
-                float* const* running) {
-  float* part = c.template scr<float>(c.P->ws_part);
-  BnOut o{};
-  for (int i = 0; i < NB; ++i) {
-    o.stats[i] = stats_out[i];
-    o.running[i] = running ? running[i] : nullptr;
+int bn_finalize(const Ctx<T>& c, const Parts& pm, int NB, int C, const int64_t* bn_off, float* running) {
+  BnSegs sg{};
+  sg.n = pm.n;
+  for (int s = 0; s < pm.n; ++s) {
+    sg.part[s] = pm.p[s];
+    sg.rows[s] = pm.rows[s];
+    sg.stats[s] = c.stats(s, 0);
   }
-  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(part, nblk, NB, C, o, running ? 1 : 0));
+  BnLayers L{};
+  for (int i = 0; i < NB; ++i) L.off[i] = bn_off[i];
+  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(sg, NB, C, L, running));
   return STDA_OK;
 }
 
-template <class T, int CIN, int COUT, bool DEC>
-int fwd_block(const Ctx<T>& c, int k, float* running) {
+// One segment's operands of mobile block k.
+template <class T>
+struct BlockView {
+  int n, hin, win, hout, wout;
+  const T* X;  // block input
+  T *X1, *Tm, *Y, *Xn;
+  uint8_t *m1, *mask;  // ReLU decisions (TRAIN), else null
+  float *a, *g;        // ECA scale and average (saved)
+  const T* skip;       // decoder blocks: the encoder output added to the block output
+};
+template <class T>
+BlockView<T> block_view(const Ctx<T>& c, int s, int k) {
   const BlockCfg& bc = kBlocks[k];
-  const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
-  const SegPlan& S = *c.S;
+  const SegPlan& S = c.S(s);
   const BlockActs& A = S.blk[k];
-  const int n = S.n;
-  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
-  const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
-  const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
-  T* X1 = c.template inner<T>(A, A.X1);
-  T* Tm = c.template inner<T>(A, A.T);
-  T* Y = c.template inner<T>(A, A.Y);
-  T* R = c.template scr<T>(c.P->ws_R);
-  float* part = c.template scr<float>(c.P->ws_part);
+  BlockView<T> v;
+  v.n = S.n;
+  v.hin = S.H >> bc.lin;
+  v.win = S.W >> bc.lin;
+  v.hout = S.H >> bc.lout;
+  v.wout = S.W >> bc.lout;
+  v.X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
+  v.X1 = c.template inner<T>(A, A.X1);
+  v.Tm = c.template inner<T>(A, A.T);
+  v.Y = c.template inner<T>(A, A.Y);
+  v.Xn = c.template act<T>(A.Xn);
+  v.m1 = c.train ? c.template inner<uint8_t>(A, A.m1) : nullptr;
+  v.mask = c.train ? c.template inner<uint8_t>(A, A.mask) : nullptr;
+  v.a = c.template act<float>(A.a);
+  v.g = c.template act<float>(A.g);
+  v.skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
+  return v;
+}
+
+// Stage-1 parameters of block k with segment s's statistics.
+template <class T>
+S1Params s1_params(const Ctx<T>& c, int s, int k) {
+  const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
   S1Params sp{};
   sp.wpw = (c.P->arch & STDA_ARCH_PW_DW) ? c.template scr<float>(c.P->ws_pwx) + c.P->pwx_off[k] : c.w + bo.pw_w;
   sp.wdw = c.w + bo.dw_w;
-  sp.stats[0] = c.stats(bo.bn_pw);
-  sp.stats[1] = c.stats(bo.bn_dw);
-  sp.stats[2] = c.stats(bo.bn_id);
+  sp.stats[0] = c.stats(s, bo.bn_pw);
+  sp.stats[1] = c.stats(s, bo.bn_dw);
+  sp.stats[2] = c.stats(s, bo.bn_id);
   sp.gamma[0] = c.w + bo.pw_g;
   sp.gamma[1] = c.w + bo.dw_g;
   sp.gamma[2] = c.w + bo.id_g;
   sp.beta[0] = c.w + bo.pw_b;
   sp.beta[1] = c.w + bo.dw_b;
   sp.beta[2] = c.w + bo.id_b;
+  return sp;
+}
+
+// ECA scale of each clip and the next block input Xn = a * Y (+ skip) over every segment; the
+// GAP partials of segment s are gap(s, clip) = gaps[s] + clip * gap_tiles[s] * COUT.
+template <class T, int COUT, bool SKIP>
+int launch_eca_next(const Ctx<T>& c, int k, const BlockView<T>* v, float* const* gaps, const int* gap_tiles,
+                    const float* weca) {
+  Batch<k_eca_next_args<T, COUT, SKIP>> b;
+  for (int s = 0; s < c.ns(); ++s) {
+    const int hw = v[s].hout * v[s].wout, tiles = tiles_for(hw, COUT / 4);
+    b.add(tiles * v[s].n, {v[s].Y, v[s].skip, v[s].Xn, gaps[s], weca, v[s].g, v[s].a, hw, gap_tiles[s], tiles});
+  }
+  KLAUNCH(tagk("eca_next", k), k_eca_next<T, COUT, SKIP><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  return STDA_OK;
+}
+
+template <class T, int CIN, int COUT, bool DEC>
+int fwd_block(const Ctx<T>& c, int k, float* running) {
+  const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
+  const int ns = c.ns();
+  BlockView<T> v[kMaxSegs];
+  S1Params sp[kMaxSegs];
+  for (int s = 0; s < ns; ++s) {
+    v[s] = block_view(c, s, k);
+    sp[s] = s1_params(c, s, k);
+  }
   // stage 1
-  const int g1 = s1_grid<CIN>(n, hin, win);
   const bool stats_pass = c.train && !c.rec_pass;
   if (stats_pass) {
-    KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<g1, 256, 0, c.st>>>(X, nullptr, nullptr, part, sp, n, hin, win));
-    float* so[3] = {c.stats(bo.bn_pw), c.stats(bo.bn_dw), c.stats(bo.bn_id)};
-    float* ro[3] = {running + bo.bn_pw, running + bo.bn_dw, running + bo.bn_id};
-    if (int r = bn_finalize(c, g1, 3, CIN, so, ro)) return r;
+    Parts pm = c.part();
+    Batch<k_s1_tile_args<T, CIN, DEC, 0>> b;
+    for (int s = 0; s < ns; ++s) {
+      const int g = s1_grid<CIN>(v[s].n, v[s].hin, v[s].win);
+      b.add(g, {v[s].X, nullptr, nullptr, pm.take(g, 6 * CIN, true), sp[s], v[s].n, v[s].hin, v[s].win});
+    }
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH(tagk("s1_stats", k), k_s1_tile<T, CIN, DEC, 0><<<b.blocks(), 256, 0, c.st>>>(b.L));
+    const int64_t offs[3] = {bo.bn_pw, bo.bn_dw, bo.bn_id};
+    if (int r = bn_finalize(c, pm, 3, CIN, offs, running)) return r;
   }
-  uint8_t* m1 = c.train ? c.template inner<uint8_t>(A, A.m1) : nullptr;
-  KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<g1, 256, 0, c.st>>>(X, X1, m1, nullptr, sp, n, hin, win));
+  {
+    Batch<k_s1_tile_args<T, CIN, DEC, 1>> b;
+    for (int s = 0; s < ns; ++s)
+      b.add(s1_grid<CIN>(v[s].n, v[s].hin, v[s].win),
+            {v[s].X, v[s].X1, v[s].m1, nullptr, sp[s], v[s].n, v[s].hin, v[s].win});
+    KLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  }
   // stage 2: main (with statistics) and residual
   constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD;
+  DenseOps<T> dm, dr;
+  for (int s = 0; s < ns; ++s) {
+    dm.add(v[s].X1, v[s].Tm, v[s].n, v[s].hout, v[s].wout);
+    dr.add(v[s].X, c.R(s), v[s].n, v[s].hout, v[s].wout);
+  }
   if (stats_pass) {
-    int nb = 0;
-    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, part, n, hout, wout, &nb))
+    Parts pm = c.part();
+    if (int r = launch_dense<T, OPF, CIN, COUT, true>(c, k, tagk("dense_fwd_main", k), dm, c.P->dense_f[k][0], &pm))
       return r;
-    float* so[1] = {c.stats(bo.bn_main)};
-    float* ro[1] = {running + bo.bn_main};
-    if (int r = bn_finalize(c, nb, 1, COUT, so, ro)) return r;
+    const int64_t offs[1] = {bo.bn_main};
+    if (int r = bn_finalize(c, pm, 1, COUT, offs, running)) return r;
   } else {
-    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), X1, c.P->dense_f[k][0], Tm, nullptr, n, hout, wout,
-                                                       nullptr))
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), dm, c.P->dense_f[k][0], nullptr))
       return r;
   }
   bool res_done = false;
   if constexpr (DEC) {
     if (c.P->arch & STDA_ARCH_RES3) {
       // DeConv3x3-s2-p1 (output padding 1): the input-gradient operator of a Conv3x3-s2-p1
-      if (int r = launch_dense<T, OP_ENC_DGRAD, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+      if (int r = launch_dense<T, OP_ENC_DGRAD, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), dr, c.P->dense_f[k][1], nullptr))
         return r;
       res_done = true;
     }
   }
   if (!res_done)
-    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), X, c.P->dense_f[k][1], R, nullptr, n, hout, wout, nullptr))
+    if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_res", k), dr, c.P->dense_f[k][1], nullptr))
       return r;
   // Y = ReLU(BN(T)) + R, GAP partials; then ECA and the skip
-  const int hw = hout * wout;
-  const int tiles = tiles_for(hw, COUT / 4);
-  float* gap = c.template scr<float>(c.P->ws_gap);
-  uint8_t* mask = c.train ? c.template inner<uint8_t>(A, A.mask) : nullptr;
-  KLAUNCH(tagk("s2_apply", k), k_s2_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Tm, R, Y, mask, gap, c.stats(bo.bn_main), c.w + bo.main_g,
-                                                        c.w + bo.main_b, hw));
-  if (c.rec_pass) return STDA_OK;  // the block output is a saved checkpoint
-  T* Xn = c.template act<T>(A.Xn);
-  const T* skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
-{
-    ProfScope ps_(tagk("eca_next", k), c.st);
-    if (skip)
-      k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, c.st>>>(Y, skip, Xn, gap, c.w + bo.eca_w,
-                                                                  c.template act<float>(A.g), c.template act<float>(A.a),
-                                                                  hw, tiles);
-    else
-      k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, c.st>>>(Y, nullptr, Xn, gap, c.w + bo.eca_w,
-                                                                   c.template act<float>(A.g),
-                                                                   c.template act<float>(A.a), hw, tiles);
+  float* gaps[kMaxSegs];
+  int gtiles[kMaxSegs];
+  {
+    Batch<k_s2_apply_args<T, COUT>> b;
+    for (int s = 0; s < ns; ++s) {
+      const int hw = v[s].hout * v[s].wout, tiles = tiles_for(hw, COUT / 4);
+      gaps[s] = c.gap(s);
+      gtiles[s] = tiles;
+      b.add(tiles * v[s].n, {v[s].Tm, c.R(s), v[s].Y, v[s].mask, gaps[s], c.stats(s, bo.bn_main), c.w + bo.main_g,
+                             c.w + bo.main_b, hw, tiles});
+    }
+    KLAUNCH(tagk("s2_apply", k), k_s2_apply<T, COUT><<<b.blocks(), 256, 0, c.st>>>(b.L));
   }
-  LAUNCH_CHECK();
+  if (c.rec_pass) return STDA_OK;  // the block output is a saved checkpoint
+  if (k >= 2) return launch_eca_next<T, COUT, true>(c, k, v, gaps, gtiles, c.w + bo.eca_w);
+  return launch_eca_next<T, COUT, false>(c, k, v, gaps, gtiles, c.w + bo.eca_w);
+}
+
+template <class T, bool SIG>
+int launch_head_fwd(const Ctx<T>& c, const float* wh, const float* bh, float* z) {
+  Batch<k_head_fwd_tile_args<T, SIG>> b;
+  for (int s = 0; s < c.ns(); ++s) {
+    const SegPlan& S = c.S(s);
+    float* zs = SIG && S.zs ? c.template act<float>(S.zs) : nullptr;
+    b.add(head_grid(S.n, S.H, S.W), {c.template act<T>(S.blk[3].Xn), wh, bh, z + S.z_off, zs, S.n, S.H, S.W});
+  }
+  KLAUNCH("head_fwd", k_head_fwd_tile<T, SIG><<<b.blocks(), 256, 0, c.st>>>(b.L));
   return STDA_OK;
 }
 
+// The network forward over every segment: one launch per kernel kind and layer.
 template <class T>
-int forward_seg(const Ctx<T>& c, const float* x, float* running, float* z) {
-  const SegPlan& S = *c.S;
+int forward_net(const Ctx<T>& c, const float* x, float* running, float* z) {
   const NetOffsets& no = net_offsets(c.P->arch);
-  const int64_t P = (int64_t)S.n * S.H * S.W;
-  const float* xs = x + S.x_off;
-  float* part = c.template scr<float>(c.P->ws_part);
-  T* s0 = c.template act<T>(S.s0);
-  const int gs = stem_grid(S.n, S.H, S.W);
-  StemArgs sa{xs, c.w + no.stem_w, c.stats(0), c.w + no.stem_g, c.w + no.stem_b, nullptr, part};
+  const int ns = c.ns();
+  auto stem_args = [&](int s, float* part) {
+    const SegPlan& S = c.S(s);
+    return StemArgs{x + S.x_off, c.w + no.stem_w, c.stats(s, 0), c.w + no.stem_g, c.w + no.stem_b, nullptr, part};
+  };
   if (c.train) {
-    KLAUNCH("stem_stats", k_stem_tile<T, 0><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, nullptr, S.n, S.H, S.W));
-    float* so[1] = {c.stats(0)};
-    float* ro[1] = {running};
-    if (int r = bn_finalize(c, gs, 1, 16, so, ro)) return r;
+    Parts pm = c.part();
+    Batch<k_stem_tile_args<T, 0>> b;
+    for (int s = 0; s < ns; ++s) {
+      const SegPlan& S = c.S(s);
+      const int g = stem_grid(S.n, S.H, S.W);
+      b.add(g, {stem_args(s, pm.take(g, 32, true)), nullptr, nullptr, nullptr, S.n, S.H, S.W});
+    }
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH("stem_stats", k_stem_tile<T, 0><<<b.blocks(), 256, 0, c.st>>>(b.L));
+    const int64_t offs[1] = {0};
+    if (int r = bn_finalize(c, pm, 1, 16, offs, running)) return r;
   }
-  KLAUNCH("stem_apply", k_stem_tile<T, 1><<<gs, 256, 0, c.st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
+  {
+    Batch<k_stem_tile_args<T, 1>> b;
+    for (int s = 0; s < ns; ++s) {
+      const SegPlan& S = c.S(s);
+      b.add(stem_grid(S.n, S.H, S.W), {stem_args(s, nullptr), nullptr, nullptr, c.template act<T>(S.s0), S.n, S.H, S.W});
+    }
+    KLAUNCH("stem_apply", k_stem_tile<T, 1><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  }
   if (int r = fwd_block<T, 16, 32, false>(c, 0, running)) return r;
   if (int r = fwd_block<T, 32, 64, false>(c, 1, running)) return r;
   if (int r = fwd_block<T, 64, 32, true>(c, 2, running)) return r;
   if (int r = fwd_block<T, 32, 16, true>(c, 3, running)) return r;
-  const int gz = head_grid(S.n, S.H, S.W);
-  if (c.P->arch & STDA_ARCH_SIGMOID) {
-    float* zs = S.zs ? c.template act<float>(S.zs) : nullptr;
-    KLAUNCH("head_fwd", k_head_fwd_tile<T, true><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
-                                                                     c.w + no.head_b, z + S.z_off, zs, S.n, S.H, S.W));
-  } else {
-    KLAUNCH("head_fwd", k_head_fwd_tile<T, false><<<gz, 256, 0, c.st>>>(c.template act<T>(S.blk[3].Xn), c.w + no.head_w,
-                                                                      c.w + no.head_b, z + S.z_off, nullptr, S.n, S.H,
-                                                                      S.W));
-  }
-  return STDA_OK;
+  if (c.P->arch & STDA_ARCH_SIGMOID) return launch_head_fwd<T, true>(c, c.w + no.head_w, c.w + no.head_b, z);
+  return launch_head_fwd<T, false>(c, c.w + no.head_w, c.w + no.head_b, z);
 }
 
 int validate_segs(const stda_segment* segs, int n_segs) {
@@ -839,31 +1015,30 @@ int forward_all(const Plan& P, const float* x, const float* w, float* running, f
   const float* wk = nullptr;
   if (int r = prepare_weights(P, w, ws, st, &wk)) return r;
   const bool train = P.mode == STDA_TRAIN;
-  for (int s = 0; s < P.n_segs; ++s) {
-    Ctx<T> c{&P, &P.seg[s], train ? saved : ws, ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, train};
-    if (!train) {
-      BnTable tab{};
-      int off = 0;
-      tab.off[tab.n] = off;
-      tab.C[tab.n++] = 16;
-      off += 32;
-      for (int k = 0; k < 4; ++k) {
-        const int cs[4] = {kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cout};
-        for (int q = 0; q < 4; ++q) {
-          tab.off[tab.n] = off;
-          tab.C[tab.n++] = cs[q];
-          off += 2 * cs[q];
-        }
+  Ctx<T> c{&P, train ? saved : ws, ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, train};
+  if (!train) {
+    BnTable tab{};
+    int off = 0;
+    tab.off[tab.n] = off;
+    tab.C[tab.n++] = 16;
+    off += 32;
+    for (int k = 0; k < 4; ++k) {
+      const int cs[4] = {kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cin, kBlocks[k].cout};
+      for (int q = 0; q < 4; ++q) {
+        tab.off[tab.n] = off;
+        tab.C[tab.n++] = cs[q];
+        off += 2 * cs[q];
       }
-      {
-        ProfScope ps_("eval_stats", st);
-        k_eval_stats<<<1, 256, 0, st>>>(running, c.stats(0), tab);
-      }
-      LAUNCH_CHECK();
     }
-    if (int r = forward_seg<T>(c, x, running, z)) return r;
+    tab.nseg = P.n_segs;
+    for (int s = 0; s < P.n_segs; ++s) tab.stats[s] = c.stats(s, 0);
+    {
+      ProfScope ps_("eval_stats", st);
+      k_eval_stats<<<1, 256, 0, st>>>(running, tab);
+    }
+    LAUNCH_CHECK();
   }
-  return STDA_OK;
+  return forward_net<T>(c, x, running, z);
 }
 
 // ------------------------------------------------------------------ folded EVAL inference
@@ -891,18 +1066,22 @@ FoldLayout fold_layout(int dtype) {
   } while (0);                        \
   LAUNCH_CHECK()
 
+// ECA partial sums of block k in the folded path: per (clip, phase, row tile) and channel.
+int64_t folded_gap_floats(const SegPlan& S, int k) {
+  const BlockCfg& b = kBlocks[k];
+  const int64_t ho = S.H >> b.lout, wo = S.W >> b.lout;
+  const int64_t rows = b.dec ? (ho / 2) * (wo / 2) : ho * wo;  // one clip's phase grid
+  return (int64_t)S.n * (b.dec ? 4 : 1) * ((rows + 63) / 64) * b.cout;
+}
+
 template <class T, int CIN, int COUT, bool DEC>
-int folded_block(const Plan& P, const SegPlan& S, int k, const char* fold, const float* wk, const float* ids, char* ws,
-                 hipStream_t st) {
-  const BlockCfg& bc = kBlocks[k];
+int folded_block(const Plan& P, int k, const char* fold, const float* wk, const float* ids, char* ws, hipStream_t st) {
   const BlockOffsets& bo = net_offsets(P.arch).blk[k];
-  const BlockActs& A = S.blk[k];
-  const int n = S.n;
-  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
-  const T* X = reinterpret_cast<const T*>(ws + (k == 0 ? S.s0 : S.blk[k - 1].Xn));
-  T* X1 = reinterpret_cast<T*>(ws + A.X1);
-  T* Y = reinterpret_cast<T*>(ws + A.Y);
-  T* Xn = reinterpret_cast<T*>(ws + A.Xn);
+  // the whole buffer is ws (EVAL), so the context's views serve here
+  const Ctx<T> c{&P, ws, ws, wk, nullptr, st, false};
+  const int ns = c.ns();
+  BlockView<T> v[kMaxSegs];
+  for (int s = 0; s < ns; ++s) v[s] = block_view(c, s, k);
   S1Params sp{};
   sp.wpw = wk + bo.pw_w;
   sp.wdw = wk + bo.dw_w;
@@ -913,25 +1092,33 @@ int folded_block(const Plan& P, const SegPlan& S, int k, const char* fold, const
   sp.beta[0] = wk + bo.pw_b;
   sp.beta[1] = wk + bo.dw_b;
   sp.beta[2] = wk + bo.id_b;
-  FLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<s1_grid<CIN>(n, hin, win), 256, 0, st>>>(X, X1, nullptr, nullptr, sp, n, hin, win));
-  constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD, PH = DEC ? 4 : 1, R = 1;
-  const int64_t rows = DEC ? (int64_t)(hout / 2) * (wout / 2) : (int64_t)hout * wout;  // one clip's phase grid
-  const int tx = (int)((rows + 64 * R - 1) / (64 * R));
-  const T* frag = reinterpret_cast<const T*>(fold + P.ws_frag);
-  float* gap = reinterpret_cast<float*>(ws + P.ws_R);  // the residual buffer is not needed here
-  FLAUNCH(tagk("s2_eval", k), k_s2_eval<T, OPF, CIN, COUT, R><<<dim3(tx, PH, n), 256, 0, st>>>(
-                                  X1, X, frag + P.dense_f[k][0], frag + P.dense_f[k][1], wk + bo.main_b, Y, gap, hout, wout));
-  const int hw = hout * wout;
-  const int tiles = tiles_for(hw, COUT / 4);
-  const T* skip = k == 2 ? reinterpret_cast<const T*>(ws + S.blk[0].Xn) : (k == 3 ? reinterpret_cast<const T*>(ws + S.s0) : nullptr);
-  float* g = reinterpret_cast<float*>(ws + A.g);
-  float* a = reinterpret_cast<float*>(ws + A.a);
-  if (skip) {
-    FLAUNCH(tagk("eca_next", k), k_eca_next<T, COUT, true><<<dim3(tiles, n), 256, 0, st>>>(Y, skip, Xn, gap, wk + bo.eca_w, g, a, hw, tx * PH));
-  } else {
-    FLAUNCH(tagk("eca_next", k), k_eca_next<T, COUT, false><<<dim3(tiles, n), 256, 0, st>>>(Y, nullptr, Xn, gap, wk + bo.eca_w, g, a, hw, tx * PH));
+  {
+    Batch<k_s1_tile_args<T, CIN, DEC, 1>> b;
+    for (int s = 0; s < ns; ++s)
+      b.add(s1_grid<CIN>(v[s].n, v[s].hin, v[s].win), {v[s].X, v[s].X1, nullptr, nullptr, sp, v[s].n, v[s].hin, v[s].win});
+    FLAUNCH(tagk("s1_apply", k), k_s1_tile<T, CIN, DEC, 1><<<b.blocks(), 256, 0, st>>>(b.L));
   }
-  return STDA_OK;
+  constexpr int OPF = DEC ? OP_DEC_FWD : OP_ENC_FWD, PH = DEC ? 4 : 1, R = 1;
+  const T* frag = reinterpret_cast<const T*>(fold + P.ws_frag);
+  // the residual buffer is not needed here: it holds the ECA partial sums, segment after segment
+  float* gap = reinterpret_cast<float*>(ws + P.ws_R);
+  float* gaps[kMaxSegs];
+  int gtiles[kMaxSegs];
+  {
+    Batch<k_s2_eval_args<T, OPF, CIN, COUT, R>> b;
+    for (int s = 0; s < ns; ++s) {
+      const int64_t rows = DEC ? (int64_t)(v[s].hout / 2) * (v[s].wout / 2) : (int64_t)v[s].hout * v[s].wout;
+      const int tx = (int)((rows + 64 * R - 1) / (64 * R));
+      gaps[s] = gap;
+      gtiles[s] = tx * PH;
+      b.add(tx * v[s].n, {v[s].X1, v[s].X, frag + P.dense_f[k][0], frag + P.dense_f[k][1], wk + bo.main_b, v[s].Y,
+                          gap, v[s].hout, v[s].wout, tx});
+      gap += folded_gap_floats(P.seg[s], k);
+    }
+    FLAUNCH(tagk("s2_eval", k), k_s2_eval<T, OPF, CIN, COUT, R><<<dim3(b.blocks(), PH), 256, 0, st>>>(b.L));
+  }
+  if (k >= 2) return launch_eca_next<T, COUT, true>(c, k, v, gaps, gtiles, wk + bo.eca_w);
+  return launch_eca_next<T, COUT, false>(c, k, v, gaps, gtiles, wk + bo.eca_w);
 }
 
 template <class T>
@@ -942,32 +1129,28 @@ int forward_folded_all(const Plan& P, const FoldLayout& L, const float* x, const
   const float* ids = wf + no.param_count;
   // working weights: the folded vector (BF16: its copy with the stage-2 weights rounded)
   const float* wk = P.dtype == STDA_BF16 ? reinterpret_cast<const float*>(fold + L.P.ws_wk) : wf;
-  for (int s = 0; s < P.n_segs; ++s) {
-    const SegPlan& S = P.seg[s];
-    // the per-(clip, phase, tile) ECA partial sums of every block fit the residual buffer
-    for (int k = 0; k < 4; ++k) {
-      const BlockCfg& b = kBlocks[k];
-      const int64_t ho = S.H >> b.lout, wo = S.W >> b.lout;
-      const int64_t rows = b.dec ? (ho / 2) * (wo / 2) : ho * wo;
-      const int64_t need = (int64_t)S.n * (b.dec ? 4 : 1) * ((rows + 63) / 64) * b.cout * (int64_t)sizeof(float);
-      if (need > (int64_t)(P.ws_part - P.ws_R)) return STDA_E_WORKSPACE;
-    }
-    T* s0 = reinterpret_cast<T*>(ws + S.s0);
-    StemArgs sa{x + S.x_off, wk + no.stem_w, ids + fold_ids_off(16), wk + no.stem_g, wk + no.stem_b, nullptr, nullptr};
-    FLAUNCH("stem_apply", k_stem_tile<T, 1><<<stem_grid(S.n, S.H, S.W), 256, 0, st>>>(sa, nullptr, nullptr, s0, S.n, S.H, S.W));
-    if (int r = folded_block<T, 16, 32, false>(P, S, 0, fold, wk, ids, ws, st)) return r;
-    if (int r = folded_block<T, 32, 64, false>(P, S, 1, fold, wk, ids, ws, st)) return r;
-    if (int r = folded_block<T, 64, 32, true>(P, S, 2, fold, wk, ids, ws, st)) return r;
-    if (int r = folded_block<T, 32, 16, true>(P, S, 3, fold, wk, ids, ws, st)) return r;
-    const T* d1 = reinterpret_cast<const T*>(ws + S.blk[3].Xn);
-    const int gz = head_grid(S.n, S.H, S.W);
-    if (P.arch & STDA_ARCH_SIGMOID) {
-      FLAUNCH("head_fwd", k_head_fwd_tile<T, true><<<gz, 256, 0, st>>>(d1, wk + no.head_w, wk + no.head_b, z + S.z_off, nullptr, S.n, S.H, S.W));
-    } else {
-      FLAUNCH("head_fwd", k_head_fwd_tile<T, false><<<gz, 256, 0, st>>>(d1, wk + no.head_w, wk + no.head_b, z + S.z_off, nullptr, S.n, S.H, S.W));
-    }
+  // the ECA partial sums of every block fit the residual buffer
+  for (int k = 0; k < 4; ++k) {
+    int64_t need = 0;
+    for (int s = 0; s < P.n_segs; ++s) need += folded_gap_floats(P.seg[s], k) * (int64_t)sizeof(float);
+    if (need > (int64_t)(P.ws_part - P.ws_R)) return STDA_E_WORKSPACE;
   }
-  return STDA_OK;
+  const Ctx<T> c{&P, ws, ws, wk, nullptr, st, false};
+  {
+    Batch<k_stem_tile_args<T, 1>> b;
+    for (int s = 0; s < P.n_segs; ++s) {
+      const SegPlan& S = P.seg[s];
+      const StemArgs sa{x + S.x_off, wk + no.stem_w, ids + fold_ids_off(16), wk + no.stem_g, wk + no.stem_b, nullptr, nullptr};
+      b.add(stem_grid(S.n, S.H, S.W), {sa, nullptr, nullptr, reinterpret_cast<T*>(ws + S.s0), S.n, S.H, S.W});
+    }
+    FLAUNCH("stem_apply", k_stem_tile<T, 1><<<b.blocks(), 256, 0, st>>>(b.L));
+  }
+  if (int r = folded_block<T, 16, 32, false>(P, 0, fold, wk, ids, ws, st)) return r;
+  if (int r = folded_block<T, 32, 64, false>(P, 1, fold, wk, ids, ws, st)) return r;
+  if (int r = folded_block<T, 64, 32, true>(P, 2, fold, wk, ids, ws, st)) return r;
+  if (int r = folded_block<T, 32, 16, true>(P, 3, fold, wk, ids, ws, st)) return r;
+  if (P.arch & STDA_ARCH_SIGMOID) return launch_head_fwd<T, true>(c, wk + no.head_w, wk + no.head_b, z);
+  return launch_head_fwd<T, false>(c, wk + no.head_w, wk + no.head_b, z);
 }
 #undef FLAUNCH
 
@@ -999,46 +1182,60 @@ int64_t wgrad_rows(int64_t cols) {
   return std::max<int64_t>(256, std::min<int64_t>(1024, fit));
 }
 
-template <class T, bool DEC, int CL, int CH, int TH, int TW>
-int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const T* lo, const T* hi, int n, int h, int w,
-                     float* dst, ColMap map, int acc) {
-  typedef WgCfg<T, DEC, CL, CH, TH, TW> Cfg;
-  const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = capped(std::min<int64_t>(ntiles, wgrad_rows(cols)));
-  if (gx >= 64) gx &= ~(int64_t)7;
-  gx = std::max<int64_t>(gx, 1);
-  float* wpart = c.template scr<float>(c.P->ws_wpart);
-  KLAUNCH(tag, k_s2_wgrad<T, DEC, CL, CH, TH, TW><<<(unsigned)gx, 256, 0, c.st>>>(lo, hi, wpart, n, h, w));
-  return colsum_to(c, wpart, (int)gx, (int)cols, dst, map, acc, "wgrad_sum" + tag.substr(5));
-}
+// One segment's operands of a stage-2 weight gradient: x the layer input (hin x win), d the
+// gradient of its output.
+template <class T>
+struct WgOps {
+  int n = 0;
+  const T* x[kMaxSegs];
+  const T* d[kMaxSegs];
+  int clips[kMaxSegs], hin[kMaxSegs], win[kMaxSegs];
+  void add(const T* xs, const T* ds, int b, int h, int w) {
+    x[n] = xs;
+    d[n] = ds;
+    clips[n] = b;
+    hin[n] = h;
+    win[n] = w;
+    ++n;
+  }
+};
 
-template <class T, bool DEC, int CL, int CH, int TH, int TW>
-int launch_wgrad_v(const Ctx<T>& c, const std::string& tag, const T* lo, const T* hi, int n, int h, int w, float* dst,
-                   ColMap map, int acc) {
-  typedef WgVCfg<T, DEC, CL, CH, TH, TW> Cfg;
-  const int64_t ntiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  const int64_t cols = (int64_t)Cfg::TAPS * CH * CL;
-  int64_t gx = capped(std::min<int64_t>(ntiles, wgrad_rows(cols)));
-  if (gx >= 64) gx &= ~(int64_t)7;
-  gx = std::max<int64_t>(gx, 1);
-  float* wpart = c.template scr<float>(c.P->ws_wpart);
-  KLAUNCH(tag, k_s2_wgrad_v<T, DEC, CL, CH, TH, TW><<<(unsigned)gx, 256, 0, c.st>>>(lo, hi, wpart, n, h, w));
-  return colsum_to(c, wpart, (int)gx, (int)cols, dst, map, acc, "wgrad_sum" + tag.substr(5));
+// Weight-gradient launch with tiling (TH, TW) over every segment: Lo / Hi operands and the grid
+// of Lo per segment; one partial row per workgroup, all segments' rows summed by one reduction.
+template <class T, bool DEC, int CL, int CH, int TH, int TW, bool VEC>
+int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const WgOps<T>& O, float* dst, ColMap map) {
+  constexpr int TAPS = VEC ? WgVCfg<T, DEC, CL, CH, TH, TW>::TAPS : WgCfg<T, DEC, CL, CH, TH, TW>::TAPS;
+  const int64_t cols = (int64_t)TAPS * CH * CL;
+  typedef std::conditional_t<VEC, k_s2_wgrad_v_args<T, DEC, CL, CH, TH, TW>, k_s2_wgrad_args<T, DEC, CL, CH, TH, TW>> A;
+  Batch<A> b;
+  Parts pm = c.wpart();
+  for (int s = 0; s < O.n; ++s) {
+    const T* lo = DEC ? O.x[s] : O.d[s];
+    const T* hi = DEC ? O.d[s] : O.x[s];
+    const int h = DEC ? O.hin[s] : O.hin[s] / 2, w = DEC ? O.win[s] : O.win[s] / 2;
+    const int64_t ntiles = (int64_t)O.clips[s] * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
+    int64_t gx = capped(std::min<int64_t>(ntiles, wgrad_rows(cols)));
+    if (gx >= 64) gx &= ~(int64_t)7;
+    gx = std::max<int64_t>(gx, 1);
+    b.add((int)gx, {lo, hi, pm.take((int)gx, cols, false), O.clips[s], h, w});
+  }
+  if (pm.over) return STDA_E_WORKSPACE;
+  if constexpr (VEC) {
+    KLAUNCH(tag, k_s2_wgrad_v<T, DEC, CL, CH, TH, TW><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  } else {
+    KLAUNCH(tag, k_s2_wgrad<T, DEC, CL, CH, TH, TW><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  }
+  return colsum_to(c, pm.base, pm.total_rows(), (int)cols, dst, map, 0, "wgrad_sum" + tag.substr(5));
 }
 
 template <class T, bool DEC, int CIN, int COUT>
-int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, const T* d, int n, int hin, int win,
-                 float* dst, int acc) {
+int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const WgOps<T>& O, float* dst) {
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][2][blk];
   constexpr int CL = DEC ? CIN : COUT, CH = DEC ? COUT : CIN;
-  const T* lo = DEC ? x : d;
-  const T* hi = DEC ? d : x;
-  const int h = DEC ? hin : hin / 2, w = DEC ? win : win / 2;
   const ColMap map{DEC ? MAP_DEC_S2 : MAP_ENC_S2, CIN, COUT};
   constexpr bool SMALL = CL * CH <= 512;  // 16 x 32 channel pairs: larger tiles fit
-#define WGV(TH_, TW_) launch_wgrad_cfg<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
-#define WGVV(TH_, TW_) launch_wgrad_v<T, DEC, CL, CH, TH_, TW_>(c, tag, lo, hi, n, h, w, dst, map, acc)
+#define WGV(TH_, TW_) launch_wgrad_cfg<T, DEC, CL, CH, TH_, TW_, false>(c, tag, O, dst, map)
+#define WGVV(TH_, TW_) launch_wgrad_cfg<T, DEC, CL, CH, TH_, TW_, true>(c, tag, O, dst, map)
   // 0, 1, 3: vector-operand kernel; 2: scalar-operand kernel (BF16) or the vector-operand kernel on
   // smaller tiles (FP32)
   constexpr bool BF = sizeof(T) == 2;
@@ -1058,29 +1255,43 @@ int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const T* x, c
 #undef WGVV
 }
 
+// One segment's operands of the fused stage-1 adjoint.
+template <class T>
+struct S1bOps {
+  const T* X;
+  const uint8_t* M1;
+  const T *dX1, *dXr, *skipg;
+  S1Params sp;
+  T* dXout;
+  const float* coef;
+  int n, h, w;
+};
+
 // Fused stage-1 adjoint of block `blk` with the tiling chosen for it (tuning kind 3): TH x TW
-// pixel tiles, MINW waves per SIMD; *rows = workgroups = rows of weight-gradient partials.
+// pixel tiles, MINW waves per SIMD; weight-gradient partial rows (one per workgroup) go to
+// *pw (pointwise) and *dw (depthwise), segment after segment.
 template <class T, int C, bool DEC, int TH, int TW, int MINW, bool LC = false>
-int launch_s1b_cfg(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T* dX1, const T* dXr, const T* skipg,
-                   const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
-  const int64_t tiles = (int64_t)n * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  const int g = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
-  const float* coef = c.template scr<float>(c.P->ws_coef);
-  KLAUNCH(tagk("s1_bwd_fused", blk), k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW, LC><<<g, 256, 0, c.st>>>(
-                                         X, M1, dX1, dXr, skipg, coef, sp, dXout, pwpart, dwpart, n, h, w));
-  *rows = g;
+int launch_s1b_cfg(const Ctx<T>& c, int blk, const S1bOps<T>* O, Parts& pw, Parts& dw) {
+  Batch<k_s1_bwd_fused_args<T, C, DEC, !DEC, TH, TW, MINW, LC>> b;
+  for (int s = 0; s < c.ns(); ++s) {
+    const S1bOps<T>& o = O[s];
+    const int64_t tiles = (int64_t)o.n * ((o.h + TH - 1) / TH) * ((o.w + TW - 1) / TW);
+    const int g = (int)std::max<int64_t>(1, capped(std::min<int64_t>(tiles, kTileGrid)));
+    b.add(g, {o.X, o.M1, o.dX1, o.dXr, o.skipg, o.coef, o.sp, o.dXout, pw.take(g, C * C, false), dw.take(g, 9 * C, false),
+              o.n, o.h, o.w});
+  }
+  if (pw.over || dw.over) return STDA_E_WORKSPACE;
+  KLAUNCH(tagk("s1_bwd_fused", blk),
+          (k_s1_bwd_fused<T, C, DEC, !DEC, TH, TW, MINW, LC><<<b.blocks(), 256, 0, c.st>>>(b.L)));
   return STDA_OK;
 }
 
 template <class T, int C, bool DEC>
-int launch_s1b(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T* dX1, const T* dXr, const T* skipg,
-               const S1Params& sp, T* dXout, float* pwpart, float* dwpart, int n, int h, int w, int* rows) {
+int launch_s1b(const Ctx<T>& c, int blk, const S1bOps<T>* O, Parts& pw, Parts& dw) {
   const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
-#define S1B(TH_, TW_, W_) \
-  launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
+#define S1B(TH_, TW_, W_) launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, O, pw, dw)
   // LC: depthwise taps and BN-adjoint coefficients read from LDS, three waves per SIMD
-#define S1L(TH_, TW_) \
-  launch_s1b_cfg<T, C, DEC, TH_, TW_, 3, true>(c, blk, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, dwpart, n, h, w, rows)
+#define S1L(TH_, TW_) launch_s1b_cfg<T, C, DEC, TH_, TW_, 3, true>(c, blk, O, pw, dw)
   if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1L(8, 16) : S1B(8, 16, 2);
   else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1L(8, 8) : S1B(8, 8, 2);
   else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1L(4, 4) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
@@ -1088,175 +1299,234 @@ int launch_s1b(const Ctx<T>& c, int blk, const T* X, const uint8_t* M1, const T*
 #undef S1L
 }
 
+// BN adjoint reduction over every segment of the launch whose partials are in pm: NS sums per
+// channel, count[s] elements per channel in segment s; gamma / beta gradients summed over the
+// segments, coefficients per segment.
 template <class T>
-int bn_bwd(const Ctx<T>& c, int nblk, int NS, int C, double n, float* const* dg, float* const* db, int acc) {
-  float* part = c.template scr<float>(c.P->ws_part);
+int bn_bwd(const Ctx<T>& c, const Parts& pm, int NS, int C, const double* count, float* const* dg, float* const* db) {
+  if (NS > 4) return STDA_E_INVALID;
+  BnBwdSegs sg{};
+  sg.n = pm.n;
+  for (int s = 0; s < pm.n; ++s) {
+    sg.part[s] = pm.p[s];
+    sg.rows[s] = pm.rows[s];
+    sg.count[s] = count[s];
+    sg.coef[s] = c.coef(s);
+  }
   BnBwdOut o{};
   for (int k = 0; k < NS - 1; ++k) {
     o.dgamma[k] = dg[k];
     o.dbeta[k] = db[k];
   }
-  KLAUNCH("bn_bwd_finalize", k_bn_bwd_reduce<<<C / 4, 256, 0, c.st>>>(part, nblk, NS, C, n, o,
-                                                                     c.template scr<float>(c.P->ws_coef), acc));
+  KLAUNCH("bn_bwd_finalize", k_bn_bwd_reduce<<<C / 4, 256, 0, c.st>>>(sg, NS, C, o, 0));
   return STDA_OK;
 }
 
-// Gradient buffers (ws): 0 dd1 (grad of d1), 1 dd0 (grad of d0), 2 de1, 3 de0, 4 ds0,
-// 5 dT, 6 dY, 7 dX1, 8 dXr, 9 dP, 10 dD, 11 dX0, 12 dTp (input module).
+// Gradient buffers (ws, one region per segment): 0 dd1 (grad of d1), 1 dd0 (grad of d0), 2 de1,
+// 3 de0, 4 ds0, 5 dT, 6 dY, 7 dX1, 8 dXr, 9 dP, 10 dD, 11 dX0, 12 dTp (input module).
+// Block k's adjoint reads the output gradient from buffer gin and writes the input gradient to
+// gout; the encoder blocks add the skip gradient from buffer gskip (decoder blocks: -1).
 template <class T, int CIN, int COUT, bool DEC>
-int bwd_block(const Ctx<T>& c, int k, const T* Gd, T* dXout, const T* skipg, float* dw, int acc) {
-  const BlockCfg& bc = kBlocks[k];
+int bwd_block(const Ctx<T>& c, int k, int gin, int gout, int gskip, float* dw) {
   const BlockOffsets& bo = net_offsets(c.P->arch).blk[k];
-  const SegPlan& S = *c.S;
-  const BlockActs& A = S.blk[k];
-  const int n = S.n;
-  const int hin = S.H >> bc.lin, win = S.W >> bc.lin, hout = S.H >> bc.lout, wout = S.W >> bc.lout;
-  const int64_t Pin = (int64_t)n * hin * win, Pout = (int64_t)n * hout * wout;
-  const T* X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
-  const T* X1 = c.template inner<T>(A, A.X1);
-  const uint8_t* M1 = c.template inner<uint8_t>(A, A.m1);
-  const T* Tm = c.template inner<T>(A, A.T);
-  const T* Y = c.template inner<T>(A, A.Y);
-  auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
-  T *dT = gb(5), *dY = gb(6), *dX1 = gb(7), *dXr = gb(8), *dP = gb(9), *dD = gb(10), *dX0 = gb(11);
-  float* part = c.template scr<float>(c.P->ws_part);
-  float* coef_e = c.template scr<float>(c.P->ws_coef_e);
-  float* ecaw = c.template scr<float>(c.P->ws_ecaw);
-  const int hw = hout * wout;
-  const int tiles = tiles_for(hw, COUT / 4);
-  float* epart = c.template scr<float>(c.P->ws_gap);
+  const int ns = c.ns();
+  // the encoder blocks receive a skip gradient (from the decoder), the decoder blocks none
+  if ((gskip >= 0) != !DEC) return STDA_E_INVALID;
+  BlockView<T> v[kMaxSegs];
+  S1Params sp[kMaxSegs];
+  int tiles[kMaxSegs];
+  double cin_n[kMaxSegs], cout_n[kMaxSegs];
+  for (int s = 0; s < ns; ++s) {
+    v[s] = block_view(c, s, k);
+    sp[s] = s1_params(c, s, k);
+    tiles[s] = tiles_for(v[s].hout * v[s].wout, COUT / 4);
+    cin_n[s] = (double)v[s].n * v[s].hin * v[s].win;
+    cout_n[s] = (double)v[s].n * v[s].hout * v[s].wout;
+  }
+  auto G = [&](int s, int i) { return c.grad(s, i); };
   // ECA adjoint partials and stage-2 BN statistics
-  KLAUNCH(tagk("eca_bwd", k), k_eca_bwd_part<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Y, epart, hw));
-  const uint8_t* mask = c.template inner<uint8_t>(A, A.mask);
-  KLAUNCH(tagk("s2_bwd_stats", k), k_s2_bwd_stats<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(
-      Gd, Tm, mask, epart, c.template act<float>(A.a), c.template act<float>(A.g), c.w + bo.eca_w, c.stats(bo.bn_main),
-      c.w + bo.main_g, c.w + bo.main_b, coef_e, ecaw, part, hw, tiles));
-  if (int r = colsum_to(c, ecaw, n, 3, dw + bo.eca_w, ColMap{MAP_IDENT, 0, 0}, acc)) return r;
   {
+    Batch<k_eca_bwd_part_args<T, COUT>> b;
+    for (int s = 0; s < ns; ++s)
+      b.add(tiles[s] * v[s].n, {G(s, gin), v[s].Y, c.gap(s), v[s].hout * v[s].wout, tiles[s]});
+    KLAUNCH(tagk("eca_bwd", k), k_eca_bwd_part<T, COUT><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  }
+  {
+    Parts pm = c.part();
+    Batch<k_s2_bwd_stats_args<T, COUT>> b;
+    for (int s = 0; s < ns; ++s)
+      b.add(tiles[s] * v[s].n, {G(s, gin), v[s].Tm, v[s].mask, c.gap(s), v[s].a, v[s].g, c.w + bo.eca_w,
+                                c.stats(s, bo.bn_main), c.w + bo.main_g, c.w + bo.main_b, c.coef_e(s), c.ecaw(s),
+                                pm.take(tiles[s] * v[s].n, 2 * COUT, false), v[s].hout * v[s].wout, tiles[s],
+                                tiles[s]});
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH(tagk("s2_bwd_stats", k), k_s2_bwd_stats<T, COUT><<<b.blocks(), 256, 0, c.st>>>(b.L));
+    // ECA weight gradient: the per-clip rows of all segments are contiguous
+    if (int r = colsum_to(c, c.ecaw(0), c.clips(), 3, dw + bo.eca_w, ColMap{MAP_IDENT, 0, 0}, 0)) return r;
     float* dg[1] = {dw + bo.main_g};
     float* db[1] = {dw + bo.main_b};
-    if (int r = bn_bwd(c, tiles * n, 2, COUT, (double)Pout, dg, db, acc)) return r;
+    if (int r = bn_bwd(c, pm, 2, COUT, cout_n, dg, db)) return r;
   }
-  KLAUNCH(tagk("s2_bwd_apply", k), k_s2_bwd_apply<T, COUT><<<dim3(tiles, n), 256, 0, c.st>>>(Gd, Tm, mask, c.template act<float>(A.a), coef_e,
-                                                            c.template scr<float>(c.P->ws_coef), c.stats(bo.bn_main),
-                                                            c.w + bo.main_g, c.w + bo.main_b, dT, dY, hw));
+  {
+    Batch<k_s2_bwd_apply_args<T, COUT>> b;
+    for (int s = 0; s < ns; ++s)
+      b.add(tiles[s] * v[s].n, {G(s, gin), v[s].Tm, v[s].mask, v[s].a, c.coef_e(s), c.coef(s), c.stats(s, bo.bn_main),
+                                c.w + bo.main_g, c.w + bo.main_b, G(s, 5), G(s, 6), v[s].hout * v[s].wout, tiles[s]});
+    KLAUNCH(tagk("s2_bwd_apply", k), k_s2_bwd_apply<T, COUT><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  }
   // dense adjoints: dX1 from dT, dXr from dY
   constexpr int OPD = DEC ? OP_DEC_DGRAD : OP_ENC_DGRAD;
-  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_main", k), dT, c.P->dense_d[k][0], dX1, nullptr, n, hin, win, nullptr))
+  DenseOps<T> dm, dr;
+  for (int s = 0; s < ns; ++s) {
+    dm.add(G(s, 5), G(s, 7), v[s].n, v[s].hin, v[s].win);
+    dr.add(G(s, 6), G(s, 8), v[s].n, v[s].hin, v[s].win);
+  }
+  if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_main", k), dm, c.P->dense_d[k][0], nullptr))
     return r;
   const bool res3 = DEC && (c.P->arch & STDA_ARCH_RES3);
   if constexpr (DEC) {
     if (res3)  // adjoint of the DeConv3x3-s2-p1 residual: a Conv3x3-s2-p1 of dY
-      if (int r = launch_dense<T, OP_ENC_FWD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+      if (int r = launch_dense<T, OP_ENC_FWD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dr, c.P->dense_d[k][1], nullptr))
         return r;
   }
   if (!res3)
-    if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dY, c.P->dense_d[k][1], dXr, nullptr, n, hin, win, nullptr))
+    if (int r = launch_dense<T, OPD, COUT, CIN, false>(c, k, tagk("dense_dgrad_res", k), dr, c.P->dense_d[k][1], nullptr))
       return r;
   // dense weight gradients
-  if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_main", k), X1, dT, n, hin, win, dw + bo.main_w, acc))
-    return r;
-  if constexpr (DEC) {
-    if (res3)  // the weight gradient of that Conv3x3-s2-p1 with input dY and output gradient X
-      if (int r = launch_wgrad<T, false, COUT, CIN>(c, k, tagk("wgrad_res", k), dY, X, n, hout, wout, dw + bo.res_w, acc))
-        return r;
-  }
-  if (!res3)
-    if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_res", k), X, dY, n, hin, win, dw + bo.res_w, acc))
-      return r;
-  // stage 1
-  S1Params sp{};
-  sp.wpw = (c.P->arch & STDA_ARCH_PW_DW) ? c.template scr<float>(c.P->ws_pwx) + c.P->pwx_off[k] : c.w + bo.pw_w;
-  sp.wdw = c.w + bo.dw_w;
-  sp.stats[0] = c.stats(bo.bn_pw);
-  sp.stats[1] = c.stats(bo.bn_dw);
-  sp.stats[2] = c.stats(bo.bn_id);
-  sp.gamma[0] = c.w + bo.pw_g;
-  sp.gamma[1] = c.w + bo.dw_g;
-  sp.gamma[2] = c.w + bo.id_g;
-  sp.beta[0] = c.w + bo.pw_b;
-  sp.beta[1] = c.w + bo.dw_b;
-  sp.beta[2] = c.w + bo.id_b;
-  const int g1 = s1_grid<CIN>(n, hin, win);
-  KLAUNCH(tagk("s1_bwd_stats", k),
-          k_s1_bwd_stats_tile<T, CIN, DEC><<<g1, 256, 0, c.st>>>(X, M1, dX1, part, sp, n, hin, win));
   {
+    WgOps<T> om, orr;
+    for (int s = 0; s < ns; ++s) {
+      om.add(v[s].X1, G(s, 5), v[s].n, v[s].hin, v[s].win);
+      if (res3)  // the weight gradient of that Conv3x3-s2-p1 with input dY and output gradient X
+        orr.add(G(s, 6), v[s].X, v[s].n, v[s].hout, v[s].wout);
+      else
+        orr.add(v[s].X, G(s, 6), v[s].n, v[s].hin, v[s].win);
+    }
+    if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_main", k), om, dw + bo.main_w)) return r;
+    if constexpr (DEC) {
+      if (res3)
+        if (int r = launch_wgrad<T, false, COUT, CIN>(c, k, tagk("wgrad_res", k), orr, dw + bo.res_w)) return r;
+    }
+    if (!res3)
+      if (int r = launch_wgrad<T, DEC, CIN, COUT>(c, k, tagk("wgrad_res", k), orr, dw + bo.res_w)) return r;
+  }
+  // stage 1
+  {
+    Parts pm = c.part();
+    Batch<k_s1_bwd_stats_tile_args<T, CIN, DEC>> b;
+    for (int s = 0; s < ns; ++s) {
+      const int g = s1_grid<CIN>(v[s].n, v[s].hin, v[s].win);
+      b.add(g, {v[s].X, v[s].m1, G(s, 7), pm.take(g, 4 * CIN, false), sp[s], v[s].n, v[s].hin, v[s].win});
+    }
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH(tagk("s1_bwd_stats", k), k_s1_bwd_stats_tile<T, CIN, DEC><<<b.blocks(), 256, 0, c.st>>>(b.L));
     float* dg[3] = {dw + bo.pw_g, dw + bo.dw_g, dw + bo.id_g};
     float* db[3] = {dw + bo.pw_b, dw + bo.dw_b, dw + bo.id_b};
-    if (int r = bn_bwd(c, g1, 4, CIN, (double)Pin, dg, db, acc)) return r;
+    if (int r = bn_bwd(c, pm, 4, CIN, cin_n, dg, db)) return r;
   }
-  // the encoder blocks receive a skip gradient (from the decoder), the decoder blocks none
-  if ((skipg != nullptr) != !DEC) return STDA_E_INVALID;
-  float* pwpart = c.template scr<float>(c.P->ws_wpart);
-  int rows = 0;
-  if (int r = launch_s1b<T, CIN, DEC>(c, k, X, M1, dX1, dXr, skipg, sp, dXout, pwpart, part, n, hin, win, &rows))
-    return r;
+  S1bOps<T> o[kMaxSegs];
+  for (int s = 0; s < ns; ++s)
+    o[s] = S1bOps<T>{v[s].X, v[s].m1, G(s, 7), G(s, 8), gskip >= 0 ? G(s, gskip) : nullptr, sp[s], G(s, gout),
+                     c.coef(s), v[s].n, v[s].hin, v[s].win};
+  Parts pw = c.wpart(), dwp = c.part();
+  if (int r = launch_s1b<T, CIN, DEC>(c, k, o, pw, dwp)) return r;
   const ColMap pwmap = (c.P->arch & STDA_ARCH_PW_DW) ? ColMap{MAP_PW_DIAG, CIN, 0}
                                                       : ColMap{DEC ? MAP_IDENT : MAP_PW_CONV, CIN, 0};
   // both weight gradients of stage 1 (pointwise, depthwise) in one reduction launch
-  const ColJob ja{pwpart, dw + bo.pw_w, pwmap, rows, CIN * CIN, (CIN * CIN + 15) / 16};
-  const ColJob jb{part, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, rows, 9 * CIN, (9 * CIN + 15) / 16};
-  KLAUNCH(tagk("s1_bwd_fused_sum", k), k_colsum2<<<ja.nblk + jb.nblk, 256, 0, c.st>>>(ja, jb, acc));
+  const int rows = pw.total_rows();
+  const ColJob ja{pw.base, dw + bo.pw_w, pwmap, rows, CIN * CIN, (CIN * CIN + 15) / 16};
+  const ColJob jb{dwp.base, dw + bo.dw_w, ColMap{MAP_DW, CIN, 0}, rows, 9 * CIN, (9 * CIN + 15) / 16};
+  KLAUNCH(tagk("s1_bwd_fused_sum", k), k_colsum2<<<ja.nblk + jb.nblk, 256, 0, c.st>>>(ja, jb, 0));
   return STDA_OK;
 }
 
+template <class T, bool SIG>
+int launch_head_bwd(const Ctx<T>& c, const float* dz, const float* wh, Parts& pm) {
+  Batch<k_head_bwd_tile_args<T, SIG>> b;
+  for (int s = 0; s < c.ns(); ++s) {
+    const SegPlan& S = c.S(s);
+    const int g = head_grid(S.n, S.H, S.W);
+    b.add(g, {dz + S.z_off, SIG ? c.template act<float>(S.zs) : nullptr, wh, c.template act<T>(S.blk[3].Xn),
+              c.grad(s, 0), pm.take(g, 10 * 16, false), S.n, S.H, S.W});
+  }
+  if (pm.over) return STDA_E_WORKSPACE;
+  KLAUNCH("head_bwd", k_head_bwd_tile<T, SIG><<<b.blocks(), 256, 0, c.st>>>(b.L));
+  return STDA_OK;
+}
+
+// The network adjoint over every segment: one launch per kernel kind and layer; parameter
+// gradients summed over all segments.
 template <class T>
-int backward_seg(const Ctx<T>& c, const float* dz, const float* x, float* dw, float* dx, int acc) {
-  const SegPlan& S = *c.S;
+int backward_net(const Ctx<T>& c, const float* dz, const float* x, float* dw, float* dx) {
   const NetOffsets& no = net_offsets(c.P->arch);
-  const int64_t P = (int64_t)S.n * S.H * S.W;
-  auto gb = [&](int i) { return c.template scr<T>(c.P->ws_g[i]); };
-  const float* dzs = dz + S.z_off;
+  const int ns = c.ns();
   // output module
   {
-    float* part = c.template scr<float>(c.P->ws_part);
-    const int gh = head_grid(S.n, S.H, S.W);
-    if (c.P->arch & STDA_ARCH_SIGMOID) {
-      KLAUNCH("head_bwd", k_head_bwd_tile<T, true><<<gh, 256, 0, c.st>>>(dzs, c.template act<float>(S.zs), c.w + no.head_w,
-                                                                       c.template act<T>(S.blk[3].Xn), gb(0), part,
-                                                                       S.n, S.H, S.W));
-    } else {
-      KLAUNCH("head_bwd", k_head_bwd_tile<T, false><<<gh, 256, 0, c.st>>>(dzs, nullptr, c.w + no.head_w,
-                                                                        c.template act<T>(S.blk[3].Xn), gb(0), part,
-                                                                        S.n, S.H, S.W));
-    }
-    if (int r = colsum_to(c, part, gh, 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, acc)) return r;
+    Parts pm = c.part();
+    const int r = (c.P->arch & STDA_ARCH_SIGMOID) ? launch_head_bwd<T, true>(c, dz, c.w + no.head_w, pm)
+                                                  : launch_head_bwd<T, false>(c, dz, c.w + no.head_w, pm);
+    if (r) return r;
+    if (int e = colsum_to(c, pm.base, pm.total_rows(), 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, 0)) return e;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
   // recompute mode: re-run a block's forward (saved statistics, no ECA) right before its adjoint
   Ctx<T> rc = c;
   rc.rec_pass = true;
-  const bool rec = S.blk[0].inner_in_ws;
+  const bool rec = c.S(0).blk[0].inner_in_ws;
   if (rec)
     if (int r = fwd_block<T, 32, 16, true>(rc, 3, nullptr)) return r;
-  if (int r = bwd_block<T, 32, 16, true>(c, 3, gb(0), gb(1), nullptr, dw, acc)) return r;
+  if (int r = bwd_block<T, 32, 16, true>(c, 3, 0, 1, -1, dw)) return r;
   if (rec)
     if (int r = fwd_block<T, 64, 32, true>(rc, 2, nullptr)) return r;
-  if (int r = bwd_block<T, 64, 32, true>(c, 2, gb(1), gb(2), nullptr, dw, acc)) return r;
+  if (int r = bwd_block<T, 64, 32, true>(c, 2, 1, 2, -1, dw)) return r;
   // encoder 1 (input e0: its gradient also receives dd0 through the skip), encoder 0
   if (rec)
     if (int r = fwd_block<T, 32, 64, false>(rc, 1, nullptr)) return r;
-  if (int r = bwd_block<T, 32, 64, false>(c, 1, gb(2), gb(3), gb(1), dw, acc)) return r;
+  if (int r = bwd_block<T, 32, 64, false>(c, 1, 2, 3, 1, dw)) return r;
   if (rec)
     if (int r = fwd_block<T, 16, 32, false>(rc, 0, nullptr)) return r;
-  if (int r = bwd_block<T, 16, 32, false>(c, 0, gb(3), gb(4), gb(0), dw, acc)) return r;
+  if (int r = bwd_block<T, 16, 32, false>(c, 0, 3, 4, 0, dw)) return r;
   // input module
-  float* part = c.template scr<float>(c.P->ws_part);
-  const int g = stem_grid(S.n, S.H, S.W);
-  StemArgs sa{x + S.x_off, c.w + no.stem_w, c.stats(0), c.w + no.stem_g, c.w + no.stem_b,
-              c.template scr<float>(c.P->ws_coef), part};
-  KLAUNCH("stem_bwd_stats",
-          k_stem_tile<T, 2><<<g, 256, 0, c.st>>>(sa, gb(4), c.template act<T>(S.s0), nullptr, S.n, S.H, S.W));
+  auto stem_args = [&](int s, float* part) {
+    const SegPlan& S = c.S(s);
+    return StemArgs{x + S.x_off, c.w + no.stem_w, c.stats(s, 0), c.w + no.stem_g, c.w + no.stem_b, c.coef(s), part};
+  };
   {
+    Parts pm = c.part();
+    Batch<k_stem_tile_args<T, 2>> b;
+    double cnt[kMaxSegs];
+    for (int s = 0; s < ns; ++s) {
+      const SegPlan& S = c.S(s);
+      const int g = stem_grid(S.n, S.H, S.W);
+      cnt[s] = (double)S.n * S.H * S.W;
+      b.add(g, {stem_args(s, pm.take(g, 2 * 16, false)), c.grad(s, 4), c.template act<T>(S.s0), nullptr, S.n, S.H, S.W});
+    }
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH("stem_bwd_stats", k_stem_tile<T, 2><<<b.blocks(), 256, 0, c.st>>>(b.L));
     float* dg[1] = {dw + no.stem_g};
     float* db[1] = {dw + no.stem_b};
-    if (int r = bn_bwd(c, g, 2, 16, (double)P, dg, db, acc)) return r;
+    if (int r = bn_bwd(c, pm, 2, 16, cnt, dg, db)) return r;
   }
-  KLAUNCH("stem_bwd_apply", k_stem_tile<T, 3><<<g, 256, 0, c.st>>>(sa, gb(4), c.template act<T>(S.s0),
-                                                                   dx ? gb(12) : nullptr, S.n, S.H, S.W));
-  if (int r = colsum_to(c, part, g, 27 * 16, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, acc)) return r;
+  {
+    Parts pm = c.part();
+    Batch<k_stem_tile_args<T, 3>> b;
+    for (int s = 0; s < ns; ++s) {
+      const SegPlan& S = c.S(s);
+      const int g = stem_grid(S.n, S.H, S.W);
+      b.add(g, {stem_args(s, pm.take(g, 27 * 16, false)), c.grad(s, 4), c.template act<T>(S.s0),
+                dx ? c.grad(s, 12) : nullptr, S.n, S.H, S.W});
+    }
+    if (pm.over) return STDA_E_WORKSPACE;
+    KLAUNCH("stem_bwd_apply", k_stem_tile<T, 3><<<b.blocks(), 256, 0, c.st>>>(b.L));
+    if (int r = colsum_to(c, pm.base, pm.total_rows(), 27 * 16, dw + no.stem_w, ColMap{MAP_STEM, 0, 0}, 0)) return r;
+  }
   if (dx) {
-    KLAUNCH("stem_dx", k_stem_dx<T><<<grid_for(P), 256, 0, c.st>>>(gb(12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W));
+    Batch<k_stem_dx_args<T>> b;
+    for (int s = 0; s < ns; ++s) {
+      const SegPlan& S = c.S(s);
+      b.add(grid_for((int64_t)S.n * S.H * S.W), {c.grad(s, 12), c.w + no.stem_w, dx + S.x_off, S.n, S.H, S.W});
+    }
+    KLAUNCH("stem_dx", k_stem_dx<T><<<b.blocks(), 256, 0, c.st>>>(b.L));
   }
   return STDA_OK;
 }
@@ -1266,11 +1536,8 @@ int backward_all(const Plan& P, const float* dz, const float* x, const float* w,
                  float* dx, char* ws, hipStream_t st) {
   const float* wk = nullptr;
   if (int r = prepare_weights(P, w, ws, st, &wk)) return r;
-  for (int s = 0; s < P.n_segs; ++s) {
-    Ctx<T> c{&P, &P.seg[s], const_cast<char*>(saved), ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, true};
-    if (int r = backward_seg<T>(c, dz, x, dw, dx, s > 0 ? 1 : 0)) return r;
-  }
-  return STDA_OK;
+  Ctx<T> c{&P, const_cast<char*>(saved), ws, wk, reinterpret_cast<float*>(ws + P.ws_dense), st, true};
+  return backward_net<T>(c, dz, x, dw, dx);
 }
 
 }  // namespace

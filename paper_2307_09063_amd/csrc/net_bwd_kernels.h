@@ -9,14 +9,31 @@ namespace stda {
 // --------------------------------------------------------------------- ECA adjoint
 // gap-like partials of sum_hw G * Y per (clip, tile, channel).
 template <class T, int C>
-__global__ __launch_bounds__(256) void k_eca_bwd_part(const T* __restrict__ Gd, const T* __restrict__ Y,
-                                                      float* __restrict__ part, int hw) {
+struct k_eca_bwd_part_args {
+  const T* Gd;
+  const T* Y;
+  float* part;
+  int hw;
+  int tiles;
+};
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_eca_bwd_part(SegL<k_eca_bwd_part_args<T, C>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_eca_bwd_part_args<T, C>& a_ = L.a[sb.s];
+  const T* __restrict__ const Gd = a_.Gd;
+  const T* __restrict__ const Y = a_.Y;
+  float* __restrict__ const part = a_.part;
+  const int hw = a_.hw;
+  const int tiles = a_.tiles;
   constexpr int G = C / 4;
   __shared__ float sm[4 * STDA_BLOCK];
   __shared__ float red[C];
-  const int b = blockIdx.y, tiles = gridDim.x;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, tile of the clip
   const int64_t items = (int64_t)hw * G, base = (int64_t)b * hw * C;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  int64_t i = (int64_t)tx * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float acc[1][4];
   zero4(acc[0]);
@@ -29,7 +46,7 @@ __global__ __launch_bounds__(256) void k_eca_bwd_part(const T* __restrict__ Gd, 
     for (int j = 0; j < 4; ++j) acc[0][j] += g[j] * y[j];
   }
   block_chan_reduce<G, 1>(acc, sm, red);
-  for (int q = threadIdx.x; q < C; q += STDA_BLOCK) part[((int64_t)b * tiles + blockIdx.x) * C + q] = red[q];
+  for (int q = threadIdx.x; q < C; q += STDA_BLOCK) part[((int64_t)b * tiles + tx) * C + q] = red[q];
 }
 
 // ECA adjoint of one clip: da = sum_hw G Y; ds = da a (1 - a); dg[c] = w0 ds[c+1] + w1 ds[c]
@@ -67,25 +84,58 @@ __device__ __forceinline__ void eca_adjoint_clip(const float* __restrict__ part,
 // ReLU mask; dM = mask * dY.  Partials part[blk][2][C]: sum dM, sum dM * that.  Tile 0 of
 // each clip writes e (coef_e[clip][C]) and the ECA weight partial (ecaw[clip][3]).
 template <class T, int C>
-__global__ __launch_bounds__(256) void k_s2_bwd_stats(const T* __restrict__ Gd, const T* __restrict__ Tm,
-                                                      const uint8_t* __restrict__ mask,
-                                                      const float* __restrict__ epart, const float* __restrict__ a_sv,
-                                                      const float* __restrict__ g_sv, const float* __restrict__ weca,
-                                                      const float* __restrict__ stats, const float* __restrict__ gamma,
-                                                      const float* __restrict__ beta, float* __restrict__ coef_e,
-                                                      float* __restrict__ ecaw, float* __restrict__ part, int hw,
-                                                      int etiles) {
+struct k_s2_bwd_stats_args {
+  const T* Gd;
+  const T* Tm;
+  const uint8_t* mask;
+  const float* epart;
+  const float* a_sv;
+  const float* g_sv;
+  const float* weca;
+  const float* stats;
+  const float* gamma;
+  const float* beta;
+  float* coef_e;
+  float* ecaw;
+  float* part;
+  int hw;
+  int etiles;
+  int tiles;
+};
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_s2_bwd_stats(SegL<k_s2_bwd_stats_args<T, C>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_bwd_stats_args<T, C>& a_ = L.a[sb.s];
+  const T* __restrict__ const Gd = a_.Gd;
+  const T* __restrict__ const Tm = a_.Tm;
+  const uint8_t* __restrict__ const mask = a_.mask;
+  const float* __restrict__ const epart = a_.epart;
+  const float* __restrict__ const a_sv = a_.a_sv;
+  const float* __restrict__ const g_sv = a_.g_sv;
+  const float* __restrict__ const weca = a_.weca;
+  const float* __restrict__ const stats = a_.stats;
+  const float* __restrict__ const gamma = a_.gamma;
+  const float* __restrict__ const beta = a_.beta;
+  float* __restrict__ const coef_e = a_.coef_e;
+  float* __restrict__ const ecaw = a_.ecaw;
+  float* __restrict__ const part = a_.part;
+  const int hw = a_.hw;
+  const int etiles = a_.etiles;
+  const int tiles = a_.tiles;
   constexpr int G = C / 4;
   __shared__ float ds_s[C], e_s[C];
   __shared__ float sm[2 * 4 * STDA_BLOCK];
   __shared__ float red[2 * C];
-  const int b = blockIdx.y, tiles = gridDim.x;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, tile of the clip
   eca_adjoint_clip<C>(epart + (int64_t)b * etiles * C, etiles, hw, a_sv + b * C, g_sv + b * C, weca, ds_s, e_s,
-                      blockIdx.x == 0 ? ecaw + b * 3 : nullptr);
-  if (blockIdx.x == 0)
+                      tx == 0 ? ecaw + b * 3 : nullptr);
+  if (tx == 0)
     for (int c = threadIdx.x; c < C; c += STDA_BLOCK) coef_e[b * C + c] = e_s[c];
   const int64_t items = (int64_t)hw * G, base = (int64_t)b * hw * C;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  int64_t i = (int64_t)tx * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float a4v[4], e4[4], mu[4], is[4], ga[4], be[4];
 #pragma unroll
@@ -115,7 +165,7 @@ __global__ __launch_bounds__(256) void k_s2_bwd_stats(const T* __restrict__ Gd, 
     }
   }
   block_chan_reduce<G, 2>(acc, sm, red);
-  const int64_t blk = (int64_t)b * tiles + blockIdx.x;
+  const int64_t blk = (int64_t)b * tiles + tx;
   for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) part[blk * 2 * C + q] = red[q];
 }
 
@@ -125,49 +175,94 @@ struct BnBwdOut {
   float* dgamma[3];
   float* dbeta[3];
 };
-// Cross-block FP64 reduction of BN adjoint partials part[blk][NS][C] fused with
-// k_bn_bwd_finalize's epilogue.  Block = 4 channels (4 NS columns) x 64 / NS row groups.
-__global__ __launch_bounds__(256) void k_bn_bwd_reduce(const float* __restrict__ part, int nrows, int NS, int C,
-                                                       double n, BnBwdOut out, float* __restrict__ coef,
-                                                       int accumulate) {
+struct BnBwdSegs {
+  int n;                        // segments
+  const float* part[kMaxSegs];  // the segment's partials part[blk][NS][C]
+  int rows[kMaxSegs];           // its partial rows
+  double count[kMaxSegs];       // elements per channel the segment's BN layers normalise
+  float* coef[kMaxSegs];        // its coefficients coef[NS][C]
+};
+// Cross-block FP64 reduction of BN adjoint partials fused with the finalize: per segment the
+// column sums give that segment's coefficients (its layers have their own statistics); the
+// gamma and beta gradients are the sums over all segments, taken in FP64 and rounded once.
+// Block = 4 channels (4 NS columns) x 64 / NS row groups.
+__global__ __launch_bounds__(256) void k_bn_bwd_reduce(BnBwdSegs sg, int NS, int C, BnBwdOut out, int accumulate) {
   __shared__ double sm[256];
   const int cols = 4 * NS, groups = 256 / cols;
   const int col = threadIdx.x % cols, rg = threadIdx.x / cols;
   const int c0 = blockIdx.x * 4;
   const int s = col / 4, c = c0 + col % 4;
-  const double acc = rg < groups ? strided_sum(part, rg, groups, nrows, (int64_t)NS * C, s * C + c) : 0.0;
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < cols) {
-    double tot = 0.0;
-    for (int k = 0; k < groups; ++k) tot += sm[k * cols + threadIdx.x];
-    sm[threadIdx.x] = tot;  // each slot is read only by the thread that owns it
+  double tsum[4] = {0.0, 0.0, 0.0, 0.0};  // threads < 4: beta, then gamma gradients over segments
+  for (int sgi = 0; sgi < sg.n; ++sgi) {
+    const double acc = rg < groups ? strided_sum(sg.part[sgi], rg, groups, sg.rows[sgi], (int64_t)NS * C, s * C + c)
+                                   : 0.0;
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < cols) {
+      double tot = 0.0;
+      for (int k = 0; k < groups; ++k) tot += sm[k * cols + threadIdx.x];
+      sm[threadIdx.x] = tot;  // each slot is read only by the thread that owns it
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int cc = c0 + threadIdx.x;
+      for (int q = 0; q < NS; ++q) {
+        tsum[q] += sm[q * 4 + threadIdx.x];
+        sg.coef[sgi][q * C + cc] = (float)(sm[q * 4 + threadIdx.x] / sg.count[sgi]);
+      }
+    }
+    __syncthreads();  // sm is reused by the next segment
   }
-  __syncthreads();
   if (threadIdx.x < 4) {
     const int cc = c0 + threadIdx.x;
-    const double db = sm[threadIdx.x];
     for (int k = 0; k < NS - 1; ++k) {
-      const double dg = sm[(1 + k) * 4 + threadIdx.x];
-      out.dbeta[k][cc] = accumulate ? (float)((double)out.dbeta[k][cc] + db) : (float)db;
-      out.dgamma[k][cc] = accumulate ? (float)((double)out.dgamma[k][cc] + dg) : (float)dg;
+      out.dbeta[k][cc] = accumulate ? (float)((double)out.dbeta[k][cc] + tsum[0]) : (float)tsum[0];
+      out.dgamma[k][cc] = accumulate ? (float)((double)out.dgamma[k][cc] + tsum[1 + k]) : (float)tsum[1 + k];
     }
-    for (int q = 0; q < NS; ++q) coef[q * C + cc] = (float)(sm[q * 4 + threadIdx.x] / n);
   }
 }
 
 // Stage-2 adjoint, apply pass: dT = gamma * invstd * (dM - k0 - that * k1); writes dT and dY.
 template <class T, int C>
-__global__ __launch_bounds__(256) void k_s2_bwd_apply(const T* __restrict__ Gd, const T* __restrict__ Tm,
-                                                      const uint8_t* __restrict__ mask,
-                                                      const float* __restrict__ a_sv, const float* __restrict__ coef_e,
-                                                      const float* __restrict__ coef, const float* __restrict__ stats,
-                                                      const float* __restrict__ gamma, const float* __restrict__ beta,
-                                                      T* __restrict__ dT, T* __restrict__ dY, int hw) {
+struct k_s2_bwd_apply_args {
+  const T* Gd;
+  const T* Tm;
+  const uint8_t* mask;
+  const float* a_sv;
+  const float* coef_e;
+  const float* coef;
+  const float* stats;
+  const float* gamma;
+  const float* beta;
+  T* dT;
+  T* dY;
+  int hw;
+  int tiles;
+};
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_s2_bwd_apply(SegL<k_s2_bwd_apply_args<T, C>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_bwd_apply_args<T, C>& a_ = L.a[sb.s];
+  const T* __restrict__ const Gd = a_.Gd;
+  const T* __restrict__ const Tm = a_.Tm;
+  const uint8_t* __restrict__ const mask = a_.mask;
+  const float* __restrict__ const a_sv = a_.a_sv;
+  const float* __restrict__ const coef_e = a_.coef_e;
+  const float* __restrict__ const coef = a_.coef;
+  const float* __restrict__ const stats = a_.stats;
+  const float* __restrict__ const gamma = a_.gamma;
+  const float* __restrict__ const beta = a_.beta;
+  T* __restrict__ const dT = a_.dT;
+  T* __restrict__ const dY = a_.dY;
+  const int hw = a_.hw;
+  const int tiles = a_.tiles;
   constexpr int G = C / 4;
-  const int b = blockIdx.y, tiles = gridDim.x;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, tile of the clip
   const int64_t items = (int64_t)hw * G, base = (int64_t)b * hw * C;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  int64_t i = (int64_t)tx * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float a4v[4], e4[4], mu[4], is[4], ga[4], be[4], k0[4], k1[4];
 #pragma unroll
@@ -202,10 +297,29 @@ __global__ __launch_bounds__(256) void k_s2_bwd_apply(const T* __restrict__ Gd, 
 // --------------------------------------------------------------------- input-module adjoint
 // dx[c](y, x) = sum_o sum_{ky,kx} dTp[o](y - ky + 1, x - kx + 1) w[o][c][ky][kx]; planar FP32.
 template <class T>
-__global__ __launch_bounds__(256) void k_stem_dx(const T* __restrict__ dTp, const float* __restrict__ w,
-                                                 float* __restrict__ dx, int B, int H, int W) {
+struct k_stem_dx_args {
+  const T* dTp;
+  const float* w;
+  float* dx;
+  int B;
+  int H;
+  int W;
+};
+template <class T>
+__global__ __launch_bounds__(256) void k_stem_dx(SegL<k_stem_dx_args<T>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_stem_dx_args<T>& a_ = L.a[sb.s];
+  const T* __restrict__ const dTp = a_.dTp;
+  const float* __restrict__ const w = a_.w;
+  float* __restrict__ const dx = a_.dx;
+  const int B = a_.B;
+  const int H = a_.H;
+  const int W = a_.W;
   const int64_t P = (int64_t)B * H * W;
-  for (int64_t p = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gridDim.x * STDA_BLOCK) {
+  for (int64_t p = (int64_t)bx * STDA_BLOCK + threadIdx.x; p < P; p += (int64_t)gx * STDA_BLOCK) {
     int b, y, x;
     pix3(p, H, W, b, y, x);
     float acc[3] = {0.f, 0.f, 0.f};

@@ -263,76 +263,94 @@ __global__ __launch_bounds__(256) void k_colsum2(ColJob a, ColJob b, int accumul
     colsum_block<16, 256>(b.part, b.nrows, b.ncols, nullptr, b.fout, b.map, accumulate, blockIdx.x - a.nblk);
 }
 
-// Batch statistics of BN layers from per-block partials.
-struct BnOut {
-  float* stats[3];
-  float* running[3];
+// Batch statistics of BN layers from per-block partials, for every segment of a launch.
+struct BnSegs {
+  int n;                        // segments, merged in this order
+  const float* part[kMaxSegs];  // the segment's partials (layout below)
+  int rows[kMaxSegs];           // its partial rows (workgroups of the statistics launch)
+  float* stats[kMaxSegs];       // its statistics buffer (running-buffer layout)
 };
-// Cross-block FP64 merge of batch-norm statistics partials fused with their finalize.
-// part[blk][NB][C][2] = (mean, m2) of the block's values per BN layer and channel, followed by
-// the blocks' counts cnt[blk] (floats) at part + nrows NB C 2.  In FP64, one pass in a fixed
-// order, about the first block's mean m0 (d_b = mean_b - m0): n = sum n_b, s = sum n_b d_b,
-// q = sum (m2_b + n_b d_b^2); mean = m0 + s / n, var = (q - s^2 / n) / n.  The block means lie
-// within a few standard deviations of each other, so nothing cancels beyond FP64's reach.
-// Writes stats_i = [mean C][invstd C]; updates the running buffer (momentum 0.1, unbiased
-// variance) when asked.  Block = 4 channels of one layer x 64 row groups.
-__global__ __launch_bounds__(256) void k_bn_stats_reduce(const float* __restrict__ part, int nrows, int NB, int C,
-                                                         BnOut out, int update_running) {
+struct BnLayers {
+  int64_t off[3];  // offsets of the NB layers in the statistics / running layout
+};
+// Cross-block FP64 merge of batch-norm statistics partials fused with their finalize, segment
+// by segment.  A segment's part[blk][NB][C][2] = (mean, m2) of the block's values per BN layer
+// and channel, followed by the blocks' counts cnt[blk] (floats) at part + rows NB C 2.  In FP64,
+// one pass in a fixed order, about the first block's mean m0 (d_b = mean_b - m0): n = sum n_b,
+// s = sum n_b d_b, q = sum (m2_b + n_b d_b^2); mean = m0 + s / n, var = (q - s^2 / n) / n.  The
+// block means lie within a few standard deviations of each other, so nothing cancels beyond
+// FP64's reach.  Writes the segment's stats = [mean C][invstd C] per layer; if `running` is not
+// null, applies one running-statistics update (momentum 0.1, unbiased variance) per segment, in
+// segment order.  Block = 4 channels of one layer x 64 row groups.
+__global__ __launch_bounds__(256) void k_bn_stats_reduce(BnSegs sg, int NB, int C, BnLayers L,
+                                                         float* __restrict__ running) {
   __shared__ double sm[64][4][3];
   const int cl = threadIdx.x & 3, rg = threadIdx.x >> 2;
   const int i = (blockIdx.x * 4) / C, c0 = (blockIdx.x * 4) % C;
   const int64_t ncols = (int64_t)NB * C * 2;
   const int64_t col = (int64_t)(i * C + c0 + cl) * 2;
-  const float* __restrict__ cnt = part + (int64_t)nrows * ncols;
-  const double m0 = (double)part[col];
-  double n = 0.0, s = 0.0, q = 0.0;
+  for (int sgi = 0; sgi < sg.n; ++sgi) {
+    const float* __restrict__ part = sg.part[sgi];
+    const int nrows = sg.rows[sgi];
+    const float* __restrict__ cnt = part + (int64_t)nrows * ncols;
+    const double m0 = (double)part[col];
+    double n = 0.0, s = 0.0, q = 0.0;
 #pragma unroll 4
-  for (int r = rg; r < nrows; r += 64) {
-    const double nb = (double)cnt[r];
-    const double d = (double)part[(int64_t)r * ncols + col] - m0;
-    n += nb;
-    s += nb * d;
-    q += (double)part[(int64_t)r * ncols + col + 1] + nb * d * d;
-  }
-  sm[rg][cl][0] = n;
-  sm[rg][cl][1] = s;
-  sm[rg][cl][2] = q;
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    const int c = c0 + threadIdx.x;
-    double nt = 0.0, st = 0.0, qt = 0.0;
-    for (int k = 0; k < 64; ++k) {
-      nt += sm[k][threadIdx.x][0];
-      st += sm[k][threadIdx.x][1];
-      qt += sm[k][threadIdx.x][2];
+    for (int r = rg; r < nrows; r += 64) {
+      const double nb = (double)cnt[r];
+      const double d = (double)part[(int64_t)r * ncols + col] - m0;
+      n += nb;
+      s += nb * d;
+      q += (double)part[(int64_t)r * ncols + col + 1] + nb * d * d;
     }
-    const double mu = nt > 0.0 ? m0 + st / nt : 0.0;
-    double var = nt > 0.0 ? (qt - st * st / nt) / nt : 0.0;
-    if (var < 0.0) var = 0.0;
-    out.stats[i][c] = (float)mu;
-    out.stats[i][C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
-    if (update_running) {
-      float* rn = out.running[i];
-      const double unb = nt > 1.0 ? var * nt / (nt - 1.0) : var;
-      rn[c] = (float)(0.9 * (double)rn[c] + 0.1 * mu);
-      rn[C + c] = (float)(0.9 * (double)rn[C + c] + 0.1 * unb);
+    sm[rg][cl][0] = n;
+    sm[rg][cl][1] = s;
+    sm[rg][cl][2] = q;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+      const int c = c0 + threadIdx.x;
+      double nt = 0.0, st = 0.0, qt = 0.0;
+      for (int k = 0; k < 64; ++k) {
+        nt += sm[k][threadIdx.x][0];
+        st += sm[k][threadIdx.x][1];
+        qt += sm[k][threadIdx.x][2];
+      }
+      const double mu = nt > 0.0 ? m0 + st / nt : 0.0;
+      double var = nt > 0.0 ? (qt - st * st / nt) / nt : 0.0;
+      if (var < 0.0) var = 0.0;
+      float* so = sg.stats[sgi] + L.off[i];
+      so[c] = (float)mu;
+      so[C + c] = (float)(1.0 / sqrt(var + (double)BN_EPS));
+      if (running) {
+        float* rn = running + L.off[i];
+        const double unb = nt > 1.0 ? var * nt / (nt - 1.0) : var;
+        rn[c] = (float)(0.9 * (double)rn[c] + 0.1 * mu);
+        rn[C + c] = (float)(0.9 * (double)rn[C + c] + 0.1 * unb);
+      }
     }
+    __syncthreads();  // sm is reused by the next segment
   }
 }
 
 // EVAL statistics: mean and 1/sqrt(var + eps) of every BN layer from the running buffer
-// (both buffers: per layer C means, then C variances / inverse standard deviations).
+// (both buffers: per layer C means, then C variances / inverse standard deviations), into the
+// statistics buffer of every segment.
 struct BnTable {
   int n;
   int off[24];
   int C[24];
+  int nseg;
+  float* stats[kMaxSegs];
 };
-__global__ void k_eval_stats(const float* __restrict__ running, float* __restrict__ stats, BnTable tab) {
-  for (int l = 0; l < tab.n; ++l) {
-    const int C = tab.C[l], off = tab.off[l];
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-      stats[off + c] = running[off + c];
-      stats[off + C + c] = 1.0f / sqrtf(running[off + C + c] + BN_EPS);
+__global__ void k_eval_stats(const float* __restrict__ running, BnTable tab) {
+  for (int sgi = 0; sgi < tab.nseg; ++sgi) {
+    float* __restrict__ stats = tab.stats[sgi];
+    for (int l = 0; l < tab.n; ++l) {
+      const int C = tab.C[l], off = tab.off[l];
+      for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        stats[off + c] = running[off + c];
+        stats[off + C + c] = 1.0f / sqrtf(running[off + C + c] + BN_EPS);
+      }
     }
   }
 }
@@ -384,21 +402,46 @@ template <int OP> struct OpGeo {
 
 // --------------------------------------------------------------- stage 2 apply + GAP
 // Y = ReLU(BN(T)) + R; per-(clip, tile) channel sums of Y for the ECA global average pool.
-// Grid (tiles, clips); gap[clip][tile][C].
+// Workgroups: clip-major (clip, tile) pairs of the segment, `tiles` per clip; gap[clip][tile][C].
 // The ReLU decision of every element is taken here, once, in FP32, and (TRAIN) stored as a
 // 4-bit mask per (pixel, channel group) byte for the adjoint.
 template <class T, int C>
-__global__ __launch_bounds__(256) void k_s2_apply(const T* __restrict__ Tm, const T* __restrict__ R, T* __restrict__ Y,
-                                                  uint8_t* __restrict__ mask, float* __restrict__ gap,
-                                                  const float* __restrict__ stats, const float* __restrict__ gamma,
-                                                  const float* __restrict__ beta, int hw) {
+struct k_s2_apply_args {
+  const T* Tm;
+  const T* R;
+  T* Y;
+  uint8_t* mask;
+  float* gap;
+  const float* stats;
+  const float* gamma;
+  const float* beta;
+  int hw;
+  int tiles;
+};
+template <class T, int C>
+__global__ __launch_bounds__(256) void k_s2_apply(SegL<k_s2_apply_args<T, C>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_apply_args<T, C>& a_ = L.a[sb.s];
+  const T* __restrict__ const Tm = a_.Tm;
+  const T* __restrict__ const R = a_.R;
+  T* __restrict__ const Y = a_.Y;
+  uint8_t* __restrict__ const mask = a_.mask;
+  float* __restrict__ const gap = a_.gap;
+  const float* __restrict__ const stats = a_.stats;
+  const float* __restrict__ const gamma = a_.gamma;
+  const float* __restrict__ const beta = a_.beta;
+  const int hw = a_.hw;
+  const int tiles = a_.tiles;
   constexpr int G = C / 4;
   __shared__ float sm[4 * STDA_BLOCK];
   __shared__ float red[C];
-  const int b = blockIdx.y, tiles = gridDim.x;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, tile of the clip
   const int64_t items = (int64_t)hw * G;
   const int64_t base = (int64_t)b * hw * C;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  int64_t i = (int64_t)tx * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   float sc[4], sh[4];
   bn_affine4(stats, gamma, beta, C, c0, sc, sh);
@@ -423,7 +466,7 @@ __global__ __launch_bounds__(256) void k_s2_apply(const T* __restrict__ Tm, cons
     for (int j = 0; j < 4; ++j) acc[0][j] += stored<T>(o[j]);  // the value as stored
   }
   block_chan_reduce<G, 1>(acc, sm, red);
-  for (int q = threadIdx.x; q < C; q += STDA_BLOCK) gap[((int64_t)b * tiles + blockIdx.x) * C + q] = red[q];
+  for (int q = threadIdx.x; q < C; q += STDA_BLOCK) gap[((int64_t)b * tiles + tx) * C + q] = red[q];
 }
 
 // ECA scale of one clip from its GAP partials (Sec. IV-C, Eq. (eca_process_equation)):
@@ -447,22 +490,47 @@ __device__ __forceinline__ void eca_scale_clip(const float* __restrict__ gap, in
 
 // Next block input Xn = a[clip][c] * Y (+ skip).  Tile 0 of each clip also saves g and a.
 template <class T, int C, bool SKIP>
-__global__ __launch_bounds__(256) void k_eca_next(const T* __restrict__ Y, const T* __restrict__ skip,
-                                                  T* __restrict__ Xn, const float* __restrict__ gap,
-                                                  const float* __restrict__ weca, float* __restrict__ g_out,
-                                                  float* __restrict__ a_out, int hw, int gap_tiles) {
+struct k_eca_next_args {
+  const T* Y;
+  const T* skip;
+  T* Xn;
+  const float* gap;
+  const float* weca;
+  float* g_out;
+  float* a_out;
+  int hw;
+  int gap_tiles;
+  int tiles;
+};
+template <class T, int C, bool SKIP>
+__global__ __launch_bounds__(256) void k_eca_next(SegL<k_eca_next_args<T, C, SKIP>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_eca_next_args<T, C, SKIP>& a_ = L.a[sb.s];
+  const T* __restrict__ const Y = a_.Y;
+  const T* __restrict__ const skip = a_.skip;
+  T* __restrict__ const Xn = a_.Xn;
+  const float* __restrict__ const gap = a_.gap;
+  const float* __restrict__ const weca = a_.weca;
+  float* __restrict__ const g_out = a_.g_out;
+  float* __restrict__ const a_out = a_.a_out;
+  const int hw = a_.hw;
+  const int gap_tiles = a_.gap_tiles;
+  const int tiles = a_.tiles;
   constexpr int G = C / 4;
   __shared__ float g_s[C], a_s[C];
-  const int b = blockIdx.y, tiles = gridDim.x;
+  const int b = bx / tiles, tx = bx - b * tiles;  // clip, tile of the clip
   eca_scale_clip<C>(gap + (int64_t)b * gap_tiles * C, gap_tiles, hw, weca, g_s, a_s);
-  if (blockIdx.x == 0)
+  if (tx == 0)
     for (int c = threadIdx.x; c < C; c += STDA_BLOCK) {
       g_out[b * C + c] = g_s[c];
       a_out[b * C + c] = a_s[c];
     }
   const int64_t items = (int64_t)hw * G;
   const int64_t base = (int64_t)b * hw * C;
-  int64_t i = (int64_t)blockIdx.x * STDA_BLOCK + threadIdx.x;
+  int64_t i = (int64_t)tx * STDA_BLOCK + threadIdx.x;
   const int c0 = (int)(i % G) * 4;
   for (; i < items; i += (int64_t)tiles * STDA_BLOCK) {
     const int64_t off = base + (i / G) * C + c0;

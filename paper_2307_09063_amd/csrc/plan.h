@@ -68,6 +68,8 @@ struct SegPlan {
   size_t s0;
   size_t zs;     // TRAIN with the sigmoid output: FP32 copy of z (in saved), else 0
   BlockActs blk[4];
+  size_t scr;     // byte offset of the segment's region in the full-resolution scratch (ws_R, ws_g)
+  int64_t clip0;  // clips of the segments before this one (per-clip scratch rows)
 };
 
 struct Plan {
@@ -77,10 +79,10 @@ struct Plan {
   size_t ws_wk, ws_dense, ws_R, ws_part, ws_sums, ws_gap, ws_eval_stats, ws_loss;
   size_t ws_g[kNumGradBufs];
   size_t ws_coef_e, ws_coef, ws_ecaw, ws_wpart, ws_frag;
-  size_t rec_T;                          // recompute scratch of the stage-2 main output
   int64_t dense_f[4][2], dense_d[4][2];  // element offsets inside ws_dense (main, residual)
   size_t ws_pwx;                         // depthwise 1x1 reading: diagonal C x C weights
   int64_t pwx_off[4];                    // element offsets inside ws_pwx per block
+  size_t part_cap, wpart_cap;            // floats of ws_part and ws_wpart
   size_t saved_bytes, ws_bytes;
 };
 

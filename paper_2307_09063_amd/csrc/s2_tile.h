@@ -66,9 +66,29 @@ __device__ __forceinline__ void s2_tile_origin(int64_t t, int nty, int ntx, int 
 }
 
 template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS, int WV = 4>
-__global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, const T* __restrict__ wfrag,
-                                                     T* __restrict__ dst, float* __restrict__ part, int B, int hd,
-                                                     int wd) {
+struct k_s2_tile_args {
+  const T* src;
+  const T* wfrag;
+  T* dst;
+  float* part;
+  int B;
+  int hd;
+  int wd;
+};
+template <class T, int OP, int K, int N, int NB, int TH, int TW, bool STATS, int WV = 4>
+__global__ __launch_bounds__(64 * WV) void k_s2_tile(SegL<k_s2_tile_args<T, OP, K, N, NB, TH, TW, STATS, WV>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_tile_args<T, OP, K, N, NB, TH, TW, STATS, WV>& a_ = L.a[sb.s];
+  const T* __restrict__ const src = a_.src;
+  const T* __restrict__ const wfrag = a_.wfrag;
+  T* __restrict__ const dst = a_.dst;
+  float* __restrict__ const part = a_.part;
+  const int B = a_.B;
+  const int hd = a_.hd;
+  const int wd = a_.wd;
   typedef S2Cfg<T, OP, K, N, NB, TH, TW, WV> C;
   constexpr int BLK = C::BLK;
   typedef typename FragT<T>::type F;
@@ -105,16 +125,16 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
   const int64_t ntiles = (int64_t)B * nty * ntx;
   // XCD-contiguous tile ranges (falls back to a plain stride when the grid is not a multiple of 8)
   int64_t t_begin, t_end, t_step;
-  if ((gridDim.x & 7) == 0) {
-    const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3, per = gridDim.x >> 3;
+  if ((gx & 7) == 0) {
+    const int xcd = bx & 7, l = bx >> 3, per = gx >> 3;
     const int64_t chunk = (ntiles + 7) / 8;
     t_begin = xcd * chunk + l;
     t_end = (xcd + 1) * chunk < ntiles ? (xcd + 1) * chunk : ntiles;
     t_step = per;
   } else {
-    t_begin = blockIdx.x;
+    t_begin = bx;
     t_end = ntiles;
-    t_step = gridDim.x;
+    t_step = gx;
   }
 
   // 2. source rectangle of tile t, HBM -> registers; the next tile's is loaded while this tile's
@@ -266,8 +286,8 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
     }
   }
   if (STATS) {
-    // part[blockIdx.x][n][2] = (mean, m2) (n = cb * NB + column), the block's count at
-    // part[gridDim.x * 2 N + blockIdx.x]: merge over the 4 lane groups, then the WV waves, in a
+    // part[bx][n][2] = (mean, m2) (n = cb * NB + column), the block's count at
+    // part[gx * 2 N + bx]: merge over the 4 lane groups, then the WV waves, in a
     // fixed order
     constexpr int ROW = 2 * NB + 1;
     static_assert(WV * ROW * 4 <= (int)sizeof(lds), "statistics scratch fits the tile buffer");
@@ -300,9 +320,9 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(const T* __restrict__ src, 
         chan_merge(na, ma, qa, nb, sm[wv * ROW + c], sm[wv * ROW + NB + c]);
         na += nb;
       }
-      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2] = ma;
-      part[((int64_t)blockIdx.x * N + cb * NB + c) * 2 + 1] = qa;
-      if (cb == 0 && c == 0) part[(int64_t)gridDim.x * 2 * N + blockIdx.x] = na;
+      part[((int64_t)bx * N + cb * NB + c) * 2] = ma;
+      part[((int64_t)bx * N + cb * NB + c) * 2 + 1] = qa;
+      if (cb == 0 && c == 0) part[(int64_t)gx * 2 * N + bx] = na;
     }
   }
 }
@@ -346,8 +366,27 @@ struct WgCfg {
 };
 
 template <class T, bool DEC, int CL, int CH, int TH, int TW>
-__global__ __launch_bounds__(256) void k_s2_wgrad(const T* __restrict__ lo, const T* __restrict__ hi,
-                                                  float* __restrict__ part, int B, int h, int w) {
+struct k_s2_wgrad_args {
+  const T* lo;
+  const T* hi;
+  float* part;
+  int B;
+  int h;
+  int w;
+};
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+__global__ __launch_bounds__(256) void k_s2_wgrad(SegL<k_s2_wgrad_args<T, DEC, CL, CH, TH, TW>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_wgrad_args<T, DEC, CL, CH, TH, TW>& a_ = L.a[sb.s];
+  const T* __restrict__ const lo = a_.lo;
+  const T* __restrict__ const hi = a_.hi;
+  float* __restrict__ const part = a_.part;
+  const int B = a_.B;
+  const int h = a_.h;
+  const int w = a_.w;
   typedef WgCfg<T, DEC, CL, CH, TH, TW> C;
   constexpr int KS = C::KS, PW_ = C::PW_, NTC = C::NTC, MTC = C::MTC, LP = C::LP, PXP = C::PXP, PY = C::PY;
   constexpr bool BF = sizeof(T) == 2;
@@ -367,16 +406,16 @@ __global__ __launch_bounds__(256) void k_s2_wgrad(const T* __restrict__ lo, cons
   const int nty = (h + TH - 1) / TH, ntx = (w + TW - 1) / TW;
   const int64_t ntiles = (int64_t)B * nty * ntx;
   int64_t t_begin, t_end, t_step;
-  if ((gridDim.x & 7) == 0) {
-    const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3, per = gridDim.x >> 3;
+  if ((gx & 7) == 0) {
+    const int xcd = bx & 7, l = bx >> 3, per = gx >> 3;
     const int64_t chunk = (ntiles + 7) / 8;
     t_begin = xcd * chunk + l;
     t_end = (xcd + 1) * chunk < ntiles ? (xcd + 1) * chunk : ntiles;
     t_step = per;
   } else {
-    t_begin = blockIdx.x;
+    t_begin = bx;
     t_end = ntiles;
-    t_step = gridDim.x;
+    t_step = gx;
   }
   for (int64_t t = t_begin; t < t_end; t += t_step) {
     int b, y0, x0;
@@ -457,7 +496,7 @@ __global__ __launch_bounds__(256) void k_s2_wgrad(const T* __restrict__ lo, cons
   }
   // lane (i, g) holds D[4g + r][i]: ch = 16 mt + 4g + r, cl = 16 j + i
   constexpr int NCOL = DEC ? C::TAPS * CH : CL;
-  float* out = part + (int64_t)blockIdx.x * C::TAPS * CH * CL;
+  float* out = part + (int64_t)bx * C::TAPS * CH * CL;
 #pragma unroll
   for (int u = 0; u < PW_; ++u) {
     const int q = wave + 4 * u;
@@ -534,8 +573,27 @@ __device__ __forceinline__ void wg_store4<bf16>(bf16* dst, const float v[4]) {
 }
 
 template <class T, bool DEC, int CL, int CH, int TH, int TW>
-__global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, const T* __restrict__ hi,
-                                                    float* __restrict__ part, int B, int h, int w) {
+struct k_s2_wgrad_v_args {
+  const T* lo;
+  const T* hi;
+  float* part;
+  int B;
+  int h;
+  int w;
+};
+template <class T, bool DEC, int CL, int CH, int TH, int TW>
+__global__ __launch_bounds__(256) void k_s2_wgrad_v(SegL<k_s2_wgrad_v_args<T, DEC, CL, CH, TH, TW>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s2_wgrad_v_args<T, DEC, CL, CH, TH, TW>& a_ = L.a[sb.s];
+  const T* __restrict__ const lo = a_.lo;
+  const T* __restrict__ const hi = a_.hi;
+  float* __restrict__ const part = a_.part;
+  const int B = a_.B;
+  const int h = a_.h;
+  const int w = a_.w;
   typedef WgVCfg<T, DEC, CL, CH, TH, TW> C;
   typedef typename WgVec<T>::type V;
   constexpr int KS = C::KS, PW_ = C::PW_, NTC = C::NTC, MTC = C::MTC, LP = C::LP, CS = C::CS, PY = C::PY;
@@ -555,16 +613,16 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
   const int nty = (h + TH - 1) / TH, ntx = (w + TW - 1) / TW;
   const int64_t ntiles = (int64_t)B * nty * ntx;
   int64_t t_begin, t_end, t_step;
-  if ((gridDim.x & 7) == 0) {
-    const int xcd = blockIdx.x & 7, l = blockIdx.x >> 3, per = gridDim.x >> 3;
+  if ((gx & 7) == 0) {
+    const int xcd = bx & 7, l = bx >> 3, per = gx >> 3;
     const int64_t chunk = (ntiles + 7) / 8;
     t_begin = xcd * chunk + l;
     t_end = (xcd + 1) * chunk < ntiles ? (xcd + 1) * chunk : ntiles;
     t_step = per;
   } else {
-    t_begin = blockIdx.x;
+    t_begin = bx;
     t_end = ntiles;
-    t_step = gridDim.x;
+    t_step = gx;
   }
   if constexpr (BF) {
     // BF16: the operands stay packed from HBM to the matrix core.  The staging units of the next
@@ -792,7 +850,7 @@ __global__ __launch_bounds__(256) void k_s2_wgrad_v(const T* __restrict__ lo, co
     }
   }
   constexpr int NCOL = DEC ? C::TAPS * CH : CL;
-  float* out = part + (int64_t)blockIdx.x * C::TAPS * CH * CL;
+  float* out = part + (int64_t)bx * C::TAPS * CH * CL;
 #pragma unroll
   for (int u = 0; u < PW_; ++u) {
     const int q = wave + 4 * u;

@@ -220,12 +220,36 @@ __device__ __forceinline__ void s1_dw_regs(const float* wd, int c0, float (&wr)[
 }
 
 // Forward.  MODE 0: per-block (mean, m2) of the three BN inputs, part[blk][3][C][2], and the
-// block's count at part[gridDim.x * 6 C + blk] (see block_chan_stats).  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)) and, if M1 is not null, the
+// block's count at part[blocks * 6 C + blk] (blocks = the segment's workgroups; see
+// block_chan_stats).  MODE 1: X1 = ReLU(BN_p(p) + BN_d(d) + BN_x(x)) and, if M1 is not null, the
 // ReLU decisions X1 > 0 as one bit per element (M1[pixel][C / 8], channel c at byte c / 8, bit
 // c % 8), which is all the adjoint needs of X1.
 template <class T, int C, bool DEC, int MODE>
-__global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __restrict__ X1, uint8_t* __restrict__ M1,
-                                                 float* __restrict__ part, S1Params prm, int B, int h, int w) {
+struct k_s1_tile_args {
+  const T* X;
+  T* X1;
+  uint8_t* M1;
+  float* part;
+  S1Params prm;
+  int B;
+  int h;
+  int w;
+};
+template <class T, int C, bool DEC, int MODE>
+__global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, MODE>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s1_tile_args<T, C, DEC, MODE>& a_ = L.a[sb.s];
+  const T* __restrict__ const X = a_.X;
+  T* __restrict__ const X1 = a_.X1;
+  uint8_t* __restrict__ const M1 = a_.M1;
+  float* __restrict__ const part = a_.part;
+  const S1Params& prm = a_.prm;
+  const int B = a_.B;
+  const int h = a_.h;
+  const int w = a_.w;
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
   constexpr int XN = (TH + 2) * RW, PN = TH * TW;  // pixels of the x tile (halo 1) and of the tile
@@ -255,21 +279,21 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
   // wave per SIMD, which pays (measured) only for the BF16 16-channel statistics pass.
   constexpr bool PIPE = MODE == 0 && C == 16 && sizeof(T) == 2;
   TileRegs<T, C, TH, TW, 1> nx;
-  if (PIPE && blockIdx.x < ntiles) {
+  if (PIPE && bx < ntiles) {
     int b, y0, x0;
-    tile_coords(blockIdx.x, h, w, TH, TW, b, y0, x0);
+    tile_coords(bx, h, w, TH, TW, b, y0, x0);
     nx.fetch(X, b, y0, x0, h, w);
   }
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     __syncthreads();
     if constexpr (PIPE) {
       nx.put(xt);
       __syncthreads();
-      if (tile + (int)gridDim.x < ntiles) {
+      if (tile + gx < ntiles) {
         int nb, ny0, nx0;
-        tile_coords(tile + gridDim.x, h, w, TH, TW, nb, ny0, nx0);
+        tile_coords(tile + gx, h, w, TH, TW, nb, ny0, nx0);
         nx.fetch(X, nb, ny0, nx0, h, w);
       }
     } else {
@@ -326,10 +350,10 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
   if (MODE == 0) {
     block_chan_stats<G, 3>(cnt, mn, q2, sm, red);
     for (int q = threadIdx.x; q < 3 * C; q += STDA_BLOCK) {
-      part[(int64_t)blockIdx.x * 6 * C + 2 * q] = red[q];               // mean of (branch q / C, channel q % C)
-      part[(int64_t)blockIdx.x * 6 * C + 2 * q + 1] = red[3 * C + q];   // m2
+      part[(int64_t)bx * 6 * C + 2 * q] = red[q];               // mean of (branch q / C, channel q % C)
+      part[(int64_t)bx * 6 * C + 2 * q + 1] = red[3 * C + q];   // m2
     }
-    if (threadIdx.x == 0) part[(int64_t)gridDim.x * 6 * C + blockIdx.x] = red[6 * C];
+    if (threadIdx.x == 0) part[(int64_t)gx * 6 * C + bx] = red[6 * C];
   }
 }
 
@@ -337,9 +361,31 @@ __global__ __launch_bounds__(256) void k_s1_tile(const T* __restrict__ X, T* __r
 // wrote); part[blk][4][C] = sum du, sum du*phat, sum du*dhat, sum du*xhat (branch outputs
 // recomputed from the tile).
 template <class T, int C, bool DEC>
-__global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__ X, const uint8_t* __restrict__ M1,
-                                                           const T* __restrict__ dX1, float* __restrict__ part,
-                                                           S1Params prm, int B, int h, int w) {
+struct k_s1_bwd_stats_tile_args {
+  const T* X;
+  const uint8_t* M1;
+  const T* dX1;
+  float* part;
+  S1Params prm;
+  int B;
+  int h;
+  int w;
+};
+template <class T, int C, bool DEC>
+__global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_tile_args<T, C, DEC>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s1_bwd_stats_tile_args<T, C, DEC>& a_ = L.a[sb.s];
+  const T* __restrict__ const X = a_.X;
+  const uint8_t* __restrict__ const M1 = a_.M1;
+  const T* __restrict__ const dX1 = a_.dX1;
+  float* __restrict__ const part = a_.part;
+  const S1Params& prm = a_.prm;
+  const int B = a_.B;
+  const int h = a_.h;
+  const int w = a_.w;
   typedef S1Geo<C> Gm;
   constexpr int TH = Gm::TH, TW = Gm::TW, G = Gm::G, RW = TW + 2;
   constexpr int XN = (TH + 2) * RW, PN = TH * TW;
@@ -369,12 +415,12 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
   // faster above 16 channels; at 16 it costs the kernel a wave per SIMD and time)
   constexpr bool PIPE = C > 16;
   TileRegs<T, C, TH, TW, 1> nx;
-  if (PIPE && blockIdx.x < ntiles) {
+  if (PIPE && bx < ntiles) {
     int b, y0, x0;
-    tile_coords(blockIdx.x, h, w, TH, TW, b, y0, x0);
+    tile_coords(bx, h, w, TH, TW, b, y0, x0);
     nx.fetch(X, b, y0, x0, h, w);
   }
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     // BF16 above 16 channels: x1 and dx1 of the thread's next item loaded one item ahead, in
@@ -401,9 +447,9 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     if constexpr (PIPE) {
       nx.put(xt);
       __syncthreads();
-      if (tile + (int)gridDim.x < ntiles) {
+      if (tile + gx < ntiles) {
         int nb, ny0, nx0;
-        tile_coords(tile + gridDim.x, h, w, TH, TW, nb, ny0, nx0);
+        tile_coords(tile + gx, h, w, TH, TW, nb, ny0, nx0);
         nx.fetch(X, nb, ny0, nx0, h, w);
       }
     } else {
@@ -454,7 +500,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
     }
   }
   block_chan_reduce_shfl<G, 4>(acc, sm, red);
-  for (int q = threadIdx.x; q < 4 * C; q += STDA_BLOCK) part[(int64_t)blockIdx.x * 4 * C + q] = red[q];
+  for (int q = threadIdx.x; q < 4 * C; q += STDA_BLOCK) part[(int64_t)bx * 4 * C + q] = red[q];
 }
 
 // Fused backward of stage 1.  With du = dX1 [X1 > 0] (decisions from the bit mask M1 of the
@@ -471,11 +517,41 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(const T* __restrict__
 // products (p = x Wp, dP Wp^T, x^T dP) run on the matrix cores, the last one accumulating in
 // registers across tiles.  Tiles are TH x TW pixels; MINW waves per SIMD bound the registers.
 template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW, bool LC = false>
-__global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict__ X, const uint8_t* __restrict__ M1,
-                                                         const T* __restrict__ dX1, const T* __restrict__ dXr,
-                                                         const T* __restrict__ skip, const float* __restrict__ coef,
-                                                         S1Params prm, T* __restrict__ dX, float* __restrict__ pwpart,
-                                                         float* __restrict__ dwpart, int B, int h, int w) {
+struct k_s1_bwd_fused_args {
+  const T* X;
+  const uint8_t* M1;
+  const T* dX1;
+  const T* dXr;
+  const T* skip;
+  const float* coef;
+  S1Params prm;
+  T* dX;
+  float* pwpart;
+  float* dwpart;
+  int B;
+  int h;
+  int w;
+};
+template <class T, int C, bool DEC, bool SKIP, int TH, int TW, int MINW, bool LC = false>
+__global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_args<T, C, DEC, SKIP, TH, TW, MINW, LC>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_s1_bwd_fused_args<T, C, DEC, SKIP, TH, TW, MINW, LC>& a_ = L.a[sb.s];
+  const T* __restrict__ const X = a_.X;
+  const uint8_t* __restrict__ const M1 = a_.M1;
+  const T* __restrict__ const dX1 = a_.dX1;
+  const T* __restrict__ const dXr = a_.dXr;
+  const T* __restrict__ const skip = a_.skip;
+  const float* __restrict__ const coef = a_.coef;
+  const S1Params& prm = a_.prm;
+  T* __restrict__ const dX = a_.dX;
+  float* __restrict__ const pwpart = a_.pwpart;
+  float* __restrict__ const dwpart = a_.dwpart;
+  const int B = a_.B;
+  const int h = a_.h;
+  const int w = a_.w;
   constexpr int G = C / 4, M = TH * TW;
   static_assert(M % 16 == 0, "matrix-core row tiles of 16 pixels");
   constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
@@ -539,7 +615,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   auto xpx = [&](int p) { return (p / TW + 2) * XW + p % TW + 2; };  // tile pixel -> x-tile LDS pixel
 
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     // the ReLU decisions and dx1 of the thread's next dD-phase item (zero off the map), one item
@@ -798,10 +874,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(const T* __restrict_
   for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) {
     const int t = q / C, c = q % C;
     const int tw = DEC ? 8 - t : t;
-    dwpart[(int64_t)blockIdx.x * 9 * C + tw * C + c] = red[q];
+    dwpart[(int64_t)bx * 9 * C + tw * C + c] = red[q];
   }
   // pointwise gradient tile (m0, n0): lane holds D[4 lg + r][li] -> (c = m0 + 4 lg + r, o = n0 + li)
-  float* pw = pwpart + (int64_t)blockIdx.x * C * C;
+  float* pw = pwpart + (int64_t)bx * C * C;
   if constexpr (NT == 1) {
     // the four waves' partial tiles, summed in wave order
     __syncthreads();  // the reduction scratch above is no longer read

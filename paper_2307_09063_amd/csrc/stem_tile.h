@@ -6,7 +6,7 @@
 // matrix cores, reading the im2col operand straight from the staged planes.  The pre-BN output
 // is never stored: every pass recomputes it.
 //   MODE 0  TRAIN statistics: part[blk][16][2] = (mean, m2) of the block's conv outputs and
-//           the block's count at part[gridDim.x * 32 + blk] (see block_chan_stats)
+//           the block's count at part[blocks * 32 + blk] (blocks = the segment's workgroups)
 //   MODE 1  s0 = ReLU(BN(conv)) with the given statistics
 //   MODE 2  adjoint statistics: dM = dS [S > 0]; part[blk][2][16] = sum dM, sum dM * that
 //   MODE 3  adjoint apply: dTp = gamma invstd (dM - k0 - that k1); weight gradient
@@ -27,8 +27,29 @@ struct StemArgs {
 };
 
 template <class T, int MODE>
-__global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restrict__ dS, const T* __restrict__ S,
-                                                   T* __restrict__ out, int B, int H, int W) {
+struct k_stem_tile_args {
+  StemArgs a;
+  const T* dS;
+  const T* S;
+  T* out;
+  int B;
+  int H;
+  int W;
+};
+template <class T, int MODE>
+__global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE>> L) {
+  const SegB sb = seg_block(L);
+  if (sb.x >= sb.gx) return;
+  const int bx = sb.x, gx = sb.gx;  // workgroup index and count within the segment
+  (void)gx;
+  const k_stem_tile_args<T, MODE>& a_ = L.a[sb.s];
+  const StemArgs& a = a_.a;
+  const T* __restrict__ const dS = a_.dS;
+  const T* __restrict__ const S = a_.S;
+  T* __restrict__ const out = a_.out;
+  const int B = a_.B;
+  const int H = a_.H;
+  const int W = a_.W;
   constexpr int TH = 8, TW = 32, M = TH * TW, C = 16, G = 4, PS = C + 4, XR = TH + 2, XC = TW + 2;
   __shared__ float xs[3 * XR * XC];
   __shared__ float wk[C * 28];
@@ -73,7 +94,7 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
   for (int s = 0; s < 7; ++s) koff[s] = koff_of(4 * s + lg);
   const int wo0 = koff_of(li), wo1 = koff_of(16 + li);  // weight gradient: columns li, 16 + li
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
     // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
@@ -209,13 +230,13 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
     block_chan_stats<G, 1>(cnt, mn, q2, sm, red);
     for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) {
       const int s = q / C, c = q % C;  // red: [mean 16][m2 16] -> part [16][2]
-      a.part[(int64_t)blockIdx.x * 2 * C + c * 2 + s] = red[q];
+      a.part[(int64_t)bx * 2 * C + c * 2 + s] = red[q];
     }
-    if (threadIdx.x == 0) a.part[(int64_t)gridDim.x * 2 * C + blockIdx.x] = red[2 * C];
+    if (threadIdx.x == 0) a.part[(int64_t)gx * 2 * C + bx] = red[2 * C];
   }
   if (MODE == 2) {
     block_chan_reduce_shfl<G, 2>(acc, sm, red);
-    for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) a.part[(int64_t)blockIdx.x * 2 * C + q] = red[q];  // [2][16]
+    for (int q = threadIdx.x; q < 2 * C; q += STDA_BLOCK) a.part[(int64_t)bx * 2 * C + q] = red[q];  // [2][16]
   }
   if (MODE == 3) {
     // lane holds D[4 lg + r][li] = dW[o = 4 lg + r][k = li (wacc0) | 16 + li (wacc1)]; the four
@@ -232,7 +253,7 @@ __global__ __launch_bounds__(256) void k_stem_tile(StemArgs a, const T* __restri
       const int hf = q / 256, o = (q / 16) % 16, ki = q % 16, kk = 16 * hf + ki;
       auto wv = [&](int w) { return tt[((w * 2 + hf) * 16 + o) * 16 + ki]; };
       const float v = ((wv(0) + wv(1)) + wv(2)) + wv(3);
-      if (kk < 27) a.part[(int64_t)blockIdx.x * 27 * C + kk * C + o] = v;
+      if (kk < 27) a.part[(int64_t)bx * 27 * C + kk * C + o] = v;
     }
   }
 }
