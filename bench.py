@@ -80,8 +80,8 @@ def kernel_work(tag, B, H, W, es):
 
 def stage2_layers(per_tag, groups, bf16):
     """Roofline of every stage-2 dense launch (the layers holding most of the arithmetic) from one
-    profiled step, {tag: {us, bound, frac}}; for a batch of several map sizes the work of every
-    segment's launch over the tag's summed time (us: mean per launch)."""
+    profiled step, {tag: {us, bound, frac}}; for a batch of several map sizes a launch covers every
+    segment (us: mean per launch)."""
     out = {}
     for t, (cnt, tms) in sorted(per_tag.items()):
         if t.split('.')[0] in ('dense_fwd_main', 'dense_fwd_res', 'dense_dgrad_main', 'dense_dgrad_res', 'wgrad_main',
@@ -97,11 +97,11 @@ def roofline(tag, avg_ms, B, H, W, dtype_bf16):
 
 
 def roofline_groups(tag, total_ms, launches, groups, dtype_bf16):
-    """Roofline of `launches` launches of the tagged kernel taking total_ms together, spread evenly
-    over the segments `groups` [(clips, H, W)] (one launch per segment per step): algorithmic work
-    of all of them over their total time, against the engine's peak or HBM, whichever binds."""
+    """Roofline of `launches` launches of the tagged kernel taking total_ms together, each over all
+    the segments `groups` [(clips, H, W)] (one launch walks the tiles of every segment): algorithmic
+    work of all of them over their total time, against the engine's peak or HBM, whichever binds."""
     es = 2 if dtype_bf16 else 4
-    per = launches / len(groups)
+    per = launches
     flops = nbytes = 0.0
     engine = None
     for B, H, W in groups:
@@ -377,8 +377,11 @@ def main():
             stda.profile_select('*')
             t2.step()
             torch.cuda.synchronize()
-            layers2 = stage2_layers(stda.profile_report(), gr, dn == 'bf16')
+            pt2 = stda.profile_report()
+            layers2 = stage2_layers(pt2, gr, dn == 'bf16')
             stda.profile_select(None)
+            dom2 = max(pt2, key=lambda t: pt2[t][1])
+            roof2 = roofline_groups(dom2, pt2[dom2][1], pt2[dom2][0], gr, dn == 'bf16')
             t2.capture()
             t2.timed(2, True)
             m2 = t2.timed(max(3, args.steps // 2), True)
@@ -386,7 +389,7 @@ def main():
             bf16_batches[other] = (sg, gr, xo, make_batch.metas, t2.w, t2.running)
             extra[other] = {'ms_per_step': round(m2, 4), 'clips_per_s': round(n2 / (m2 / 1e3), 1), 'dtype': dn,
                             'recompute': rec, 'segments': [list(g) for g in gr], 'tiles': tiles2,
-                            'roofline_stage2_layers': layers2}
+                            'roofline': roof2, 'roofline_stage2_layers': layers2}
             print(f'bench: {other}: {m2:.3f} ms/step ({n2 / (m2 / 1e3):.0f} clips/s)', file=sys.stderr, flush=True)
             t2.graph.close()
             del t2, yo
