@@ -42,7 +42,7 @@ typedef enum {
   STDA_E_SHAPE = -2,       /* H or W not a multiple of 4, below 8, or above 4096          */
   STDA_E_WORKSPACE = -3,   /* ws / saved smaller than the size query says                 */
   STDA_E_HIP = -4,         /* a HIP runtime call or launch failed                         */
-  STDA_E_NONFINITE = -5    /* reserved: a host-side reduction saw NaN / Inf               */
+  STDA_E_NONFINITE = -5    /* stda_autotune: a timed step's loss was NaN / Inf            */
 } stda_status;
 
 typedef enum { STDA_FP32 = 0, STDA_BF16 = 1 } stda_dtype;  /* activation / weight storage  */
@@ -337,7 +337,10 @@ int stda_get_grid_cap(void);
  * The per-variant times and the choice are written as text lines
  * "kind<TAB>block<TAB>ms_v0<TAB>ms_v1...<TAB>chosen" into host `report` (NUL-terminated,
  * truncated to cap; may be NULL) and the size needed into *needed (may be NULL).  Blocks the
- * host until the trials are done.  The per-kernel timing hook must be off.
+ * host until the trials are done.  The per-kernel timing hook must be off.  Returns
+ * STDA_E_NONFINITE (with the previous choice restored) when a variant's last timed step ends with
+ * a NaN / Inf loss.  The choice table is process-wide: other threads' calls may run during the
+ * trials with whichever variants are set at the time.
  */
 int stda_autotune(const stda_segment* segs /*host*/, int n_segs, const float* x, const float* y,
                   const float* w, float* running, float* z, double* loss_dev, float* dz, float* dw,
@@ -403,6 +406,18 @@ size_t rd_synth_workspace_size(int n_clips, int N, int M);
 int rd_synth(const rd_scene* scenes, int n_clips, int N, int M, uint32_t seed, float noise_sigma,
              int clip_base, float* x_out, float* clean_out, void* ws, size_t ws_bytes,
              hipStream_t stream);
+
+/*
+ * rd_synth with the scene table in HOST memory (n_clips rd_scene): the table is copied into the
+ * end of the workspace and the stream synchronized before the synthesis is enqueued, so the host
+ * array may be reused as soon as the call returns (not capturable into a graph).  ws must hold
+ * rd_synth_host_workspace_size(n_clips, N, M) bytes; outputs, statuses and the synthesis itself
+ * as rd_synth (the same results).
+ */
+size_t rd_synth_host_workspace_size(int n_clips, int N, int M);
+int rd_synth_host(const rd_scene* scenes_host, int n_clips, int N, int M, uint32_t seed,
+                  float noise_sigma, int clip_base, float* x_out, float* clean_out, void* ws,
+                  size_t ws_bytes, hipStream_t stream);
 
 #ifdef __cplusplus
 }

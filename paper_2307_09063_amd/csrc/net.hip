@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdio>
 #include <cstring>
@@ -584,11 +585,18 @@ int tiles_for(int64_t hw, int G) {
 // of the dense stage-2 layers (0..2 the LDS-tiled kernel with the tilings listed in
 // launch_s2_variant, 3 the register-gather kernel), 2 their weight gradient (tilings listed in
 // launch_wgrad), 3 the fused stage-1 adjoint (tilings listed in launch_s1b).  Set by
-// stda_tune_set (the autotuner); 0 by default.
+// stda_tune_set (the autotuner); 0 by default.  Atomic entries: a call that plans while another
+// thread tunes reads each entry whole (which tiling a launch gets is then up to the ordering).
 constexpr int kS2Variants = 4;
 constexpr int kTuneKinds = 4;
 constexpr double kTuneMargin = 0.03;
-int g_s2_variant[2][kTuneKinds][4] = {};
+std::atomic<int> g_s2_variant[2][kTuneKinds][4] = {};
+int tuned(int dtype_idx, int kind, int blk) {
+  return g_s2_variant[dtype_idx][kind][blk].load(std::memory_order_relaxed);
+}
+void set_tuned(int dtype_idx, int kind, int blk, int v) {
+  g_s2_variant[dtype_idx][kind][blk].store(v, std::memory_order_relaxed);
+}
 
 // Dense stride-2 layer on LDS tiles over every segment; with STATS, each segment's BN partials
 // go to a region of *pm.
@@ -677,7 +685,7 @@ template <class T, int OP, int K, int N, bool STATS>
 int launch_dense(const Ctx<T>& c, int blk, const std::string& tag, const DenseOps<T>& D, int64_t frag_off, Parts* pm) {
   const T* frag = c.template scr<T>(c.P->ws_frag) + frag_off;
   const bool dgrad = OP == OP_ENC_DGRAD || OP == OP_DEC_DGRAD;
-  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][dgrad ? 1 : 0][blk];
+  const int v = tuned(sizeof(T) == 2 ? 1 : 0, dgrad ? 1 : 0, blk);
   return launch_s2_variant<T, OP, K, N, STATS>(v, c, tag, D, frag, pm);
 }
 
@@ -1230,7 +1238,7 @@ int launch_wgrad_cfg(const Ctx<T>& c, const std::string& tag, const WgOps<T>& O,
 
 template <class T, bool DEC, int CIN, int COUT>
 int launch_wgrad(const Ctx<T>& c, int blk, const std::string& tag, const WgOps<T>& O, float* dst) {
-  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][2][blk];
+  const int v = tuned(sizeof(T) == 2 ? 1 : 0, 2, blk);
   constexpr int CL = DEC ? CIN : COUT, CH = DEC ? COUT : CIN;
   const ColMap map{DEC ? MAP_DEC_S2 : MAP_ENC_S2, CIN, COUT};
   constexpr bool SMALL = CL * CH <= 512;  // 16 x 32 channel pairs: larger tiles fit
@@ -1288,7 +1296,7 @@ int launch_s1b_cfg(const Ctx<T>& c, int blk, const S1bOps<T>* O, Parts& pw, Part
 
 template <class T, int C, bool DEC>
 int launch_s1b(const Ctx<T>& c, int blk, const S1bOps<T>* O, Parts& pw, Parts& dw) {
-  const int v = g_s2_variant[sizeof(T) == 2 ? 1 : 0][3][blk];
+  const int v = tuned(sizeof(T) == 2 ? 1 : 0, 3, blk);
 #define S1B(TH_, TW_, W_) launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, O, pw, dw)
   // LC: depthwise taps and BN-adjoint coefficients read from LDS, three waves per SIMD
 #define S1L(TH_, TW_) launch_s1b_cfg<T, C, DEC, TH_, TW_, 3, true>(c, blk, O, pw, dw)
@@ -1797,7 +1805,7 @@ int stda_tune_set(int kind, int dtype, int block, int variant) {
   if (kind < 0 || kind >= kTuneKinds || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
       variant < 0 || variant >= kS2Variants)
     return STDA_E_INVALID;
-  g_s2_variant[dtype][kind][block] = variant;
+  set_tuned(dtype, kind, block, variant);
   return STDA_OK;
 }
 
@@ -1805,7 +1813,7 @@ int stda_tune_get(int kind, int dtype, int block, int* variant) {
   if (kind < 0 || kind >= kTuneKinds || (dtype != STDA_FP32 && dtype != STDA_BF16) || block < 0 || block > 3 ||
       !variant)
     return STDA_E_INVALID;
-  *variant = g_s2_variant[dtype][kind][block];
+  *variant = tuned(dtype, kind, block);
   return STDA_OK;
 }
 
@@ -1830,11 +1838,16 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
     return r;
   };
   int saved_choice[kTuneKinds][4];
-  std::memcpy(saved_choice, g_s2_variant[dtype], sizeof(saved_choice));
+  for (int kind = 0; kind < kTuneKinds; ++kind)
+    for (int b = 0; b < 4; ++b) saved_choice[kind][b] = tuned(dtype, kind, b);
+  auto restore = [&]() {
+    for (int kind = 0; kind < kTuneKinds; ++kind)
+      for (int b = 0; b < 4; ++b) set_tuned(dtype, kind, b, saved_choice[kind][b]);
+  };
   double cost[kTuneKinds][4][kS2Variants] = {};
   for (int v = 0; v < kS2Variants; ++v) {
     for (int kind = 0; kind < kTuneKinds; ++kind)
-      for (int b = 0; b < 4; ++b) g_s2_variant[dtype][kind][b] = v;
+      for (int b = 0; b < 4; ++b) set_tuned(dtype, kind, b, v);
     int r = step();  // untimed
     if (!r) {
       stda_profile_select("*");
@@ -1842,7 +1855,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
     }
     if (r) {
       stda_profile_select(nullptr);
-      std::memcpy(g_s2_variant[dtype], saved_choice, sizeof(saved_choice));
+      restore();
       return r;
     }
     Prof& p = prof();
@@ -1856,7 +1869,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
         p.on = false;
         p.tag.clear();
         p.used = 0;
-        std::memcpy(g_s2_variant[dtype], saved_choice, sizeof(saved_choice));
+        restore();
         return STDA_E_HIP;
       }
       const std::string& t = p.evtag[i / 2];
@@ -1872,6 +1885,19 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
     p.on = false;
     p.tag.clear();
     p.used = 0;
+    // the loss of the last timed step: times measured on NaN / Inf values are not kept
+    double loss_h = 0.0;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&loss_h, loss_dev, sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      g_last_hip = (int)e;
+      restore();
+      return STDA_E_HIP;
+    }
+    if (!std::isfinite(loss_h)) {
+      restore();
+      return STDA_E_NONFINITE;
+    }
   }
   std::string out;
   char line[256];
@@ -1883,7 +1909,7 @@ int stda_autotune(const stda_segment* segs, int n_segs, const float* x, const fl
       for (int v = 1; v < kS2Variants; ++v)
         if (cost[kind][b][v] < cost[kind][b][best] && cost[kind][b][v] < (1.0 - kTuneMargin) * cost[kind][b][0])
           best = v;
-      g_s2_variant[dtype][kind][b] = best;
+      set_tuned(dtype, kind, b, best);
       int n = std::snprintf(line, sizeof(line), "%d\t%d", kind, b);
       for (int v = 0; v < kS2Variants; ++v)
         n += std::snprintf(line + n, sizeof(line) - n, "\t%.6f", cost[kind][b][v] / reps);

@@ -249,4 +249,24 @@ int rd_synth(const rd_scene* scenes, int n_clips, int N, int M, uint32_t seed, f
   return STDA_OK;
 }
 
+size_t rd_synth_host_workspace_size(int n_clips, int N, int M) {
+  const size_t base = rd_synth_workspace_size(n_clips, N, M);
+  if (base == 0) return 0;
+  return (base + 255) / 256 * 256 + (size_t)n_clips * sizeof(rd_scene);
+}
+
+int rd_synth_host(const rd_scene* scenes_host, int n_clips, int N, int M, uint32_t seed, float noise_sigma,
+                  int clip_base, float* x_out, float* clean_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!scenes_host || !x_out || !ws || n_clips < 1 || clip_base < 0) return STDA_E_INVALID;
+  if (N < 8 || M < 8 || N > RD_PTS || M > RD_PTS || (N & (N - 1)) || (M & (M - 1))) return STDA_E_SHAPE;
+  if (ws_bytes < rd_synth_host_workspace_size(n_clips, N, M)) return STDA_E_WORKSPACE;
+  const size_t base = (rd_synth_workspace_size(n_clips, N, M) + 255) / 256 * 256;
+  rd_scene* dev = reinterpret_cast<rd_scene*>(static_cast<char*>(ws) + base);
+  // the table is in the workspace, and the host array free to reuse, when this returns
+  if (hipMemcpyAsync(dev, scenes_host, (size_t)n_clips * sizeof(rd_scene), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return STDA_E_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return STDA_E_HIP;
+  return rd_synth(dev, n_clips, N, M, seed, noise_sigma, clip_base, x_out, clean_out, ws, base, stream);
+}
+
 }  // extern "C"

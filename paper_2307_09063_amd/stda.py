@@ -78,6 +78,8 @@ def _load():
         'stda_adamw_step': (I, [P, P, P, P, I64, P, P, P]),
         'rd_synth_workspace_size': (SZ, [I, I, I]),
         'rd_synth': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
+        'rd_synth_host_workspace_size': (SZ, [I, I, I]),
+        'rd_synth_host': (I, [P, I, I, I, U32, F, I, P, P, P, SZ, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -94,7 +96,8 @@ EXPORTS = ('stda_status_string', 'stda_last_hip_error', 'stda_param_count', 'std
            'stda_backward', 'stda_mse_loss', 'stda_sgd_step', 'stda_sinr', 'stda_train_step_graph_create',
            'stda_graph_launch', 'stda_graph_destroy', 'stda_forward_graph_create', 'stda_profile_select',
            'stda_profile_read', 'stda_profile_report', 'stda_set_grid_cap', 'stda_get_grid_cap', 'stda_tune_count', 'stda_tune_set', 'stda_tune_get',
-           'stda_autotune', 'stda_cfar', 'stda_evm', 'stda_adamw_step', 'rd_synth_workspace_size', 'rd_synth')
+           'stda_autotune', 'stda_cfar', 'stda_evm', 'stda_adamw_step', 'rd_synth_workspace_size', 'rd_synth',
+           'rd_synth_host_workspace_size', 'rd_synth_host')
 
 
 def _check(status, what):
@@ -488,6 +491,21 @@ def rd_synth(scenes_dev, n_clips, N, M, seed, noise_sigma, x_out, clean_out=None
         ws = alloc_bytes(rd_synth_workspace_size(n_clips, N, M), x_out.device)
     _check(_lib.rd_synth(_ptr(scenes_dev), n_clips, N, M, int(seed) & 0xFFFFFFFF, float(noise_sigma),
                          clip_base, _ptr(x_out), _ptr(clean_out), _ptr(ws), ws.numel(), _stream()), 'rd_synth')
+
+
+def rd_synth_host_workspace_size(n_clips, N, M):
+    return int(_lib.rd_synth_host_workspace_size(n_clips, N, M))
+
+
+def rd_synth_host(tab, N, M, seed, noise_sigma, x_out, clean_out=None, ws=None, clip_base=0):
+    """rd_synth from a host scene table (numpy array of the rd_scene layout), copied by the library."""
+    raw = np.ascontiguousarray(tab)
+    n = len(raw)
+    if ws is None:
+        ws = alloc_bytes(rd_synth_host_workspace_size(n, N, M), x_out.device)
+    _check(_lib.rd_synth_host(ctypes.c_void_p(raw.ctypes.data), n, N, M, int(seed) & 0xFFFFFFFF,
+                              float(noise_sigma), clip_base, _ptr(x_out), _ptr(clean_out), _ptr(ws), ws.numel(),
+                              _stream()), 'rd_synth_host')
 
 
 def upload_scenes(tab, device='cuda'):

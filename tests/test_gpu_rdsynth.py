@@ -44,6 +44,24 @@ def test_rd_synth_parity(case):
         assert np.all(got.reshape(-1, N * M).min(axis=1) >= 0.0)
 
 
+def test_rd_synth_host_table_equals_device_table():
+    """rd_synth_host (scene table in host memory, copied by the library) gives bit for bit what
+    rd_synth gives for the same table uploaded by the caller; the host array may change as soon as
+    the call returns."""
+    from paper_2307_09063_amd import stda
+    B, N, M = 3, 64, 32
+    print('rd_synth host table', file=sys.stderr, flush=True)
+    tab, meta = inputs.make_scenes(B, N, M, seed=11, targets=(1, 3), intf=(1, 2), clutter=True)
+    x_dev, c_dev = stda.synthesize(tab, meta)
+    x = torch.empty_like(x_dev)
+    c = torch.empty_like(c_dev)
+    host = tab.copy()
+    stda.rd_synth_host(host, N, M, meta['seed'], meta['noise_sigma'], x, c)
+    host[:] = np.zeros_like(host)  # the copy was taken before the call returned
+    torch.cuda.synchronize()
+    assert torch.equal(x, x_dev) and torch.equal(c, c_dev)
+
+
 def test_rd_synth_clip_base_and_chunks():
     """Synthesising clips 2..3 alone with clip_base = 2 reproduces them bit for bit."""
     from paper_2307_09063_amd import stda

@@ -111,6 +111,16 @@ def test_validation_before_launch(S):
     assert lib.rd_synth(fake, 1, 48, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -2
     assert lib.rd_synth(fake, 1, 64, 2048, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -2
     assert lib.rd_synth(fake, 1, 64, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, 16, None) == -3
+    # rd_synth_host: the same checks, the host table's room counted in its workspace size
+    lib.rd_synth_workspace_size.restype = ctypes.c_size_t
+    lib.rd_synth_host_workspace_size.restype = ctypes.c_size_t
+    from paper_2307_09063_amd import inputs
+    assert (lib.rd_synth_host_workspace_size(4, 64, 64)
+            >= lib.rd_synth_workspace_size(4, 64, 64) + 4 * inputs.SCENE_DTYPE.itemsize)
+    assert lib.rd_synth_host(None, 1, 64, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -1
+    assert lib.rd_synth_host(fake, 1, 48, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, big, None) == -2
+    need = lib.rd_synth_host_workspace_size(1, 64, 64)
+    assert lib.rd_synth_host(fake, 1, 64, 64, 1, ctypes.c_float(1.0), 0, fake, None, fake, need - 1, None) == -3
     assert lib.stda_status_string(-2).decode().startswith('unsupported shape')
     # CA-CFAR / EVM argument checks
     d = ctypes.c_double
