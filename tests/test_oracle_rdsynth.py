@@ -1,7 +1,7 @@
 """Pins of the oracle RD-map synthesizer and metrics: Philox known answers, Box-Muller moments,
 Parseval, closed-form Hann tone spectra, brute-force DFT, analytic peak positions and their motion
-over the three frames, the ghost case of identical chirps, the IF gate, and the SINR / EVM closed
-forms.  CPU only."""
+over the three frames, the physical beat frequency of a converted aggressor record, the ghost case
+of identical chirps, the IF gate, and the SINR / EVM closed forms.  CPU only."""
 import json
 import os
 
@@ -288,3 +288,54 @@ def test_table4_draws_and_amplitude():
         assert abs(amp ** 2 - p_sig / 10 ** (a['sir_db'] / 10)) <= 1e-6 * amp ** 2
         e = tab[b]['intf'][0, 0]
         assert e['coherent'] == 1 and abs(e['wrap'] / 2 ** 32 - a['bandwidth'] / inputs.F_S) < 1e-8
+
+
+def test_aggressor_record_matches_the_physical_beat_frequency():
+    """The interferer record built from an aggressor's physical parameters (carrier, sweep
+    bandwidth and duration, radial velocity, ramp timing; Sec. III-A's beat of the aggressor ramp
+    against the victim ramp) against the beat frequency evaluated from first principles: at victim
+    sample n of chirp m (time m T_chirp + n / f_s) the aggressor sits at f_c,i + f_D + S_i ((t -
+    t_off) mod T_i), the victim at f_c + S_v n / f_s, S_v = B f_s / N, f_D = -v f_c,i / c.  Checked
+    (1) on the record's integer fields as the synthesizer reads them (2 q n + f0 + (s0 + m dl) mod
+    wrap), and (2) on the oracle's synthesized interference itself, whose phase advances between
+    samples n and n + 1 by the physical beat at n + 1/2; wherever the aggressor ramp does not
+    restart inside the chirp."""
+    rng = np.random.default_rng(21)
+    N, M = 256, 16
+    checked = recs = 0
+    for trial in range(6):
+        fc_i = inputs.FC_VICTIM + rng.uniform(-1.5e6, 1.5e6)
+        t_i = rng.uniform(30e-6, 60e-6)          # longer than a chirp: at most one restart in it
+        b_i = rng.uniform(0.8, 1.2) * inputs.B_VICTIM * inputs.F_S / N * t_i   # slope near the victim's
+        v = rng.uniform(-23.0, 23.0)
+        t_off = rng.uniform(0.0, t_i)
+        tab, meta = inputs.make_scenes(1, N, M, seed=40 + trial, targets=(1, 1), intf=(0, 0))
+        for f in range(3):
+            tab[0]['n_tones'][f] = 0
+            tab[0]['n_intf'][f] = 1
+            inputs.aggressor_record(tab[0]['intf'][f, 0], N, fc_i, b_i, t_i, v, t_off, rng.random(), 1.0)
+        e = tab[0]['intf'][0, 0]
+        q, f0, dl, s0, wrap = (int(e[k]) for k in ('q', 'f0', 'dl', 's0', 'wrap'))
+        n = np.arange(N)
+        s_v = inputs.B_VICTIM * inputs.F_S / N
+        f_d = -v * fc_i / inputs.C_LIGHT
+        sc = inputs.scene_dict(tab, meta)
+        sc['noise_sigma'] = 0.0
+        s = R.beat_signal(sc, 0, 0)
+        for m in range(M):
+            tm = m * inputs.T_CHIRP + n / inputs.F_S
+            ramp = (tm - t_off) % t_i
+            beat = (fc_i + f_d + b_i / t_i * ramp - inputs.FC_VICTIM - s_v * n / inputs.F_S) / inputs.F_S
+            no_restart = ((m * inputs.T_CHIRP - t_off) % t_i) + n / inputs.F_S < t_i
+            rec = (2 * q * n + f0 + (s0 + m * dl) % wrap) / 2.0 ** 32
+            assert np.abs(rec - beat)[no_restart].max() < 1e-6, (trial, m)
+            recs += int(no_restart.sum())
+            # the synthesized signal: phase step between n and n + 1 = beat at n + 1/2 (mod 1)
+            mid = (beat[:-1] + beat[1:]) / 2
+            ok = no_restart[:-1] & no_restart[1:] & (np.abs(rec[:-1]) < 0.5) & (np.abs(rec[1:]) < 0.5)
+            with np.errstate(divide='ignore', invalid='ignore'):
+                step = np.angle(s[1:, m] / s[:-1, m]) / (2 * np.pi)
+            d = (step - mid + 0.5) % 1.0 - 0.5
+            assert np.abs(d[ok]).max() < 1e-6 if ok.any() else True, (trial, m)
+            checked += int(ok.sum())
+    assert recs > 5000 and checked > 100, (recs, checked)
