@@ -104,8 +104,10 @@ int stda_get_arch(void);
 
 /*
  * Byte sizes of `saved` (kept from a TRAIN forward to its backward) and `ws` (scratch of a
- * single call; one size serves forward, backward and loss).  `recompute` != 0 keeps only the
- * block-boundary checkpoints in `saved` and recomputes block internals during the backward.
+ * single call; one size serves forward, backward and loss).  `recompute` != 0 keeps the
+ * block-boundary checkpoints and each block's output before ECA (with its stage-2 ReLU decisions)
+ * in `saved` and recomputes the other block internals (stage-1 output, stage-2 pre-BN) during the
+ * backward.
  */
 int stda_workspace_size(const stda_segment* segs /*host*/, int n_segs, int dtype, int mode,
                         int recompute, size_t* saved_bytes /*host out*/,

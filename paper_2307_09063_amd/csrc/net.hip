@@ -430,7 +430,7 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
     S.s0 = acts.take(es * 16 * n * HW);
     S.zs = sigmoid_save ? sv.take(sizeof(float) * n * HW) : 0;
     // recompute: one scratch set of block internals in ws per segment, shared by its blocks
-    size_t rx1 = 0, rty = 0, rt = 0, rmask = 0, rm1 = 0;
+    size_t rx1 = 0, rt = 0, rm1 = 0;
     if (rec) {
       size_t mx1 = 0, mty = 0;
       for (int k = 0; k < 4; ++k) {
@@ -441,8 +441,6 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
       rx1 = ws.take(es * mx1);
       rm1 = ws.take(mx1 / 8);
       rt = ws.take(es * mty);
-      rty = ws.take(es * mty);
-      rmask = ws.take(mty / 4);
     }
     for (int k = 0; k < 4; ++k) {
       const BlockCfg& b = kBlocks[k];
@@ -452,16 +450,16 @@ void build_plan(const stda_segment* segs, int n_segs, int dtype, int mode, int r
       if (rec) {
         A.X1 = rx1;
         A.T = rt;
-        A.Y = rty;
-        A.mask = rmask;
         A.m1 = rm1;
       } else {
         A.X1 = acts.take(es * b.cin * n * hin * win);
         A.T = acts.take(es * b.cout * n * hout * wout);
-        A.Y = acts.take(es * b.cout * n * hout * wout);
-        A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
         A.m1 = train ? acts.take((size_t)b.cin * n * hin * win / 8) : 0;
       }
+      // the block output before ECA and the stage-2 ReLU decisions are kept in both modes: the
+      // recompute rebuilds the rest of the block (x1, its decisions, t) from the block input
+      A.Y = acts.take(es * b.cout * n * hout * wout);
+      A.mask = train ? acts.take((size_t)b.cout * n * hout * wout / 4) : 0;
       A.Xn = acts.take(es * b.cout * n * hout * wout);
       A.a = acts.take(sizeof(float) * b.cout * n);
       A.g = acts.take(sizeof(float) * b.cout * n);
@@ -750,10 +748,10 @@ BlockView<T> block_view(const Ctx<T>& c, int s, int k) {
   v.X = k == 0 ? c.template act<T>(S.s0) : c.template act<T>(S.blk[k - 1].Xn);
   v.X1 = c.template inner<T>(A, A.X1);
   v.Tm = c.template inner<T>(A, A.T);
-  v.Y = c.template inner<T>(A, A.Y);
+  v.Y = c.template act<T>(A.Y);
   v.Xn = c.template act<T>(A.Xn);
   v.m1 = c.train ? c.template inner<uint8_t>(A, A.m1) : nullptr;
-  v.mask = c.train ? c.template inner<uint8_t>(A, A.mask) : nullptr;
+  v.mask = c.train ? c.template act<uint8_t>(A.mask) : nullptr;
   v.a = c.template act<float>(A.a);
   v.g = c.template act<float>(A.g);
   v.skip = k == 2 ? c.template act<T>(S.blk[0].Xn) : (k == 3 ? c.template act<T>(S.s0) : nullptr);
@@ -841,6 +839,9 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
     if (int r = launch_dense<T, OPF, CIN, COUT, false>(c, k, tagk("dense_fwd_main", k), dm, c.P->dense_f[k][0], nullptr))
       return r;
   }
+  // recompute: x1, its decisions and t are rebuilt; the block output y, its ReLU decisions and
+  // everything after them were kept from the forward
+  if (c.rec_pass) return STDA_OK;
   bool res_done = false;
   if constexpr (DEC) {
     if (c.P->arch & STDA_ARCH_RES3) {
@@ -867,7 +868,6 @@ int fwd_block(const Ctx<T>& c, int k, float* running) {
     }
     KLAUNCH(tagk("s2_apply", k), k_s2_apply<T, COUT><<<b.blocks(), 256, 0, c.st>>>(b.L));
   }
-  if (c.rec_pass) return STDA_OK;  // the block output is a saved checkpoint
   if (k >= 2) return launch_eca_next<T, COUT, true>(c, k, v, gaps, gtiles, c.w + bo.eca_w);
   return launch_eca_next<T, COUT, false>(c, k, v, gaps, gtiles, c.w + bo.eca_w);
 }
@@ -1477,7 +1477,8 @@ int backward_net(const Ctx<T>& c, const float* dz, const float* x, float* dw, fl
     if (int e = colsum_to(c, pm.base, pm.total_rows(), 10 * 16, dw + no.head_w, ColMap{MAP_HEAD, 0, 0}, 0)) return e;
   }
   // decoder 1 (input d0, output d1 = ECA + s0), decoder 0 (input e1, output d0 = ECA + e0)
-  // recompute mode: re-run a block's forward (saved statistics, no ECA) right before its adjoint
+  // recompute mode: rebuild a block's x1, its decisions and t (saved statistics) right before its
+  // adjoint
   Ctx<T> rc = c;
   rc.rec_pass = true;
   const bool rec = c.S(0).blk[0].inner_in_ws;

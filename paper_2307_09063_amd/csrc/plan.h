@@ -59,7 +59,7 @@ const NetOffsets& net_offsets(int arch);
 struct BlockActs {
   size_t X1, T, Y, Xn, a, g, mask;  // mask: stage-2 ReLU decisions, 4 bits per byte
   size_t m1;                        // stage-1 ReLU decisions (X1 > 0), 1 bit per element
-  bool inner_in_ws;                 // X1, T, Y, mask, m1 live in ws (recomputed in the backward)
+  bool inner_in_ws;                 // X1, T, m1 live in ws (recomputed in the backward)
 };
 struct SegPlan {
   int n, H, W;
