@@ -720,7 +720,7 @@ int bn_finalize(const Ctx<T>& c, const Parts& pm, int NB, int C, const int64_t* 
   }
   BnLayers L{};
   for (int i = 0; i < NB; ++i) L.off[i] = bn_off[i];
-  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C / 4, 256, 0, c.st>>>(sg, NB, C, L, running));
+  KLAUNCH("bn_finalize", k_bn_stats_reduce<<<NB * C, 256, 0, c.st>>>(sg, NB, C, L, running));
   return STDA_OK;
 }
 
@@ -1326,7 +1326,7 @@ int bn_bwd(const Ctx<T>& c, const Parts& pm, int NS, int C, const double* count,
     o.dgamma[k] = dg[k];
     o.dbeta[k] = db[k];
   }
-  KLAUNCH("bn_bwd_finalize", k_bn_bwd_reduce<<<C / 4, 256, 0, c.st>>>(sg, NS, C, o, 0));
+  KLAUNCH("bn_bwd_finalize", k_bn_bwd_reduce<<<NS * C, 256, 0, c.st>>>(sg, NS, C, o, 0));
   return STDA_OK;
 }
 

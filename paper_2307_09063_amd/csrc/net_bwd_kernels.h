@@ -185,39 +185,36 @@ struct BnBwdSegs {
 // Cross-block FP64 reduction of BN adjoint partials fused with the finalize: per segment the
 // column sums give that segment's coefficients (its layers have their own statistics); the
 // gamma and beta gradients are the sums over all segments, taken in FP64 and rounded once.
-// Block = 4 channels (4 NS columns) x 64 / NS row groups.
+// Block = one (sum q, channel c) column, blockIdx.x = q C + c; its 256 threads take every 256th
+// row, added in a fixed tree order.  Column q = 0 (the beta gradient, shared by the NS - 1 layers)
+// writes dbeta, q >= 1 writes dgamma[q - 1].
 __global__ __launch_bounds__(256) void k_bn_bwd_reduce(BnBwdSegs sg, int NS, int C, BnBwdOut out, int accumulate) {
-  __shared__ double sm[256];
-  const int cols = 4 * NS, groups = 256 / cols;
-  const int col = threadIdx.x % cols, rg = threadIdx.x / cols;
-  const int c0 = blockIdx.x * 4;
-  const int s = col / 4, c = c0 + col % 4;
-  double tsum[4] = {0.0, 0.0, 0.0, 0.0};  // threads < 4: beta, then gamma gradients over segments
+  __shared__ double sm[STDA_BLOCK];
+  const int q = blockIdx.x / C, c = blockIdx.x % C;
+  double tot = 0.0;
   for (int sgi = 0; sgi < sg.n; ++sgi) {
-    const double acc = rg < groups ? strided_sum(sg.part[sgi], rg, groups, sg.rows[sgi], (int64_t)NS * C, s * C + c)
-                                   : 0.0;
-    sm[threadIdx.x] = acc;
+    const float* __restrict__ part = sg.part[sgi];
+    double a = 0.0;
+#pragma unroll 4
+    for (int r = threadIdx.x; r < sg.rows[sgi]; r += STDA_BLOCK) a += (double)part[(int64_t)r * NS * C + q * C + c];
+    sm[threadIdx.x] = a;
     __syncthreads();
-    if (threadIdx.x < cols) {
-      double tot = 0.0;
-      for (int k = 0; k < groups; ++k) tot += sm[k * cols + threadIdx.x];
-      sm[threadIdx.x] = tot;  // each slot is read only by the thread that owns it
+#pragma unroll
+    for (int half = STDA_BLOCK / 2; half > 0; half >>= 1) {
+      if ((int)threadIdx.x < half) sm[threadIdx.x] += sm[threadIdx.x + half];
+      __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-      const int cc = c0 + threadIdx.x;
-      for (int q = 0; q < NS; ++q) {
-        tsum[q] += sm[q * 4 + threadIdx.x];
-        sg.coef[sgi][q * C + cc] = (float)(sm[q * 4 + threadIdx.x] / sg.count[sgi]);
-      }
+    if (threadIdx.x == 0) {
+      tot += sm[0];
+      sg.coef[sgi][q * C + c] = (float)(sm[0] / sg.count[sgi]);
     }
     __syncthreads();  // sm is reused by the next segment
   }
-  if (threadIdx.x < 4) {
-    const int cc = c0 + threadIdx.x;
-    for (int k = 0; k < NS - 1; ++k) {
-      out.dbeta[k][cc] = accumulate ? (float)((double)out.dbeta[k][cc] + tsum[0]) : (float)tsum[0];
-      out.dgamma[k][cc] = accumulate ? (float)((double)out.dgamma[k][cc] + tsum[1 + k]) : (float)tsum[1 + k];
+  if (threadIdx.x == 0) {
+    if (q == 0) {
+      for (int k = 0; k < NS - 1; ++k) out.dbeta[k][c] = accumulate ? (float)((double)out.dbeta[k][c] + tot) : (float)tot;
+    } else {
+      out.dgamma[q - 1][c] = accumulate ? (float)((double)out.dgamma[q - 1][c] + tot) : (float)tot;
     }
   }
 }

@@ -281,14 +281,23 @@ struct BnLayers {
 // block means lie within a few standard deviations of each other, so nothing cancels beyond
 // FP64's reach.  Writes the segment's stats = [mean C][invstd C] per layer; if `running` is not
 // null, applies one running-statistics update (momentum 0.1, unbiased variance) per segment, in
-// segment order.  Block = 4 channels of one layer x 64 row groups.
+// segment order.  Block = one channel of one layer; its 256 threads take every 256th row and
+// their (n, s, q) are added in a fixed tree order.
+__device__ __forceinline__ void tree3(double (*sm)[3]) {
+#pragma unroll
+  for (int half = STDA_BLOCK / 2; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sm[threadIdx.x][k] += sm[threadIdx.x + half][k];
+    __syncthreads();
+  }
+}
 __global__ __launch_bounds__(256) void k_bn_stats_reduce(BnSegs sg, int NB, int C, BnLayers L,
                                                          float* __restrict__ running) {
-  __shared__ double sm[64][4][3];
-  const int cl = threadIdx.x & 3, rg = threadIdx.x >> 2;
-  const int i = (blockIdx.x * 4) / C, c0 = (blockIdx.x * 4) % C;
+  __shared__ double sm[STDA_BLOCK][3];
+  const int i = blockIdx.x / C, c = blockIdx.x % C;
   const int64_t ncols = (int64_t)NB * C * 2;
-  const int64_t col = (int64_t)(i * C + c0 + cl) * 2;
+  const int64_t col = (int64_t)(i * C + c) * 2;
   for (int sgi = 0; sgi < sg.n; ++sgi) {
     const float* __restrict__ part = sg.part[sgi];
     const int nrows = sg.rows[sgi];
@@ -296,25 +305,20 @@ __global__ __launch_bounds__(256) void k_bn_stats_reduce(BnSegs sg, int NB, int 
     const double m0 = (double)part[col];
     double n = 0.0, s = 0.0, q = 0.0;
 #pragma unroll 4
-    for (int r = rg; r < nrows; r += 64) {
+    for (int r = threadIdx.x; r < nrows; r += STDA_BLOCK) {
       const double nb = (double)cnt[r];
       const double d = (double)part[(int64_t)r * ncols + col] - m0;
       n += nb;
       s += nb * d;
       q += (double)part[(int64_t)r * ncols + col + 1] + nb * d * d;
     }
-    sm[rg][cl][0] = n;
-    sm[rg][cl][1] = s;
-    sm[rg][cl][2] = q;
+    sm[threadIdx.x][0] = n;
+    sm[threadIdx.x][1] = s;
+    sm[threadIdx.x][2] = q;
     __syncthreads();
-    if (threadIdx.x < 4) {
-      const int c = c0 + threadIdx.x;
-      double nt = 0.0, st = 0.0, qt = 0.0;
-      for (int k = 0; k < 64; ++k) {
-        nt += sm[k][threadIdx.x][0];
-        st += sm[k][threadIdx.x][1];
-        qt += sm[k][threadIdx.x][2];
-      }
+    tree3(sm);
+    if (threadIdx.x == 0) {
+      const double nt = sm[0][0], st = sm[0][1], qt = sm[0][2];
       const double mu = nt > 0.0 ? m0 + st / nt : 0.0;
       double var = nt > 0.0 ? (qt - st * st / nt) / nt : 0.0;
       if (var < 0.0) var = 0.0;
