@@ -119,6 +119,30 @@ def test_packed_eval_and_folded_equal_per_size(dtype):
         np.testing.assert_array_equal(z, zr)
 
 
+def test_eight_small_segments_equal_per_size():
+    """The most segments a launch takes (8), of small and ragged sizes whose grids are not
+    multiples of 8 (so later segments start after idle workgroup slots): a TRAIN step against the
+    sizes run one at a time, as above."""
+    from paper_2307_09063_amd import stda as S
+    parts = [(1, 8, 8), (2, 12, 16), (1, 16, 8), (1, 20, 28), (2, 8, 32), (1, 36, 12), (1, 24, 24), (1, 16, 40)]
+    _say('multiseg 8 segments')
+    xs, ys = zip(*(U.maps(n, H, W, seed=3 * n + H + 5 * W) for n, H, W in parts))
+    w, r = U.weights(), U.running()
+    zs, dwr, dxs, run = [], np.zeros(net.param_count()), [], r.copy()
+    for (n, H, W), x, y in zip(parts, xs, ys):
+        z, run, dw, dx, _ = _train(S, S.uniform_segments(n, H, W), x, y, w, run, S.FP32, 0)
+        zs.append(z)
+        dwr += dw
+        dxs.append(dx)
+    z, rp, dw, dx, _ = _train(S, S.packed_segments(parts), np.concatenate([a.ravel() for a in xs]),
+                              np.concatenate([a.ravel() for a in ys]), w, r, S.FP32, 0)
+    np.testing.assert_array_equal(z, np.concatenate(zs))
+    np.testing.assert_array_equal(rp, run)
+    np.testing.assert_array_equal(dx, np.concatenate(dxs))
+    bad = U.grad_failures(dw, dwr, 1e-6, elem=1e-5)
+    assert not bad, bad
+
+
 def test_packed_launch_count_equals_one_size():
     """The packed three-size step issues as many launches as a step on one size."""
     from paper_2307_09063_amd import stda as S
