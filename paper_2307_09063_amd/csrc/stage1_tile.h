@@ -59,6 +59,14 @@ template <int C, int NPIX>
 __device__ __forceinline__ int s1e(int px, int c) {
   return s1c<C, NPIX>(px, c >> 2) + (c & 3);
 }
+// Channels 4q .. 4q + 3 of pixel px0 + dpx of a tile: in the planar layouts a pixel step is a
+// fixed float offset, so a neighbourhood is one base address plus constant offsets (immediate
+// offsets of the LDS reads); the swizzled layout computes each address.
+template <int C, int NPIX>
+__device__ __forceinline__ float4 s1_nbr(const float* lds, int px0, int q, int dpx) {
+  if constexpr (S1Lds<C, NPIX>::SWZ) return *reinterpret_cast<const float4*>(lds + s1c<C, NPIX>(px0 + dpx, q));
+  else return *reinterpret_cast<const float4*>(lds + s1c<C, NPIX>(px0, q) + 4 * dpx);
+}
 
 // Rows y0-HALO .. y0+TH+HALO-1 and columns x0-HALO .. x0+TW+HALO-1 of clip b -> lds, pixel
 // (row, col) of the haloed tile at LDS pixel row * (TW + 2 HALO) + col.
@@ -175,34 +183,19 @@ __device__ __forceinline__ void lds_gemm(AF A, BF B, float* Cm, int ldc) {
   }
 }
 
-// Depthwise branch (4 channels) of the pixel at padded LDS position (r, c).
-template <int C, int NPIX>
-// wr: this thread's 4 channels of the 9 taps, held in registers.
-__device__ __forceinline__ void s1_dw_lds(const float* xt, int RW, int r, int c, int c0, const float (&wr)[9][4],
-                                          float dv[4]) {
+// Depthwise branch (4 channels) of the pixel at padded LDS position (r, c) of a tile with rows of RW
+// pixels.  wr: this thread's 4 channels of the 9 taps, held in registers.
+template <int C, int NPIX, int RW>
+__device__ __forceinline__ void s1_dw_lds(const float* xt, int r, int c, int c0, const float (&wr)[9][4], float dv[4]) {
   zero4(dv);
+  const int p0 = (r - 1) * RW + c - 1;  // top-left neighbour
 #pragma unroll
   for (int t = 0; t < 9; ++t) {
-    const float4 v = *reinterpret_cast<const float4*>(xt + s1c<C, NPIX>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
+    const float4 v = s1_nbr<C, NPIX>(xt, p0, c0 >> 2, (t / 3) * RW + t % 3);
     dv[0] += wr[t][0] * v.x;
     dv[1] += wr[t][1] * v.y;
     dv[2] += wr[t][2] * v.z;
     dv[3] += wr[t][3] * v.w;
-  }
-}
-
-// The same, also returning the 9 neighbourhood values it read.
-template <int C, int NPIX>
-__device__ __forceinline__ void s1_dw_lds_keep(const float* xt, int RW, int r, int c, int c0, const float (&wr)[9][4],
-                                               float dv[4], float4 (&xn)[9]) {
-  zero4(dv);
-#pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    xn[t] = *reinterpret_cast<const float4*>(xt + s1c<C, NPIX>((r + t / 3 - 1) * RW + c + t % 3 - 1, c0 >> 2));
-    dv[0] += wr[t][0] * xn[t].x;
-    dv[1] += wr[t][1] * xn[t].y;
-    dv[2] += wr[t][2] * xn[t].z;
-    dv[3] += wr[t][3] * xn[t].w;
   }
 }
 
@@ -320,7 +313,7 @@ __global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, 
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
+      s1_dw_lds<C, XN, RW>(xt, r + 1, cc + 1, c0, wr, dv);
       if (MODE == 0) {
         cnt += 1.f;
         const float rk = __builtin_amdgcn_rcpf(cnt);
@@ -482,7 +475,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
       xv[1] = xq.y;
       xv[2] = xq.z;
       xv[3] = xq.w;
-      s1_dw_lds<C, XN>(xt, RW, r + 1, cc + 1, c0, wr, dv);
+      s1_dw_lds<C, XN, RW>(xt, r + 1, cc + 1, c0, wr, dv);
       if constexpr (!PF) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         m = M1[off >> 3];
@@ -675,7 +668,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
         zero4(dv);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-          xn[t] = *reinterpret_cast<const float4*>(xt + s1c<C, XN>((r + 1 + t / 3 - 1) * XW + cc + 1 + t % 3 - 1, c0 >> 2));
+          xn[t] = s1_nbr<C, XN>(xt, r * XW + cc, c0 >> 2, (t / 3) * XW + t % 3);
           const float4 w4 = W4(t);
           dv[0] += w4.x * xn[t].x;
           dv[1] += w4.y * xn[t].y;
@@ -809,8 +802,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
           const int dy = dyi - 1;
           float4 col[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            col[k] = *reinterpret_cast<const float4*>(ddt + s1c<C, DN>((r + 1 - dy) * DWd + cc + k, c0 >> 2));
+          for (int k = 0; k < 4; ++k) col[k] = s1_nbr<C, DN>(ddt, r * DWd + cc, c0 >> 2, (1 - dy) * DWd + k);
 #pragma unroll
           for (int k = 2; k >= 0; --k) {
             const float4 w4 = W4(dyi * 3 + 2 - k);
