@@ -10,6 +10,15 @@
 
 namespace stda {
 
+// Workgroup barrier over LDS data only: this wave's LDS accesses complete, then s_barrier.  Unlike
+// __syncthreads it leaves vector-memory loads in flight, among them loads that write LDS for a
+// later phase (whose issuer waits for them and synchronises again before they are read).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// Wait until every vector-memory access this wave issued has completed (s_waitcnt vmcnt(0); in
+// the gfx9 encoding vmcnt sits in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 are left at
+// their maxima, i.e. not waited for).
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // BF16 storage: raw 16-bit pattern, converted to/from FP32 at every load/store.
 struct bf16 {
   uint16_t v;

@@ -108,6 +108,38 @@ __device__ __forceinline__ void load_tile(const T* __restrict__ X, int b, int y0
   }
 }
 
+// FP32, planar layouts: the same tile fetched by buffer loads that write LDS directly, one
+// instruction per 64 consecutive pixels of one 4-channel plane (a plane holds its pixels as
+// consecutive 16-byte chunks, the order in which a load's 64 lanes write).  The LDS layout is that
+// of NPIXL >= the tile's pixels, a multiple of 64, so that every lane of every load writes inside
+// its plane: no lane is masked off, and each wave issues the same loads on every path (the
+// compiler's waits for loads issued before these then leave these in flight).  Issued without
+// VGPRs and without a wait: the caller waits for its own wave's loads (wait_vmem) and
+// then synchronises the workgroup before the tile is read; barriers in between must leave vector
+// memory in flight (lds_barrier).  A pixel off the map, or past the tile, gets an offset beyond
+// the clip's buffer range, which the range check turns into zeros.  A clip is at most 4096 x 4096
+// pixels of 16 channels here (1 GiB), inside the 2 GiB a buffer range can describe.
+template <int C, int TH, int TW, int HALO, int NPIXL>
+__device__ __forceinline__ void load_tile_dma(const float* X, int b, int y0, int x0, int h, int w, float* lds) {
+  constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, NPIX = RH * RW, G = C / 4;
+  constexpr int NCH = NPIXL / 64;  // 64-pixel chunks of a plane
+  static_assert(NPIXL % 64 == 0 && NPIXL >= NPIX && !S1Lds<C, NPIXL>::SWZ, "planar layout of whole 64-pixel chunks");
+  static_assert((G * NCH) % (STDA_BLOCK / 64) == 0, "the same number of loads in every wave");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int bytes = h * w * (C * 4);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X + (int64_t)b * h * w * C), (short)0, bytes, 0x00020000);
+#pragma unroll
+  for (int i = 0; i < G * NCH / (STDA_BLOCK / 64); ++i) {
+    const int j = wave + i * (STDA_BLOCK / 64), q = j / NCH, p0 = (j % NCH) * 64, px = p0 + lane;
+    const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
+    const bool in = px < NPIX && y >= 0 && y < h && x >= 0 && x < w;
+    const int off = in ? ((y * w + x) * C + 4 * q) * 4 : (int)0x80000000u;
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds + s1c<C, NPIXL>(p0, q)), 16, off,
+                                             0, 0, 0);
+  }
+}
+
 // The same tile in two halves, for software pipelining across a grid-stride tile loop: fetch()
 // issues this thread's loads into registers in storage form (they stay in flight until put()),
 // put() converts them and writes the LDS tile in load_tile's layout.
@@ -550,9 +582,14 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
   constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
   constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
   constexpr int XN = (TH + 4) * XW, DN = (TH + 2) * DWd;  // pixels of the x and dD tiles
-  constexpr int XT = S1Lds<C, XN>::SIZE;
+  // FP32 at 16 channels (not LC): the next tile's x is fetched into a second buffer during a tile,
+  // the x tiles laid out for whole 64-pixel chunks (XNL pixels)
+  constexpr bool DMA = std::is_same<T, float>::value && C == 16 && !LC;
+  constexpr int XNL = DMA ? (XN + 63) / 64 * 64 : XN;
+  constexpr int XT = S1Lds<C, XNL>::SIZE;
   static_assert(XT >= 4 * 9 * C + 9 * C && XT >= 4 * 256, "reduction scratch aliases the x tile");
   __shared__ float xt[XT];
+  __shared__ float xt2[DMA ? XT : 1];
   __shared__ float ddt[S1Lds<C, DN>::SIZE];
   __shared__ float dpt[S1Lds<C, M>::SIZE];
   __shared__ float dut[S1Lds<C, M>::SIZE];
@@ -608,7 +645,25 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
   auto xpx = [&](int p) { return (p / TW + 2) * XW + p % TW + 2; };  // tile pixel -> x-tile LDS pixel
 
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
-  for (int tile = bx; tile < ntiles; tile += gx) {
+  // Tile loop.  With DMA a tile's x was fetched during the previous tile (or before the loop) and
+  // the next tile's is fetched into the other buffer during this one: two tiles per iteration, the
+  // first in xt, the second in xt2, unrolled so that each copy names its buffers and reads of the
+  // current one do not wait for the loads into the other.
+  if constexpr (DMA)
+    if (bx < ntiles) {
+      int b, y0, x0;
+      tile_coords(bx, h, w, TH, TW, b, y0, x0);
+      load_tile_dma<C, TH, TW, 2, XNL>(X, b, y0, x0, h, w, xt);
+    }
+  constexpr int NU = DMA ? 2 : 1;
+  for (int tile0 = bx; tile0 < ntiles; tile0 += NU * gx)
+#pragma unroll
+  for (int half = 0; half < NU; ++half) {
+    const int tile = tile0 + half * gx;
+    if (half > 0 && tile >= ntiles) break;
+    float* const xc = half ? xt2 : xt;   // this tile's x
+    float* const xnx = half ? xt : xt2;  // the next tile's (DMA)
+    (void)xnx;
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     // the ReLU decisions and dx1 of the thread's next dD-phase item (zero off the map), one item
@@ -631,12 +686,18 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
         raw_zero4(ng);
       }
     };
-    if constexpr (PF) a2_load(threadIdx.x);
-    __syncthreads();
-    load_tile<T, C, TH, TW, 2, !LC>(X, b, y0, x0, h, w, xt);  // LC: one load at a time (register peak)
-    __syncthreads();
+    if constexpr (DMA) {
+      wait_vmem();  // this wave's part of the tile is in LDS
+      if constexpr (PF) a2_load(threadIdx.x);
+      __syncthreads();  // and every other wave's
+    } else {
+      if constexpr (PF) a2_load(threadIdx.x);
+      __syncthreads();
+      load_tile<T, C, TH, TW, 2, !LC>(X, b, y0, x0, h, w, xc);  // LC: one load at a time (register peak)
+      __syncthreads();
+    }
     // A1: pointwise branch of the tile, qt = x Wp
-    lds_gemm_s<M, C, C>([&](int p, int kk) { return xt[s1e<C, XN>(xpx(p), kk)]; },
+    lds_gemm_s<M, C, C>([&](int p, int kk) { return xc[s1e<C, XNL>(xpx(p), kk)]; },
                         [&](int kk, int n) { return wp[kk * C + n]; },
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     __syncthreads();
@@ -668,7 +729,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
         zero4(dv);
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-          xn[t] = s1_nbr<C, XN>(xt, r * XW + cc, c0 >> 2, (t / 3) * XW + t % 3);
+          xn[t] = s1_nbr<C, XNL>(xc, r * XW + cc, c0 >> 2, (t / 3) * XW + t % 3);
           const float4 w4 = W4(t);
           dv[0] += w4.x * xn[t].x;
           dv[1] += w4.y * xn[t].y;
@@ -733,6 +794,14 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
     // B1: pointwise transpose, qt[p][c] = sum_o dP[p][o] wp[c][o]
     lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
+    if constexpr (DMA) {  // the next tile's x, into the other buffer, in flight until that tile starts
+      // (after the last tile this tile again, never read: every path issues the same loads, so
+      // waits for loads issued before them need not wait for these).  Issued after this tile's
+      // last LDS writes, which would otherwise wait for them.
+      int nb, ny0, nx0;
+      tile_coords(tile + gx < ntiles ? tile + gx : tile, h, w, TH, TW, nb, ny0, nx0);
+      load_tile_dma<C, TH, TW, 2, XNL>(X, nb, ny0, nx0, h, w, xnx);
+    }
     // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles);
     // with a single 16 x 16 tile (16 channels) the 4 waves take a quarter of the pixels each
     if constexpr (NT == 1) {
@@ -740,7 +809,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
       const int pb = wave * MQ;
 #pragma unroll 4
       for (int p = 0; p < MQ; p += 4)
-        pwacc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(pb + p + lg), li)], dpt[s1e<C, M>(pb + p + lg, li)],
+        pwacc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(xc[s1e<C, XNL>(xpx(pb + p + lg), li)], dpt[s1e<C, M>(pb + p + lg, li)],
                                                         pwacc[0], 0, 0, 0);
     } else {
 #pragma unroll
@@ -750,12 +819,13 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
           const int m0 = (t / (C / 16)) * 16, n0 = (t % (C / 16)) * 16;
 #pragma unroll 4
           for (int p = 0; p < M; p += 4)
-            pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xt[s1e<C, XN>(xpx(p + lg), m0 + li)],
+            pwacc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xc[s1e<C, XNL>(xpx(p + lg), m0 + li)],
                                                             dpt[s1e<C, M>(p + lg, n0 + li)], pwacc[u], 0, 0, 0);
         }
       }
     }
-    __syncthreads();
+    if constexpr (DMA) lds_barrier();
+    else __syncthreads();
     // B2: dX on the tile.  C < 64: two horizontally adjacent pixels per item, whose 3 x 3
     // neighbourhoods of dD share 6 of the 12 values read; C = 64 keeps one pixel per item, since the
     // pair does not fit its register budget.
@@ -784,10 +854,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
         for (int s = 0; s < 2; ++s) {
           if (s == 1 && !second) break;
           const float* rr = rp[s];
-          const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px + s), c0 >> 2));
+          const float4 xq = *reinterpret_cast<const float4*>(xc + s1c<C, XNL>(xpx(px + s), c0 >> 2));
           const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px + s, c0 >> 2));
           const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px + s, c0 >> 2));
-          const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
+          const float xv[4] = {xq.x, xq.y, xq.z, xq.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
 #pragma unroll
           for (int j = 0; j < 4; ++j) acc[s][j] = xa[j] * du[j] + xb[j] * xv[j] + xe[j] + rr[j] + qv[j];
           if (SKIP)
@@ -831,10 +901,10 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         float rr[4], acc[4];
         ld4(dXr + off, rr);
-        const float4 xc = *reinterpret_cast<const float4*>(xt + s1c<C, XN>(xpx(px), c0 >> 2));
+        const float4 xq = *reinterpret_cast<const float4*>(xc + s1c<C, XNL>(xpx(px), c0 >> 2));
         const float4 qc = *reinterpret_cast<const float4*>(qt + s1c<C, M>(px, c0 >> 2));
         const float4 uc = *reinterpret_cast<const float4*>(dut + s1c<C, M>(px, c0 >> 2));
-        const float xv[4] = {xc.x, xc.y, xc.z, xc.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
+        const float xv[4] = {xq.x, xq.y, xq.z, xq.w}, qv[4] = {qc.x, qc.y, qc.z, qc.w}, du[4] = {uc.x, uc.y, uc.z, uc.w};
         const float4 xa4 = CF4(6), xb4 = CF4(7), xe4 = CF4(8);
         const float xa[4] = {xa4.x, xa4.y, xa4.z, xa4.w}, xb[4] = {xb4.x, xb4.y, xb4.z, xb4.w};
         const float xe[4] = {xe4.x, xe4.y, xe4.z, xe4.w};
@@ -861,6 +931,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
       }
     }
   }
+  if constexpr (DMA) wait_vmem();  // the last (unused) fetch has landed
   __syncthreads();
   block_chan_reduce_shfl<G, 9>(dwacc, sm, red);
   for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) {
