@@ -666,32 +666,41 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
     (void)xnx;
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
-    // the ReLU decisions and dx1 of the thread's next dD-phase item (zero off the map), one item
-    // ahead: the first item's loads overlap the staging and the first product, each later one the
-    // previous item.  Not at 64 channels, whose tiles have no registers to spare: there each item
-    // loads its own.
-    constexpr int NA = (TH + 2) * DWd * G;
+    // the ReLU decisions and dx1 of the thread's dD-phase items (zero off the map), loaded ahead:
+    // BF16 at 16 channels all of them (at most 3) at the tile start, so that their latencies
+    // overlap each other, the staging and the first product (measured faster there; FP32, whose
+    // x tile is already fetched a tile ahead, gained nothing for 16 more registers); otherwise one
+    // item ahead, the first item's loads overlapping the staging and the first product, each later
+    // one the previous item.  Not at 64 channels, whose tiles have no registers to spare: there
+    // each item loads its own.
+    constexpr int NA = (TH + 2) * DWd * G, NAI = (NA + STDA_BLOCK - 1) / STDA_BLOCK;
     constexpr bool PF = C < 64 && !LC;  // (LC: registers go to a third wave instead)
+    constexpr bool PALL = PF && C == 16 && NAI <= 3 && sizeof(T) == 2;
+    constexpr int NPF = PALL ? NAI : 1, NUNR = PALL ? NAI : 1;
     typedef typename Raw4<T>::type R4;  // held in storage form until used
-    R4 ng;
-    uint32_t nm;  // the byte of M1 holding this thread's 4 decisions
-    auto a2_load = [&](int e) {
+    R4 ng[NPF];
+    uint32_t nm[NPF];  // the byte of M1 holding this thread's 4 decisions
+    auto a2_load = [&](int e, int k) {
       const int px = e / G, y = y0 - 1 + px / DWd, x = x0 - 1 + px % DWd;
       if (e < NA && y >= 0 && y < h && x >= 0 && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        nm = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
-        raw_ld4(dX1 + off, ng);
+        nm[k] = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
+        raw_ld4(dX1 + off, ng[k]);
       } else {
-        nm = 0;
-        raw_zero4(ng);
+        nm[k] = 0;
+        raw_zero4(ng[k]);
       }
+    };
+    auto a2_first = [&]() {
+#pragma unroll
+      for (int k = 0; k < NPF; ++k) a2_load(threadIdx.x + k * STDA_BLOCK, k);
     };
     if constexpr (DMA) {
       wait_vmem();  // this wave's part of the tile is in LDS
-      if constexpr (PF) a2_load(threadIdx.x);
+      if constexpr (PF) a2_first();
       __syncthreads();  // and every other wave's
     } else {
-      if constexpr (PF) a2_load(threadIdx.x);
+      if constexpr (PF) a2_first();
       __syncthreads();
       load_tile<T, C, TH, TW, 2, !LC>(X, b, y0, x0, h, w, xc);  // LC: one load at a time (register peak)
       __syncthreads();
@@ -702,16 +711,20 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     __syncthreads();
     // A2: dD on the tile + halo 1, dP on the tile (zero off the map)
-    for (int e = threadIdx.x; e < NA; e += STDA_BLOCK) {
+#pragma unroll NUNR
+    for (int i = 0; i < NAI; ++i) {
+      const int e = threadIdx.x + i * STDA_BLOCK;
+      if (e >= NA) break;
       const int px = e / G, r = px / DWd, cc = px % DWd;  // position in the dD tile
       const int y = y0 - 1 + r, x = x0 - 1 + cc;
       const bool center = r >= 1 && r <= TH && cc >= 1 && cc <= TW;
       float g[4];
       uint32_t m;
       if constexpr (PF) {
-        m = nm;
-        raw_cvt4(ng, g);
-        if (e + STDA_BLOCK < NA) a2_load(e + STDA_BLOCK);
+        m = nm[PALL ? i : 0];
+        raw_cvt4(ng[PALL ? i : 0], g);
+        if constexpr (!PALL)
+          if (e + STDA_BLOCK < NA) a2_load(e + STDA_BLOCK, 0);
       }
       float od[4], op[4], uv[4];
       zero4(od);
