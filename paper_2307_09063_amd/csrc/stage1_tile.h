@@ -140,36 +140,38 @@ __device__ __forceinline__ void load_tile_dma(const float* X, int b, int y0, int
   }
 }
 
-// BF16 at 16 channels: the tile's raw BF16 pixels fetched by buffer loads that write LDS directly
-// into a staging buffer (NPIXL pixels x 32 bytes, pixel after pixel as in HBM; a load's 64 lanes
-// write 32 pixels, two 16-byte halves each), for stage1_put_bf16 to convert into load_tile's FP32
-// layout.  Waits, synchronisation and out-of-map zeros as for load_tile_dma.
-template <int C, int TH, int TW, int HALO, int NPIXL>
-__device__ __forceinline__ void load_tile_dma_bf16(const bf16* X, int b, int y0, int x0, int h, int w, uint32_t* stg) {
+// The tile's pixels in storage form (BF16, or FP32 where a second x buffer does not fit) fetched
+// by buffer loads that write LDS directly into a staging buffer (NPIXL pixels of C values, pixel
+// after pixel as in HBM; a load's 64 lanes write 64 consecutive 16-byte chunks), for
+// stage1_put_raw to convert into load_tile's FP32 layout.  Waits, synchronisation and out-of-map
+// zeros as for load_tile_dma.
+template <class T, int C, int TH, int TW, int HALO, int NPIXL>
+__device__ __forceinline__ void load_tile_dma_raw(const T* X, int b, int y0, int x0, int h, int w, uint32_t* stg) {
   constexpr int RW = TW + 2 * HALO, RH = TH + 2 * HALO, NPIX = RH * RW;
-  constexpr int CH = C * 2 / 16, PPI = 64 / CH, NI = NPIXL / PPI;  // 16-byte chunks per pixel, pixels per load
-  static_assert(C == 16 && NPIXL % PPI == 0 && NPIXL >= NPIX, "whole loads of 16-channel pixels");
+  constexpr int CH = C * (int)sizeof(T) / 16, PPI = 64 / CH, NI = NPIXL / PPI;  // chunks per pixel, pixels per load
+  static_assert(64 % CH == 0 && NPIXL % PPI == 0 && NPIXL >= NPIX, "whole loads of whole pixels");
   static_assert(NI % (STDA_BLOCK / 64) == 0, "the same number of loads in every wave");
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int bytes = h * w * (C * 2);
+  const int bytes = h * w * (C * (int)sizeof(T));
   const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16*>(X + (int64_t)b * h * w * C), (short)0, bytes, 0x00020000);
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(X + (int64_t)b * h * w * C), (short)0, bytes, 0x00020000);
 #pragma unroll
   for (int i = 0; i < NI / (STDA_BLOCK / 64); ++i) {
     const int j = wave + i * (STDA_BLOCK / 64), px = j * PPI + lane / CH, hc = lane % CH;
     const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
     const bool in = px < NPIX && y >= 0 && y < h && x >= 0 && x < w;
-    const int off = in ? (y * w + x) * (C * 2) + hc * 16 : (int)0x80000000u;
+    const int off = in ? (y * w + x) * (C * (int)sizeof(T)) + hc * 16 : (int)0x80000000u;
     __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stg + j * 256), 16, off, 0, 0, 0);
   }
 }
-// The staged BF16 tile of NPIX pixels -> FP32 LDS tile in the layout of S1Lds<C, NPIXL>.
-template <int C, int NPIX, int NPIXL>
-__device__ __forceinline__ void stage1_put_bf16(const uint32_t* stg, float* lds) {
+// The staged tile of NPIX pixels -> FP32 LDS tile in the layout of S1Lds<C, NPIXL>.
+template <class T, int C, int NPIX, int NPIXL>
+__device__ __forceinline__ void stage1_put_raw(const uint32_t* stg, float* lds) {
   constexpr int G = C / 4;
+  const T* st = reinterpret_cast<const T*>(stg);
   for (int e = threadIdx.x; e < NPIX * G; e += STDA_BLOCK) {
     const int px = e / G, q = e % G;
-    const uint2 r = *reinterpret_cast<const uint2*>(stg + px * (C / 2) + 2 * q);
+    const typename Raw4<T>::type r = *reinterpret_cast<const typename Raw4<T>::type*>(st + px * C + 4 * q);
     float v[4];
     raw_cvt4(r, v);
     *reinterpret_cast<float4*>(lds + s1c<C, NPIXL>(px, q)) = make_float4(v[0], v[1], v[2], v[3]);
@@ -618,19 +620,26 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
   constexpr int XW = TW + 4, DWd = TW + 2;  // row widths of the x tile (halo 2) and dD tile (halo 1)
   constexpr int NT = (C / 16) * (C / 16), NTW = (NT + 3) / 4;  // pointwise-gradient tiles (per wave)
   constexpr int XN = (TH + 4) * XW, DN = (TH + 2) * DWd;  // pixels of the x and dD tiles
-  // 16 channels (not LC): the next tile's x is fetched by buffer loads into LDS during a tile.
-  // FP32 (DMA): straight into a second x buffer, the x tiles laid out for whole 64-pixel chunks
-  // (XNL pixels).  BF16 (DMAB): raw into a staging buffer, converted into the x tile at the start
-  // of the tile it belongs to.
-  constexpr bool DMA = std::is_same<T, float>::value && C == 16 && !LC;
-  constexpr bool DMAB = sizeof(T) == 2 && C == 16 && !LC;
-  constexpr int XNL = DMA ? (XN + 63) / 64 * 64 : XN;
+  // Not LC: the next tile's x is fetched by buffer loads into LDS during a tile.  FP32 at 16
+  // channels (DMA): straight into a second x buffer, the x tiles laid out for whole 64-pixel
+  // chunks (XNL pixels).  BF16, and FP32 at 64 channels (DMAB): in storage form into a staging
+  // buffer, converted into the x tile at the start of the tile it belongs to (FP32 at 32 channels:
+  // neither buffer fits beside the tile's others at two workgroups per CU).
+  // Each only where the added buffer keeps MINW workgroups' LDS within the CU's 160 KiB.
+  constexpr int LDS_REST = 4 * (S1Lds<C, DN>::SIZE + 3 * S1Lds<C, M>::SIZE + C * C + 18 * C);  // ddt .. cf
+  constexpr int LDS_CAP = 160 * 1024 / MINW, XN64 = (XN + 63) / 64 * 64;
+  constexpr int SPPI = 64 * 16 / (C * (int)sizeof(T));                // pixels per staging load
+  constexpr int XSL = (XN + 4 * SPPI - 1) / (4 * SPPI) * (4 * SPPI);  // staged pixels (whole loads in every wave)
+  constexpr bool DMA =
+      std::is_same<T, float>::value && C == 16 && !LC && LDS_REST + 8 * S1Lds<C, XN64>::SIZE <= LDS_CAP;
+  constexpr bool DMAB = !LC && !DMA && (sizeof(T) == 2 || C == 64) &&
+                        LDS_REST + 4 * S1Lds<C, XN>::SIZE + XSL * C * (int)sizeof(T) <= LDS_CAP;
+  constexpr int XNL = DMA ? XN64 : XN;
   constexpr int XT = S1Lds<C, XNL>::SIZE;
   static_assert(XT >= 4 * 9 * C + 9 * C && XT >= 4 * 256, "reduction scratch aliases the x tile");
   __shared__ float xt[XT];
   __shared__ float xt2[DMA ? XT : 1];
-  constexpr int XSL = (XN + 127) / 128 * 128;  // staged pixels (whole loads of 32 in every wave)
-  __shared__ uint32_t xst[DMAB ? XSL * C / 2 : 1];
+  __shared__ uint32_t xst[DMAB ? XSL * C * sizeof(T) / 4 : 1];
   __shared__ float ddt[S1Lds<C, DN>::SIZE];
   __shared__ float dpt[S1Lds<C, M>::SIZE];
   __shared__ float dut[S1Lds<C, M>::SIZE];
@@ -695,7 +704,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
       int b, y0, x0;
       tile_coords(bx, h, w, TH, TW, b, y0, x0);
       if constexpr (DMA) load_tile_dma<C, TH, TW, 2, XNL>(X, b, y0, x0, h, w, xt);
-      else load_tile_dma_bf16<C, TH, TW, 2, XSL>(reinterpret_cast<const bf16*>(X), b, y0, x0, h, w, xst);
+      else load_tile_dma_raw<T, C, TH, TW, 2, XSL>(X, b, y0, x0, h, w, xst);
     }
   constexpr int NU = DMA ? 2 : 1;
   for (int tile0 = bx; tile0 < ntiles; tile0 += NU * gx)
@@ -745,7 +754,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
       wait_vmem();  // this wave's part of the staged tile is in LDS
       if constexpr (PF) a2_first();
       __syncthreads();  // and every other wave's
-      stage1_put_bf16<C, XN, XNL>(xst, xc);
+      stage1_put_raw<T, C, XN, XNL>(xst, xc);
       __syncthreads();
     } else {
       if constexpr (PF) a2_first();
@@ -856,7 +865,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
     lds_gemm_s<M, C, C>([&](int p, int o) { return dpt[s1e<C, M>(p, o)]; }, [&](int o, int n) { return wp[n * C + o]; },
                         [&](int p, int n, float v) { qt[s1e<C, M>(p, n)] = v; });
     if constexpr (DMA || DMAB) {
-      // the next tile's x, into the other buffer (BF16: the staging buffer, free once this tile's
+      // the next tile's x, into the other buffer (DMAB: the staging buffer, free once this tile's
       // x was converted), in flight until that tile starts (after the last tile this tile again,
       // never read: every path issues the same loads, so waits for loads issued before them need
       // not wait for these).  Issued after this tile's last LDS writes, which would otherwise wait
@@ -864,7 +873,7 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
       int nb, ny0, nx0;
       tile_coords(tile + gx < ntiles ? tile + gx : tile, h, w, TH, TW, nb, ny0, nx0);
       if constexpr (DMA) load_tile_dma<C, TH, TW, 2, XNL>(X, nb, ny0, nx0, h, w, xnx);
-      else load_tile_dma_bf16<C, TH, TW, 2, XSL>(reinterpret_cast<const bf16*>(X), nb, ny0, nx0, h, w, xst);
+      else load_tile_dma_raw<T, C, TH, TW, 2, XSL>(X, nb, ny0, nx0, h, w, xst);
     }
     // C: pointwise weight gradient, dWp[c][o] += sum_p x[p][c] dP[p][o] (registers, across tiles);
     // with a single 16 x 16 tile (16 channels) the 4 waves take a quarter of the pixels each
