@@ -14,6 +14,11 @@ namespace stda {
 // __syncthreads it leaves vector-memory loads in flight, among them loads that write LDS for a
 // later phase (whose issuer waits for them and synchronises again before they are read).
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+// An LDS address as the LDS address space's pointer (the destination operand of loads that write
+// LDS directly).
+__device__ __forceinline__ __attribute__((address_space(3))) void* lds_ptr(const void* p) {
+  return (__attribute__((address_space(3))) void*)(p);
+}
 // Wait until every vector-memory access this wave issued has completed (s_waitcnt vmcnt(0); in
 // the gfx9 encoding vmcnt sits in bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 are left at
 // their maxima, i.e. not waited for).

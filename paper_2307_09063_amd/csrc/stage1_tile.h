@@ -135,8 +135,7 @@ __device__ __forceinline__ void load_tile_dma(const float* X, int b, int y0, int
     const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
     const bool in = px < NPIX && y >= 0 && y < h && x >= 0 && x < w;
     const int off = in ? ((y * w + x) * C + 4 * q) * 4 : (int)0x80000000u;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(lds + s1c<C, NPIXL>(p0, q)), 16, off,
-                                             0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, lds_ptr(lds + s1c<C, NPIXL>(p0, q)), 16, off, 0, 0, 0);
   }
 }
 
@@ -161,7 +160,7 @@ __device__ __forceinline__ void load_tile_dma_raw(const T* X, int b, int y0, int
     const int y = y0 - HALO + px / RW, x = x0 - HALO + px % RW;
     const bool in = px < NPIX && y >= 0 && y < h && x >= 0 && x < w;
     const int off = in ? (y * w + x) * (C * (int)sizeof(T)) + hc * 16 : (int)0x80000000u;
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)(stg + j * 256), 16, off, 0, 0, 0);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, lds_ptr(stg + j * 256), 16, off, 0, 0, 0);
   }
 }
 // The staged tile of NPIX pixels -> FP32 LDS tile in the layout of S1Lds<C, NPIXL>.
@@ -322,6 +321,17 @@ __global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, 
   __shared__ float wd[9 * C];
   __shared__ float sm[MODE == 0 ? 4 * (6 * C + 1) : 1];
   __shared__ float red[MODE == 0 ? 6 * C + 1 : 1];
+  // BF16 (DMAB): the next tile's x is fetched in storage form by buffer loads into an LDS staging
+  // buffer during a tile and converted at the start of the tile it belongs to; only where the
+  // staging buffer keeps four workgroups (of 40 KiB at most) per CU.
+  constexpr int LDS_BASE =
+      4 * (S1Lds<C, XN>::SIZE + S1Lds<C, PN>::SIZE + C * C + 9 * C + (MODE == 0 ? 5 * (6 * C + 1) : 2));
+  constexpr int SPPI = 64 * 16 / (C * (int)sizeof(T));                // pixels per staging load
+  constexpr int XSL = (XN + 4 * SPPI - 1) / (4 * SPPI) * (4 * SPPI);  // staged pixels (whole loads in every wave)
+  // (Not the 16-channel statistics pass, whose register prefetch below measured faster.)
+  constexpr bool DMAB =
+      sizeof(T) == 2 && !(MODE == 0 && C == 16) && LDS_BASE + XSL * C * (int)sizeof(T) <= 40 * 1024;
+  __shared__ uint32_t xst[DMAB ? XSL * C * sizeof(T) / 4 : 1];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
   float wr[9][4];
@@ -340,18 +350,28 @@ __global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, 
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   // PIPE: the x tile of the block's next tile is fetched while this one is computed.  It costs a
   // wave per SIMD, which pays (measured) only for the BF16 16-channel statistics pass.
-  constexpr bool PIPE = MODE == 0 && C == 16 && sizeof(T) == 2;
+  constexpr bool PIPE = !DMAB && MODE == 0 && C == 16 && sizeof(T) == 2;
   TileRegs<T, C, TH, TW, 1> nx;
   if (PIPE && bx < ntiles) {
     int b, y0, x0;
     tile_coords(bx, h, w, TH, TW, b, y0, x0);
     nx.fetch(X, b, y0, x0, h, w);
   }
+  if constexpr (DMAB)
+    if (bx < ntiles) {
+      int b, y0, x0;
+      tile_coords(bx, h, w, TH, TW, b, y0, x0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(X, b, y0, x0, h, w, xst);
+    }
   for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
+    if constexpr (DMAB) wait_vmem();  // this wave's part of the staged tile is in LDS
     __syncthreads();
-    if constexpr (PIPE) {
+    if constexpr (DMAB) {
+      stage1_put_raw<T, C, XN, XN>(xst, xt);
+      __syncthreads();
+    } else if constexpr (PIPE) {
       nx.put(xt);
       __syncthreads();
       if (tile + gx < ntiles) {
@@ -367,7 +387,16 @@ __global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, 
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
                               [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
-    __syncthreads();
+    if constexpr (DMAB) {
+      // the next tile's x (after the last tile this tile again, never read), in flight until
+      // that tile starts; issued after this tile's last LDS writes, which would otherwise wait
+      int nb, ny0, nx0;
+      tile_coords(tile + gx < ntiles ? tile + gx : tile, h, w, TH, TW, nb, ny0, nx0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(X, nb, ny0, nx0, h, w, xst);
+      lds_barrier();
+    } else {
+      __syncthreads();
+    }
     for (int e = threadIdx.x; e < TH * TW * G; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
@@ -410,6 +439,7 @@ __global__ __launch_bounds__(256) void k_s1_tile(SegL<k_s1_tile_args<T, C, DEC, 
       }
     }
   }
+  if constexpr (DMAB) wait_vmem();  // the last (unused) fetch has landed
   if (MODE == 0) {
     block_chan_stats<G, 3>(cnt, mn, q2, sm, red);
     for (int q = threadIdx.x; q < 3 * C; q += STDA_BLOCK) {
@@ -458,6 +488,18 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
   __shared__ float wd[9 * C];
   __shared__ float sm[4 * 4 * C];
   __shared__ float red[4 * C];
+  // BF16 (DMAB): the next tile's x is fetched in storage form by buffer loads into an LDS staging
+  // buffer during a tile and converted at the start of the tile it belongs to; the thread's items
+  // (at most two) load their x1 decisions and dx1 at the tile start, before that fetch is issued,
+  // so that waiting for them does not wait for it.  Only where the staging buffer keeps four
+  // workgroups (of 40 KiB at most) per CU.
+  constexpr int NI = TH * TW * G;
+  constexpr int LDS_BASE = 4 * (S1Lds<C, XN>::SIZE + S1Lds<C, PN>::SIZE + C * C + 9 * C + 20 * C);
+  constexpr int SPPI = 64 * 16 / (C * (int)sizeof(T));                // pixels per staging load
+  constexpr int XSL = (XN + 4 * SPPI - 1) / (4 * SPPI) * (4 * SPPI);  // staged pixels (whole loads in every wave)
+  constexpr bool DMAB =
+      sizeof(T) == 2 && NI <= 2 * STDA_BLOCK && LDS_BASE + XSL * C * (int)sizeof(T) <= 40 * 1024;
+  __shared__ uint32_t xst[DMAB ? XSL * C * sizeof(T) / 4 : 1];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
   float wr[9][4];
@@ -476,38 +518,52 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
   const int ntiles = B * ((h + TH - 1) / TH) * ((w + TW - 1) / TW);
   // PIPE: the x tile of the block's next tile is fetched while this one is computed (measured
   // faster above 16 channels; at 16 it costs the kernel a wave per SIMD and time)
-  constexpr bool PIPE = C > 16;
+  constexpr bool PIPE = !DMAB && C > 16;
   TileRegs<T, C, TH, TW, 1> nx;
   if (PIPE && bx < ntiles) {
     int b, y0, x0;
     tile_coords(bx, h, w, TH, TW, b, y0, x0);
     nx.fetch(X, b, y0, x0, h, w);
   }
+  if constexpr (DMAB)
+    if (bx < ntiles) {
+      int b, y0, x0;
+      tile_coords(bx, h, w, TH, TW, b, y0, x0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(X, b, y0, x0, h, w, xst);
+    }
   for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, h, w, TH, TW, b, y0, x0);
     // BF16 above 16 channels: x1 and dx1 of the thread's next item loaded one item ahead, in
     // storage form (the first item's loads overlap the staging and the product); otherwise each
     // item loads its own in place (measured faster there: the 16-channel tiles lose a wave per SIMD)
-    constexpr int NI = TH * TW * G;
-    constexpr bool PF = sizeof(T) == 2 && C > 16;
+    constexpr bool PF = sizeof(T) == 2 && C > 16 && !DMAB;
     typedef typename Raw4<T>::type R4;
-    R4 ng;
-    uint32_t nm;  // the byte of M1 holding this thread's 4 decisions
-    auto item_load = [&](int e) {
+    R4 ng, ng2;
+    uint32_t nm, nm2;  // the byte of M1 holding this thread's 4 decisions (ng2, nm2: DMAB's second item)
+    auto item_load_to = [&](int e, R4& g, uint32_t& m) {
       const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
       if (e < NI && y < h && x < w) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        nm = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
-        raw_ld4(dX1 + off, ng);
+        m = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
+        raw_ld4(dX1 + off, g);
       } else {
-        nm = 0;
-        raw_zero4(ng);
+        m = 0;
+        raw_zero4(g);
       }
     };
+    auto item_load = [&](int e) { item_load_to(e, ng, nm); };
+    if constexpr (DMAB) {
+      wait_vmem();  // this wave's part of the staged tile is in LDS
+      item_load(threadIdx.x);
+      if constexpr (NI > STDA_BLOCK) item_load_to(threadIdx.x + STDA_BLOCK, ng2, nm2);
+    }
     if constexpr (PF) item_load(threadIdx.x);
     __syncthreads();
-    if constexpr (PIPE) {
+    if constexpr (DMAB) {
+      stage1_put_raw<T, C, XN, XN>(xst, xt);
+      __syncthreads();
+    } else if constexpr (PIPE) {
       nx.put(xt);
       __syncthreads();
       if (tile + gx < ntiles) {
@@ -522,7 +578,16 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
     lds_gemm_s<TH * TW, C, C>([&](int p, int k) { return xt[s1e<C, XN>((p / TW + 1) * RW + p % TW + 1, k)]; },
                               [&](int k, int n) { return wp[k * C + n]; },
                               [&](int p, int n, float v) { pt[s1e<C, PN>(p, n)] = v; });
-    __syncthreads();
+    if constexpr (DMAB) {
+      // the next tile's x (after the last tile this tile again, never read), in flight until
+      // that tile starts; issued after this tile's last LDS writes, which would otherwise wait
+      int nb, ny0, nx0;
+      tile_coords(tile + gx < ntiles ? tile + gx : tile, h, w, TH, TW, nb, ny0, nx0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(X, nb, ny0, nx0, h, w, xst);
+      lds_barrier();
+    } else {
+      __syncthreads();
+    }
     for (int e = threadIdx.x; e < NI; e += STDA_BLOCK) {
       const int px = e / G, r = px / TW, cc = px % TW;
       const int y = y0 + r, x = x0 + cc;
@@ -532,6 +597,10 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
         m = nm;
         raw_cvt4(ng, g);
         if (e + STDA_BLOCK < NI) item_load(e + STDA_BLOCK);
+      } else if constexpr (DMAB) {
+        const bool first = e < STDA_BLOCK;
+        m = first ? nm : nm2;
+        raw_cvt4(first ? ng : ng2, g);
       }
       if (y >= h || x >= w) continue;
       float pv[4], dv[4], xv[4];
@@ -546,7 +615,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
       xv[2] = xq.z;
       xv[3] = xq.w;
       s1_dw_lds<C, XN, RW>(xt, r + 1, cc + 1, c0, wr, dv);
-      if constexpr (!PF) {
+      if constexpr (!PF && !DMAB) {
         const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
         m = M1[off >> 3];
         ld4(dX1 + off, g);
@@ -562,6 +631,7 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
       }
     }
   }
+  if constexpr (DMAB) wait_vmem();  // the last (unused) fetch has landed
   block_chan_reduce_shfl<G, 4>(acc, sm, red);
   for (int q = threadIdx.x; q < 4 * C; q += STDA_BLOCK) part[(int64_t)bx * 4 * C + q] = red[q];
 }
