@@ -51,7 +51,8 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
   const int H = a_.H;
   const int W = a_.W;
   constexpr int TH = 8, TW = 32, M = TH * TW, C = 16, G = 4, PS = C + 4, XR = TH + 2, XC = TW + 2;
-  __shared__ float xs[3 * XR * XC];
+  constexpr int NX = 3 * XR * XC, NXL = (NX + 255) / 256 * 256;  // staged values (NXL: whole loads in every wave)
+  __shared__ float xs[NXL];
   __shared__ float wk[C * 28];
   __shared__ float tt[M * PS];   // conv output of the tile (then dTp in MODE 3)
   __shared__ float sm[4 * (2 * C + 1)];
@@ -94,9 +95,33 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
   for (int s = 0; s < 7; ++s) koff[s] = koff_of(4 * s + lg);
   const int wo0 = koff_of(li), wo1 = koff_of(16 + li);  // weight gradient: columns li, 16 + li
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+  // MODE 0..2 (DMAX): the next tile's three planes are fetched by buffer loads that write LDS
+  // directly (one value per lane, 64 consecutive values of the staged layout per load) once this
+  // tile's product has read them; the fetch is in flight during this tile's items and is waited
+  // for at the next tile's start.  A value off the map gets an offset past the clip's buffer range,
+  // which the range check turns into 0.  (MODE 3 reads the planes again for its weight gradient.)
+  constexpr bool DMAX = MODE <= 2;
+  auto xs_fetch = [&](int t) {
+    int fb, fy0, fx0;
+    tile_coords(t, H, W, TH, TW, fb, fy0, fx0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.x + (int64_t)fb * 3 * H * W),
+                                                                        (short)0, 3 * H * W * 4, 0x00020000);
+#pragma unroll
+    for (int i = 0; i < NXL / STDA_BLOCK; ++i) {
+      const int j = wave + i * (STDA_BLOCK / 64), q = j * 64 + lane;
+      const int c = q / (XR * XC), r = (q / XC) % XR, cc = q % XC;
+      const int y = fy0 - 1 + r, x = fx0 - 1 + cc;
+      const bool in = q < NX && y >= 0 && y < H && x >= 0 && x < W;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, lds_ptr(xs + j * 64), 4, in ? ((c * H + y) * W + x) * 4 : (int)0x80000000u,
+                                               0, 0, 0);
+    }
+  };
+  if constexpr (DMAX)
+    if (bx < ntiles) xs_fetch(bx);
   for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
+    if constexpr (DMAX) wait_vmem();  // this wave's part of the planes is in LDS (before the loads below)
     // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
     // their latency overlaps them
     constexpr int KI = (M * G + STDA_BLOCK - 1) / STDA_BLOCK;
@@ -117,9 +142,9 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
       }
     }
     __syncthreads();
-    {
+    if constexpr (!DMAX) {
       // the three planes of the tile plus halo; all loads issued before the LDS writes
-      constexpr int NX = 3 * XR * XC, KX = (NX + STDA_BLOCK - 1) / STDA_BLOCK;
+      constexpr int KX = (NX + STDA_BLOCK - 1) / STDA_BLOCK;
       float xv[KX];
 #pragma unroll
       for (int k = 0; k < KX; ++k) {
@@ -133,8 +158,8 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
         const int q = threadIdx.x + k * STDA_BLOCK;
         if (q < NX) xs[q] = xv[k];
       }
+      __syncthreads();
     }
-    __syncthreads();
     {
       // conv GEMM tt[p][o] = sum_k im2col(p, k) w[o][k] on the matrix cores: wave w takes the
       // 16-pixel row tiles w, w + 4, w + 8, w + 12, as NCH independent chains at a time (four in
@@ -164,6 +189,7 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
       }
     }
     __syncthreads();
+    if constexpr (DMAX) xs_fetch(tile + gx < ntiles ? tile + gx : tile);  // (after the last tile: unused)
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
       const int e = threadIdx.x + k * STDA_BLOCK;
@@ -220,6 +246,7 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
       }
     }
   }
+  if constexpr (DMAX) wait_vmem();  // the last (unused) fetch has landed
   if (MODE == 0) {
     float mn[1][4], q2[1][4];
 #pragma unroll
