@@ -45,15 +45,37 @@ __global__ __launch_bounds__(256) void k_head_fwd_tile(SegL<k_head_fwd_tile_args
   constexpr int TH = kHeadTH, TW = kHeadTW, C = 16, RW = TW + 2, XN = (TH + 2) * RW;
   __shared__ float xt[S1Lds<C, XN>::SIZE];
   __shared__ float wt[9 * C];  // [tap][c]
+  // BF16 (DMAB): the next tile's input is fetched in storage form by buffer loads into an LDS
+  // staging buffer as soon as this tile's is converted, in flight during this tile's outputs
+  constexpr bool DMAB = sizeof(T) == 2;
+  constexpr int SPPI = 64 * 16 / (C * (int)sizeof(T));                // pixels per staging load
+  constexpr int XSL = (XN + 4 * SPPI - 1) / (4 * SPPI) * (4 * SPPI);  // staged pixels (whole loads in every wave)
+  __shared__ uint32_t xst[DMAB ? XSL * C * sizeof(T) / 4 : 1];
   for (int q = threadIdx.x; q < 9 * C; q += STDA_BLOCK) wt[q] = w[(q % C) * 9 + q / C];
   const float b0 = bias[0];
   const int ntiles = B * ((H + TH - 1) / TH) * ((W + TW - 1) / TW);
+  if constexpr (DMAB)
+    if (bx < ntiles) {
+      int b, y0, x0;
+      tile_coords(bx, H, W, TH, TW, b, y0, x0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(d, b, y0, x0, H, W, xst);
+    }
   for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
-    __syncthreads();
-    load_tile<T, C, TH, TW, 1>(d, b, y0, x0, H, W, xt);
-    __syncthreads();
+    if constexpr (DMAB) {
+      wait_vmem();      // this wave's part of the staged tile is in LDS
+      __syncthreads();  // every wave's, and the previous tile's outputs have read xt
+      stage1_put_raw<T, C, XN, XN>(xst, xt);
+      __syncthreads();
+      int nb, ny0, nx0;  // the next tile (after the last tile this tile again, never read)
+      tile_coords(tile + gx < ntiles ? tile + gx : tile, H, W, TH, TW, nb, ny0, nx0);
+      load_tile_dma_raw<T, C, TH, TW, 1, XSL>(d, nb, ny0, nx0, H, W, xst);
+    } else {
+      __syncthreads();
+      load_tile<T, C, TH, TW, 1>(d, b, y0, x0, H, W, xt);
+      __syncthreads();
+    }
     const int r = threadIdx.x / TW, cc = threadIdx.x % TW;  // one pixel per thread
     const int y = y0 + r, x = x0 + cc;
     if (y < H && x < W) {
@@ -75,6 +97,7 @@ __global__ __launch_bounds__(256) void k_head_fwd_tile(SegL<k_head_fwd_tile_args
       z[o] = acc;
     }
   }
+  if constexpr (DMAB) wait_vmem();  // the last (unused) fetch has landed
 }
 
 template <class T, bool SIG>
@@ -123,6 +146,17 @@ __global__ __launch_bounds__(256) void k_head_bwd_tile(SegL<k_head_bwd_tile_args
   for (int tile = bx; tile < ntiles; tile += gx) {
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
+    // the thread's G items' d, loaded before dz is staged so that their latencies overlap it and
+    // each other (held in storage form until used)
+    typename Raw4<T>::type dr[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int px = (threadIdx.x + k * STDA_BLOCK) / G, y = y0 + px / TW, x = x0 + px % TW;
+      if (y < H && x < W)
+        raw_ld4(d + (((int64_t)b * H + y) * W + x) * C + c0, dr[k]);
+      else
+        raw_zero4(dr[k]);
+    }
     __syncthreads();
     for (int q = threadIdx.x; q < (TH + 2) * RW; q += STDA_BLOCK) {
       const int y = y0 - 1 + q / RW, x = x0 - 1 + q % RW;
@@ -143,7 +177,7 @@ __global__ __launch_bounds__(256) void k_head_bwd_tile(SegL<k_head_bwd_tile_args
       if (y >= H || x >= W) continue;
       const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
       float dv[4], o[4];
-      ld4(d + off, dv);
+      raw_cvt4(dr[k], dv);
       zero4(o);
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
