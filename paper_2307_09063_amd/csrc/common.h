@@ -78,6 +78,18 @@ template <> struct Raw4<float> { typedef float4 type; };
 template <> struct Raw4<bf16> { typedef uint2 type; };
 __device__ __forceinline__ void raw_ld4(const float* p, float4& r) { r = *reinterpret_cast<const float4*>(p); }
 __device__ __forceinline__ void raw_ld4(const bf16* p, uint2& r) { r = *reinterpret_cast<const uint2*>(p); }
+// The same four channels by a buffer load at byte offset off (an offset past the buffer's range
+// reads 0): no branch around the load, so every thread issues the same loads.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void raw_bld4(__amdgpu_buffer_rsrc_t rs, int off, float4& r) {
+  const u32x4_t q = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+  r = make_float4(__uint_as_float(q.x), __uint_as_float(q.y), __uint_as_float(q.z), __uint_as_float(q.w));
+}
+__device__ __forceinline__ void raw_bld4(__amdgpu_buffer_rsrc_t rs, int off, uint2& r) {
+  const u32x2_t q = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+  r = make_uint2(q.x, q.y);
+}
 __device__ __forceinline__ void raw_zero4(float4& r) { r = make_float4(0.f, 0.f, 0.f, 0.f); }
 __device__ __forceinline__ void raw_zero4(uint2& r) { r = make_uint2(0u, 0u); }
 __device__ __forceinline__ void raw_cvt4(const float4& r, float v[4]) {

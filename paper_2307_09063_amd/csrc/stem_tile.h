@@ -122,37 +122,45 @@ __global__ __launch_bounds__(256) void k_stem_tile(SegL<k_stem_tile_args<T, MODE
     int b, y0, x0;
     tile_coords(tile, H, W, TH, TW, b, y0, x0);
     if constexpr (DMAX) wait_vmem();  // this wave's part of the planes is in LDS (before the loads below)
-    // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
-    // their latency overlaps them
-    constexpr int KI = (M * G + STDA_BLOCK - 1) / STDA_BLOCK;
-    typename Raw4<T>::type pg[KI], ps[KI];  // storage form: converted where used
-    if constexpr (MODE >= 2) {
-#pragma unroll
-      for (int k = 0; k < KI; ++k) {
-        const int e = threadIdx.x + k * STDA_BLOCK;
-        const int px = e / G, y = y0 + px / TW, x = x0 + px % TW;
-        if (e < M * G && y < H && x < W) {
-          const int64_t off = (((int64_t)b * H + y) * W + x) * C + c0;
-          raw_ld4(dS + off, pg[k]);
-          raw_ld4(S + off, ps[k]);
-        } else {
-          raw_zero4(pg[k]);
-          raw_zero4(ps[k]);
-        }
-      }
-    }
-    __syncthreads();
-    if constexpr (!DMAX) {
-      // the three planes of the tile plus halo; all loads issued before the LDS writes
-      constexpr int KX = (NX + STDA_BLOCK - 1) / STDA_BLOCK;
-      float xv[KX];
+    // MODE 3: the three planes of the tile plus halo, loaded into registers first (then dS and S
+    // below), so that writing them to LDS waits for these loads only (the product does not wait
+    // for dS and S)
+    constexpr int KX = (NX + STDA_BLOCK - 1) / STDA_BLOCK;
+    float xv[DMAX ? 1 : KX];
+    if constexpr (!DMAX) {  // buffer loads: 0 off the map, no branch around the loads
+      const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(a.x + (int64_t)b * 3 * H * W),
+                                                                          (short)0, 3 * H * W * 4, 0x00020000);
 #pragma unroll
       for (int k = 0; k < KX; ++k) {
         const int q = threadIdx.x + k * STDA_BLOCK;
         const int c = q / (XR * XC), r = (q / XC) % XR, cc = q % XC;
         const int y = y0 - 1 + r, x = x0 - 1 + cc;
-        xv[k] = (q < NX && y >= 0 && y < H && x >= 0 && x < W) ? a.x[(((int64_t)b * 3 + c) * H + y) * W + x] : 0.f;
+        const bool in = q < NX && y >= 0 && y < H && x >= 0 && x < W;
+        xv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rx, in ? ((c * H + y) * W + x) * 4 : (int)0x80000000u, 0, 0));
       }
+    }
+    // adjoint modes: this thread's dS and S, loaded before the staging and the GEMM so that
+    // their latency overlaps them; buffer loads (0 off the map), so that every thread issues the
+    // same loads and the planes' wait above need not wait for these
+    constexpr int KI = M * G / STDA_BLOCK;
+    static_assert(M * G % STDA_BLOCK == 0, "whole items per thread");
+    typename Raw4<T>::type pg[KI], ps[KI];  // storage form: converted where used
+    if constexpr (MODE >= 2) {
+      const int cb = H * W * C * (int)sizeof(T);  // bytes of one clip (at most 1 GiB here)
+      const __amdgpu_buffer_rsrc_t rg =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(dS + (int64_t)b * H * W * C), (short)0, cb, 0x00020000);
+      const __amdgpu_buffer_rsrc_t rsv =
+          __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(S + (int64_t)b * H * W * C), (short)0, cb, 0x00020000);
+#pragma unroll
+      for (int k = 0; k < KI; ++k) {
+        const int px = (threadIdx.x + k * STDA_BLOCK) / G, y = y0 + px / TW, x = x0 + px % TW;
+        const int off = y < H && x < W ? ((y * W + x) * C + c0) * (int)sizeof(T) : (int)0x80000000u;
+        raw_bld4(rg, off, pg[k]);
+        raw_bld4(rsv, off, ps[k]);
+      }
+    }
+    __syncthreads();  // the previous tile's readers of xs and tt are done
+    if constexpr (!DMAX) {
 #pragma unroll
       for (int k = 0; k < KX; ++k) {
         const int q = threadIdx.x + k * STDA_BLOCK;
