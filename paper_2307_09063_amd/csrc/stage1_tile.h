@@ -801,16 +801,21 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
     typedef typename Raw4<T>::type R4;  // held in storage form until used
     R4 ng[NPF];
     uint32_t nm[NPF];  // the byte of M1 holding this thread's 4 decisions
+    // loaded ahead by buffer loads over this clip, which read 0 off the map: no branch around
+    // them, so every thread issues the same loads and a wait for one item's operands need not
+    // wait for the later items'
+    const int64_t cpx = (int64_t)b * h * w;  // the clip's first pixel
+    const __amdgpu_buffer_rsrc_t rm1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(M1 + cpx * (C / 8)),
+                                                                         (short)0, h * w * (C / 8), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rdx1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(dX1 + cpx * C), (short)0,
+                                                                          h * w * C * (int)sizeof(T), 0x00020000);
     auto a2_load = [&](int e, int k) {
       const int px = e / G, y = y0 - 1 + px / DWd, x = x0 - 1 + px % DWd;
-      if (e < NA && y >= 0 && y < h && x >= 0 && x < w) {
-        const int64_t off = (((int64_t)b * h + y) * w + x) * C + c0;
-        nm[k] = M1[off >> 3];  // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
-        raw_ld4(dX1 + off, ng[k]);
-      } else {
-        nm[k] = 0;
-        raw_zero4(ng[k]);
-      }
+      const bool in = e < NA && y >= 0 && y < h && x >= 0 && x < w;
+      const int off = (y * w + x) * C + c0;  // element offset in the clip
+      // byte (pixel, c0 / 8) of the mask: C / 8 bytes per pixel
+      nm[k] = __builtin_amdgcn_raw_buffer_load_b8(rm1, in ? off >> 3 : (int)0x80000000u, 0, 0);
+      raw_bld4(rdx1, in ? off * (int)sizeof(T) : (int)0x80000000u, ng[k]);
     };
     auto a2_first = [&]() {
 #pragma unroll
@@ -915,17 +920,19 @@ __global__ __launch_bounds__(256, MINW) void k_s1_bwd_fused(SegL<k_s1_bwd_fused_
     // pair ahead: the first pair's loads overlap the two products that follow
     constexpr int NB2 = (M / 2) * G;
     R4 nr[2], ns[2];
-    auto b2_load = [&](int e) {
+    const __amdgpu_buffer_rsrc_t rdxr = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(dXr + cpx * C), (short)0,
+                                                                          h * w * C * (int)sizeof(T), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rskp = __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(SKIP ? skip + cpx * C : dXr),
+                                                                          (short)0, h * w * C * (int)sizeof(T), 0x00020000);
+    auto b2_load = [&](int e) {  // buffer loads as above
       const int px = 2 * (e / G), y = y0 + px / TW, x = x0 + px % TW;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        raw_zero4(nr[s]);
-        raw_zero4(ns[s]);
-        if (e < NB2 && y < h && x + s < w) {
-          const int64_t off = (((int64_t)b * h + y) * w + x + s) * C + c0;
-          raw_ld4(dXr + off, nr[s]);
-          if (SKIP) raw_ld4(skip + off, ns[s]);
-        }
+        const bool in = e < NB2 && y < h && x + s < w;
+        const int off = in ? ((y * w + x + s) * C + c0) * (int)sizeof(T) : (int)0x80000000u;
+        raw_bld4(rdxr, off, nr[s]);
+        if (SKIP) raw_bld4(rskp, off, ns[s]);
+        else raw_zero4(ns[s]);
       }
     };
     constexpr bool PF2 = !LC;  // dX phase: load one pair ahead (else each pair loads its own)
