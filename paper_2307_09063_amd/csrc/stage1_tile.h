@@ -491,14 +491,15 @@ __global__ __launch_bounds__(256) void k_s1_bwd_stats_tile(SegL<k_s1_bwd_stats_t
   // BF16 (DMAB): the next tile's x is fetched in storage form by buffer loads into an LDS staging
   // buffer during a tile and converted at the start of the tile it belongs to; the thread's items
   // (at most two) load their x1 decisions and dx1 at the tile start, before that fetch is issued,
-  // so that waiting for them does not wait for it.  Only where the staging buffer keeps four
-  // workgroups (of 40 KiB at most) per CU.
+  // so that waiting for them does not wait for it.  Only where the staging buffer keeps three
+  // workgroups (of 53 KiB at most) per CU: the kernel's registers allow no more than three above
+  // 16 channels, and at 16 channels it still fits four.
   constexpr int NI = TH * TW * G;
   constexpr int LDS_BASE = 4 * (S1Lds<C, XN>::SIZE + S1Lds<C, PN>::SIZE + C * C + 9 * C + 20 * C);
   constexpr int SPPI = 64 * 16 / (C * (int)sizeof(T));                // pixels per staging load
   constexpr int XSL = (XN + 4 * SPPI - 1) / (4 * SPPI) * (4 * SPPI);  // staged pixels (whole loads in every wave)
   constexpr bool DMAB =
-      sizeof(T) == 2 && NI <= 2 * STDA_BLOCK && LDS_BASE + XSL * C * (int)sizeof(T) <= 40 * 1024;
+      sizeof(T) == 2 && NI <= 2 * STDA_BLOCK && LDS_BASE + XSL * C * (int)sizeof(T) <= 160 * 1024 / 3;
   __shared__ uint32_t xst[DMAB ? XSL * C * sizeof(T) / 4 : 1];
   stage1_load_weights<C, DEC>(prm.wpw, prm.wdw, wp, wd);
   const int c0 = (threadIdx.x % G) * 4;
