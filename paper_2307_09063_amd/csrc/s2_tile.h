@@ -148,16 +148,19 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(SegL<k_s2_tile_args<T, OP, 
     s2_tile_origin(tt, nty, ntx, TH, TW, lb, ly0, lx0);
     const int sy0 = C::DOWN ? 2 * ly0 - 1 : ly0 / 2 - C::SOFF;
     const int sx0 = C::DOWN ? 2 * lx0 - 1 : lx0 / 2 - C::SOFF;
+    // buffer loads over the clip, reading 0 off the map and past the rectangle: no branch around
+    // them, so every thread issues the same loads (and the stores after them are counted exactly)
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<T*>(src + (int64_t)lb * hs * ws * K), (short)0, hs * ws * K * (int)sizeof(T), 0x00020000);
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int e = threadIdx.x + i * BLK;
-      v[i] = make_uint4(0u, 0u, 0u, 0u);
-      if (e < TOTAL) {
-        const int c = e % CH, px = e / CH;
-        const int sy = sy0 + px / SW, sx = sx0 + px % SW;
-        if (sy >= 0 && sy < hs && sx >= 0 && sx < ws)
-          v[i] = *reinterpret_cast<const uint4*>(src + (((int64_t)lb * hs + sy) * ws + sx) * K + c * VE);
-      }
+      const int c = e % CH, px = e / CH;
+      const int sy = sy0 + px / SW, sx = sx0 + px % SW;
+      const bool ok = e < TOTAL && sy >= 0 && sy < hs && sx >= 0 && sx < ws;
+      const u32x4_t q = __builtin_amdgcn_raw_buffer_load_b128(rs, ok ? ((sy * ws + sx) * K + c * VE) * (int)sizeof(T)
+                                                                     : (int)0x80000000u, 0, 0);
+      v[i] = make_uint4(q.x, q.y, q.z, q.w);
     }
   };
   if (t_begin < t_end) load_src(t_begin);
@@ -271,17 +274,28 @@ __global__ __launch_bounds__(64 * WV) void k_s2_tile(SegL<k_s2_tile_args<T, OP, 
         }
     }
     __syncthreads();
-    // 5. staging -> global, 16-byte vectors, contiguous along each tile row
+    // 5. staging -> global, 16-byte vectors, contiguous along each tile row.  Buffer stores over
+    // this clip's output, an offset past its range (off the map or past the tile) dropping the
+    // store: no branch around them, so every thread issues the same stores and the next tile's
+    // wait for its source loads (issued before these) need not wait for these stores.  A clip's
+    // output is at most 1 GiB here (4096 x 4096 pixels of 16 FP32 channels at full resolution).
     {
       constexpr int CH = NB / VE;
-      constexpr int TOTAL = TH * TW * CH;
-      for (int e = threadIdx.x; e < TOTAL; e += BLK) {
-        const int c = e % CH, p = e / CH;
+      constexpr int TOTAL = TH * TW * CH, NSI = (TOTAL + BLK - 1) / BLK;
+      const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+          dst + (int64_t)b * hd * wd * N, (short)0, hd * wd * N * (int)sizeof(T), 0x00020000);
+#pragma unroll
+      for (int k = 0; k < NSI; ++k) {
+        const int e = threadIdx.x + k * BLK, ec = e < TOTAL ? e : TOTAL - 1;
+        const int c = ec % CH, p = ec / CH;
         const int ty = p / TW, tx = p % TW;
         const int y = y0 + ty, x = x0 + tx;
-        if (y < hd && x < wd)
-          *reinterpret_cast<uint4*>(dst + (((int64_t)b * hd + y) * wd + x) * N + cb * NB + c * VE) =
-              *reinterpret_cast<const uint4*>(tile_lds + p * C::OP_ + c * VE);
+        const bool ok = e < TOTAL && y < hd && x < wd;
+        const uint4 q = *reinterpret_cast<const uint4*>(tile_lds + p * C::OP_ + c * VE);
+        __builtin_amdgcn_raw_buffer_store_b128(u32x4_t{q.x, q.y, q.z, q.w}, rd,
+                                               ok ? ((y * wd + x) * N + cb * NB + c * VE) * (int)sizeof(T)
+                                                  : (int)0x80000000u,
+                                               0, 0);
       }
     }
   }
