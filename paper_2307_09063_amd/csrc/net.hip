@@ -1298,8 +1298,9 @@ template <class T, int C, bool DEC>
 int launch_s1b(const Ctx<T>& c, int blk, const S1bOps<T>* O, Parts& pw, Parts& dw) {
   const int v = tuned(sizeof(T) == 2 ? 1 : 0, 3, blk);
 #define S1B(TH_, TW_, W_) launch_s1b_cfg<T, C, DEC, TH_, TW_, W_>(c, blk, O, pw, dw)
-  // LC: depthwise taps and BN-adjoint coefficients read from LDS, three waves per SIMD
-#define S1L(TH_, TW_) launch_s1b_cfg<T, C, DEC, TH_, TW_, 3, true>(c, blk, O, pw, dw)
+  // LC: depthwise taps and BN-adjoint coefficients read from LDS, three waves per SIMD at 16
+  // channels (above, the LDS of three workgroups does not fit and two are asked for)
+#define S1L(TH_, TW_) launch_s1b_cfg<T, C, DEC, TH_, TW_, C == 16 ? 3 : 2, true>(c, blk, O, pw, dw)
   if constexpr (C == 16) return v == 1 ? S1B(16, 8, 2) : v == 2 ? S1B(4, 32, 2) : v == 3 ? S1L(8, 16) : S1B(8, 16, 2);
   else if constexpr (C == 32) return v == 1 ? S1B(4, 16, 2) : v == 2 ? S1B(16, 4, 2) : v == 3 ? S1L(8, 8) : S1B(8, 8, 2);
   else return v == 1 ? S1B(2, 8, 2) : v == 2 ? S1L(4, 4) : v == 3 ? S1B(4, 4, 1) : S1B(4, 4, 2);
